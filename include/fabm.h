@@ -1,0 +1,171 @@
+/*
+ * fabm.h -- C ABI of the MI355X (gfx950) library for the fractional
+ * Adams-Bashforth-Moulton predictor-corrector (Diethelm's method) as stated in
+ * Section 2 of Baban, Bonchis, Fikl, Rosu, "Parallel simulations for
+ * Fractional-Order Systems" (arXiv:1611.08678).
+ *
+ * Problem (Section 2, eq. (1)): D_*^alpha y(t) = f(t, y(t)) on [0, T], with
+ * 0 < alpha <= 1 and y(0) = y0 (for alpha <= 1 no higher initial derivative
+ * enters). The grid is t_n = n h, n = 0..N, T = N h. One step of the scheme
+ * (eq. (2) predictor, then the corrector) is, for target t = n + 1:
+ *
+ *   P_t  = sum_{k=0}^{t-1} b_{t-1-k} f_k
+ *   C_t  = c_{t-1} f_0 + sum_{k=1}^{t-1} a_{t-1-k} f_k
+ *   yP_t = y0 + h^alpha P_t,            fP_t = f(t_t, yP_t)
+ *   y_t  = y0 + h^alpha (C_t + fP_t / Gamma(alpha + 2)),  f_t = f(t_t, y_t)
+ *
+ * with b_m = ((m+1)^a - m^a)/Gamma(a+1),
+ *      a_m = ((m+2)^(a+1) - 2(m+1)^(a+1) + m^(a+1))/Gamma(a+2),
+ *      c_m = (m^(a+1) - (m-a)(m+1)^a)/Gamma(a+2)          (Section 2).
+ * (The paper prints b_m with a "+"; the minus sign is the one that makes the
+ * rule exact for constant f and is what this library computes.)
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked (device) are device memory on the current HIP device;
+ *     pointers marked (host) are host memory read before the call returns.
+ *     All floating point is IEEE binary64, row-major, state index fastest.
+ *   - The caller owns every buffer, including the workspace. The library never
+ *     allocates device memory; fabm_plan allocates host memory only (and one
+ *     small pinned staging buffer with its event).
+ *   - All device work is enqueued on `stream` and the call returns without
+ *     synchronising. Argument errors are detected on the host, before
+ *     anything is enqueued, and reported through the return value.
+ *   - Device pointers must be 8-byte aligned. Calls that share a plan must not
+ *     overlap in time unless they use distinct workspaces.
+ */
+#ifndef FABM_H
+#define FABM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FABM_OK = 0,
+    FABM_ERR_INVALID_ARG = 1, /* bad alpha/h/N/dim/pointer/size */
+    FABM_ERR_UNSUPPORTED = 2, /* valid request this library does not run (e.g. 1 < alpha < 2) */
+    FABM_ERR_WORKSPACE = 3,   /* workspace missing or smaller than required */
+    FABM_ERR_DEVICE = 4       /* a HIP call or kernel launch failed */
+} fabm_status;
+
+/* Right-hand sides f(t, y; theta) (the systems named in Section 1; the paper
+ * prints no equations, these are the usual textbook forms). Parameter layout
+ * of theta for each:
+ *   LINEAR     f = A y + b0 + b1 t; theta = A (d*d, row-major), b0 (d), b1 (d)
+ *   CHEN       (a(y-x), (c-a)x - xz + cy, xy - bz);  theta = (a, b, c), d = 3
+ *   ROSSLER    (-y-z, x + a y, b + z(x-c));          theta = (a, b, c), d = 3
+ *   VDP        (v, mu(1-x^2)v - x);                  theta = (mu),      d = 2
+ *   FINANCIAL  (z + (y-a)x, 1 - b y - x^2, -x - cz); theta = (a, b, c), d = 3 */
+typedef enum {
+    FABM_SYS_LINEAR = 0,
+    FABM_SYS_CHEN = 1,
+    FABM_SYS_ROSSLER = 2,
+    FABM_SYS_VDP = 3,
+    FABM_SYS_FINANCIAL = 4
+} fabm_system;
+
+/* How the history sums P_t, C_t are contracted.
+ *   DIRECT:  every step reduces the whole history against the weight rows
+ *            (an HBM/latency-bound GEMV per step).
+ *   BLOCKED: history split into past-block -> future-block Toeplitz tiles
+ *            contracted in bulk, plus a short sequential near-diagonal band.
+ *   AUTO:    the planner's choice. */
+typedef enum { FABM_PATH_AUTO = 0, FABM_PATH_DIRECT = 1, FABM_PATH_BLOCKED = 2 } fabm_path;
+
+/* Arithmetic of the far-history tiles of the BLOCKED path. The weights, the
+ * near-diagonal band and the corrector update are always binary64. */
+typedef enum { FABM_FAR_FP64 = 0, FABM_FAR_FP32 = 1, FABM_FAR_FP16X2 = 2 } fabm_far_prec;
+
+typedef struct {
+    fabm_system system;
+    int32_t dim;             /* state dimension d: LINEAR 1..64, else the system's own */
+    fabm_path path;
+    fabm_far_prec far_prec;
+    int64_t max_batch;       /* largest batch a call will pass (>= 1) */
+    int64_t max_steps;       /* largest N of any instance (>= 1) */
+    int64_t max_total_steps; /* largest sum of N over a batch; 0 means max_batch*max_steps */
+    int32_t tile_L;          /* BLOCKED block length, multiple of 64; 0 lets the planner choose */
+    int32_t flags;           /* reserved, must be 0 */
+} fabm_plan_desc;
+
+typedef struct fabm_plan_s *fabm_plan_t;
+
+/* Human-readable name of a status code (static string). */
+const char *fabm_status_string(fabm_status s);
+
+/* Number of entries of theta for a system of dimension dim (-1 if invalid). */
+int32_t fabm_n_params(fabm_system system, int32_t dim);
+
+/* Build a plan for the description. On success *out receives a host-side
+ * handle and *workspace_bytes (may be NULL) the device workspace size that
+ * covers any call within the described maxima. Errors: INVALID_ARG for a
+ * null pointer, unknown system, dim out of range, max_* < 1, bad tile_L or
+ * nonzero flags; UNSUPPORTED for a far precision the path does not offer. */
+fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *workspace_bytes);
+
+/* Release a plan (host memory only). NULL is ignored. */
+void fabm_plan_destroy(fabm_plan_t plan);
+
+/* Exact workspace bytes for one call with `batch` instances of lengths N
+ * (host, [batch]). Same checks as the solve calls on N. */
+fabm_status fabm_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *N,
+                                size_t *bytes);
+
+/* One trajectory (Section 2, eq. (1)-(2) and the corrector).
+ *   alpha  in (0, 1]  (1 < alpha < 2: UNSUPPORTED; else INVALID_ARG)
+ *   h      > 0, finite;   N >= 1, N <= plan max_steps
+ *   y0     (device) [d]           initial state y(0)
+ *   params (device) [n_params]    theta of the plan's system (may be NULL if n_params == 0)
+ *   y_out  (device) [N+1][d]      receives y_0 .. y_N
+ *   status (device) [1] int64     0, or the first step index whose state is not
+ *                                 finite (that row and all later rows are NaN),
+ *                                 or -1 if an inter-workgroup wait inside a
+ *                                 persistent kernel exceeded its 10 s bound
+ *                                 (rows not known to be final are NaN)
+ *   workspace (device), workspace_bytes >= fabm_workspace_size(plan, 1, &N). */
+fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes, double alpha,
+                       double h, int64_t N, const double *y0, const double *params,
+                       double *y_out, int64_t *status, hipStream_t stream);
+
+/* A batch of independent trajectories of one system, each with its own
+ * alpha, h, N, y0 and theta (ragged lengths), in one enqueue.
+ *   alpha, h (host) [batch];  N (host) [batch]
+ *   y0      (device) [batch][d];  params (device) [batch][n_params]
+ *   row_off (host) [batch]  first row of instance i in y_out; the rows
+ *           row_off[i] .. row_off[i] + N[i] must not overlap another instance's
+ *   y_out   (device) [total rows][d];  status (device) [batch] int64 as in fabm_solve. */
+fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                             int64_t batch, const double *alpha, const double *h,
+                             const int64_t *N, const double *y0, const double *params,
+                             const int64_t *row_off, double *y_out, int64_t *status,
+                             hipStream_t stream);
+
+/* Weight tables of Section 2 for one alpha, lags m = 0..n-1:
+ *   b (device) [n], a (device) [n], c (device) [n]  (any may be NULL).
+ * Computed in binary64 with cancellation-free rearrangements of the defining
+ * power differences (expm1/log1p for b, an all-positive binomial series for
+ * the second difference in a, a short series for c). */
+fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *c,
+                         hipStream_t stream);
+
+/* History sums alone for a given history (teacher forcing): for t = 1..N,
+ *   P[t-1] = sum_{k<t} b_{t-1-k} f[k],   C[t-1] = c_{t-1} f[0] + sum_{1<=k<t} a_{t-1-k} f[k]
+ *   f (device) [N][dim];  P, C (device) [N][dim].
+ * `path` selects the contraction kernel (DIRECT or BLOCKED, AUTO = BLOCKED);
+ * `far_prec` the far-tile arithmetic of BLOCKED. Workspace: at least
+ * fabm_history_workspace_size(N, dim) bytes. */
+fabm_status fabm_history_sums(double alpha, int64_t N, int32_t dim, const double *f, double *P,
+                              double *C, fabm_path path, fabm_far_prec far_prec,
+                              void *workspace, size_t workspace_bytes, hipStream_t stream);
+size_t fabm_history_workspace_size(int64_t N, int32_t dim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FABM_H */

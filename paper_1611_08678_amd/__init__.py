@@ -1,0 +1,246 @@
+"""MI355X (gfx950) library for the fractional Adams-Bashforth-Moulton
+predictor-corrector (Diethelm's method; Section 2 of arXiv:1611.08678).
+
+This module is a thin ctypes binding of the C ABI in ``include/fabm.h``: the
+functions carry the same names and arguments; torch tensors stand in for
+device pointers and the current torch stream for the HIP stream. All
+arithmetic runs in the HIP kernels of ``libfabm.so``; if that library is not
+built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libfabm.so")
+
+# enums of fabm.h
+FABM_OK, FABM_ERR_INVALID_ARG, FABM_ERR_UNSUPPORTED, FABM_ERR_WORKSPACE, FABM_ERR_DEVICE = range(5)
+FABM_SYS_LINEAR, FABM_SYS_CHEN, FABM_SYS_ROSSLER, FABM_SYS_VDP, FABM_SYS_FINANCIAL = range(5)
+FABM_PATH_AUTO, FABM_PATH_DIRECT, FABM_PATH_BLOCKED = range(3)
+FABM_FAR_FP64, FABM_FAR_FP32, FABM_FAR_FP16X2 = range(3)
+
+SYSTEMS = {"linear": FABM_SYS_LINEAR, "chen": FABM_SYS_CHEN, "rossler": FABM_SYS_ROSSLER,
+           "vdp": FABM_SYS_VDP, "financial": FABM_SYS_FINANCIAL}
+PATHS = {"auto": FABM_PATH_AUTO, "direct": FABM_PATH_DIRECT, "blocked": FABM_PATH_BLOCKED}
+FAR_PRECS = {"fp64": FABM_FAR_FP64, "fp32": FABM_FAR_FP32, "fp16x2": FABM_FAR_FP16X2}
+
+# exported symbols of the C ABI (checked by the test suite against fabm.h)
+EXPORTS = ("fabm_status_string", "fabm_n_params", "fabm_plan", "fabm_plan_destroy",
+           "fabm_workspace_size", "fabm_solve", "fabm_solve_batch", "fabm_weights",
+           "fabm_history_sums", "fabm_history_workspace_size")
+
+
+class FabmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+
+
+class _PlanDesc(C.Structure):
+    _fields_ = [("system", C.c_int), ("dim", C.c_int32), ("path", C.c_int),
+                ("far_prec", C.c_int), ("max_batch", C.c_int64), ("max_steps", C.c_int64),
+                ("max_total_steps", C.c_int64), ("tile_L", C.c_int32), ("flags", C.c_int32)]
+
+
+_lib = None
+_VP = C.c_void_p
+_I64P = C.POINTER(C.c_int64)
+_DP = C.POINTER(C.c_double)
+
+
+def load():
+    """Load libfabm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO):
+        raise ImportError(f"HIP library not built: {SO} is missing "
+                          "(run __graft_entry__.build() or python -m paper_1611_08678_amd.build)")
+    L = C.CDLL(SO)
+    L.fabm_status_string.argtypes = [C.c_int]
+    L.fabm_status_string.restype = C.c_char_p
+    L.fabm_n_params.argtypes = [C.c_int, C.c_int32]
+    L.fabm_n_params.restype = C.c_int32
+    L.fabm_plan.argtypes = [C.POINTER(_PlanDesc), C.POINTER(_VP), C.POINTER(C.c_size_t)]
+    L.fabm_plan.restype = C.c_int
+    L.fabm_plan_destroy.argtypes = [_VP]
+    L.fabm_plan_destroy.restype = None
+    L.fabm_workspace_size.argtypes = [_VP, C.c_int64, _I64P, C.POINTER(C.c_size_t)]
+    L.fabm_workspace_size.restype = C.c_int
+    L.fabm_solve.argtypes = [_VP, _VP, C.c_size_t, C.c_double, C.c_double, C.c_int64, _VP, _VP,
+                             _VP, _VP, _VP]
+    L.fabm_solve.restype = C.c_int
+    L.fabm_solve_batch.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP, _VP,
+                                   _I64P, _VP, _VP, _VP]
+    L.fabm_solve_batch.restype = C.c_int
+    L.fabm_weights.argtypes = [C.c_double, C.c_int64, _VP, _VP, _VP, _VP]
+    L.fabm_weights.restype = C.c_int
+    L.fabm_history_sums.argtypes = [C.c_double, C.c_int64, C.c_int32, _VP, _VP, _VP, C.c_int,
+                                    C.c_int, _VP, C.c_size_t, _VP]
+    L.fabm_history_sums.restype = C.c_int
+    L.fabm_history_workspace_size.argtypes = [C.c_int64, C.c_int32]
+    L.fabm_history_workspace_size.restype = C.c_size_t
+    _lib = L
+    return L
+
+
+def status_string(code: int) -> str:
+    try:
+        return load().fabm_status_string(int(code)).decode()
+    except ImportError:
+        return "?"
+
+
+def _check(code: int, where: str):
+    if code != FABM_OK:
+        raise FabmError(code, where)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None for None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _enum(v, table):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def fabm_n_params(system, dim: int) -> int:
+    return int(load().fabm_n_params(_enum(system, SYSTEMS), int(dim)))
+
+
+@dataclass
+class Plan:
+    handle: C.c_void_p
+    workspace_bytes: int
+    system: int
+    dim: int
+    n_params: int
+    path: int
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.fabm_plan_destroy(self.handle)
+            self.handle = None
+
+
+def fabm_plan(system, dim: int, path="auto", far_prec="fp64", max_batch: int = 1,
+              max_steps: int = 1, max_total_steps: int = 0, tile_L: int = 0) -> Plan:
+    L = load()
+    desc = _PlanDesc(_enum(system, SYSTEMS), int(dim), _enum(path, PATHS),
+                     _enum(far_prec, FAR_PRECS), int(max_batch), int(max_steps),
+                     int(max_total_steps), int(tile_L), 0)
+    h = C.c_void_p()
+    ws = C.c_size_t()
+    _check(L.fabm_plan(C.byref(desc), C.byref(h), C.byref(ws)), "fabm_plan")
+    return Plan(h, int(ws.value), desc.system, desc.dim, fabm_n_params(desc.system, desc.dim),
+                desc.path)
+
+
+def fabm_workspace_size(plan: Plan, N) -> int:
+    import numpy as np
+    Ns = np.ascontiguousarray(np.atleast_1d(N), dtype=np.int64)
+    out = C.c_size_t()
+    _check(load().fabm_workspace_size(plan.handle, Ns.size, Ns.ctypes.data_as(_I64P),
+                                      C.byref(out)), "fabm_workspace_size")
+    return int(out.value)
+
+
+def fabm_solve(plan: Plan, workspace, alpha: float, h: float, N: int, y0, params, y_out,
+               status, stream=None):
+    _check(load().fabm_solve(plan.handle, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                             float(alpha), float(h), int(N), _ptr(y0), _ptr(params), _ptr(y_out),
+                             _ptr(status), _stream(stream)), "fabm_solve")
+
+
+def fabm_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out, status,
+                     stream=None):
+    import numpy as np
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    hh = np.ascontiguousarray(h, dtype=np.float64)
+    Ns = np.ascontiguousarray(N, dtype=np.int64)
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    _check(load().fabm_solve_batch(plan.handle, _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), al.size,
+                                   al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
+                                   Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
+                                   ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
+                                   _stream(stream)), "fabm_solve_batch")
+
+
+def fabm_weights(alpha: float, n: int, b, a, c, stream=None):
+    _check(load().fabm_weights(float(alpha), int(n), _ptr(b), _ptr(a), _ptr(c), _stream(stream)),
+           "fabm_weights")
+
+
+def fabm_history_workspace_size(N: int, dim: int) -> int:
+    return int(load().fabm_history_workspace_size(int(N), int(dim)))
+
+
+def fabm_history_sums(alpha: float, N: int, dim: int, f, P, Cs, path="auto", far_prec="fp64",
+                      workspace=None, stream=None):
+    _check(load().fabm_history_sums(float(alpha), int(N), int(dim), _ptr(f), _ptr(P), _ptr(Cs),
+                                    _enum(path, PATHS), _enum(far_prec, FAR_PRECS),
+                                    _ptr(workspace),
+                                    0 if workspace is None else workspace.numel() * workspace.element_size(),
+                                    _stream(stream)), "fabm_history_sums")
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrappers: allocate outputs and workspace with torch, then call
+# the ABI above. No arithmetic happens here.
+# ---------------------------------------------------------------------------
+def _workspace(nbytes: int):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_prec="fp64",
+          plan: Plan | None = None):
+    """One trajectory; returns (y [N+1, d] float64 device tensor, status int)."""
+    import torch
+    y0 = torch.as_tensor(y0, dtype=torch.float64, device="cuda").contiguous().reshape(-1)
+    th = torch.as_tensor(theta, dtype=torch.float64, device="cuda").contiguous().reshape(-1)
+    d = y0.numel()
+    if plan is None:
+        plan = fabm_plan(system, d, path, far_prec, 1, N)
+    ws = _workspace(fabm_workspace_size(plan, [N]))
+    y = torch.empty((N + 1, d), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int64, device="cuda")
+    fabm_solve(plan, ws, alpha, h, N, y0, th, y, st)
+    return y, st
+
+
+def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64",
+                plan: Plan | None = None):
+    """Ragged batch; returns (y_rows [sum(N+1), d], row_off numpy, status tensor)."""
+    import numpy as np
+    import torch
+    y0s = torch.as_tensor(y0s, dtype=torch.float64, device="cuda").contiguous()
+    B, d = y0s.shape
+    th = torch.as_tensor(thetas, dtype=torch.float64, device="cuda").contiguous().reshape(B, -1)
+    Ns = np.ascontiguousarray(Ns, dtype=np.int64)
+    row_off = np.zeros(B, dtype=np.int64)
+    row_off[1:] = np.cumsum(Ns + 1)[:-1]
+    if plan is None:
+        plan = fabm_plan(system, d, path, far_prec, B, int(Ns.max()), int(Ns.sum()))
+    ws = _workspace(fabm_workspace_size(plan, Ns))
+    y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
+    st = torch.zeros(B, dtype=torch.int64, device="cuda")
+    fabm_solve_batch(plan, ws, alphas, hs, Ns, y0s, th, row_off, y, st)
+    return y, row_off, st

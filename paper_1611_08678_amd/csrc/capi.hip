@@ -1,0 +1,538 @@
+// capi.hip -- the C ABI declared in include/fabm.h: argument validation,
+// path choice, workspace layout, per-call instance metadata and schedules,
+// kernel dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fabm.h"
+#include "fabm_blocked.h"
+#include "fabm_device.h"
+#include "fabm_launch.h"
+
+using fabm::InstMeta;
+
+struct fabm_plan_s {
+    fabm_plan_desc desc;
+    int32_t n_params;
+    int device;
+    int grid_G;          // workgroups of the persistent single-trajectory kernels
+    char *h_stage;       // pinned staging: instance table, then the far-task schedule
+    size_t stage_cap;
+    hipEvent_t stage_ev; // recorded after the staging copy; waited on before reuse
+    bool stage_pending;
+    uint64_t timeout_ticks;  // bound of every inter-workgroup wait (device wall clock)
+    // BLOCKED pipeline: second stream, event rings, cached schedule
+    hipStream_t s_far;
+    hipEvent_t ev_band[32], ev_far[32], ev_fork, ev_join;
+    bool have_pipe;
+    fabm::PipeSchedule sched;  // schedule of the last block count used
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxLinearDim = 64;
+constexpr int64_t kGridDirectMinSteps = 8192;  // single trajectories this long use the grid kernel
+constexpr int kGridMax = 256;                  // MI355X compute units
+constexpr int64_t kAutoBlockedMinSteps = 1024;
+constexpr uint64_t kWaitTimeoutSeconds = 10;  // no legitimate wait comes near this
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool aligned8(const void *p) { return p && ((uintptr_t)p & 7u) == 0; }
+
+int32_t n_params_of(int sys, int d)
+{
+    switch (sys) {
+    case FABM_SYS_LINEAR: return (d >= 1 && d <= kMaxLinearDim) ? d * d + 2 * d : -1;
+    case FABM_SYS_CHEN:
+    case FABM_SYS_ROSSLER:
+    case FABM_SYS_FINANCIAL: return d == 3 ? 3 : -1;
+    case FABM_SYS_VDP: return d == 2 ? 1 : -1;
+    default: return -1;
+    }
+}
+
+fabm_status check_alpha_h(double alpha, double h)
+{
+    if (!std::isfinite(alpha) || !std::isfinite(h) || h <= 0.0 || alpha <= 0.0)
+        return FABM_ERR_INVALID_ARG;
+    if (alpha > 1.0 && alpha < 2.0) return FABM_ERR_UNSUPPORTED;
+    if (alpha > 1.0) return FABM_ERR_INVALID_ARG;
+    return FABM_OK;
+}
+
+enum class Path { Direct, Blocked, Unsupported };
+
+Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
+{
+    switch (pl->desc.path) {
+    case FABM_PATH_DIRECT: return Path::Direct;
+    case FABM_PATH_BLOCKED: return batch == 1 ? Path::Blocked : Path::Unsupported;
+    default: return (batch == 1 && N[0] >= kAutoBlockedMinSteps) ? Path::Blocked : Path::Direct;
+    }
+}
+
+// Device workspace of one solve call (offsets in bytes). The first
+// `stage_bytes` bytes are copied from the plan's pinned staging buffer.
+struct Layout {
+    Path path;
+    size_t meta, items, reds, tt_off, tt_slot, stage_bytes;
+    size_t w, f, part, carry, far, task_slot, scratch, sync, n_sync_words, total;
+    int64_t wlen;
+    int NB;
+};
+
+const fabm::PipeSchedule &schedule_for(const fabm_plan_s *pl, int NB)
+{
+    fabm_plan_s *mp = const_cast<fabm_plan_s *>(pl);  // host-side cache only
+    if (mp->sched.NB != NB) fabm::pipe_schedule(NB, mp->sched);
+    return mp->sched;
+}
+
+Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
+{
+    Layout L{};
+    L.path = choose_path(pl, batch, N);
+    const int d = pl->desc.dim;
+    int64_t sumN = 0, sumRows = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        sumN += N[i];
+        sumRows += N[i] + 1;
+    }
+    size_t off = 0;
+    L.meta = off;
+    off += sizeof(InstMeta) * (size_t)batch;
+    if (L.path == Path::Blocked) {
+        const int Lb = fabm::pipe_block_len();
+        L.NB = (int)((N[0] + 1 + Lb - 1) / Lb);
+        const fabm::PipeSchedule &S = schedule_for(pl, L.NB);
+        L.wlen = (int64_t)L.NB * Lb + Lb;
+        const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;  // one [2d][256] tile of sums
+        off = (off + 15) / 16 * 16;
+        L.items = off;
+        off += sizeof(int4) * S.items.size();
+        L.reds = off;
+        off += sizeof(int4) * S.reds.size();
+        L.tt_off = off;
+        off += sizeof(int) * S.tt_off.size();
+        L.tt_slot = off;
+        off += sizeof(int) * S.tt_slot.size();
+        L.stage_bytes = off;
+        off = align_up(off);
+        L.w = off;
+        off = align_up(off + sizeof(double) * 3 * (size_t)L.wlen);
+        L.f = off;  // component-major history [d][NB*256]
+        off = align_up(off + sizeof(double) * (size_t)d * (size_t)L.NB * Lb);
+        L.carry = off;
+        off = align_up(off + 2 * blk);
+        L.far = off;
+        off = align_up(off + blk * (size_t)L.NB);
+        L.task_slot = off;
+        off = align_up(off + blk * (size_t)S.n_slots);
+        L.scratch = off;
+        off = align_up(off + blk * (size_t)S.max_scratch);
+        L.sync = off;
+        L.n_sync_words = 64;
+        off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
+    } else {
+        L.wlen = 0;
+        L.stage_bytes = off;
+        off = align_up(off);
+        L.w = off;
+        off = align_up(off + sizeof(double) * 3 * (size_t)sumN);
+        L.f = off;
+        off = align_up(off + sizeof(double) * (size_t)d * (size_t)sumRows);
+        L.part = off;  // grid-kernel partials [G][2d]
+        off = align_up(off + sizeof(double) * 2 * (size_t)d * kGridMax);
+        L.sync = off;
+        L.n_sync_words = 64;
+        off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
+    }
+    L.total = off;
+    return L;
+}
+
+void host_scalars(double alpha, double h, InstMeta &m)
+{
+    m.alpha = alpha;
+    m.h = h;
+    // extended precision on the host, one rounding to binary64
+    const long double al = alpha;
+    m.ha = (double)std::pow((long double)h, al);
+    m.ig1 = (double)(1.0L / std::tgamma(al + 1.0L));
+    m.ig2 = (double)(1.0L / std::tgamma(al + 2.0L));
+}
+
+fabm_status ok_or_device(hipError_t e) { return e == hipSuccess ? FABM_OK : FABM_ERR_DEVICE; }
+
+// Device-side resources of a plan, created at its first solve so that
+// fabm_plan itself touches no device.
+fabm_status ensure_device(fabm_plan_s *pl)
+{
+    if (pl->h_stage) return FABM_OK;
+    int cus = 0;
+    if (hipGetDevice(&pl->device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) !=
+            hipSuccess)
+        return FABM_ERR_DEVICE;
+    pl->grid_G = std::min(cus, kGridMax);
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, pl->device) !=
+            hipSuccess ||
+        rate_khz <= 0)
+        rate_khz = 100000;  // gfx9 constant clock: 100 MHz
+    pl->timeout_ticks = (uint64_t)rate_khz * 1000u * kWaitTimeoutSeconds;
+    pl->stage_cap = sizeof(InstMeta) * (size_t)pl->desc.max_batch;
+    if (hipHostMalloc((void **)&pl->h_stage, pl->stage_cap, hipHostMallocDefault) != hipSuccess) {
+        pl->h_stage = nullptr;
+        return FABM_ERR_DEVICE;
+    }
+    if (hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(pl->h_stage);
+        pl->h_stage = nullptr;
+        return FABM_ERR_DEVICE;
+    }
+    return FABM_OK;
+}
+
+// Second stream and event rings of the BLOCKED pipeline (first blocked call).
+fabm_status ensure_pipe(fabm_plan_s *pl)
+{
+    if (pl->have_pipe) return FABM_OK;
+    if (hipStreamCreateWithFlags(&pl->s_far, hipStreamNonBlocking) != hipSuccess)
+        return FABM_ERR_DEVICE;
+    for (int i = 0; i < 32; ++i)
+        if (hipEventCreateWithFlags(&pl->ev_band[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&pl->ev_far[i], hipEventDisableTiming) != hipSuccess)
+            return FABM_ERR_DEVICE;
+    if (hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)
+        return FABM_ERR_DEVICE;
+    pl->have_pipe = true;
+    return FABM_OK;
+}
+
+// Grow the pinned staging buffer (only between calls, after the last copy
+// out of it has completed).
+fabm_status ensure_stage(fabm_plan_s *pl, size_t bytes)
+{
+    if (bytes <= pl->stage_cap) return FABM_OK;
+    (void)hipHostFree(pl->h_stage);
+    pl->h_stage = nullptr;
+    pl->stage_cap = 0;
+    if (hipHostMalloc((void **)&pl->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
+        return FABM_ERR_DEVICE;
+    pl->stage_cap = bytes;
+    return FABM_OK;
+}
+
+fabm_status wait_staging(fabm_plan_s *pl)
+{
+    if (pl->stage_pending) {
+        if (hipEventSynchronize(pl->stage_ev) != hipSuccess) return FABM_ERR_DEVICE;
+        pl->stage_pending = false;
+    }
+    return FABM_OK;
+}
+
+fabm_status stage_copy(fabm_plan_s *pl, size_t bytes, void *dst, hipStream_t s)
+{
+    if (hipMemcpyAsync(dst, pl->h_stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        return FABM_ERR_DEVICE;
+    if (hipEventRecord(pl->stage_ev, s) != hipSuccess) return FABM_ERR_DEVICE;
+    pl->stage_pending = true;
+    return FABM_OK;
+}
+
+// Shared body of fabm_solve and fabm_solve_batch after validation.
+fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *alpha,
+                      const double *h, const int64_t *N, const double *y0, const double *params,
+                      const int64_t *row_off, double *y_out, int64_t *status, hipStream_t s)
+{
+    const int d = pl->desc.dim;
+    const Layout L = layout_for(pl, batch, N);
+    if (L.path == Path::Unsupported) return FABM_ERR_UNSUPPORTED;
+    fabm_status st = ensure_device(pl);
+    if (st != FABM_OK) return st;
+    if ((st = wait_staging(pl)) != FABM_OK) return st;
+    if ((st = ensure_stage(pl, L.stage_bytes)) != FABM_OK) return st;
+
+    InstMeta *hm = (InstMeta *)(pl->h_stage + L.meta);
+    int64_t w_off = 0, f_off = 0, maxw = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        InstMeta &m = hm[i];
+        host_scalars(alpha[i], h[i], m);
+        m.N = N[i];
+        m.row_off = row_off ? row_off[i] : 0;
+        m.wlen = L.path == Path::Blocked ? L.wlen : N[i];
+        m.w_off = w_off;
+        m.p_off = (int64_t)pl->n_params * i;
+        m.f_off = f_off;
+        w_off += 3 * m.wlen;
+        f_off += N[i] + 1;
+        maxw = std::max(maxw, m.wlen);
+    }
+    char *base = (char *)ws;
+    if (L.path == Path::Blocked) {
+        const fabm::PipeSchedule &S = schedule_for(pl, L.NB);
+        std::memcpy(pl->h_stage + L.items, S.items.data(), sizeof(int4) * S.items.size());
+        std::memcpy(pl->h_stage + L.reds, S.reds.data(), sizeof(int4) * S.reds.size());
+        std::memcpy(pl->h_stage + L.tt_off, S.tt_off.data(), sizeof(int) * S.tt_off.size());
+        std::memcpy(pl->h_stage + L.tt_slot, S.tt_slot.data(), sizeof(int) * S.tt_slot.size());
+    }
+    if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
+
+    InstMeta *dmeta = (InstMeta *)(base + L.meta);
+    double *W = (double *)(base + L.w);
+    uint32_t *sync = (uint32_t *)(base + L.sync);
+    if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK) return st;
+    if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
+        FABM_OK)
+        return st;
+    double *Yi = y_out + (row_off ? row_off[0] : 0) * d;  // single-trajectory kernels
+
+    if (L.path == Path::Blocked) {
+        if ((st = ensure_pipe(pl)) != FABM_OK) return st;
+        const fabm::PipeSchedule &S = schedule_for(pl, L.NB);
+        fabm::PipeArgs A{};
+        A.meta = dmeta;
+        A.params = params;
+        A.y0 = y0;
+        A.Y = Yi;
+        A.W = W;
+        A.Fc = (double *)(base + L.f);
+        A.carry = (double *)(base + L.carry);
+        A.far = (double *)(base + L.far);
+        A.task_slot = (double *)(base + L.task_slot);
+        A.scratch = (double *)(base + L.scratch);
+        A.items = (const int4 *)(base + L.items);
+        A.reds = (const int4 *)(base + L.reds);
+        A.tt_off = (const int *)(base + L.tt_off);
+        A.tt_slot = (const int *)(base + L.tt_slot);
+        A.dead = sync;
+        A.status = status;
+        A.NB = L.NB;
+        // fork the far stream off the caller's stream, join it back at the end
+        if (hipEventRecord(pl->ev_fork, s) != hipSuccess ||
+            hipStreamWaitEvent(pl->s_far, pl->ev_fork, 0) != hipSuccess)
+            return FABM_ERR_DEVICE;
+        if ((st = ok_or_device(fabm::enqueue_pipe(pl->desc.system, d, A, S, s, pl->s_far,
+                                                  pl->ev_band, pl->ev_far, 32))) != FABM_OK)
+            return st;
+        if (hipEventRecord(pl->ev_join, pl->s_far) != hipSuccess ||
+            hipStreamWaitEvent(s, pl->ev_join, 0) != hipSuccess)
+            return FABM_ERR_DEVICE;
+        return FABM_OK;
+    }
+    double *F = (double *)(base + L.f);
+    if (batch == 1 && N[0] >= kGridDirectMinSteps) {
+        double *part = (double *)(base + L.part);
+        return ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta,
+                                                     params, y0, F, W, Yi, status, part, sync,
+                                                     pl->timeout_ticks, s));
+    }
+    return ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, batch, params, y0, F,
+                                               W, y_out, status, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fabm_status_string(fabm_status s)
+{
+    switch (s) {
+    case FABM_OK: return "ok";
+    case FABM_ERR_INVALID_ARG: return "invalid argument";
+    case FABM_ERR_UNSUPPORTED: return "unsupported";
+    case FABM_ERR_WORKSPACE: return "workspace too small";
+    case FABM_ERR_DEVICE: return "device error";
+    default: return "unknown status";
+    }
+}
+
+int32_t fabm_n_params(fabm_system system, int32_t dim) { return n_params_of(system, dim); }
+
+fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *workspace_bytes)
+{
+    if (!desc || !out) return FABM_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int32_t np = n_params_of(desc->system, desc->dim);
+    if (np < 0) return FABM_ERR_INVALID_ARG;
+    if (desc->max_batch < 1 || desc->max_steps < 1 || desc->max_total_steps < 0 ||
+        desc->flags != 0 || desc->max_steps > ((int64_t)1 << 30))
+        return FABM_ERR_INVALID_ARG;
+    if (desc->tile_L < 0 || desc->tile_L % 64 != 0) return FABM_ERR_INVALID_ARG;
+    if (desc->path != FABM_PATH_AUTO && desc->path != FABM_PATH_DIRECT &&
+        desc->path != FABM_PATH_BLOCKED)
+        return FABM_ERR_INVALID_ARG;
+    if (desc->far_prec != FABM_FAR_FP64 && desc->far_prec != FABM_FAR_FP32 &&
+        desc->far_prec != FABM_FAR_FP16X2)
+        return FABM_ERR_INVALID_ARG;
+    // far tiles run in FP64 only in this build; the block length is fixed
+    if (desc->far_prec != FABM_FAR_FP64) return FABM_ERR_UNSUPPORTED;
+    if (desc->tile_L != 0 && desc->tile_L != fabm::pipe_block_len())
+        return FABM_ERR_UNSUPPORTED;
+    // kernels keep the state in registers: LINEAR up to d = 4
+    if (desc->system == FABM_SYS_LINEAR && desc->dim > 4) return FABM_ERR_UNSUPPORTED;
+
+    fabm_plan_s *pl = new (std::nothrow) fabm_plan_s();
+    if (!pl) return FABM_ERR_INVALID_ARG;
+    pl->desc = *desc;
+    pl->n_params = np;
+    pl->grid_G = kGridMax;
+    if (workspace_bytes) {
+        const int64_t total =
+            desc->max_total_steps ? desc->max_total_steps : desc->max_batch * desc->max_steps;
+        std::vector<int64_t> Ns((size_t)desc->max_batch, 0);
+        int64_t left = total;
+        for (auto &n : Ns) {
+            n = std::max<int64_t>(1, std::min(desc->max_steps, left));
+            left -= n;
+        }
+        size_t ws = desc->path == FABM_PATH_BLOCKED && desc->max_batch > 1
+                        ? 0
+                        : layout_for(pl, desc->max_batch, Ns.data()).total;
+        int64_t one = desc->max_steps;
+        ws = std::max(ws, layout_for(pl, 1, &one).total);
+        *workspace_bytes = ws;
+    }
+    *out = pl;
+    return FABM_OK;
+}
+
+void fabm_plan_destroy(fabm_plan_t plan)
+{
+    if (!plan) return;
+    if (plan->h_stage) {
+        if (plan->stage_pending) (void)hipEventSynchronize(plan->stage_ev);
+        (void)hipEventDestroy(plan->stage_ev);
+        (void)hipHostFree(plan->h_stage);
+    }
+    if (plan->have_pipe) {
+        (void)hipStreamSynchronize(plan->s_far);
+        for (int i = 0; i < 32; ++i) {
+            (void)hipEventDestroy(plan->ev_band[i]);
+            (void)hipEventDestroy(plan->ev_far[i]);
+        }
+        (void)hipEventDestroy(plan->ev_fork);
+        (void)hipEventDestroy(plan->ev_join);
+        (void)hipStreamDestroy(plan->s_far);
+    }
+    delete plan;
+}
+
+fabm_status fabm_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *N, size_t *bytes)
+{
+    if (!plan || !N || !bytes || batch < 1 || batch > plan->desc.max_batch)
+        return FABM_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < batch; ++i)
+        if (N[i] < 1 || N[i] > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
+    const Layout L = layout_for(plan, batch, N);
+    if (L.path == Path::Unsupported) return FABM_ERR_UNSUPPORTED;
+    *bytes = L.total;
+    return FABM_OK;
+}
+
+fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes, double alpha,
+                       double h, int64_t N, const double *y0, const double *params,
+                       double *y_out, int64_t *status, hipStream_t stream)
+{
+    if (!plan) return FABM_ERR_INVALID_ARG;
+    fabm_status st = check_alpha_h(alpha, h);
+    if (st != FABM_OK) return st;
+    if (N < 1 || N > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
+    if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && !aligned8(params)) return FABM_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
+    if (workspace_bytes < layout_for(plan, 1, &N).total) return FABM_ERR_WORKSPACE;
+    return run_solve(plan, workspace, 1, &alpha, &h, &N, y0, params, nullptr, y_out, status,
+                     stream);
+}
+
+fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                             int64_t batch, const double *alpha, const double *h,
+                             const int64_t *N, const double *y0, const double *params,
+                             const int64_t *row_off, double *y_out, int64_t *status,
+                             hipStream_t stream)
+{
+    if (!plan || !alpha || !h || !N || !row_off) return FABM_ERR_INVALID_ARG;
+    if (batch < 1 || batch > plan->desc.max_batch) return FABM_ERR_INVALID_ARG;
+    const int64_t total_cap = plan->desc.max_total_steps
+                                  ? plan->desc.max_total_steps
+                                  : plan->desc.max_batch * plan->desc.max_steps;
+    int64_t sumN = 0;
+    std::vector<std::pair<int64_t, int64_t>> spans((size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) {
+        fabm_status st = check_alpha_h(alpha[i], h[i]);
+        if (st != FABM_OK) return st;
+        if (N[i] < 1 || N[i] > plan->desc.max_steps || row_off[i] < 0)
+            return FABM_ERR_INVALID_ARG;
+        sumN += N[i];
+        spans[(size_t)i] = {row_off[i], row_off[i] + N[i] + 1};
+    }
+    if (sumN > total_cap) return FABM_ERR_INVALID_ARG;
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return FABM_ERR_INVALID_ARG;
+    if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && !aligned8(params)) return FABM_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
+    const Layout L = layout_for(plan, batch, N);
+    if (L.path == Path::Unsupported) return FABM_ERR_UNSUPPORTED;
+    if (workspace_bytes < L.total) return FABM_ERR_WORKSPACE;
+    return run_solve(plan, workspace, batch, alpha, h, N, y0, params, row_off, y_out, status,
+                     stream);
+}
+
+fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *c,
+                         hipStream_t stream)
+{
+    fabm_status st = check_alpha_h(alpha, 1.0);
+    if (st != FABM_OK) return st;
+    if (n < 1) return FABM_ERR_INVALID_ARG;
+    if ((b && !aligned8(b)) || (a && !aligned8(a)) || (c && !aligned8(c)))
+        return FABM_ERR_INVALID_ARG;
+    InstMeta m{};
+    host_scalars(alpha, 1.0, m);
+    return ok_or_device(fabm::launch_weights_one(alpha, m.ig1, m.ig2, n, b, a, c, stream));
+}
+
+size_t fabm_history_workspace_size(int64_t N, int32_t dim)
+{
+    (void)dim;
+    if (N < 1) return 0;
+    return align_up(sizeof(double) * 3 * (size_t)N);
+}
+
+fabm_status fabm_history_sums(double alpha, int64_t N, int32_t dim, const double *f, double *P,
+                              double *C, fabm_path path, fabm_far_prec far_prec,
+                              void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    fabm_status st = check_alpha_h(alpha, 1.0);
+    if (st != FABM_OK) return st;
+    if (N < 1 || dim < 1) return FABM_ERR_INVALID_ARG;
+    if (dim > 4) return FABM_ERR_UNSUPPORTED;
+    if (!aligned8(f) || !aligned8(P) || !aligned8(C)) return FABM_ERR_INVALID_ARG;
+    if (far_prec != FABM_FAR_FP64 && far_prec != FABM_FAR_FP32 && far_prec != FABM_FAR_FP16X2)
+        return FABM_ERR_INVALID_ARG;
+    if (path != FABM_PATH_AUTO && path != FABM_PATH_DIRECT && path != FABM_PATH_BLOCKED)
+        return FABM_ERR_INVALID_ARG;
+    if (path != FABM_PATH_DIRECT) return FABM_ERR_UNSUPPORTED;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0 ||
+        workspace_bytes < fabm_history_workspace_size(N, dim))
+        return FABM_ERR_WORKSPACE;
+    InstMeta m{};
+    host_scalars(alpha, 1.0, m);
+    double *W = (double *)workspace;
+    if ((st = ok_or_device(fabm::launch_weights_one(alpha, m.ig1, m.ig2, N, W, W + N, W + 2 * N,
+                                                    stream))) != FABM_OK)
+        return st;
+    return ok_or_device(fabm::launch_history_direct(W, N, dim, f, P, C, stream));
+}
+
+}  // extern "C"

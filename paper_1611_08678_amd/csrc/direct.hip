@@ -1,0 +1,372 @@
+// direct.hip -- the DIRECT contraction path: at every step t the whole
+// history f_0..f_{t-1} is reduced against the weight rows b_{t-1-k} and
+// a_{t-1-k} (Section 2: the predictor sum of eq. (2) and the corrector sum),
+// followed by the PECE update. Two shapes:
+//
+//  * k_direct_wg: one 256-thread workgroup per trajectory. Each step is a
+//    coalesced strided pass over the history, a wavefront butterfly sum and an
+//    LDS combine of the four wavefronts; lane 0 then forms y_t and f_t. Used
+//    for batches of independent trajectories and for short ones.
+//
+//  * k_direct_grid: one long trajectory over the whole GPU (one persistent
+//    workgroup per compute unit, cooperative launch so all are resident).
+//    Each step every workgroup reduces a contiguous slice of [0, t), writes
+//    its partial and signals an arrival counter; workgroup 0 waits for all
+//    arrivals, adds the partials in a fixed order (deterministic), forms row t
+//    and publishes it. Step time is bound by HBM streaming of the history and
+//    weight rows at large t and by the two inter-workgroup hand-offs at small t.
+#include "fabm_device.h"
+#include "fabm_launch.h"
+
+namespace fabm {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+
+template <int D>
+__device__ __forceinline__ void block_sum2(double (&sp)[D], double (&sc)[D],
+                                           double (*red)[2 * D], int tid)
+{
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        sp[i] = wave_sum(sp[i]);
+        sc[i] = wave_sum(sc[i]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            red[wv][i] = sp[i];
+            red[wv][D + i] = sc[i];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double a = red[0][i], c = red[0][D + i];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            a += red[w][i];
+            c += red[w][D + i];
+        }
+        sp[i] = a;
+        sc[i] = c;
+    }
+}
+
+// Partial history sums over k in [lo, hi) for target t (strided by the block).
+template <int D>
+__device__ __forceinline__ void partial_sums(const double *__restrict__ Fh,
+                                             const double *__restrict__ wb,
+                                             const double *__restrict__ wa,
+                                             const double *__restrict__ wc, int64_t t, int64_t lo,
+                                             int64_t hi, int tid, double (&sp)[D], double (&sc)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) sp[i] = sc[i] = 0.0;
+    for (int64_t k = lo + tid; k < hi; k += kBlock) {
+        const double bw = wb[t - 1 - k];
+        const double aw = (k == 0) ? wc[t - 1] : wa[t - 1 - k];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double fk = Fh[k * D + i];
+            sp[i] = fma(bw, fk, sp[i]);
+            sc[i] = fma(aw, fk, sc[i]);
+        }
+    }
+}
+
+template <int SYS, int D>
+__global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict__ meta,
+                                                      const double *__restrict__ params,
+                                                      const double *__restrict__ y0g,
+                                                      double *__restrict__ F,
+                                                      const double *__restrict__ W,
+                                                      double *__restrict__ Y,
+                                                      int64_t *__restrict__ status)
+{
+    __shared__ double red[kWaves][2 * D];
+    __shared__ int64_t s_dead;
+    const int inst = blockIdx.x, tid = threadIdx.x;
+    const InstMeta m = meta[inst];
+    const int64_t N = m.N;
+    const double *wb = W + m.w_off, *wa = wb + m.wlen, *wc = wa + m.wlen;
+    double *Fh = F + m.f_off * D, *Yh = Y + m.row_off * D;
+    const double *p = params + m.p_off;
+    double y0[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) y0[i] = y0g[(int64_t)inst * D + i];
+
+    if (tid == 0) {
+        double f0[D];
+        rhs<SYS, D>(0.0, y0, f0, p);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            Fh[i] = f0[i];
+            Yh[i] = y0[i];
+        }
+        s_dead = 0;
+    }
+    __syncthreads();
+
+    for (int64_t t = 1; t <= N; ++t) {
+        if (s_dead) break;
+        double sp[D], sc[D];
+        partial_sums<D>(Fh, wb, wa, wc, t, 0, t, tid, sp, sc);
+        block_sum2<D>(sp, sc, red, tid);
+        if (tid == 0) {
+            double y[D], f[D];
+            pece_update<SYS, D>(m, (double)t * m.h, y0, sp, sc, p, y, f);
+            if (!finite_all(y) || !finite_all(f)) {
+                s_dead = t;
+            } else {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    Fh[t * D + i] = f[i];
+                    Yh[t * D + i] = y[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t dead = s_dead;
+    if (tid == 0) status[inst] = dead;
+    if (dead)
+        for (int64_t r = dead + tid; r <= N; r += kBlock)
+#pragma unroll
+            for (int i = 0; i < D; ++i) Yh[r * D + i] = __builtin_nan("");
+}
+
+// sync[0]: arrival counter (monotone, G per step); sync[1]: number of final
+// rows published (rows 0..sync[1]-1 of F and Y are complete); sync[2]: step at
+// which the trajectory stopped being finite (0 while finite); sync[3]: abort
+// (a bounded wait timed out). All four are flags in the sense of flag_read.
+template <int SYS, int D>
+__global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restrict__ meta,
+                                                        const double *__restrict__ params,
+                                                        const double *__restrict__ y0g,
+                                                        double *__restrict__ F,
+                                                        const double *__restrict__ W,
+                                                        double *__restrict__ Y,
+                                                        int64_t *__restrict__ status,
+                                                        double *__restrict__ part,
+                                                        uint32_t *__restrict__ sync,
+                                                        uint64_t timeout_ticks)
+{
+    __shared__ double red[kWaves][2 * D];
+    __shared__ int s_stop;
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    const InstMeta m = meta[0];
+    const int64_t N = m.N;
+    const double *wb = W + m.w_off, *wa = wb + m.wlen, *wc = wa + m.wlen;
+    const double *p = params;
+    double y0[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) y0[i] = y0g[i];
+
+    if (g == 0 && tid == 0) {
+        double f0[D];
+        rhs<SYS, D>(0.0, y0, f0, p);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            F[i] = f0[i];
+            Y[i] = y0[i];
+        }
+        flag_publish(&sync[1], 1u);
+    }
+
+    for (int64_t t = 1; t <= N; ++t) {
+        if (tid == 0) {
+            const bool ok = wait_geq(&sync[1], (uint32_t)t, &sync[3], timeout_ticks);
+            s_stop = !ok || flag_read(&sync[2]) != 0u;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        fence_acquire();
+        const int64_t lo = (t * g) / G, hi = (t * (g + 1)) / G;
+        double sp[D], sc[D];
+        partial_sums<D>(F, wb, wa, wc, t, lo, hi, tid, sp, sc);
+        block_sum2<D>(sp, sc, red, tid);
+        if (tid == 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                part[(int64_t)g * 2 * D + i] = sp[i];
+                part[(int64_t)g * 2 * D + D + i] = sc[i];
+            }
+            fence_release();
+            __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (g == 0) {
+            if (tid == 0) s_stop = !wait_geq(&sync[0], (uint32_t)(G * t), &sync[3], timeout_ticks);
+            __syncthreads();
+            if (s_stop) break;
+            fence_acquire();
+            double qp[D], qc[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                qp[i] = tid < G ? part[(int64_t)tid * 2 * D + i] : 0.0;
+                qc[i] = tid < G ? part[(int64_t)tid * 2 * D + D + i] : 0.0;
+            }
+            __syncthreads();  // red[] is reused by the combine below
+            block_sum2<D>(qp, qc, red, tid);
+            if (tid == 0) {
+                double y[D], f[D];
+                pece_update<SYS, D>(m, (double)t * m.h, y0, qp, qc, p, y, f);
+                if (!finite_all(y) || !finite_all(f)) {
+                    flag_max(&sync[2], (uint32_t)t);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        F[t * D + i] = f[i];
+                        Y[t * D + i] = y[i];
+                    }
+                }
+                flag_publish(&sync[1], (uint32_t)(t + 1));
+            }
+        }
+        __syncthreads();  // red[] reuse in the next step
+    }
+    if (g == 0) {
+        const bool aborted = flag_read(&sync[3]) != 0u;
+        const int64_t dead = flag_read(&sync[2]);
+        // first row not known to be final
+        const int64_t bad = aborted ? (int64_t)flag_read(&sync[1]) : dead;
+        if (tid == 0) status[0] = aborted ? -1 : dead;
+        if (bad)
+            for (int64_t r = bad + tid; r <= N; r += kBlock)
+#pragma unroll
+                for (int i = 0; i < D; ++i) Y[r * D + i] = __builtin_nan("");
+    }
+}
+
+// Teacher-forced sums for all targets t = 1..N: block = 256 consecutive targets;
+// sources are staged through LDS 256 at a time together with the 511 weights
+// the block needs for that source chunk.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_history_direct(const double *__restrict__ W,
+                                                           int64_t N,
+                                                           const double *__restrict__ f,
+                                                           double *__restrict__ P,
+                                                           double *__restrict__ C)
+{
+    __shared__ double sf[kBlock * D];
+    __shared__ double sb[2 * kBlock], sa[2 * kBlock];
+    const double *wb = W, *wa = W + N, *wc = W + 2 * N;
+    const int tid = threadIdx.x;
+    const int64_t T0 = 1 + (int64_t)blockIdx.x * kBlock;  // first target of the block
+    const int64_t t = T0 + tid;
+    const int64_t tmax = min(T0 + kBlock - 1, N);
+    double sp[D], sc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) sp[i] = sc[i] = 0.0;
+    for (int64_t k0 = 0; k0 < tmax; k0 += kBlock) {
+        __syncthreads();
+        for (int j = tid; j < kBlock * D; j += kBlock) {
+            const int64_t r = k0 + j / D;
+            sf[j] = r < N ? f[k0 * D + j] : 0.0;
+        }
+        // lag of (target T0 + x, source k0 + j) is T0 - 1 - k0 + x - j, x - j in [-255, 255]
+        for (int j = tid; j < 2 * kBlock; j += kBlock) {
+            const int64_t lag = T0 - 1 - k0 + (j - (kBlock - 1));
+            const bool ok = lag >= 0 && lag < N;
+            sb[j] = ok ? wb[lag] : 0.0;
+            sa[j] = ok ? wa[lag] : 0.0;
+        }
+        __syncthreads();
+        if (t <= N) {
+            const int jmax = (int)min((int64_t)kBlock, t - k0);
+            for (int j = 0; j < jmax; ++j) {
+                const int li = tid - j + (kBlock - 1);
+                const double bw = sb[li];
+                const double aw = (k0 + j == 0) ? wc[t - 1] : sa[li];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    sp[i] = fma(bw, sf[j * D + i], sp[i]);
+                    sc[i] = fma(aw, sf[j * D + i], sc[i]);
+                }
+            }
+        }
+    }
+    if (t <= N) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            P[(t - 1) * D + i] = sp[i];
+            C[(t - 1) * D + i] = sc[i];
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)(b < 1024 ? b : 1024)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch over (system, dimension). LINEAR is instantiated for the small
+// dimensions the direct kernels keep in registers.
+// ---------------------------------------------------------------------------
+template <template <int, int> class K>
+struct Dispatch;
+
+#define FABM_DIRECT_CASES(MACRO)                                   \
+    MACRO(SYS_LINEAR, 1) MACRO(SYS_LINEAR, 2) MACRO(SYS_LINEAR, 3) \
+    MACRO(SYS_LINEAR, 4) MACRO(SYS_CHEN, 3) MACRO(SYS_ROSSLER, 3)  \
+    MACRO(SYS_VDP, 2) MACRO(SYS_FINANCIAL, 3)
+
+hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
+                            const double *params, const double *y0, double *F, const double *W,
+                            double *Y, int64_t *status, hipStream_t s)
+{
+#define FABM_WG_CASE(S, DD)                                                                   \
+    if (sys == S && d == DD) {                                                                \
+        hipLaunchKernelGGL((k_direct_wg<S, DD>), dim3((unsigned)batch), dim3(kBlock), 0, s, \
+                           meta, params, y0, F, W, Y, status);                               \
+        return hipGetLastError();                                                             \
+    }
+    FABM_DIRECT_CASES(FABM_WG_CASE)
+#undef FABM_WG_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const double *params,
+                              const double *y0, double *F, const double *W, double *Y,
+                              int64_t *status, double *part, uint32_t *sync,
+                              uint64_t timeout_ticks, hipStream_t s)
+{
+    void *args[] = {(void *)&meta, (void *)&params, (void *)&y0,     (void *)&F,
+                    (void *)&W,    (void *)&Y,      (void *)&status, (void *)&part,
+                    (void *)&sync, (void *)&timeout_ticks};
+#define FABM_GRID_CASE(S, DD)                                                                \
+    if (sys == S && d == DD)                                                                 \
+        return hipLaunchCooperativeKernel((const void *)k_direct_grid<S, DD>, dim3(G),     \
+                                          dim3(kBlock), args, 0, s);
+    FABM_DIRECT_CASES(FABM_GRID_CASE)
+#undef FABM_GRID_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_history_direct(const double *W, int64_t N, int d, const double *f, double *P,
+                                 double *C, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((N + kBlock - 1) / kBlock);
+    switch (d) {
+    case 1: hipLaunchKernelGGL(k_history_direct<1>, dim3(blocks), dim3(kBlock), 0, s, W, N, f, P, C); break;
+    case 2: hipLaunchKernelGGL(k_history_direct<2>, dim3(blocks), dim3(kBlock), 0, s, W, N, f, P, C); break;
+    case 3: hipLaunchKernelGGL(k_history_direct<3>, dim3(blocks), dim3(kBlock), 0, s, W, N, f, P, C); break;
+    case 4: hipLaunchKernelGGL(k_history_direct<4>, dim3(blocks), dim3(kBlock), 0, s, W, N, f, P, C); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fabm

@@ -1,0 +1,150 @@
+// fabm_device.h -- device-side building blocks shared by the kernels of the
+// library: per-instance metadata, the right-hand sides f(t, y; theta) of the
+// supported systems, wavefront reductions and inter-workgroup flags.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fabm {
+
+constexpr int kWave = 64;
+
+// Per-instance scalars and offsets, prepared on the host for every call.
+// h^alpha and the Gamma reciprocals are computed on the host (std::pow,
+// std::tgamma) so no kernel evaluates Gamma.
+struct InstMeta {
+    double alpha;
+    double h;
+    double ha;   // h^alpha
+    double ig1;  // 1 / Gamma(alpha + 1)
+    double ig2;  // 1 / Gamma(alpha + 2)
+    int64_t N;       // number of steps (targets t = 1..N)
+    int64_t row_off; // first row of this instance in the caller's y_out
+    int64_t w_off;   // offset (doubles) of its weight tables: b at w_off, a at +N, c at +2N
+    int64_t p_off;   // offset (doubles) of its parameters
+    int64_t f_off;   // first row of this instance in the (packed) history buffer
+    int64_t wlen;    // length of each weight table (>= N; padded for blocked tiles)
+};
+static_assert(sizeof(InstMeta) == 88, "InstMeta layout");
+
+enum : int { SYS_LINEAR = 0, SYS_CHEN = 1, SYS_ROSSLER = 2, SYS_VDP = 3, SYS_FINANCIAL = 4 };
+
+// f(t, y; theta) for the fixed set of systems (textbook forms; parameter
+// layout as documented in fabm.h). D is the state dimension.
+template <int SYS, int D>
+__device__ __forceinline__ void rhs(double t, const double (&y)[D], double (&f)[D],
+                                    const double *__restrict__ p)
+{
+    if constexpr (SYS == SYS_LINEAR) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s = fma(p[D * D + D + i], t, p[D * D + i]);
+#pragma unroll
+            for (int j = 0; j < D; ++j) s = fma(p[i * D + j], y[j], s);
+            f[i] = s;
+        }
+    } else if constexpr (SYS == SYS_CHEN) {
+        const double a = p[0], b = p[1], c = p[2];
+        f[0] = a * (y[1] - y[0]);
+        f[1] = (c - a) * y[0] - y[0] * y[2] + c * y[1];
+        f[2] = y[0] * y[1] - b * y[2];
+    } else if constexpr (SYS == SYS_ROSSLER) {
+        const double a = p[0], b = p[1], c = p[2];
+        f[0] = -y[1] - y[2];
+        f[1] = fma(a, y[1], y[0]);
+        f[2] = fma(y[2], y[0] - c, b);
+    } else if constexpr (SYS == SYS_VDP) {
+        const double mu = p[0];
+        f[0] = y[1];
+        f[1] = mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
+    } else if constexpr (SYS == SYS_FINANCIAL) {
+        const double a = p[0], b = p[1], c = p[2];
+        f[0] = fma(y[1] - a, y[0], y[2]);
+        f[1] = 1.0 - b * y[1] - y[0] * y[0];
+        f[2] = -y[0] - c * y[2];
+    }
+}
+
+// One corrector step from the two history sums (Section 2): returns y_t and
+// f_t, given P_t, C_t, y0 and the step scalars.
+template <int SYS, int D>
+__device__ __forceinline__ void pece_update(const InstMeta &m, double tt, const double (&y0)[D],
+                                            const double (&P)[D], const double (&Cs)[D],
+                                            const double *__restrict__ p, double (&y)[D],
+                                            double (&f)[D])
+{
+    double yp[D], fp[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) yp[i] = fma(m.ha, P[i], y0[i]);
+    rhs<SYS, D>(tt, yp, fp, p);
+#pragma unroll
+    for (int i = 0; i < D; ++i) y[i] = fma(m.ha, fma(fp[i], m.ig2, Cs[i]), y0[i]);
+    rhs<SYS, D>(tt, y, f, p);
+}
+
+template <int D>
+__device__ __forceinline__ bool finite_all(const double (&v)[D])
+{
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < D; ++i) ok = ok && isfinite(v[i]);
+    return ok;
+}
+
+// Butterfly sum over a 64-lane wavefront; every lane receives the total.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
+// Flags shared between workgroups on different XCDs. Each XCD has its own L2;
+// an ordinary (even atomic) load or store of a flag may be served from, or
+// left dirty in, the local L2 with nothing forcing it across. Flags are
+// therefore only touched with read-modify-write atomics, which every XCD
+// performs at the same coherence point; data published under a flag is made
+// visible by the release fence before the flag write and the acquire fence
+// after the flag read.
+__device__ __forceinline__ uint32_t flag_read(uint32_t *p)
+{
+    return __hip_atomic_fetch_add(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_publish(uint32_t *p, uint32_t v)
+{
+    fence_release();
+    __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_max(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin until *p >= v (then acquire), or until *abort becomes nonzero or
+// `timeout_ticks` of the constant-rate wall clock have passed (then *abort is
+// raised and false is returned). Every wait of a persistent kernel is bounded
+// this way, so a scheduling mistake ends the launch with an error instead of a
+// hung GPU.
+__device__ __forceinline__ bool wait_geq(uint32_t *p, uint32_t v, uint32_t *abort,
+                                         uint64_t timeout_ticks)
+{
+    const uint64_t deadline = wall_clock64() + timeout_ticks;
+    for (;;) {
+        if (flag_read(p) >= v) {
+            fence_acquire();
+            return true;
+        }
+        if (flag_read(abort) != 0u) return false;
+        if (wall_clock64() > deadline) {
+            flag_max(abort, 1u);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+}  // namespace fabm

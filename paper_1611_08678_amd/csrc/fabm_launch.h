@@ -1,0 +1,54 @@
+// fabm_launch.h -- host-side launchers of the library's kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fabm {
+
+struct InstMeta;
+
+// Weight tables for every instance of a call (one table per instance).
+hipError_t launch_weights(const InstMeta *meta, int64_t batch, int64_t maxN, double *W,
+                          hipStream_t s);
+hipError_t launch_weights_one(double al, double ig1, double ig2, int64_t n, double *b, double *a,
+                              double *c, hipStream_t s);
+
+// Zero-fill of 32-bit words (a kernel, so it is safe inside captured graphs).
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+
+// DIRECT path, one workgroup per instance.
+hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
+                            const double *params, const double *y0, double *F, const double *W,
+                            double *Y, int64_t *status, hipStream_t s);
+
+// DIRECT path, one trajectory spread over the whole GPU (persistent,
+// cooperative launch); `part` holds [G][2d] doubles, `sync` 4 zeroed words.
+// Every inter-workgroup wait gives up after `timeout_ticks` of the device's
+// constant-rate wall clock (status -1).
+hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const double *params,
+                              const double *y0, double *F, const double *W, double *Y,
+                              int64_t *status, double *part, uint32_t *sync,
+                              uint64_t timeout_ticks, hipStream_t s);
+
+// BLOCKED path, one trajectory, as an event-ordered pipeline: band kernels on
+// `s`, far-tile kernels on `s2` (see fabm_blocked.h). `ev_band` and `ev_far`
+// are rings of n_ev events.
+struct PipeArgs;
+struct PipeSchedule;
+hipError_t enqueue_pipe(int sys, int d, const PipeArgs &A, const PipeSchedule &S, hipStream_t s,
+                        hipStream_t s2, hipEvent_t *ev_band, hipEvent_t *ev_far, int n_ev);
+int pipe_block_len();
+
+// Single-launch persistent variant of the BLOCKED path (not dispatched).
+struct BlockedArgs;
+hipError_t launch_blocked_single(int sys, int d, int G, const BlockedArgs &A, hipStream_t s);
+size_t blocked_smem_bytes(int d);
+int blocked_block_len();
+
+// Teacher-forced history sums, direct contraction (one thread per target row
+// and component group).
+hipError_t launch_history_direct(const double *W, int64_t N, int d, const double *f, double *P,
+                                 double *C, hipStream_t s);
+
+}  // namespace fabm

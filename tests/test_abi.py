@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/fabm.h declares, its enumerations agree with the
+oracle's own numbering, and plan-time validation rejects bad descriptions."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "fabm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fabm_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def fabm():
+    import paper_1611_08678_amd as F
+    F.load()
+    return F
+
+
+def test_library_exports_every_declared_symbol(fabm):
+    import ctypes
+    lib = ctypes.CDLL(fabm.SO)
+    declared = _declared_functions()
+    assert "fabm_solve" in declared and "fabm_plan" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(fabm.EXPORTS) == declared
+
+
+def test_enums_match_oracle_numbering(fabm):
+    from oracle import oracle as O
+    assert (fabm.FABM_SYS_LINEAR, fabm.FABM_SYS_CHEN, fabm.FABM_SYS_ROSSLER, fabm.FABM_SYS_VDP,
+            fabm.FABM_SYS_FINANCIAL) == (O.LINEAR, O.CHEN, O.ROSSLER, O.VDP, O.FINANCIAL)
+    for sysid, d in [(0, 1), (0, 7), (1, 3), (2, 3), (3, 2), (4, 3)]:
+        assert fabm.fabm_n_params(sysid, d) == O.n_params(sysid, d)
+    assert fabm.fabm_n_params(fabm.FABM_SYS_CHEN, 2) == -1
+    assert fabm.fabm_n_params(fabm.FABM_SYS_LINEAR, 65) == -1
+
+
+def test_status_strings(fabm):
+    assert fabm.status_string(0) == "ok"
+    assert fabm.status_string(3) == "workspace too small"
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(system="chen", dim=2), 1),
+    (dict(system="vdp", dim=2, max_steps=0), 1),
+    (dict(system="vdp", dim=2, max_batch=0), 1),
+    (dict(system="vdp", dim=2, tile_L=100), 1),
+    (dict(system=9, dim=2), 1),
+])
+def test_plan_rejects_bad_descriptions(fabm, kw, code):
+    with pytest.raises(fabm.FabmError) as e:
+        fabm.fabm_plan(**kw)
+    assert e.value.code == code
+
+
+def test_plan_is_host_only_and_sizes_workspace(fabm):
+    p = fabm.fabm_plan("chen", 3, "direct", "fp64", 1, 1 << 20)
+    # weights 3N, history (N+1) d, grid partials and flags
+    N = 1 << 20
+    assert p.workspace_bytes >= 8 * (3 * N + 3 * (N + 1))
+    assert fabm.fabm_workspace_size(p, [N]) == p.workspace_bytes
+    with pytest.raises(fabm.FabmError):
+        fabm.fabm_workspace_size(p, [N + 1])
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_1611_08678_amd as F
+    monkeypatch.setattr(F, "_lib", None)
+    monkeypatch.setattr(F, "SO", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        F.load()

@@ -1,0 +1,107 @@
+"""GPU parity of the BLOCKED single-trajectory path (band + MFMA far tiles)
+against the CPU oracle, through the C ABI. Same tolerances as the DIRECT
+tests: 1e-11 normwise for non-chaotic systems over the whole trajectory; for
+Chen, 1e-11 up to the oracle's own one-ulp sensitivity horizon."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.test_gpu_direct import _chen_horizon, _to_np, relerr
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1611_08678_amd as F
+    F.load()
+    return F
+
+
+def _lin(d, seed):
+    rng = np.random.default_rng(seed)
+    A = -(2 * np.eye(d) + rng.standard_normal((d, d)) / 8)
+    th = np.concatenate([A.ravel(), rng.standard_normal(d), 0.05 * rng.standard_normal(d)])
+    return th, rng.uniform(-1.5, 1.5, d)
+
+
+@pytest.mark.parametrize("N", [1, 255, 256, 511, 600, 5000])
+def test_blocked_linear_full_trajectory(F, orc, N):
+    th, y0 = _lin(2, 31)
+    y, st = F.solve("linear", th, 0.8, 0.01, N, y0, path="blocked")
+    ref, _, _, rst = orc.solve(0, th, 0.8, 0.01, N, y0)
+    assert int(st.item()) == rst == 0
+    assert relerr(_to_np(y), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("sysname,d,theta,alpha,h,N", [
+    ("vdp", 2, [1.3], 0.9, 0.01, 7000),
+    ("financial", 3, [3.0, 0.1, 1.0], 0.85, 0.01, 4100),
+    ("linear", 1, [-1.0, 0.0, 0.0], 0.5, 0.005, 2000),
+    ("linear", 4, None, 0.95, 0.01, 3333),
+])
+def test_blocked_systems(F, orc, sysname, d, theta, alpha, h, N):
+    rng = np.random.default_rng(5)
+    if theta is None:
+        theta, y0 = _lin(d, 9)
+    else:
+        y0 = rng.uniform(-1, 1, d) if sysname != "linear" else np.ones(d)
+    y, st = F.solve(sysname, theta, alpha, h, N, y0, path="blocked")
+    sid = {"vdp": 3, "financial": 4, "linear": 0}[sysname]
+    ref, _, _, rst = orc.solve(sid, theta, alpha, h, N, y0)
+    assert int(st.item()) == rst == 0
+    assert relerr(_to_np(y), ref) <= 1e-11
+
+
+def test_blocked_chen_prefix(F, orc):
+    from paper_1611_08678_amd import workloads as W
+    N = 1 << 14
+    w = W.chen(N=N)
+    hz, ref, _ = _chen_horizon(orc, w, N)
+    y, st = F.solve(w["system"], w["theta"][0], w["alpha"][0], w["h"][0], N, w["y0"][0],
+                    path="blocked")
+    yy = _to_np(y)
+    assert int(st.item()) == 0
+    assert relerr(yy[:hz], ref[:hz]) <= 1e-11
+    assert np.all(np.isfinite(yy)) and np.abs(yy).max() < 200.0
+
+
+def test_blocked_deterministic_and_blowup(F, orc):
+    from paper_1611_08678_amd import workloads as W
+    w = W.chen(N=5000)
+    ys = [_to_np(F.solve(w["system"], w["theta"][0], w["alpha"][0], w["h"][0], 5000,
+                         w["y0"][0], path="blocked")[0]) for _ in range(2)]
+    assert np.array_equal(ys[0], ys[1])
+    th = np.array([60.0, 0.0, 0.0])
+    y, st = F.solve("linear", th, 0.9, 0.5, 2000, [1.0], path="blocked")
+    _, _, _, rst = orc.solve(0, th, 0.9, 0.5, 2000, [1.0])
+    assert int(st.item()) == rst > 0
+    yy = _to_np(y)
+    assert np.all(np.isnan(yy[rst:])) and np.all(np.isfinite(yy[:rst]))
+
+
+def test_blocked_chen_full_size(F, orc):
+    """Full N = 2^20 in the benchmark's launch configuration: finite, bounded,
+    status 0, and the first 4096 steps match the oracle (before rounding
+    differences of a chaotic system amplify)."""
+    from paper_1611_08678_amd import workloads as W
+    w = W.chen()
+    N = int(w["N"][0])
+    y, st = F.solve(w["system"], w["theta"][0], w["alpha"][0], w["h"][0], N, w["y0"][0],
+                    path="blocked")
+    yy = _to_np(y)
+    assert int(st.item()) == 0
+    assert np.all(np.isfinite(yy)) and np.abs(yy).max() < 200.0
+    ref, _, _, _ = orc.solve(w["system"], w["theta"][0], w["alpha"][0], w["h"][0], 4096,
+                             w["y0"][0])
+    assert relerr(yy[:4097], ref) <= 1e-11
+
+
+@pytest.mark.skip(reason=(
+    "single-launch persistent BLOCKED variant (blocked_persistent.hip) is switched off: its "
+    "launch with far tasks (N=600, three blocks) did not complete on MI355X, also after the "
+    "flag fix; inter-workgroup flag polling compiled to plain cached loads. The dispatched "
+    "BLOCKED path is the event-ordered pipeline tested above."))
+def test_blocked_persistent_variant_far_tasks():
+    pass
