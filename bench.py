@@ -5,10 +5,11 @@ alpha = 0.95, y0 = (-9, -5, 14), h = 0.001, N = 2^20 steps (d = 3). One
 bench "step" is one complete solve (weight generation, history contraction,
 predictor/corrector updates, output) with inputs already in device memory.
 
-Prints one JSON line: steps*states/s of the headline path (`value`), history
-GFLOP/s (2 d N (N+1) flops per trajectory), the per-path breakdown (direct vs
-blocked), the roofline of the dominant kernel and the CPU oracle timed on a
-bounded sample of the same trajectory.
+Prints one JSON line: steps*states/s of the headline (BLOCKED) path as
+`value`, history GFLOP/s (2 d N (N+1) flops per trajectory), the per-path
+breakdown (DIRECT vs BLOCKED), the roofline of the dominant kernel from HIP
+events recorded by the library on the kernel's own stream, and the CPU oracle
+timed on a bounded sample of the same trajectory.
 """
 from __future__ import annotations
 
@@ -23,6 +24,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+BLK = 256  # rows per block of the BLOCKED path
 
 
 def parse():
@@ -36,10 +39,12 @@ def parse():
                     help="timed solves of the (slow) direct comparison path")
     ap.add_argument("--cpu-sample", type=int, default=1 << 15,
                     help="steps of the oracle sample for cpu_baseline (0 disables)")
+    ap.add_argument("--no-kernel-times", action="store_true",
+                    help="skip the instrumented solve that measures per-kernel time")
     return ap.parse_args()
 
 
-def time_path(F, w, path: str, steps: int, warmup: int):
+def setup(F, w, path):
     import torch
     N = int(w["N"][0])
     d = w["d"]
@@ -49,13 +54,19 @@ def time_path(F, w, path: str, steps: int, warmup: int):
     th = torch.as_tensor(w["theta"][0], device="cuda").contiguous()
     y = torch.empty((N + 1, d), dtype=torch.float64, device="cuda")
     st = torch.zeros(1, dtype=torch.int64, device="cuda")
-    args = (plan, ws, float(w["alpha"][0]), float(w["h"][0]), N, y0, th, y, st)
+    return plan, (plan, ws, float(w["alpha"][0]), float(w["h"][0]), N, y0, th, y, st), y, st
+
+
+def time_path(F, w, path: str, steps: int, warmup: int, kernel_times: bool):
+    import torch
+    plan, args, y, st = setup(F, w, path)
     for _ in range(warmup):
         F.fabm_solve(*args)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in evs:
         a.record(stream)
@@ -64,7 +75,35 @@ def time_path(F, w, path: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per = [a.elapsed_time(b) / 1e3 for a, b in evs]
-    return dict(path=path, wall_s=wall, solve_s=per, y=y.cpu().numpy(), status=int(st.item()))
+    out = dict(path=path, wall_s=wall, solve_s=per, y=y.cpu().numpy(), status=int(st.item()))
+    if kernel_times:
+        # one extra, instrumented solve: the library records an event pair on
+        # each kernel's own stream around every launch
+        F.fabm_plan_set_profiling(plan, True)
+        F.fabm_solve(*args)
+        torch.cuda.synchronize()
+        out["kernel_times"] = F.fabm_plan_kernel_times(plan)
+        F.fabm_plan_set_profiling(plan, False)
+    return out
+
+
+def blocked_work(N: int, d: int):
+    """Algorithmic history flops of the BLOCKED path by where they are done:
+    far tiles (sources in blocks < J-2 of a target in block J), the band's own
+    near tile (block J-2) and the row-by-row band (blocks J-1, J)."""
+    nb = (N + 1 + BLK - 1) // BLK
+    far = near = 0
+    for J in range(nb):
+        lo, hi = J * BLK, min(J * BLK + BLK - 1, N)
+        rows = max(0, hi - max(lo, 1) + 1)  # targets t >= 1 in this block
+        if J >= 3:
+            far += rows * BLK * (J - 2)
+        if J >= 2:
+            near += rows * BLK
+    per_pair = 2 * 2 * d  # two weight tables, d components, FMA = 2 flops
+    total = 2.0 * d * N * (N + 1)
+    return dict(far=far * per_pair, near=near * per_pair,
+                band=total - (far + near) * per_pair, total=total)
 
 
 def cpu_baseline(w, n_sample: int, N: int):
@@ -83,13 +122,46 @@ def cpu_baseline(w, n_sample: int, N: int):
                       sample_seconds=dt)
 
 
+def roofline(head: str, kt: dict, N: int, d: int, t_solve: float):
+    """Roofline object of the dominant kernel class of the headline path."""
+    if not kt:
+        return None
+    dom = max(kt, key=lambda k: kt[k][0])
+    secs, launches = kt[dom]
+    if dom == "far_tiles":
+        flops = blocked_work(N, d)["far"]
+        ach = flops / secs / 1e12
+        return dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=None, kernel="k_far_items",
+                    launches=launches, avg_launch_s=secs / launches,
+                    algorithmic_flops_per_solve=flops)
+    if dom == "band":
+        wk = blocked_work(N, d)
+        flops = wk["band"] + wk["near"]
+        ach = flops / secs / 1e12
+        # one CU of FP64 vector/matrix throughput (the band runs on one CU)
+        peak = FP64_MFMA_PEAK_TFLOPS / 256.0
+        return dict(bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
+                    traffic=None, kernel="k_band_block", launches=launches,
+                    avg_launch_s=secs / launches, algorithmic_flops_per_solve=flops,
+                    note="latency-bound: one LDS broadcast and barrier per step on one CU; "
+                         "peak is one CU's FP64 rate")
+    if dom == "direct_grid":
+        alg_bytes = 4.0 * N * (N + 1) * (d + 2)  # sum_t 8 t (d + 2): history row + two weights
+        ach = alg_bytes / secs / 1e9
+        return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=ach / HBM_PEAK_GBS, traffic=None, kernel="k_direct_grid",
+                    launches=launches, avg_launch_s=secs / launches,
+                    algorithmic_bytes_per_solve=alg_bytes)
+    return dict(bound="unknown", kernel=dom, seconds=secs)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
-    import torch
     import paper_1611_08678_amd as F
     from paper_1611_08678_amd import workloads as W
 
@@ -98,10 +170,12 @@ def main():
     N, d = int(w["N"][0]), w["d"]
     flops = 2.0 * d * N * (N + 1)
     results = {}
-    for path in [p for p in args.paths.split(",") if p]:
-        head_path = path == "blocked" or "blocked" not in args.paths
+    paths = [p for p in args.paths.split(",") if p]
+    for path in paths:
+        head_path = path == "blocked" or "blocked" not in paths
         r = time_path(F, w, path, args.steps if head_path else args.direct_steps,
-                      args.warmup if head_path else 0)
+                      args.warmup if head_path else 0,
+                      kernel_times=head_path and not args.no_kernel_times)
         results[path] = r
         print(f"# {path}: solve times {['%.4f' % s for s in r['solve_s']]} s", file=sys.stderr,
               flush=True)
@@ -109,18 +183,6 @@ def main():
     r = results[head]
     t = float(np.mean(r["solve_s"]))
     value = N * d / t
-
-    # roofline of the dominant kernel of the headline path
-    if head == "direct":
-        alg_bytes = 4.0 * N * (N + 1) * (d + 2)  # sum_t 8 t (d + 2): history row + two weights
-        achieved = alg_bytes / t / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, kernel="k_direct_grid",
-                    algorithmic_bytes=alg_bytes)
-    else:
-        achieved = flops / t / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=78.6, unit="TFLOP/s",
-                    frac=achieved / 78.6, traffic=None, kernel="k_blocked")
 
     out = {
         "metric": "steps*states/s (history GFLOP/s alongside), blocked vs direct, at stated rel err",
@@ -135,8 +197,12 @@ def main():
                       "steps_states_per_s": N * d / float(np.mean(v["solve_s"])),
                       "history_gflops": flops / float(np.mean(v["solve_s"])) / 1e9,
                       "status": v["status"]} for k, v in results.items()},
-        "roofline": roof,
     }
+    kt = r.get("kernel_times")
+    if kt:
+        out["kernel_times_s"] = {k: v[0] for k, v in kt.items() if v[1]}
+        out["kernel_launches"] = {k: v[1] for k, v in kt.items() if v[1]}
+    out["roofline"] = roofline(head, {k: v for k, v in (kt or {}).items() if v[1]}, N, d, t)
     if "direct" in results and "blocked" in results:
         out["blocked_speedup_over_direct"] = (np.mean(results["direct"]["solve_s"]) /
                                               np.mean(results["blocked"]["solve_s"]))

@@ -25,8 +25,12 @@
  *     pointers marked (host) are host memory read before the call returns.
  *     All floating point is IEEE binary64, row-major, state index fastest.
  *   - The caller owns every buffer, including the workspace. The library never
- *     allocates device memory; fabm_plan allocates host memory only (and one
- *     small pinned staging buffer with its event).
+ *     allocates device memory. fabm_plan allocates host memory only; the first
+ *     solve of a plan adds a pinned staging buffer (grown as needed) and, for
+ *     BLOCKED, two non-blocking default-priority streams (band, far tiles)
+ *     and rings of events, all released by fabm_plan_destroy. Work on those
+ *     streams is ordered after everything already on `stream`, and `stream`
+ *     waits for both before anything enqueued on it later.
  *   - All device work is enqueued on `stream` and the call returns without
  *     synchronising. Argument errors are detected on the host, before
  *     anything is enqueued, and reported through the return value.
@@ -95,6 +99,11 @@ typedef struct {
 
 typedef struct fabm_plan_s *fabm_plan_t;
 
+/* Description of the last HIP failure behind a FABM_ERR_DEVICE returned to
+ * this thread (the failing call and the HIP error string); "" if none. The
+ * string stays valid until the thread's next failing call. */
+const char *fabm_last_error(void);
+
 /* Human-readable name of a status code (static string). */
 const char *fabm_status_string(fabm_status s);
 
@@ -152,6 +161,27 @@ fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace
  * the second difference in a, a short series for c). */
 fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *c,
                          hipStream_t stream);
+
+/* Kernel classes of fabm_plan_kernel_times. */
+typedef enum {
+    FABM_KERNEL_WEIGHTS = 0,     /* weight tables */
+    FABM_KERNEL_DIRECT_WG = 1,   /* DIRECT, one workgroup per trajectory */
+    FABM_KERNEL_DIRECT_GRID = 2, /* DIRECT, one trajectory over the whole GPU */
+    FABM_KERNEL_BAND = 3,        /* BLOCKED band (sequential steps of one block) */
+    FABM_KERNEL_FAR_TILES = 4,   /* BLOCKED far tiles (MFMA Toeplitz items) */
+    FABM_KERNEL_FAR_REDUCE = 5,  /* BLOCKED far-sum reductions */
+    FABM_KERNEL_HISTORY = 6,     /* fabm_history_sums contraction */
+    FABM_KERNEL_COUNT = 7
+} fabm_kernel_class;
+
+/* Instrumentation. While enabled, every solve call of the plan records a pair
+ * of timing events on the launching stream around each of its kernels (this
+ * adds some overhead). fabm_plan_kernel_times then synchronises on those
+ * events and returns, per class, the summed kernel time of the last call in
+ * seconds[FABM_KERNEL_COUNT] and the number of launches in
+ * launches[FABM_KERNEL_COUNT] (host arrays). */
+fabm_status fabm_plan_set_profiling(fabm_plan_t plan, int32_t enable);
+fabm_status fabm_plan_kernel_times(fabm_plan_t plan, double *seconds, int64_t *launches);
 
 /* History sums alone for a given history (teacher forcing): for t = 1..N,
  *   P[t-1] = sum_{k<t} b_{t-1-k} f[k],   C[t-1] = c_{t-1} f[0] + sum_{1<=k<t} a_{t-1-k} f[k]

@@ -28,15 +28,24 @@ PATHS = {"auto": FABM_PATH_AUTO, "direct": FABM_PATH_DIRECT, "blocked": FABM_PAT
 FAR_PRECS = {"fp64": FABM_FAR_FP64, "fp32": FABM_FAR_FP32, "fp16x2": FABM_FAR_FP16X2}
 
 # exported symbols of the C ABI (checked by the test suite against fabm.h)
-EXPORTS = ("fabm_status_string", "fabm_n_params", "fabm_plan", "fabm_plan_destroy",
+EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan", "fabm_plan_destroy",
            "fabm_workspace_size", "fabm_solve", "fabm_solve_batch", "fabm_weights",
-           "fabm_history_sums", "fabm_history_workspace_size")
+           "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
+           "fabm_plan_kernel_times")
+KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "band", "far_tiles", "far_reduce",
+                  "history")
 
 
 class FabmError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
-        super().__init__(f"{where}: {status_string(code)} ({code})")
+        detail = ""
+        if code == FABM_ERR_DEVICE:
+            try:
+                detail = " [" + load().fabm_last_error().decode() + "]"
+            except Exception:
+                pass
+        super().__init__(f"{where}: {status_string(code)} ({code}){detail}")
 
 
 class _PlanDesc(C.Structure):
@@ -59,7 +68,13 @@ def load():
     if not os.path.exists(SO):
         raise ImportError(f"HIP library not built: {SO} is missing "
                           "(run __graft_entry__.build() or python -m paper_1611_08678_amd.build)")
+    # torch brings its own HIP runtime (same soname as the system one). Load it
+    # first so libfabm binds to the runtime torch uses: two HIP/HSA runtimes in
+    # one process cannot both open the device.
+    import torch  # noqa: F401
     L = C.CDLL(SO)
+    L.fabm_last_error.argtypes = []
+    L.fabm_last_error.restype = C.c_char_p
     L.fabm_status_string.argtypes = [C.c_int]
     L.fabm_status_string.restype = C.c_char_p
     L.fabm_n_params.argtypes = [C.c_int, C.c_int32]
@@ -83,6 +98,10 @@ def load():
     L.fabm_history_sums.restype = C.c_int
     L.fabm_history_workspace_size.argtypes = [C.c_int64, C.c_int32]
     L.fabm_history_workspace_size.restype = C.c_size_t
+    L.fabm_plan_set_profiling.argtypes = [_VP, C.c_int32]
+    L.fabm_plan_set_profiling.restype = C.c_int
+    L.fabm_plan_kernel_times.argtypes = [_VP, _DP, _I64P]
+    L.fabm_plan_kernel_times.restype = C.c_int
     _lib = L
     return L
 
@@ -181,6 +200,20 @@ def fabm_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_
                                    Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                                    ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
                                    _stream(stream)), "fabm_solve_batch")
+
+
+def fabm_plan_set_profiling(plan: Plan, enable: bool):
+    _check(load().fabm_plan_set_profiling(plan.handle, int(bool(enable))),
+           "fabm_plan_set_profiling")
+
+
+def fabm_plan_kernel_times(plan: Plan):
+    """{kernel class: (seconds, launches)} of the last profiled call."""
+    n = len(KERNEL_CLASSES)
+    sec = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    _check(load().fabm_plan_kernel_times(plan.handle, sec, cnt), "fabm_plan_kernel_times")
+    return {k: (float(sec[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
 
 def fabm_weights(alpha: float, n: int, b, a, c, stream=None):

@@ -18,6 +18,8 @@ HIPCC_FLAGS = [
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
+    # keep MFMA accumulators in ordinary VGPRs (no per-iteration AGPR copies)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 

@@ -25,6 +25,7 @@
 #include "fabm_device.h"
 #include "fabm_launch.h"
 #include "fabm_tiles.h"
+#include "fabm_timer.h"
 
 namespace fabm {
 
@@ -191,39 +192,37 @@ __global__ __launch_bounds__(kBlk) void k_far_items(PipeArgs A, int item0)
     }
 }
 
-// Workgroups [0, nred): add the items of a multi-item task in order.
-// Workgroup nred (when Jfin >= 0): finalise the far sum of target block Jfin.
+// Workgroups [0, 2D*nred): workgroup (task, cw) adds the items of a
+// multi-item task in order for output column group cw. Workgroups
+// [2D*nred, 2D*nred + 2D) (when Jfin >= 0): finalise column group cw of the
+// far sum of target block Jfin from its task partials in source order.
 template <int D>
 __global__ __launch_bounds__(kBlk) void k_far_reduce(PipeArgs A, int red0, int nred, int Jfin)
 {
     const int tid = threadIdx.x;
-    if ((int)blockIdx.x < nred) {
-        const int4 rd = A.reds[red0 + blockIdx.x];
-        double *out = A.task_slot + (int64_t)rd.x * 2 * D * kBlk;
-#pragma unroll
-        for (int cw = 0; cw < 2 * D; ++cw) {
-            double s = 0.0;
-            for (int k = 0; k < rd.z; ++k)
-                s += A.scratch[((int64_t)(rd.y + k) * 2 * D + cw) * kBlk + tid];
-            out[cw * kBlk + tid] = s;
-        }
+    const int b = blockIdx.x;
+    if (b < 2 * D * nred) {
+        const int4 rd = A.reds[red0 + b / (2 * D)];
+        const int cw = b % (2 * D);
+        double s = 0.0;
+        for (int k = 0; k < rd.z; ++k)
+            s += A.scratch[((int64_t)(rd.y + k) * 2 * D + cw) * kBlk + tid];
+        A.task_slot[((int64_t)rd.x * 2 * D + cw) * kBlk + tid] = s;
         return;
     }
+    const int cw = b - 2 * D * nred;
     const InstMeta m = A.meta[0];
     const int64_t pitch = (int64_t)A.NB * kBlk;
-    const double *wa = A.W + m.wlen, *wc = wa + m.wlen;
-    const int64_t T = (int64_t)Jfin * kBlk + tid;
-    const double ca = wc[T - 1] - wa[T - 1];  // source row 0 takes c_{T-1}, not a_{T-1}
     const int k0 = A.tt_off[Jfin], k1 = A.tt_off[Jfin + 1];
-    double *fj = A.far + (int64_t)Jfin * 2 * D * kBlk;
-#pragma unroll
-    for (int cw = 0; cw < 2 * D; ++cw) {
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k)
-            s += A.task_slot[((int64_t)A.tt_slot[k] * 2 * D + cw) * kBlk + tid];
-        if (cw >= D) s = fma(ca, A.Fc[(cw - D) * pitch], s);
-        fj[cw * kBlk + tid] = s;
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k)
+        s += A.task_slot[((int64_t)A.tt_slot[k] * 2 * D + cw) * kBlk + tid];
+    if (cw >= D) {  // source row 0 takes c_{T-1}, not a_{T-1}
+        const double *wa = A.W + m.wlen, *wc = wa + m.wlen;
+        const int64_t T = (int64_t)Jfin * kBlk + tid;
+        s = fma(wc[T - 1] - wa[T - 1], A.Fc[(cw - D) * pitch], s);
     }
+    A.far[((int64_t)Jfin * 2 * D + cw) * kBlk + tid] = s;
 }
 
 __global__ void k_pipe_status(PipeArgs A)
@@ -234,61 +233,90 @@ __global__ void k_pipe_status(PipeArgs A)
 // ---------------------------------------------------------------------------
 // Host side: one enqueue of the whole pipeline.
 // ---------------------------------------------------------------------------
-size_t pipe_band_smem(int d) { return sizeof(double) * (4 * kBlk + 2 * d + 8 * d * kBlk) + 16; }
+// The band kernel asks for more LDS than a compute unit (160 KiB) can share
+// with a far-tile workgroup (8 d KiB... 48 KiB for d = 3): far tiles then
+// never land on the band's CU, whose single workgroup is latency-bound.
+constexpr size_t kCuLds = 160 * 1024;
+size_t pipe_far_smem(int d);
+size_t pipe_band_smem(int d)
+{
+    const size_t need = sizeof(double) * (4 * kBlk + 2 * d + 8 * d * kBlk) + 16;
+    const size_t exclusive = kCuLds - pipe_far_smem(d) + 1024;
+    return need > exclusive ? need : exclusive;
+}
 size_t pipe_far_smem(int d) { return sizeof(double) * 8 * d * kBlk; }
 
 template <int SYS, int D>
 static hipError_t enqueue_pipe_t(const PipeArgs &A, const PipeSchedule &S, hipStream_t s,
                                  hipStream_t s2, hipEvent_t *ev_band, hipEvent_t *ev_far,
-                                 int n_ev)
+                                 int n_ev, KernelTimer *T, const char **where)
 {
+    // on failure *where names the call that failed
+#define FABM_PIPE_TRY(what, expr)          \
+    do {                                   \
+        const hipError_t e_ = (expr);      \
+        if (e_ != hipSuccess) {            \
+            *where = what;                 \
+            return e_;                     \
+        }                                  \
+    } while (0)
     static bool attr_done = false;
     const size_t smb = pipe_band_smem(D), smf = pipe_far_smem(D);
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_band_block<SYS, D>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smb);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)k_far_items<D>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)smf);
-        if (e != hipSuccess) return e;
+        FABM_PIPE_TRY("hipFuncSetAttribute(band LDS)",
+                      hipFuncSetAttribute((const void *)k_band_block<SYS, D>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smb));
+        FABM_PIPE_TRY("hipFuncSetAttribute(far LDS)",
+                      hipFuncSetAttribute((const void *)k_far_items<D>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smf));
         attr_done = true;
     }
     const int NB = S.NB;
     for (int J = 0; J < NB; ++J) {
-        if (J >= 3) {
-            hipError_t e = hipStreamWaitEvent(s, ev_far[J % n_ev], 0);
-            if (e != hipSuccess) return e;
-        }
+        if (J >= 3)
+            FABM_PIPE_TRY("hipStreamWaitEvent(band <- far)", hipStreamWaitEvent(s, ev_far[J % n_ev], 0));
+        if (T) FABM_PIPE_TRY("timer begin", T->begin(KC_BAND, s));
         hipLaunchKernelGGL((k_band_block<SYS, D>), dim3(1), dim3(kBlk), smb, s, A, J);
+        FABM_PIPE_TRY("launch k_band_block", hipGetLastError());
+        if (T) FABM_PIPE_TRY("timer end", T->end(s));
         const int I = J;
         const int i0 = S.step_item_off[I], i1 = S.step_item_off[I + 1];
         const int r0 = S.step_red_off[I], r1 = S.step_red_off[I + 1];
         const int Jfin = I + 3 < NB ? I + 3 : -1;
         if (i1 > i0 || r1 > r0 || Jfin >= 0) {
-            hipError_t e = hipEventRecord(ev_band[I % n_ev], s);
-            if (e == hipSuccess) e = hipStreamWaitEvent(s2, ev_band[I % n_ev], 0);
-            if (e != hipSuccess) return e;
-            if (i1 > i0)
+            FABM_PIPE_TRY("hipEventRecord(band)", hipEventRecord(ev_band[I % n_ev], s));
+            FABM_PIPE_TRY("hipStreamWaitEvent(far <- band)",
+                          hipStreamWaitEvent(s2, ev_band[I % n_ev], 0));
+            if (i1 > i0) {
+                if (T) FABM_PIPE_TRY("timer begin", T->begin(KC_FAR_ITEMS, s2));
                 hipLaunchKernelGGL(k_far_items<D>, dim3(i1 - i0), dim3(kBlk), smf, s2, A, i0);
-            const int nb = (r1 - r0) + (Jfin >= 0 ? 1 : 0);
-            if (nb > 0)
+                FABM_PIPE_TRY("launch k_far_items", hipGetLastError());
+                if (T) FABM_PIPE_TRY("timer end", T->end(s2));
+            }
+            const int nb = 2 * D * ((r1 - r0) + (Jfin >= 0 ? 1 : 0));
+            if (nb > 0) {
+                if (T) FABM_PIPE_TRY("timer begin", T->begin(KC_FAR_REDUCE, s2));
                 hipLaunchKernelGGL(k_far_reduce<D>, dim3(nb), dim3(kBlk), 0, s2, A, r0, r1 - r0,
                                    Jfin);
-            if (Jfin >= 0) {
-                e = hipEventRecord(ev_far[Jfin % n_ev], s2);
-                if (e != hipSuccess) return e;
+                FABM_PIPE_TRY("launch k_far_reduce", hipGetLastError());
+                if (T) FABM_PIPE_TRY("timer end", T->end(s2));
             }
+            if (Jfin >= 0)
+                FABM_PIPE_TRY("hipEventRecord(far)", hipEventRecord(ev_far[Jfin % n_ev], s2));
         }
     }
     hipLaunchKernelGGL(k_pipe_status, dim3(1), dim3(64), 0, s, A);
-    return hipGetLastError();
+    FABM_PIPE_TRY("launch k_pipe_status", hipGetLastError());
+    return hipSuccess;
+#undef FABM_PIPE_TRY
 }
 
 hipError_t enqueue_pipe(int sys, int d, const PipeArgs &A, const PipeSchedule &S, hipStream_t s,
-                        hipStream_t s2, hipEvent_t *ev_band, hipEvent_t *ev_far, int n_ev)
+                        hipStream_t s2, hipEvent_t *ev_band, hipEvent_t *ev_far, int n_ev,
+                        KernelTimer *T, const char **where)
 {
 #define FABM_PIPE_CASE(SS, DD) \
-    if (sys == SS && d == DD) return enqueue_pipe_t<SS, DD>(A, S, s, s2, ev_band, ev_far, n_ev);
+    if (sys == SS && d == DD) return enqueue_pipe_t<SS, DD>(A, S, s, s2, ev_band, ev_far, n_ev, T, where);
     FABM_PIPE_CASE(SYS_LINEAR, 1)
     FABM_PIPE_CASE(SYS_LINEAR, 2)
     FABM_PIPE_CASE(SYS_LINEAR, 3)
@@ -298,6 +326,7 @@ hipError_t enqueue_pipe(int sys, int d, const PipeArgs &A, const PipeSchedule &S
     FABM_PIPE_CASE(SYS_VDP, 2)
     FABM_PIPE_CASE(SYS_FINANCIAL, 3)
 #undef FABM_PIPE_CASE
+    *where = "no BLOCKED kernel for this system/dimension";
     return hipErrorInvalidValue;
 }
 

@@ -3,6 +3,8 @@
 // kernel dispatch.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -11,6 +13,7 @@
 #include "fabm_blocked.h"
 #include "fabm_device.h"
 #include "fabm_launch.h"
+#include "fabm_timer.h"
 
 using fabm::InstMeta;
 
@@ -25,13 +28,31 @@ struct fabm_plan_s {
     bool stage_pending;
     uint64_t timeout_ticks;  // bound of every inter-workgroup wait (device wall clock)
     // BLOCKED pipeline: second stream, event rings, cached schedule
-    hipStream_t s_far;
-    hipEvent_t ev_band[32], ev_far[32], ev_fork, ev_join;
+    hipStream_t s_band, s_far;
+    hipEvent_t ev_band[32], ev_far[32], ev_fork, ev_join, ev_join2;
     bool have_pipe;
     fabm::PipeSchedule sched;  // schedule of the last block count used
+    fabm::KernelTimer timer;   // optional per-kernel timing
 };
 
 namespace {
+
+// Last HIP failure seen by this thread (returned by fabm_last_error).
+thread_local char g_last_error[256] = "";
+
+fabm_status record_hip(const char *what, hipError_t e)
+{
+    if (e == hipSuccess) return FABM_OK;
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", what, hipGetErrorString(e),
+                  (int)e);
+    return FABM_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr)                                           \
+    do {                                                        \
+        const fabm_status s_ = record_hip(#expr, (expr));       \
+        if (s_ != FABM_OK) return s_;                           \
+    } while (0)
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxLinearDim = 64;
@@ -167,7 +188,7 @@ void host_scalars(double alpha, double h, InstMeta &m)
     m.ig2 = (double)(1.0L / std::tgamma(al + 2.0L));
 }
 
-fabm_status ok_or_device(hipError_t e) { return e == hipSuccess ? FABM_OK : FABM_ERR_DEVICE; }
+fabm_status ok_or_device(hipError_t e) { return record_hip("kernel launch", e); }
 
 // Device-side resources of a plan, created at its first solve so that
 // fabm_plan itself touches no device.
@@ -175,10 +196,8 @@ fabm_status ensure_device(fabm_plan_s *pl)
 {
     if (pl->h_stage) return FABM_OK;
     int cus = 0;
-    if (hipGetDevice(&pl->device) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) !=
-            hipSuccess)
-        return FABM_ERR_DEVICE;
+    HIP_TRY(hipGetDevice(&pl->device));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device));
     pl->grid_G = std::min(cus, kGridMax);
     int rate_khz = 0;
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, pl->device) !=
@@ -187,31 +206,36 @@ fabm_status ensure_device(fabm_plan_s *pl)
         rate_khz = 100000;  // gfx9 constant clock: 100 MHz
     pl->timeout_ticks = (uint64_t)rate_khz * 1000u * kWaitTimeoutSeconds;
     pl->stage_cap = sizeof(InstMeta) * (size_t)pl->desc.max_batch;
-    if (hipHostMalloc((void **)&pl->h_stage, pl->stage_cap, hipHostMallocDefault) != hipSuccess) {
+    hipError_t e = hipHostMalloc((void **)&pl->h_stage, pl->stage_cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
         pl->h_stage = nullptr;
-        return FABM_ERR_DEVICE;
+        return record_hip("hipHostMalloc(staging)", e);
     }
-    if (hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming) != hipSuccess) {
+    e = hipEventCreateWithFlags(&pl->stage_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
         (void)hipHostFree(pl->h_stage);
         pl->h_stage = nullptr;
-        return FABM_ERR_DEVICE;
+        return record_hip("hipEventCreateWithFlags(staging)", e);
     }
     return FABM_OK;
 }
 
-// Second stream and event rings of the BLOCKED pipeline (first blocked call).
+// Streams and event rings of the BLOCKED pipeline (first blocked call). The
+// band keeps a compute unit to itself through its LDS request (blocked.hip);
+// streams restricted by a CU mask failed to launch the band kernel on MI355X
+// ("out of memory"), so plain streams are used.
 fabm_status ensure_pipe(fabm_plan_s *pl)
 {
     if (pl->have_pipe) return FABM_OK;
-    if (hipStreamCreateWithFlags(&pl->s_far, hipStreamNonBlocking) != hipSuccess)
-        return FABM_ERR_DEVICE;
-    for (int i = 0; i < 32; ++i)
-        if (hipEventCreateWithFlags(&pl->ev_band[i], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&pl->ev_far[i], hipEventDisableTiming) != hipSuccess)
-            return FABM_ERR_DEVICE;
-    if (hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)
-        return FABM_ERR_DEVICE;
+    HIP_TRY(hipStreamCreateWithFlags(&pl->s_band, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&pl->s_far, hipStreamNonBlocking));
+    for (int i = 0; i < 32; ++i) {
+        HIP_TRY(hipEventCreateWithFlags(&pl->ev_band[i], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&pl->ev_far[i], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming));
     pl->have_pipe = true;
     return FABM_OK;
 }
@@ -224,8 +248,7 @@ fabm_status ensure_stage(fabm_plan_s *pl, size_t bytes)
     (void)hipHostFree(pl->h_stage);
     pl->h_stage = nullptr;
     pl->stage_cap = 0;
-    if (hipHostMalloc((void **)&pl->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
-        return FABM_ERR_DEVICE;
+    HIP_TRY(hipHostMalloc((void **)&pl->h_stage, bytes, hipHostMallocDefault));
     pl->stage_cap = bytes;
     return FABM_OK;
 }
@@ -233,7 +256,7 @@ fabm_status ensure_stage(fabm_plan_s *pl, size_t bytes)
 fabm_status wait_staging(fabm_plan_s *pl)
 {
     if (pl->stage_pending) {
-        if (hipEventSynchronize(pl->stage_ev) != hipSuccess) return FABM_ERR_DEVICE;
+        HIP_TRY(hipEventSynchronize(pl->stage_ev));
         pl->stage_pending = false;
     }
     return FABM_OK;
@@ -241,9 +264,8 @@ fabm_status wait_staging(fabm_plan_s *pl)
 
 fabm_status stage_copy(fabm_plan_s *pl, size_t bytes, void *dst, hipStream_t s)
 {
-    if (hipMemcpyAsync(dst, pl->h_stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-        return FABM_ERR_DEVICE;
-    if (hipEventRecord(pl->stage_ev, s) != hipSuccess) return FABM_ERR_DEVICE;
+    HIP_TRY(hipMemcpyAsync(dst, pl->h_stage, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(pl->stage_ev, s));
     pl->stage_pending = true;
     return FABM_OK;
 }
@@ -289,7 +311,11 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
     double *W = (double *)(base + L.w);
     uint32_t *sync = (uint32_t *)(base + L.sync);
+    fabm::KernelTimer *T = pl->timer.on ? &pl->timer : nullptr;
+    if (T) T->reset();
+    if (T) T->begin(fabm::KC_WEIGHTS, s);
     if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK) return st;
+    if (T) T->end(s);
     if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
         FABM_OK)
         return st;
@@ -316,32 +342,42 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.dead = sync;
         A.status = status;
         A.NB = L.NB;
-        // fork the far stream off the caller's stream, join it back at the end
-        if (hipEventRecord(pl->ev_fork, s) != hipSuccess ||
-            hipStreamWaitEvent(pl->s_far, pl->ev_fork, 0) != hipSuccess)
-            return FABM_ERR_DEVICE;
-        if ((st = ok_or_device(fabm::enqueue_pipe(pl->desc.system, d, A, S, s, pl->s_far,
-                                                  pl->ev_band, pl->ev_far, 32))) != FABM_OK)
-            return st;
-        if (hipEventRecord(pl->ev_join, pl->s_far) != hipSuccess ||
-            hipStreamWaitEvent(s, pl->ev_join, 0) != hipSuccess)
-            return FABM_ERR_DEVICE;
+        // fork the band and far streams off the caller's stream, join both back
+        HIP_TRY(hipEventRecord(pl->ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(pl->s_band, pl->ev_fork, 0));
+        HIP_TRY(hipStreamWaitEvent(pl->s_far, pl->ev_fork, 0));
+        const char *where = "";
+        const hipError_t pe = fabm::enqueue_pipe(pl->desc.system, d, A, S, pl->s_band, pl->s_far,
+                                                 pl->ev_band, pl->ev_far, 32, T, &where);
+        if (pe != hipSuccess) return record_hip(where, pe);
+        HIP_TRY(hipEventRecord(pl->ev_join, pl->s_far));
+        HIP_TRY(hipEventRecord(pl->ev_join2, pl->s_band));
+        HIP_TRY(hipStreamWaitEvent(s, pl->ev_join, 0));
+        HIP_TRY(hipStreamWaitEvent(s, pl->ev_join2, 0));
         return FABM_OK;
     }
     double *F = (double *)(base + L.f);
     if (batch == 1 && N[0] >= kGridDirectMinSteps) {
         double *part = (double *)(base + L.part);
-        return ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta,
-                                                     params, y0, F, W, Yi, status, part, sync,
-                                                     pl->timeout_ticks, s));
+        if (T) T->begin(fabm::KC_DIRECT_GRID, s);
+        st = ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta, params,
+                                                   y0, F, W, Yi, status, part, sync,
+                                                   pl->timeout_ticks, s));
+        if (T) T->end(s);
+        return st;
     }
-    return ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, batch, params, y0, F,
-                                               W, y_out, status, s));
+    if (T) T->begin(fabm::KC_DIRECT_WG, s);
+    st = ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, batch, params, y0, F, W,
+                                             y_out, status, s));
+    if (T) T->end(s);
+    return st;
 }
 
 }  // namespace
 
 extern "C" {
+
+const char *fabm_last_error(void) { return g_last_error; }
 
 const char *fabm_status_string(fabm_status s)
 {
@@ -415,13 +451,16 @@ void fabm_plan_destroy(fabm_plan_t plan)
     }
     if (plan->have_pipe) {
         (void)hipStreamSynchronize(plan->s_far);
+        (void)hipStreamSynchronize(plan->s_band);
         for (int i = 0; i < 32; ++i) {
             (void)hipEventDestroy(plan->ev_band[i]);
             (void)hipEventDestroy(plan->ev_far[i]);
         }
         (void)hipEventDestroy(plan->ev_fork);
         (void)hipEventDestroy(plan->ev_join);
+        (void)hipEventDestroy(plan->ev_join2);
         (void)hipStreamDestroy(plan->s_far);
+        (void)hipStreamDestroy(plan->s_band);
     }
     delete plan;
 }
@@ -500,6 +539,19 @@ fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *
     InstMeta m{};
     host_scalars(alpha, 1.0, m);
     return ok_or_device(fabm::launch_weights_one(alpha, m.ig1, m.ig2, n, b, a, c, stream));
+}
+
+fabm_status fabm_plan_set_profiling(fabm_plan_t plan, int32_t enable)
+{
+    if (!plan) return FABM_ERR_INVALID_ARG;
+    plan->timer.on = enable != 0;
+    return FABM_OK;
+}
+
+fabm_status fabm_plan_kernel_times(fabm_plan_t plan, double *seconds, int64_t *launches)
+{
+    if (!plan || !seconds || !launches) return FABM_ERR_INVALID_ARG;
+    return ok_or_device(plan->timer.totals(seconds, launches, fabm::KC_COUNT));
 }
 
 size_t fabm_history_workspace_size(int64_t N, int32_t dim)

@@ -36,8 +36,10 @@ hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const
 // are rings of n_ev events.
 struct PipeArgs;
 struct PipeSchedule;
+struct KernelTimer;
 hipError_t enqueue_pipe(int sys, int d, const PipeArgs &A, const PipeSchedule &S, hipStream_t s,
-                        hipStream_t s2, hipEvent_t *ev_band, hipEvent_t *ev_far, int n_ev);
+                        hipStream_t s2, hipEvent_t *ev_band, hipEvent_t *ev_far, int n_ev,
+                        KernelTimer *T, const char **where);
 int pipe_block_len();
 
 // Single-launch persistent variant of the BLOCKED path (not dispatched).

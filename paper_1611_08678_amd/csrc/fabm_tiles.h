@@ -44,11 +44,11 @@ __device__ __forceinline__ void toeplitz_block_fp64(const double *__restrict__ w
 #pragma unroll
     for (int i = 0; i < D; ++i) acc[i][0] = acc[i][1] = (dbl4){0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t q = qa; q < qb; ++q) {
+    // operands of one q: A slices of both weight tables, B slices of each component
+    auto load_q = [&](int64_t q, double (&ab)[4], double (&aa)[4], double (&bf)[D][4]) {
         const int64_t col = colT + rho - q;  // history column of this lane's B entries
         const bool ok = col >= k0 && col < k1;
         const int64_t wbase = kTile * q + rho - kq - 1;
-        double ab[4], aa[4], bf[D][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             ab[j] = wb[wbase - 4 * j];
@@ -61,6 +61,14 @@ __device__ __forceinline__ void toeplitz_block_fp64(const double *__restrict__ w
                 bf[i][j] = ok ? v : 0.0;
             }
         }
+    };
+    double ab[4], aa[4], bf[D][4];
+    if (qa < qb) load_q(qa, ab, aa, bf);
+    for (int64_t q = qa; q < qb; ++q) {
+        // issue the next q's loads before this q's products (latency hidden
+        // behind 24 MFMAs)
+        double nab[4], naa[4], nbf[D][4];
+        if (q + 1 < qb) load_q(q + 1, nab, naa, nbf);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -68,6 +76,15 @@ __device__ __forceinline__ void toeplitz_block_fp64(const double *__restrict__ w
                 acc[i][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab[j], bf[i][j], acc[i][0], 0, 0, 0);
                 acc[i][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[j], bf[i][j], acc[i][1], 0, 0, 0);
             }
+        if (q + 1 < qb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ab[j] = nab[j];
+                aa[j] = naa[j];
+#pragma unroll
+                for (int i = 0; i < D; ++i) bf[i][j] = nbf[i][j];
+            }
+        }
     }
     // accumulator element v of lane l is D[sigma = 4 v + l/16][rho = l % 16]
 #pragma unroll
