@@ -25,7 +25,6 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
-BLK = 256  # rows per block of the BLOCKED path
 
 
 def parse():
@@ -87,25 +86,6 @@ def time_path(F, w, path: str, steps: int, warmup: int, kernel_times: bool):
     return out
 
 
-def blocked_work(N: int, d: int):
-    """Algorithmic history flops of the BLOCKED path by where they are done:
-    far tiles (sources in blocks < J-2 of a target in block J), the band's own
-    near tile (block J-2) and the row-by-row band (blocks J-1, J)."""
-    nb = (N + 1 + BLK - 1) // BLK
-    far = near = 0
-    for J in range(nb):
-        lo, hi = J * BLK, min(J * BLK + BLK - 1, N)
-        rows = max(0, hi - max(lo, 1) + 1)  # targets t >= 1 in this block
-        if J >= 3:
-            far += rows * BLK * (J - 2)
-        if J >= 2:
-            near += rows * BLK
-    per_pair = 2 * 2 * d  # two weight tables, d components, FMA = 2 flops
-    total = 2.0 * d * N * (N + 1)
-    return dict(far=far * per_pair, near=near * per_pair,
-                band=total - (far + near) * per_pair, total=total)
-
-
 def cpu_baseline(w, n_sample: int, N: int):
     """Oracle (single trajectory, one thread) on the first n_sample steps of the
     same trajectory, scaled to the full N by the N(N+1) cost of the history sums."""
@@ -122,37 +102,29 @@ def cpu_baseline(w, n_sample: int, N: int):
                       sample_seconds=dt)
 
 
-def roofline(head: str, kt: dict, N: int, d: int, t_solve: float):
-    """Roofline object of the dominant kernel class of the headline path."""
+def roofline(kt: dict, N: int, d: int):
+    """Roofline object of the dominant kernel of the headline path, from the
+    library's per-launch HIP events (recorded on the kernel's own stream)."""
     if not kt:
         return None
     dom = max(kt, key=lambda k: kt[k][0])
     secs, launches = kt[dom]
-    if dom == "far_tiles":
-        flops = blocked_work(N, d)["far"]
+    flops = 2.0 * d * N * (N + 1)  # algorithmic history flops of one solve
+    if dom == "blocked_step":
+        # every history flop of the BLOCKED path is done inside the step
+        # kernels (MFMA near/far windows plus the sequential band)
         ach = flops / secs / 1e12
         return dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=None, kernel="k_far_items",
+                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=None, kernel="k_step",
                     launches=launches, avg_launch_s=secs / launches,
-                    algorithmic_flops_per_solve=flops)
-    if dom == "band":
-        wk = blocked_work(N, d)
-        flops = wk["band"] + wk["near"]
-        ach = flops / secs / 1e12
-        # one CU of FP64 vector/matrix throughput (the band runs on one CU)
-        peak = FP64_MFMA_PEAK_TFLOPS / 256.0
-        return dict(bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
-                    traffic=None, kernel="k_band_block", launches=launches,
-                    avg_launch_s=secs / launches, algorithmic_flops_per_solve=flops,
-                    note="latency-bound: one LDS broadcast and barrier per step on one CU; "
-                         "peak is one CU's FP64 rate")
+                    algorithmic_flops_per_launch=flops / launches)
     if dom == "direct_grid":
         alg_bytes = 4.0 * N * (N + 1) * (d + 2)  # sum_t 8 t (d + 2): history row + two weights
         ach = alg_bytes / secs / 1e9
         return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS, traffic=None, kernel="k_direct_grid",
                     launches=launches, avg_launch_s=secs / launches,
-                    algorithmic_bytes_per_solve=alg_bytes)
+                    algorithmic_bytes_per_launch=alg_bytes / launches)
     return dict(bound="unknown", kernel=dom, seconds=secs)
 
 
@@ -202,7 +174,7 @@ def main():
     if kt:
         out["kernel_times_s"] = {k: v[0] for k, v in kt.items() if v[1]}
         out["kernel_launches"] = {k: v[1] for k, v in kt.items() if v[1]}
-    out["roofline"] = roofline(head, {k: v for k, v in (kt or {}).items() if v[1]}, N, d, t)
+    out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, d)
     if "direct" in results and "blocked" in results:
         out["blocked_speedup_over_direct"] = (np.mean(results["direct"]["solve_s"]) /
                                               np.mean(results["blocked"]["solve_s"]))

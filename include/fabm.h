@@ -26,11 +26,8 @@
  *     All floating point is IEEE binary64, row-major, state index fastest.
  *   - The caller owns every buffer, including the workspace. The library never
  *     allocates device memory. fabm_plan allocates host memory only; the first
- *     solve of a plan adds a pinned staging buffer (grown as needed) and, for
- *     BLOCKED, two non-blocking default-priority streams (band, far tiles)
- *     and rings of events, all released by fabm_plan_destroy. Work on those
- *     streams is ordered after everything already on `stream`, and `stream`
- *     waits for both before anything enqueued on it later.
+ *     solve of a plan adds a pinned staging buffer (grown as needed), released
+ *     by fabm_plan_destroy.
  *   - All device work is enqueued on `stream` and the call returns without
  *     synchronising. Argument errors are detected on the host, before
  *     anything is enqueued, and reported through the return value.
@@ -167,11 +164,10 @@ typedef enum {
     FABM_KERNEL_WEIGHTS = 0,     /* weight tables */
     FABM_KERNEL_DIRECT_WG = 1,   /* DIRECT, one workgroup per trajectory */
     FABM_KERNEL_DIRECT_GRID = 2, /* DIRECT, one trajectory over the whole GPU */
-    FABM_KERNEL_BAND = 3,        /* BLOCKED band (sequential steps of one block) */
-    FABM_KERNEL_FAR_TILES = 4,   /* BLOCKED far tiles (MFMA Toeplitz items) */
-    FABM_KERNEL_FAR_REDUCE = 5,  /* BLOCKED far-sum reductions */
-    FABM_KERNEL_HISTORY = 6,     /* fabm_history_sums contraction */
-    FABM_KERNEL_COUNT = 7
+    FABM_KERNEL_BLOCKED_STEP = 3, /* BLOCKED step: one band block plus the MFMA
+                                     near and far windows of one source block */
+    FABM_KERNEL_HISTORY = 4,      /* fabm_history_sums contraction */
+    FABM_KERNEL_COUNT = 5
 } fabm_kernel_class;
 
 /* Instrumentation. While enabled, every solve call of the plan records a pair

@@ -322,6 +322,66 @@ int64_t oracle_solve(int system, int d, const double *theta, double alpha, doubl
     return solve_one(&r, alpha, h, N, y0, wb, wa, wc, y, yp, f);
 }
 
+/* One step of the same scheme from a given history (teacher forcing), to
+ * check single rows of trajectories too long to re-solve: with f_0..f_{t-1}
+ * read from f_hist (row-major [t][d]), the step n = t-1 of solve_one, with
+ * the same arithmetic, writes y_t to y_out. mag_out[i] receives
+ * h^a (sum_k |b_{n-k} f_k| + |c_n f_0| + sum_{k>=1} |a_{n-k} f_k|), the size
+ * of the terms whose rounding the result carries. Weight tables of length
+ * >= t are required. */
+void oracle_step_from_history(int system, int d, const double *theta, double alpha, double h,
+                              int64_t t, const double *y0, const double *f_hist,
+                              const double *wb, const double *wa, const double *wc,
+                              double *y_out, double *mag_out)
+{
+    orc_rhs r = {system, d, theta, 0, 0};
+    double ha, ig2;
+    step_scalars(alpha, h, &ha, &ig2);
+    const int64_t n = t - 1;
+    long double *SP = malloc(sizeof(long double) * d), *SC = malloc(sizeof(long double) * d);
+    long double *MG = malloc(sizeof(long double) * d);
+    double *ypr = malloc(sizeof(double) * d), *fp = malloc(sizeof(double) * d);
+    for (int i = 0; i < d; ++i) {
+        SP[i] = 0.0L;
+        SC[i] = (long double)wc[n] * f_hist[i];
+        MG[i] = fabsl(SC[i]);
+    }
+    for (int64_t k = 0; k <= n; ++k) {
+        const double *fk = f_hist + k * d;
+        long double wbk = wb[n - k];
+        for (int i = 0; i < d; ++i) {
+            SP[i] += wbk * fk[i];
+            MG[i] += fabsl(wbk * fk[i]);
+        }
+        if (k >= 1) {
+            long double wak = wa[n - k];
+            for (int i = 0; i < d; ++i) {
+                SC[i] += wak * fk[i];
+                MG[i] += fabsl(wak * fk[i]);
+            }
+        }
+    }
+    for (int i = 0; i < d; ++i) ypr[i] = y0[i] + ha * (double)SP[i];
+    rhs_eval(&r, (double)t * h, ypr, fp);
+    for (int i = 0; i < d; ++i) {
+        y_out[i] = y0[i] + ha * ((double)SC[i] + fp[i] * ig2);
+        mag_out[i] = ha * (double)MG[i];
+    }
+    free(SP);
+    free(SC);
+    free(MG);
+    free(ypr);
+    free(fp);
+}
+
+/* f(t_k, y_k) for rows k = 0..n-1 of y (row-major [n][d]), t_k = k h. */
+void oracle_rhs_rows(int system, int d, const double *theta, double h, int64_t n,
+                     const double *y, double *f)
+{
+    orc_rhs r = {system, d, theta, 0, 0};
+    for (int64_t k = 0; k < n; ++k) rhs_eval(&r, (double)k * h, y + k * d, f + k * d);
+}
+
 /* Same scheme with a caller-supplied right-hand side (oracle-only problems
  * such as manufactured solutions). */
 int64_t oracle_solve_cb(orc_rhs_cb cb, void *user, int d, double alpha, double h,

@@ -63,6 +63,9 @@ def lib():
                                      _D, _D, _D, _D]
         L.oracle_adjoint.restype = C.c_int64
         L.oracle_rhs.argtypes = [C.c_int, C.c_int, _D, C.c_double, _D, _D]
+        L.oracle_rhs_rows.argtypes = [C.c_int, C.c_int, _D, C.c_double, C.c_int64, _D, _D]
+        L.oracle_step_from_history.argtypes = [C.c_int, C.c_int, _D, C.c_double, C.c_double,
+                                               C.c_int64, _D, _D, _D, _D, _D, _D, _D]
         L.oracle_n_params.argtypes = [C.c_int, C.c_int]
         L.oracle_n_params.restype = C.c_int
         L.oracle_dim.argtypes = [C.c_int, C.c_int]
@@ -100,6 +103,32 @@ def rhs(system: int, theta, t: float, y):
     f = np.empty_like(y)
     lib().oracle_rhs(system, y.size, _p(th), float(t), _p(y), _p(f))
     return f
+
+
+def rhs_rows(system: int, theta, h: float, y):
+    """f(t_k, y_k) for every row k of y ([n, d]), t_k = k h."""
+    y = _f64(y)
+    f = np.empty_like(y)
+    lib().oracle_rhs_rows(system, y.shape[1], _p(_f64(theta).ravel()), float(h), y.shape[0],
+                          _p(y), _p(f))
+    return f
+
+
+def step_from_history(system: int, theta, alpha: float, h: float, t: int, y0, f_hist,
+                      weights_bac):
+    """Teacher-forced step: y_t from the history rows f_0..f_{t-1} (f_hist has
+    at least t rows), with weight tables of length >= t. Returns (y_t, mag)
+    where mag is h^alpha times the sum of the magnitudes of the history terms."""
+    y0 = _f64(y0).ravel()
+    d = y0.size
+    f = _f64(f_hist)
+    assert f.shape[0] >= t and f.shape[1] == d
+    wb, wa, wc = (_f64(w) for w in weights_bac)
+    assert min(wb.size, wa.size, wc.size) >= t
+    y, mag = np.empty(d), np.empty(d)
+    lib().oracle_step_from_history(system, d, _p(_f64(theta).ravel()), float(alpha), float(h),
+                                   int(t), _p(y0), _p(f), _p(wb), _p(wa), _p(wc), _p(y), _p(mag))
+    return y, mag
 
 
 def solve(system: int, theta, alpha: float, h: float, N: int, y0, weights_bac=None):

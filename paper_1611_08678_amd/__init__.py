@@ -32,8 +32,7 @@ EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan"
            "fabm_workspace_size", "fabm_solve", "fabm_solve_batch", "fabm_weights",
            "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
            "fabm_plan_kernel_times")
-KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "band", "far_tiles", "far_reduce",
-                  "history")
+KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history")
 
 
 class FabmError(RuntimeError):

@@ -22,16 +22,11 @@ struct fabm_plan_s {
     int32_t n_params;
     int device;
     int grid_G;          // workgroups of the persistent single-trajectory kernels
-    char *h_stage;       // pinned staging: instance table, then the far-task schedule
+    char *h_stage;       // pinned staging of the per-call instance table
     size_t stage_cap;
     hipEvent_t stage_ev; // recorded after the staging copy; waited on before reuse
     bool stage_pending;
     uint64_t timeout_ticks;  // bound of every inter-workgroup wait (device wall clock)
-    // BLOCKED pipeline: second stream, event rings, cached schedule
-    hipStream_t s_band, s_far;
-    hipEvent_t ev_band[32], ev_far[32], ev_fork, ev_join, ev_join2;
-    bool have_pipe;
-    fabm::PipeSchedule sched;  // schedule of the last block count used
     fabm::KernelTimer timer;   // optional per-kernel timing
 };
 
@@ -101,18 +96,11 @@ Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 // `stage_bytes` bytes are copied from the plan's pinned staging buffer.
 struct Layout {
     Path path;
-    size_t meta, items, reds, tt_off, tt_slot, stage_bytes;
-    size_t w, f, part, carry, far, task_slot, scratch, sync, n_sync_words, total;
+    size_t meta, stage_bytes;
+    size_t w, f, part, carry, acc, sync, n_sync_words, total;
     int64_t wlen;
     int NB;
 };
-
-const fabm::PipeSchedule &schedule_for(const fabm_plan_s *pl, int NB)
-{
-    fabm_plan_s *mp = const_cast<fabm_plan_s *>(pl);  // host-side cache only
-    if (mp->sched.NB != NB) fabm::pipe_schedule(NB, mp->sched);
-    return mp->sched;
-}
 
 Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 {
@@ -128,20 +116,10 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
     L.meta = off;
     off += sizeof(InstMeta) * (size_t)batch;
     if (L.path == Path::Blocked) {
-        const int Lb = fabm::pipe_block_len();
+        const int Lb = fabm::step_block_len();
         L.NB = (int)((N[0] + 1 + Lb - 1) / Lb);
-        const fabm::PipeSchedule &S = schedule_for(pl, L.NB);
         L.wlen = (int64_t)L.NB * Lb + Lb;
-        const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;  // one [2d][256] tile of sums
-        off = (off + 15) / 16 * 16;
-        L.items = off;
-        off += sizeof(int4) * S.items.size();
-        L.reds = off;
-        off += sizeof(int4) * S.reds.size();
-        L.tt_off = off;
-        off += sizeof(int) * S.tt_off.size();
-        L.tt_slot = off;
-        off += sizeof(int) * S.tt_slot.size();
+        const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;  // one [2d][256] block of sums
         L.stage_bytes = off;
         off = align_up(off);
         L.w = off;
@@ -150,12 +128,8 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
         off = align_up(off + sizeof(double) * (size_t)d * (size_t)L.NB * Lb);
         L.carry = off;
         off = align_up(off + 2 * blk);
-        L.far = off;
+        L.acc = off;  // near + far sums of every target block
         off = align_up(off + blk * (size_t)L.NB);
-        L.task_slot = off;
-        off = align_up(off + blk * (size_t)S.n_slots);
-        L.scratch = off;
-        off = align_up(off + blk * (size_t)S.max_scratch);
         L.sync = off;
         L.n_sync_words = 64;
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
@@ -220,26 +194,6 @@ fabm_status ensure_device(fabm_plan_s *pl)
     return FABM_OK;
 }
 
-// Streams and event rings of the BLOCKED pipeline (first blocked call). The
-// band keeps a compute unit to itself through its LDS request (blocked.hip);
-// streams restricted by a CU mask failed to launch the band kernel on MI355X
-// ("out of memory"), so plain streams are used.
-fabm_status ensure_pipe(fabm_plan_s *pl)
-{
-    if (pl->have_pipe) return FABM_OK;
-    HIP_TRY(hipStreamCreateWithFlags(&pl->s_band, hipStreamNonBlocking));
-    HIP_TRY(hipStreamCreateWithFlags(&pl->s_far, hipStreamNonBlocking));
-    for (int i = 0; i < 32; ++i) {
-        HIP_TRY(hipEventCreateWithFlags(&pl->ev_band[i], hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&pl->ev_far[i], hipEventDisableTiming));
-    }
-    HIP_TRY(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&pl->ev_join2, hipEventDisableTiming));
-    pl->have_pipe = true;
-    return FABM_OK;
-}
-
 // Grow the pinned staging buffer (only between calls, after the last copy
 // out of it has completed).
 fabm_status ensure_stage(fabm_plan_s *pl, size_t bytes)
@@ -299,13 +253,6 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         maxw = std::max(maxw, m.wlen);
     }
     char *base = (char *)ws;
-    if (L.path == Path::Blocked) {
-        const fabm::PipeSchedule &S = schedule_for(pl, L.NB);
-        std::memcpy(pl->h_stage + L.items, S.items.data(), sizeof(int4) * S.items.size());
-        std::memcpy(pl->h_stage + L.reds, S.reds.data(), sizeof(int4) * S.reds.size());
-        std::memcpy(pl->h_stage + L.tt_off, S.tt_off.data(), sizeof(int) * S.tt_off.size());
-        std::memcpy(pl->h_stage + L.tt_slot, S.tt_slot.data(), sizeof(int) * S.tt_slot.size());
-    }
     if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
 
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
@@ -313,18 +260,16 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     uint32_t *sync = (uint32_t *)(base + L.sync);
     fabm::KernelTimer *T = pl->timer.on ? &pl->timer : nullptr;
     if (T) T->reset();
-    if (T) T->begin(fabm::KC_WEIGHTS, s);
+    if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
     if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK) return st;
-    if (T) T->end(s);
+    if (T) HIP_TRY(T->end(s));
     if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
         FABM_OK)
         return st;
     double *Yi = y_out + (row_off ? row_off[0] : 0) * d;  // single-trajectory kernels
 
     if (L.path == Path::Blocked) {
-        if ((st = ensure_pipe(pl)) != FABM_OK) return st;
-        const fabm::PipeSchedule &S = schedule_for(pl, L.NB);
-        fabm::PipeArgs A{};
+        fabm::StepArgs A{};
         A.meta = dmeta;
         A.params = params;
         A.y0 = y0;
@@ -332,44 +277,29 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.W = W;
         A.Fc = (double *)(base + L.f);
         A.carry = (double *)(base + L.carry);
-        A.far = (double *)(base + L.far);
-        A.task_slot = (double *)(base + L.task_slot);
-        A.scratch = (double *)(base + L.scratch);
-        A.items = (const int4 *)(base + L.items);
-        A.reds = (const int4 *)(base + L.reds);
-        A.tt_off = (const int *)(base + L.tt_off);
-        A.tt_slot = (const int *)(base + L.tt_slot);
+        A.acc = (double *)(base + L.acc);
         A.dead = sync;
         A.status = status;
         A.NB = L.NB;
-        // fork the band and far streams off the caller's stream, join both back
-        HIP_TRY(hipEventRecord(pl->ev_fork, s));
-        HIP_TRY(hipStreamWaitEvent(pl->s_band, pl->ev_fork, 0));
-        HIP_TRY(hipStreamWaitEvent(pl->s_far, pl->ev_fork, 0));
         const char *where = "";
-        const hipError_t pe = fabm::enqueue_pipe(pl->desc.system, d, A, S, pl->s_band, pl->s_far,
-                                                 pl->ev_band, pl->ev_far, 32, T, &where);
+        const hipError_t pe = fabm::enqueue_steps(pl->desc.system, d, A, s, T, &where);
         if (pe != hipSuccess) return record_hip(where, pe);
-        HIP_TRY(hipEventRecord(pl->ev_join, pl->s_far));
-        HIP_TRY(hipEventRecord(pl->ev_join2, pl->s_band));
-        HIP_TRY(hipStreamWaitEvent(s, pl->ev_join, 0));
-        HIP_TRY(hipStreamWaitEvent(s, pl->ev_join2, 0));
         return FABM_OK;
     }
     double *F = (double *)(base + L.f);
     if (batch == 1 && N[0] >= kGridDirectMinSteps) {
         double *part = (double *)(base + L.part);
-        if (T) T->begin(fabm::KC_DIRECT_GRID, s);
+        if (T) HIP_TRY(T->begin(fabm::KC_DIRECT_GRID, s));
         st = ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta, params,
                                                    y0, F, W, Yi, status, part, sync,
                                                    pl->timeout_ticks, s));
-        if (T) T->end(s);
+        if (T) HIP_TRY(T->end(s));
         return st;
     }
-    if (T) T->begin(fabm::KC_DIRECT_WG, s);
+    if (T) HIP_TRY(T->begin(fabm::KC_DIRECT_WG, s));
     st = ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, batch, params, y0, F, W,
                                              y_out, status, s));
-    if (T) T->end(s);
+    if (T) HIP_TRY(T->end(s));
     return st;
 }
 
@@ -411,7 +341,7 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
         return FABM_ERR_INVALID_ARG;
     // far tiles run in FP64 only in this build; the block length is fixed
     if (desc->far_prec != FABM_FAR_FP64) return FABM_ERR_UNSUPPORTED;
-    if (desc->tile_L != 0 && desc->tile_L != fabm::pipe_block_len())
+    if (desc->tile_L != 0 && desc->tile_L != fabm::step_block_len())
         return FABM_ERR_UNSUPPORTED;
     // kernels keep the state in registers: LINEAR up to d = 4
     if (desc->system == FABM_SYS_LINEAR && desc->dim > 4) return FABM_ERR_UNSUPPORTED;
@@ -448,19 +378,6 @@ void fabm_plan_destroy(fabm_plan_t plan)
         if (plan->stage_pending) (void)hipEventSynchronize(plan->stage_ev);
         (void)hipEventDestroy(plan->stage_ev);
         (void)hipHostFree(plan->h_stage);
-    }
-    if (plan->have_pipe) {
-        (void)hipStreamSynchronize(plan->s_far);
-        (void)hipStreamSynchronize(plan->s_band);
-        for (int i = 0; i < 32; ++i) {
-            (void)hipEventDestroy(plan->ev_band[i]);
-            (void)hipEventDestroy(plan->ev_far[i]);
-        }
-        (void)hipEventDestroy(plan->ev_fork);
-        (void)hipEventDestroy(plan->ev_join);
-        (void)hipEventDestroy(plan->ev_join2);
-        (void)hipStreamDestroy(plan->s_far);
-        (void)hipStreamDestroy(plan->s_band);
     }
     delete plan;
 }

@@ -12,56 +12,47 @@
 namespace fabm {
 
 // ---------------------------------------------------------------------------
-// Event-ordered pipeline (dispatched). Rows are cut into blocks of 256.
-// For a target in block J:
-//   band  : sources in blocks J-1 and J, added one row at a time by the band
-//           kernel of block J-1 / J (scatter after each row is formed);
-//   near  : sources in block J-2, one 256x256 MFMA tile computed by the band
-//           kernel of block J before its first step;
-//   far   : sources in blocks [0, J-2), cut going back from J-2 into chunks of
-//           2, 4, 8, ... blocks ("tasks"); a task becomes computable when the
-//           band kernel of its last source block has finished ("far step" of
-//           that block). Tasks longer than kItemBlocks are split into items
-//           whose partials are added in order within the same far step.
-// Band kernels run on the caller's stream; far steps on a second stream; the
-// far step of block I waits for band block I, and band block J waits for the
-// far step of block J-3, which finalises the far sum of J (all its tasks, in
-// source order). Nothing waits inside a kernel.
+// Step pipeline (dispatched). Rows are cut into blocks of 256 and, inside a
+// block, into 16 columns of 16 rows (polyphase split of the Toeplitz sums:
+// row 16 kappa + tau lies in column kappa). For a target in column c of block
+// J the history splits by column lag q = c - kappa:
+//   band : sources in blocks J-1 and J, added one row at a time while those
+//          blocks are walked (q <= 16 + rho for rho = c - 16 J);
+//   near : q in [rho + 17, 47], i.e. the rest of block J-2 and the part of
+//          block J-3 in columns above 16 (J-3) + rho;
+//   far  : q >= 48, cut into windows q in [16 m, 16 m + 16), m = 3 .. J.
+// Window m of target J reads source columns 16 (J - m) + rho - u (u < 16),
+// which all lie in blocks J-m-1 and J-m, so it can be added as soon as block
+// J - m is final, and every target J reads the same columns in that step.
+// Launch s of the pipeline (s = -1 .. NB-2) is one kernel:
+//   workgroup 0   : band of block s + 1;
+//   workgroup 1   : near part of target s + 2 (sources up to block s);
+//   workgroups 2..: far window m = J - s of every target J >= s + 3.
+// Every launch depends on the previous one only, through ordinary stream
+// order: no events, flags or waits.
 // ---------------------------------------------------------------------------
-constexpr int kItemBlocks = 16;
+constexpr int kStepThreads = 1024;  // 16 wavefronts, four per SIMD
+constexpr int kNearWaves = 8;       // wavefronts sharing the near part
+constexpr int kMaxFarWg = 254;      // far workgroups per launch (+ band + near <= 256 CUs)
 
-struct PipeArgs {
+struct StepArgs {
     const InstMeta *meta;
     const double *params;
     const double *y0;
-    double *Y;            // caller rows [N+1][D]
-    const double *W;      // b, a, c tables of length meta->wlen each
-    double *Fc;           // component-major history [D][NB*256]
-    double *carry;        // [2][2D][256] band accumulators handed to the next block
-    double *far;          // [NB][2D][256] finalised far sums
-    double *task_slot;    // [n_slots][2D][256] partial of each far task
-    double *scratch;      // [max_scratch][2D][256] item partials of one far step
-    const int4 *items;    // {J, I0, I1, dest}: dest >= 0 task slot, else scratch -dest-1
-    const int4 *reds;     // {slot, scratch_first, n_items, 0}: multi-item task sums
-    const int *tt_off;    // [NB+1] tasks of each target (CSR over tt_slot)
-    const int *tt_slot;   // task slots in source order
-    uint32_t *dead;       // [0]: first non-finite step (0 while finite)
+    double *Y;          // caller rows [N+1][D]
+    const double *W;    // b, a, c tables of length meta->wlen each
+    double *Fc;         // component-major history [D][NB*256]
+    double *carry;      // [2][2D][256] band sums handed to the next block
+    double *acc;        // [NB][2D][4][64] near + far sums of each target block,
+                        //   in the register order of the 16x16 MFMA result
+    uint32_t *dead;     // [0]: first non-finite step (0 while finite), or kDeadWatchdog
     int64_t *status;
     int NB;
 };
 
-struct PipeSchedule {
-    int NB = 0;
-    std::vector<int4> items;         // grouped by far step
-    std::vector<int> step_item_off;  // [NB+1]
-    std::vector<int4> reds;          // grouped by far step
-    std::vector<int> step_red_off;   // [NB+1]
-    std::vector<int> tt_off;         // [NB+1]
-    std::vector<int> tt_slot;
-    int n_slots = 0;
-    int max_scratch = 0;
-};
-void pipe_schedule(int NB, PipeSchedule &s);
+// Value of StepArgs::dead when a bounded wait inside the band gave up
+// (reported as status -1).
+constexpr uint32_t kDeadWatchdog = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
 // Single-launch persistent variant (not dispatched; see blocked_persistent.hip).

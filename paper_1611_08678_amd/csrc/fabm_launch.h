@@ -31,16 +31,15 @@ hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const
                               int64_t *status, double *part, uint32_t *sync,
                               uint64_t timeout_ticks, hipStream_t s);
 
-// BLOCKED path, one trajectory, as an event-ordered pipeline: band kernels on
-// `s`, far-tile kernels on `s2` (see fabm_blocked.h). `ev_band` and `ev_far`
-// are rings of n_ev events.
-struct PipeArgs;
-struct PipeSchedule;
+// BLOCKED path, one trajectory, as a sequence of step kernels on stream `s`
+// (decomposition in fabm_blocked.h). On failure *where names the call.
+struct StepArgs;
 struct KernelTimer;
-hipError_t enqueue_pipe(int sys, int d, const PipeArgs &A, const PipeSchedule &S, hipStream_t s,
-                        hipStream_t s2, hipEvent_t *ev_band, hipEvent_t *ev_far, int n_ev,
-                        KernelTimer *T, const char **where);
-int pipe_block_len();
+hipError_t enqueue_steps(int sys, int d, const StepArgs &A, hipStream_t s, KernelTimer *T,
+                         const char **where);
+int step_block_len();
+size_t step_smem_bytes(int d);
+void step_grid(int NB, int s, int *grid, int *wpw);
 
 // Single-launch persistent variant of the BLOCKED path (not dispatched).
 struct BlockedArgs;

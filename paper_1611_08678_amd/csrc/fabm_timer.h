@@ -14,11 +14,9 @@ enum : int {
     KC_WEIGHTS = 0,
     KC_DIRECT_WG = 1,
     KC_DIRECT_GRID = 2,
-    KC_BAND = 3,
-    KC_FAR_ITEMS = 4,
-    KC_FAR_REDUCE = 5,
-    KC_HISTORY = 6,
-    KC_COUNT = 7
+    KC_BLOCKED_STEP = 3,
+    KC_HISTORY = 4,
+    KC_COUNT = 5
 };
 
 struct KernelTimer {

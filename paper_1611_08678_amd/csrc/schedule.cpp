@@ -1,5 +1,6 @@
-// schedule.cpp -- host-side schedules of the single-trajectory BLOCKED path
-// (see fabm_blocked.h). Pure host code, no device calls.
+// schedule.cpp -- host-side task schedule of the single-launch persistent
+// variant of the BLOCKED path (not dispatched; see blocked_persistent.hip).
+// Pure host code, no device calls.
 #include <algorithm>
 #include <tuple>
 #include <vector>
@@ -54,59 +55,6 @@ void blocked_schedule(int NB, int4 *tasks, int *queue, int *task_off)
         return tasks[a].x < tasks[b].x;
     });
     std::copy(order.begin(), order.end(), queue);
-}
-
-void pipe_schedule(int NB, PipeSchedule &s)
-{
-    s = PipeSchedule();
-    s.NB = NB;
-    // far tasks of every target, in source order, each with its own slot
-    struct Task { int J, lo, hi, slot; };
-    std::vector<std::vector<Task>> by_step((size_t)std::max(NB, 1));
-    s.tt_off.assign((size_t)NB + 1, 0);
-    std::vector<std::pair<int, int>> tmp;
-    for (int J = 0; J < NB; ++J) {
-        s.tt_off[(size_t)J] = (int)s.tt_slot.size();
-        if (J < 3) continue;  // blocks 0..2 have no far range
-        tmp.clear();
-        int e = J - 2, sz = 2;  // far range [0, J-2), chunks 2, 4, 8, ... from its near end
-        while (e > 0) {
-            const int lo = std::max(0, e - sz);
-            tmp.push_back({lo, e});
-            e = lo;
-            sz *= 2;
-        }
-        std::reverse(tmp.begin(), tmp.end());
-        for (auto &c : tmp) {
-            const int slot = s.n_slots++;
-            s.tt_slot.push_back(slot);
-            by_step[(size_t)(c.second - 1)].push_back(Task{J, c.first, c.second, slot});
-        }
-    }
-    s.tt_off[(size_t)NB] = (int)s.tt_slot.size();
-    s.step_item_off.assign((size_t)NB + 1, 0);
-    s.step_red_off.assign((size_t)NB + 1, 0);
-    for (int I = 0; I < NB; ++I) {
-        s.step_item_off[(size_t)I] = (int)s.items.size();
-        s.step_red_off[(size_t)I] = (int)s.reds.size();
-        auto &v = by_step[(size_t)I];
-        std::sort(v.begin(), v.end(), [](const Task &a, const Task &b) { return a.J < b.J; });
-        int scratch = 0;
-        for (const Task &t : v) {
-            const int n = (t.hi - t.lo + kItemBlocks - 1) / kItemBlocks;
-            if (n == 1) {
-                s.items.push_back(int4{t.J, t.lo, t.hi, t.slot});
-                continue;
-            }
-            const int first = scratch;
-            for (int a = t.lo; a < t.hi; a += kItemBlocks)
-                s.items.push_back(int4{t.J, a, std::min(a + kItemBlocks, t.hi), -(scratch++) - 1});
-            s.reds.push_back(int4{t.slot, first, n, 0});
-        }
-        s.max_scratch = std::max(s.max_scratch, scratch);
-    }
-    s.step_item_off[(size_t)NB] = (int)s.items.size();
-    s.step_red_off[(size_t)NB] = (int)s.reds.size();
 }
 
 }  // namespace fabm

@@ -42,6 +42,16 @@ def test_enums_match_oracle_numbering(fabm):
     assert fabm.fabm_n_params(fabm.FABM_SYS_LINEAR, 65) == -1
 
 
+def test_kernel_classes_match_header(fabm):
+    src = open(os.path.join(ROOT, "include", "fabm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    found = {m.group(1).lower(): int(m.group(2))
+             for m in re.finditer(r"FABM_KERNEL_([A-Z_]+)\s*=\s*(\d+)", src)}
+    count = found.pop("count")
+    assert count == len(fabm.KERNEL_CLASSES)
+    assert {k: i for i, k in enumerate(fabm.KERNEL_CLASSES)} == found
+
+
 def test_status_strings(fabm):
     assert fabm.status_string(0) == "ok"
     assert fabm.status_string(3) == "workspace too small"

@@ -1,4 +1,4 @@
-"""GPU parity of the BLOCKED single-trajectory path (band + MFMA far tiles)
+"""GPU parity of the BLOCKED single-trajectory path (band + MFMA windows)
 against the CPU oracle, through the C ABI. Same tolerances as the DIRECT
 tests: 1e-11 normwise for non-chaotic systems over the whole trajectory; for
 Chen, 1e-11 up to the oracle's own one-ulp sensitivity horizon."""
@@ -96,12 +96,45 @@ def test_blocked_chen_full_size(F, orc):
     ref, _, _, _ = orc.solve(w["system"], w["theta"][0], w["alpha"][0], w["h"][0], 4096,
                              w["y0"][0])
     assert relerr(yy[:4097], ref) <= 1e-11
+    # sampled rows anywhere in the trajectory: the oracle re-forms step t from
+    # the GPU's own history (f_k = f(t_k, y_k) of the GPU rows). Both sides sum
+    # the same terms; the bound is the probabilistic recursive-summation bound
+    # 10 sqrt(t) u times the magnitude of the history terms, plus 4 u |y_t|.
+    u = np.finfo(np.float64).eps / 2
+    wts = orc.weights(w["alpha"][0], N)
+    f = orc.rhs_rows(w["system"], w["theta"][0], w["h"][0], yy)
+    for t in (4097, 65541, 1 << 19, N - 257, N):
+        yt, mag = orc.step_from_history(w["system"], w["theta"][0], w["alpha"][0], w["h"][0],
+                                        t, w["y0"][0], f, wts)
+        tol = 10.0 * np.sqrt(t) * u * mag + 4 * u * np.abs(yt)
+        assert np.all(np.abs(yy[t] - yt) <= tol), (t, yy[t], yt, mag)
+
+
+def test_blocked_kernel_times(F):
+    """The profiling interface reports one step launch per 256-row block."""
+    import torch
+    from paper_1611_08678_amd import workloads as W
+    w = W.chen(N=20000)
+    N, d = 20000, 3
+    plan = F.fabm_plan(w["system"], d, "blocked", "fp64", 1, N)
+    ws = torch.empty(F.fabm_workspace_size(plan, [N]), dtype=torch.uint8, device="cuda")
+    y0 = torch.as_tensor(w["y0"][0], device="cuda")
+    th = torch.as_tensor(w["theta"][0], device="cuda")
+    y = torch.empty((N + 1, d), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int64, device="cuda")
+    F.fabm_plan_set_profiling(plan, True)
+    F.fabm_solve(plan, ws, float(w["alpha"][0]), float(w["h"][0]), N, y0, th, y, st)
+    torch.cuda.synchronize()
+    kt = F.fabm_plan_kernel_times(plan)
+    assert kt["blocked_step"][1] == (N + 1 + 255) // 256
+    assert kt["blocked_step"][0] > 0 and kt["weights"][1] == 1
+    assert int(st.item()) == 0
 
 
 @pytest.mark.skip(reason=(
     "single-launch persistent BLOCKED variant (blocked_persistent.hip) is switched off: its "
     "launch with far tasks (N=600, three blocks) did not complete on MI355X, also after the "
     "flag fix; inter-workgroup flag polling compiled to plain cached loads. The dispatched "
-    "BLOCKED path is the event-ordered pipeline tested above."))
+    "BLOCKED path is the step-kernel pipeline tested above."))
 def test_blocked_persistent_variant_far_tasks():
     pass

@@ -239,3 +239,20 @@ def test_batch_equals_single_and_thread_invariant(orc, monkeypatch):
     for i in range(B):
         yi, _, _, _ = orc.solve(orc.ROSSLER, th[i], alphas[i], 0.005, int(Ns[i]), y0[i])
         assert np.array_equal(y[off[i]: off[i] + Ns[i] + 1], yi)
+
+
+def test_step_from_history_matches_solver_rows(orc):
+    """The teacher-forced single step is the solver's step: fed the solver's own
+    history it reproduces every sampled row exactly, and its magnitude sum is
+    at least the size of the history part of the update."""
+    th = [35.0, 3.0, 28.0]
+    alpha, h, N = 0.95, 0.001, 3000
+    y0 = [-9.0, -5.0, 14.0]
+    y, _, f, st = orc.solve(1, th, alpha, h, N, y0)
+    assert st == 0
+    assert np.array_equal(orc.rhs_rows(1, th, h, y), f)
+    wts = orc.weights(alpha, N)
+    for t in (1, 2, 255, 256, 257, 1777, N):
+        yt, mag = orc.step_from_history(1, th, alpha, h, t, y0, f, wts)
+        assert np.array_equal(yt, y[t])
+        assert np.all(mag > 0) and np.all(np.abs(y[t] - np.asarray(y0)) <= mag + 1.0)
