@@ -50,20 +50,21 @@ constexpr int n_params_of_sys(int sys, int d)
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Band: block J walked row by row by wavefronts 0..4 of workgroup 0.
+// Band: block J walked row by row by wavefronts 0..3 of workgroup 0.
 //
-// Wavefront 0 forms every row. Lane l holds the sums of the four target rows
-// l, 64 + l, 128 + l, 192 + l of block J. At row t = 64 g + r the sums of
-// lane r, group g are read out (readlane) and every lane evaluates the
-// predictor and corrector with those same values, so f_t is present in all
-// lanes without a broadcast; each lane then adds w[T-1-t] f_t to its targets
-// T. No barrier is taken inside the walk. f_t and y_t go to LDS and a counter
-// in LDS publishes how many rows are final.
-// Wavefronts 1..4 hold the sums of the 256 rows of block J+1 (wavefront k,
-// lane l: row 64 (k-1) + l) and add each published f_t as it appears; their
-// sums are handed to the next block through `carry`.
+// Wavefront w holds, one per lane, the sums of rows 64 w + l of block J and
+// of block J+1, and forms rows 64 w .. 64 w + 63 itself. At row t its sums in
+// lane t - 64 w are read out (readlane) and every lane evaluates the predictor
+// and corrector with those same values, so f_t is present in all lanes without
+// a broadcast; each lane then adds w[T-1-t] f_t to its own target T of block
+// J. Nothing else is on that chain: rows are published in LDS (f_t, y_t, and a
+// row counter every 8 rows), the other wavefronts add them to their sums as
+// they appear, and the contributions of the wavefront's own rows to block J+1
+// are added after its turn. Every target's sums are still accumulated in row
+// order. The sums of block J+1 go to the next launch through `carry`.
 // ---------------------------------------------------------------------------
-constexpr int kBandWaves = 5;
+constexpr int kBandWaves = 4;
+constexpr int kPublishEvery = 8;           // rows between counter updates
 constexpr uint32_t kSpinLimit = 1u << 26;  // polls of the row counter before giving up
 
 __device__ __forceinline__ double readlane_f64(double x, int l)
@@ -74,15 +75,36 @@ __device__ __forceinline__ double readlane_f64(double x, int l)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Wait until at least `need` rows are published. Returns the published count,
+// or -1 if the walk stopped (a non-finite row) or the wait gave up (then the
+// block is marked with -2).
+__device__ __forceinline__ int band_wait_rows(int *s_cnt, int *s_dead, int need)
+{
+    uint32_t spins = 0;
+    for (;;) {
+        const int c = __hip_atomic_load(s_cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (c > kBlk) return -1;
+        if (c >= need) return c;
+        if (++spins > kSpinLimit) {
+            __hip_atomic_store(s_dead, -2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(s_cnt, kBlk + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 template <int SYS, int D>
 __device__ __forceinline__ void band_block(const StepArgs &A, int J, char *smem)
 {
+    constexpr int NP = n_params_of_sys(SYS, D);
     double *sb = (double *)smem;  // b lags 0..511
     double *sa = sb + 2 * kBlk;   // a lags 0..511
     double *sF = sa + 2 * kBlk;   // [256][D] f of this block's rows
     double *sY = sF + kBlk * D;   // [256][D] y of this block's rows
-    int *s_cnt = (int *)(sY + kBlk * D);  // rows of this block formed so far
-    int *s_dead = s_cnt + 1;              // first non-finite row (block-relative), or -1
+    double *sTh = sY + kBlk * D;  // theta, for systems with many parameters
+    int *s_cnt = (int *)(sTh + NP);  // rows of this block published so far (> 256: stop)
+    int *s_dead = s_cnt + 1;         // first non-finite row (block-relative), -1, or -2
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const InstMeta m = A.meta[0];
     const int64_t N = m.N;
@@ -97,10 +119,16 @@ __device__ __forceinline__ void band_block(const StepArgs &A, int J, char *smem)
         for (int e = tid; e < nrows * D; e += nthr) A.Y[t0 * D + e] = __builtin_nan("");
         return;
     }
-    constexpr int NP = n_params_of_sys(SYS, D);
-    double th[NP], y0[D];
+    // theta in registers when short; a linear system's matrix is read from LDS
+    constexpr bool kThLds = NP > 12;
+    double thr[kThLds ? 1 : NP], y0[D];
+    if constexpr (!kThLds) {
 #pragma unroll
-    for (int k = 0; k < NP; ++k) th[k] = A.params[k];
+        for (int k = 0; k < NP; ++k) thr[k] = A.params[k];
+    } else {
+        for (int k = tid; k < NP; k += nthr) sTh[k] = A.params[k];
+    }
+    const double *th = kThLds ? sTh : thr;
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = A.y0[i];
     for (int j = tid; j < 2 * kBlk; j += nthr) {
@@ -110,7 +138,7 @@ __device__ __forceinline__ void band_block(const StepArgs &A, int J, char *smem)
     // f_0 (block 0 forms row 0 here; later blocks need it for the c - a fix)
     double f0[D];
     if (J == 0) {
-        rhs<SYS, D>(0.0, y0, f0, th);
+        rhs<SYS, D>(0.0, y0, f0, A.params);
     } else {
 #pragma unroll
         for (int i = 0; i < D; ++i) f0[i] = A.Fc[i * pitch];
@@ -126,136 +154,171 @@ __device__ __forceinline__ void band_block(const StepArgs &A, int J, char *smem)
             }
         }
     }
-
-    if (wave == 0) {
-        // sums of rows 64 g + lane of block J
-        double pc[4][D], cc[4][D];
-        const double *cin = A.carry + (int64_t)(J & 1) * 2 * D * kBlk;
-        const double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int row = 64 * g + lane;
-            const int64_t T = t0 + row;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                if (J == 0) {
-                    // source row 0 feeds targets 1..255 with b_{T-1} and c_{T-1}
-                    pc[g][i] = T >= 1 ? wb[T - 1] * f0[i] : 0.0;
-                    cc[g][i] = T >= 1 ? wc[T - 1] * f0[i] : 0.0;
-                } else {
-                    pc[g][i] = cin[i * kBlk + row];
-                    cc[g][i] = cin[(D + i) * kBlk + row];
-                }
-            }
-            if (J >= 2) {
-                // near + far sums, stored in MFMA result order: row 16 rho + sigma
-                // is element sigma/4 of lane 16 (sigma % 4) + rho
-                const int rho = row >> 4, sig = row & 15;
-                const int e = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
-                const double dca = wc[T - 1] - wa[T - 1];
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    pc[g][i] += aj[i * kBlk + e];
-                    // source row 0 takes c_{T-1} where the tiles used a_{T-1}
-                    cc[g][i] = fma(dca, f0[i], cc[g][i] + aj[(D + i) * kBlk + e]);
-                }
-            }
-        }
-        __syncthreads();
-        bool alive = true;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int r0 = (g == 0 && J == 0) ? 1 : 0;
-            const int r1 = nrows - 64 * g < 64 ? nrows - 64 * g : 64;
-            for (int r = r0; alive && r < r1; ++r) {
-                const int row = 64 * g + r;
-                const int64_t t = t0 + row;
-                double P[D], Cs[D], y[D], f[D];
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    P[i] = readlane_f64(pc[g][i], r);
-                    Cs[i] = readlane_f64(cc[g][i], r);
-                }
-                pece_update<SYS, D>(m, (double)t * m.h, y0, P, Cs, th, y, f);
-                if (!finite_all(y) || !finite_all(f)) {
-                    if (lane == 0) *s_dead = row;
-                    alive = false;
-                    break;
-                }
-                if (lane == 0) {
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        sF[row * D + i] = f[i];
-                        sY[row * D + i] = y[i];
-                    }
-                    __hip_atomic_store(s_cnt, row + 1, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-                // targets 64 g2 + lane > row (lags of earlier rows are clamped
-                // to 0; those sums are no longer read)
-#pragma unroll
-                for (int g2 = g; g2 < 4; ++g2) {
-                    const int lag = 64 * g2 + lane - row - 1;
-                    const int lc = lag > 0 ? lag : 0;
-                    const double bw = sb[lc], aw = sa[lc];
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        pc[g2][i] = fma(bw, f[i], pc[g2][i]);
-                        cc[g2][i] = fma(aw, f[i], cc[g2][i]);
-                    }
-                }
-            }
-        }
-        if (!alive && lane == 0)
-            __hip_atomic_store(s_cnt, kBlk + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __syncthreads();
-    } else {
-        // wavefronts 1..4: sums of row 64 (wave-1) + lane of block J+1
-        const int row = 64 * (wave - 1) + lane;
-        double pn[D], cn[D];
+    // sums of target row `row` of block J (pc, cc) and of block J+1 (pn, cn)
+    const int row = 64 * wave + lane;
+    const int64_t T = t0 + row;
+    double pc[D], cc[D], pn[D], cn[D];
+    if (J == 0) {
+        // source row 0 takes b_{T-1} and c_{T-1}
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            // source row 0 of block 0 takes b_{T-1} and c_{T-1}
-            pn[i] = J == 0 ? wb[kBlk + row - 1] * f0[i] : 0.0;
-            cn[i] = J == 0 ? wc[kBlk + row - 1] * f0[i] : 0.0;
+            pc[i] = T >= 1 ? wb[T - 1] * f0[i] : 0.0;
+            cc[i] = T >= 1 ? wc[T - 1] * f0[i] : 0.0;
+            pn[i] = wb[kBlk + row - 1] * f0[i];
+            cn[i] = wc[kBlk + row - 1] * f0[i];
         }
-        __syncthreads();
-        int done = J == 0 ? 1 : 0;
-        uint32_t spins = 0;
-        while (done < nrows) {
-            const int avail = __hip_atomic_load(s_cnt, __ATOMIC_ACQUIRE,
-                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (avail > kBlk) break;  // the walk stopped at a non-finite row
-            if (avail == done) {
-                if (++spins > kSpinLimit) {
-                    if (lane == 0) __hip_atomic_store(s_dead, -2, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            for (; done < avail; ++done) {
-                const int lag = kBlk + row - done - 1;
-                const double bw = sb[lag], aw = sa[lag];
+    } else {
+        const double *cin = A.carry + (int64_t)(J & 1) * 2 * D * kBlk;
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    const double f = sF[done * D + i];
-                    pn[i] = fma(bw, f, pn[i]);
-                    cn[i] = fma(aw, f, cn[i]);
-                }
-            }
+        for (int i = 0; i < D; ++i) {
+            pc[i] = cin[i * kBlk + row];
+            cc[i] = cin[(D + i) * kBlk + row];
+            pn[i] = cn[i] = 0.0;
         }
-        __syncthreads();
-        if (*s_dead == -1) {
-            double *cout = A.carry + (int64_t)((J + 1) & 1) * 2 * D * kBlk;
+        if (J >= 2) {
+            // near + far sums, stored in MFMA result order: row 16 rho + sigma
+            // is element sigma/4 of lane 16 (sigma % 4) + rho
+            const int rho = row >> 4, sig = row & 15;
+            const int e = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
+            const double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
+            const double dca = wc[T - 1] - wa[T - 1];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                cout[i * kBlk + row] = pn[i];
-                cout[(D + i) * kBlk + row] = cn[i];
+                pc[i] += aj[i * kBlk + e];
+                // source row 0 takes c_{T-1} where the tiles used a_{T-1}
+                cc[i] = fma(dca, f0[i], cc[i] + aj[(D + i) * kBlk + e]);
             }
         }
     }
+    __syncthreads();
+
+    const int lo = 64 * wave < nrows ? 64 * wave : nrows;  // rows this wavefront forms:
+    const int hi = 64 * wave + 64 < nrows ? 64 * wave + 64 : nrows;  // [lo, hi)
+    int done = J == 0 ? 1 : 0;  // rows already in this wavefront's sums
+    bool go = true;
+    // rows formed by earlier wavefronts: both blocks' sums
+    while (go && done < lo) {
+        const int c = band_wait_rows(s_cnt, s_dead, done + 1);
+        if (c < 0) {
+            go = false;
+            break;
+        }
+        const int upto = c < lo ? c : lo;
+        for (; done < upto; ++done) {
+            const double bw = sb[row - done - 1], aw = sa[row - done - 1];
+            const double bn = sb[kBlk + row - done - 1], an = sa[kBlk + row - done - 1];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const double f = sF[done * D + i];
+                pc[i] = fma(bw, f, pc[i]);
+                cc[i] = fma(aw, f, cc[i]);
+                pn[i] = fma(bn, f, pn[i]);
+                cn[i] = fma(an, f, cn[i]);
+            }
+        }
+    }
+    // this wavefront's rows. The sums read out for row t leave out row t-1,
+    // whose contribution enters the predictor and the corrector directly:
+    //   yP_t = y0 + h^a P'_t + (h^a b_0) f_{t-1},
+    //   y_t  = y0 + h^a C'_t + (h^a a_0) f_{t-1} + (h^a / Gamma(a+2)) f(t, yP_t),
+    // so the dependent chain of a step is the two evaluations of f; adding
+    // row t-1 to the other sums and reading out those of row t+1 overlap it.
+    const int first = done;
+    const double hb0 = m.ha * sb[0], ha0 = m.ha * sa[0], hig2 = m.ha * m.ig2;
+    double fprev[D], ypb[D], ycb[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        // the first row's sums are complete
+        const int l0 = first - lo < 63 ? first - lo : 63;
+        ypb[i] = fma(m.ha, readlane_f64(pc[i], l0), y0[i]);
+        ycb[i] = fma(m.ha, readlane_f64(cc[i], l0), y0[i]);
+        fprev[i] = 0.0;
+    }
+    int bad = -1;  // first non-finite row formed by this wavefront
+    for (int t = first; go && t < hi; ++t) {
+        const double tt = (double)(t0 + t) * m.h;
+        double yp[D], fp[D], yc[D], y[D], f[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) yp[i] = fma(hb0, fprev[i], ypb[i]);
+        rhs<SYS, D>(tt, yp, fp, th);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            yc[i] = fma(ha0, fprev[i], ycb[i]);
+            y[i] = fma(hig2, fp[i], yc[i]);
+        }
+        rhs<SYS, D>(tt, y, f, th);
+        // off the chain: row t-1 into the sums of the later rows (lags of
+        // rows <= t-1 are clamped; those sums are no longer read), then the
+        // sums of row t+1
+        const int lag = row - t;
+        const int lc = lag > 0 ? lag : 0;
+        const double bw = sb[lc], aw = sa[lc];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            pc[i] = fma(bw, fprev[i], pc[i]);
+            cc[i] = fma(aw, fprev[i], cc[i]);
+        }
+        const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
+        bool nf = false;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            ypb[i] = fma(m.ha, readlane_f64(pc[i], ln), y0[i]);
+            ycb[i] = fma(m.ha, readlane_f64(cc[i], ln), y0[i]);
+            nf |= !isfinite(y[i]);
+            nf |= !isfinite(f[i]);
+            fprev[i] = f[i];
+        }
+        if (nf && bad < 0) bad = t;
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                sF[t * D + i] = f[i];
+                sY[t * D + i] = y[i];
+            }
+        }
+        if ((t + 1) % kPublishEvery == 0 || t + 1 == hi) {
+            if (bad >= 0) {
+                if (lane == 0) {
+                    *s_dead = bad;
+                    __hip_atomic_store(s_cnt, kBlk + 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                go = false;
+                break;
+            }
+            if (lane == 0)
+                __hip_atomic_store(s_cnt, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        done = t + 1;
+    }
+    if (go) {
+        // own rows into block J+1 (f_t was written to LDS by lane 0 of this
+        // wavefront), then rows formed by later wavefronts
+        __builtin_amdgcn_wave_barrier();
+        for (int t = first; t < hi; ++t) {
+            const double bn = sb[kBlk + row - t - 1], an = sa[kBlk + row - t - 1];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const double f = sF[t * D + i];
+                pn[i] = fma(bn, f, pn[i]);
+                cn[i] = fma(an, f, cn[i]);
+            }
+        }
+        while (done < nrows) {
+            const int c = band_wait_rows(s_cnt, s_dead, done + 1);
+            if (c < 0) break;
+            for (; done < c; ++done) {
+                const double bn = sb[kBlk + row - done - 1], an = sa[kBlk + row - done - 1];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const double f = sF[done * D + i];
+                    pn[i] = fma(bn, f, pn[i]);
+                    cn[i] = fma(an, f, cn[i]);
+                }
+            }
+        }
+    }
+    __syncthreads();
     // rows of this block: final ones from LDS, NaN from the first non-finite on
     const int dead = *s_dead;
     const int valid = dead == -1 ? nrows : (dead < 0 ? 0 : dead);
@@ -265,26 +328,61 @@ __device__ __forceinline__ void band_block(const StepArgs &A, int J, char *smem)
 #pragma unroll
         for (int i = 0; i < D; ++i) A.Fc[i * pitch + t0 + e] = sF[e * D + i];
     }
-    if (dead != -1 && tid == 0) *A.dead = dead == -2 ? kDeadWatchdog : (uint32_t)(t0 + dead);
+    if (dead == -1) {
+        double *cout = A.carry + (int64_t)((J + 1) & 1) * 2 * D * kBlk;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            cout[i * kBlk + row] = pn[i];
+            cout[(D + i) * kBlk + row] = cn[i];
+        }
+    } else if (tid == 0) {
+        *A.dead = dead == -2 ? kDeadWatchdog : (uint32_t)(t0 + dead);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// One column lag q = 16 m + u of a target block, for both weight tables and
-// all components, added into `acc` (one wavefront). kc = 16 (J - m) is the
-// source column of rho = 0 at u = 0; source columns outside [0, kmax] are
-// masked to zero.
+// MFMA windows. Launch s reads only the history of source columns
+// 16 s - 15 .. 16 s + 15 (blocks s - 1 and s), for every target. Each
+// workgroup stages those 31 columns in LDS (zero for negative rows), with a
+// pitch of 17 doubles per column so that the 16 lanes of a K-slot read 16
+// distinct even bank pairs.
 // ---------------------------------------------------------------------------
+constexpr int kSrcCols = 31;
+constexpr int kColPitch = 17;
+
+template <int D>
+constexpr size_t staged_bytes()
+{
+    return sizeof(double) * D * kSrcCols * kColPitch;
+}
+
+template <int D>
+__device__ __forceinline__ void stage_sources(const StepArgs &A, int s, double *sB)
+{
+    const int64_t pitch = (int64_t)A.NB * kBlk;
+    const int64_t r0 = (int64_t)kBlk * s - kTile * (kSrcCols - kTile);  // row of column 16 s - 15
+    for (int e = threadIdx.x; e < D * kSrcCols * kTile; e += blockDim.x) {
+        const int i = e / (kSrcCols * kTile), rem = e - i * (kSrcCols * kTile);
+        const int c = rem / kTile, tau = rem - c * kTile;
+        const int64_t row = r0 + kTile * c + tau;
+        sB[(i * kSrcCols + c) * kColPitch + tau] = row >= 0 ? A.Fc[i * pitch + row] : 0.0;
+    }
+}
+
+// One column lag q = 16 m + u of a target block, for both weight tables and
+// all components, added into `acc` (one wavefront). The history column of
+// lane rho is staged column rho - u + coff; columns past the staged range
+// (coff > 15 only) belong to blocks not yet formed and are masked to zero.
 template <int D>
 __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__restrict__ wb,
-                                           const double *__restrict__ wa,
-                                           const double *__restrict__ Fc, int64_t pitch,
-                                           int64_t kc, int64_t m, int u, int64_t kmax)
+                                           const double *__restrict__ wa, const double *sB,
+                                           int64_t m, int u, int coff)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int r16 = lane & 15, kq = lane >> 4;  // A row sigma / B column rho; K slot
-    const int64_t kappa = kc + r16 - u;
-    const bool ok = kappa >= 0 && kappa <= kmax;
-    const int64_t fb = ok ? kTile * kappa + kq : 0;  // masked lanes read row 0
+    const int c = r16 - u + coff;
+    const bool ok = c < kSrcCols;
+    const int sbase = (ok ? c : 0) * kColPitch + kq;
     const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -292,7 +390,7 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
         double bf[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double v = Fc[i * pitch + fb + 4 * j];
+            const double v = sB[i * kSrcCols * kColPitch + sbase + 4 * j];
             bf[i] = ok ? v : 0.0;
         }
 #pragma unroll
@@ -304,12 +402,12 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
 }
 
 // Far windows of step s: wavefront g of G handles targets J = s + 3 + g,
-// s + 3 + g + G, ... (window m = J - s, sources in blocks s - 1 and s).
+// s + 3 + g + G, ... (window m = J - s: staged columns rho - u + 15).
 template <int D>
-__device__ __forceinline__ void far_windows(const StepArgs &A, int s, int g, int G)
+__device__ __forceinline__ void far_windows(const StepArgs &A, int s, int g, int G,
+                                            const double *sB)
 {
     const InstMeta m = A.meta[0];
-    const int64_t pitch = (int64_t)A.NB * kBlk;
     const double *wb = A.W, *wa = wb + m.wlen;
     const int lane = threadIdx.x & (kWave - 1);
     for (int J = s + 3 + g; J < A.NB; J += G) {
@@ -323,9 +421,8 @@ __device__ __forceinline__ void far_windows(const StepArgs &A, int s, int g, int
                 for (int v = 0; v < 4; ++v)
                     acc[t][i][v] = s == 0 ? 0.0 : aj[((t * D + i) * 4 + v) * kWave];
         const int64_t mm = J - s;
-        for (int u = 0; u < kTile; ++u)
-            window_lag<D>(acc, wb, wa, A.Fc, pitch, (int64_t)kTile * s, mm, u,
-                          (int64_t)kTile * s + kTile - 1);
+#pragma unroll 2
+        for (int u = 0; u < kTile; ++u) window_lag<D>(acc, wb, wa, sB, mm, u, kTile - 1);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -335,14 +432,15 @@ __device__ __forceinline__ void far_windows(const StepArgs &A, int s, int g, int
     }
 }
 
-// Near part of target block J = s + 2: column lags 17..47 (windows m = 2,
-// all u, and m = 1, u = 1..15), masked to source columns <= 16 s + 15.
+// Near part of target block J = s + 2: column lags 17..47, i.e. window m = 2
+// (all u, staged columns rho - u + 15) and window m = 1 for u = 1..15
+// (staged columns rho - u + 31, masked past column 30), split over the first
+// kNearWaves wavefronts and added in LDS in a fixed order.
 template <int D>
-__device__ __forceinline__ void near_part(const StepArgs &A, int s, char *smem)
+__device__ __forceinline__ void near_part(const StepArgs &A, int s, const double *sB,
+                                          double *red)
 {
-    double *red = (double *)smem;  // [kNearWaves][2D][4][64]
     const InstMeta m = A.meta[0];
-    const int64_t pitch = (int64_t)A.NB * kBlk;
     const double *wb = A.W, *wa = wb + m.wlen;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid >> 6;
     const int J = s + 2;
@@ -354,10 +452,10 @@ __device__ __forceinline__ void near_part(const StepArgs &A, int s, char *smem)
         for (int i = 0; i < D; ++i) acc[t][i] = (dbl4){0.0, 0.0, 0.0, 0.0};
     const int p0 = kLags * w / kNearWaves, p1 = kLags * (w + 1) / kNearWaves;
     for (int p = p0; p < p1; ++p) {
-        const int mm = p < kTile ? 2 : 1;
-        const int u = p < kTile ? p : p - (kTile - 1);
-        window_lag<D>(acc, wb, wa, A.Fc, pitch, (int64_t)kTile * (J - mm), mm, u,
-                      (int64_t)kTile * s + kTile - 1);
+        if (p < kTile)
+            window_lag<D>(acc, wb, wa, sB, 2, p, kTile - 1);
+        else
+            window_lag<D>(acc, wb, wa, sB, 1, p - (kTile - 1), 2 * kTile - 1);
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -366,7 +464,7 @@ __device__ __forceinline__ void near_part(const StepArgs &A, int s, char *smem)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 red[((w * 2 * D + t * D + i) * 4 + v) * kWave + lane] = acc[t][i][v];
-    __syncthreads();  // the eight near wavefronts
+    __syncthreads();  // the near wavefronts
     double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
     for (int e = tid; e < 2 * D * kBlk; e += kNearWaves * kWave) {
         double v = s == 0 ? 0.0 : aj[e];
@@ -387,11 +485,16 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         return;
     }
     if (*A.dead != 0u) return;  // the trajectory has ended; later rows are NaN
+    double *sB = (double *)smem;
+    stage_sources<D>(A, s, sB);
+    __syncthreads();
     if (b == 1) {
-        if (wave < kNearWaves) near_part<D>(A, s, smem);
+        if (wave < kNearWaves)
+            near_part<D>(A, s, sB, (double *)(smem + staged_bytes<D>()));
         return;
     }
-    if (wave < wpw) far_windows<D>(A, s, (b - 2) * wpw + wave, ((int)gridDim.x - 2) * wpw);
+    if (wave < wpw)
+        far_windows<D>(A, s, (b - 2) * wpw + wave, ((int)gridDim.x - 2) * wpw, sB);
 }
 
 __global__ void k_step_status(StepArgs A)
@@ -410,8 +513,9 @@ __global__ void k_step_status(StepArgs A)
 // itself and each far workgroup owns four SIMDs.
 size_t step_smem_bytes(int d)
 {
-    const size_t band = sizeof(double) * (4 * kBlk + 2 * kBlk * (size_t)d) + 16;
-    const size_t near = sizeof(double) * kNearWaves * 2 * (size_t)d * kBlk;
+    const size_t band = sizeof(double) * (4 * kBlk + 2 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    const size_t near = sizeof(double) * (kNearWaves * 2 * (size_t)d * kBlk +
+                                          (size_t)d * kSrcCols * kColPitch);
     const size_t exclusive = 81 * 1024;
     return std::max(band, std::max(near, exclusive));
 }
