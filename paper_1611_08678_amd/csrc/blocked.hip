@@ -41,6 +41,7 @@ constexpr int kBlk = 256;  // rows per block (= band threads)
 constexpr int kTile = 16;  // polyphase factor = MFMA edge
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 constexpr int n_params_of_sys(int sys, int d)
 {
@@ -95,7 +96,7 @@ __device__ __forceinline__ int band_wait_rows(int *s_cnt, int *s_dead, int need)
 }
 
 template <int SYS, int D>
-__device__ __forceinline__ void band_block(const StepArgs &A, int J, char *smem)
+__device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
     double *sb = (double *)smem;  // b lags 0..511
@@ -349,15 +350,18 @@ __device__ __forceinline__ void band_block(const StepArgs &A, int J, char *smem)
 // ---------------------------------------------------------------------------
 constexpr int kSrcCols = 31;
 constexpr int kColPitch = 17;
+// Result layout of v_mfma_f32_16x16x4f32: element v of lane l is row
+// 4 (l / 16) + v when true, row 4 v + l / 16 (as for binary64) when false.
+constexpr bool kF32RowMajorLanes = false;
 
-template <int D>
+template <int D, typename T = double>
 constexpr size_t staged_bytes()
 {
-    return sizeof(double) * D * kSrcCols * kColPitch;
+    return sizeof(T) * D * kSrcCols * kColPitch;
 }
 
-template <int D>
-__device__ __forceinline__ void stage_sources(const StepArgs &A, int s, double *sB)
+template <int D, typename T>
+__device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB)
 {
     const int64_t pitch = (int64_t)A.NB * kBlk;
     const int64_t r0 = (int64_t)kBlk * s - kTile * (kSrcCols - kTile);  // row of column 16 s - 15
@@ -365,7 +369,7 @@ __device__ __forceinline__ void stage_sources(const StepArgs &A, int s, double *
         const int i = e / (kSrcCols * kTile), rem = e - i * (kSrcCols * kTile);
         const int c = rem / kTile, tau = rem - c * kTile;
         const int64_t row = r0 + kTile * c + tau;
-        sB[(i * kSrcCols + c) * kColPitch + tau] = row >= 0 ? A.Fc[i * pitch + row] : 0.0;
+        sB[(i * kSrcCols + c) * kColPitch + tau] = row >= 0 ? (T)A.Fc[i * pitch + row] : (T)0;
     }
 }
 
@@ -401,43 +405,102 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
     }
 }
 
-// Far windows of step s: wavefront g of G handles targets J = s + 3 + g,
-// s + 3 + g + G, ... (window m = J - s: staged columns rho - u + 15).
+// The same column lag on the binary32 matrix cores (v_mfma_f32_16x16x4f32):
+// weights and history rounded to binary32, products summed in binary32.
 template <int D>
-__device__ __forceinline__ void far_windows(const StepArgs &A, int s, int g, int G,
-                                            const double *sB)
+__device__ __forceinline__ void window_lag_f32(flt4 (&acc)[2][D], const float *__restrict__ wb,
+                                               const float *__restrict__ wa, const float *sB,
+                                               int64_t m, int u)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int sbase = (r16 - u + kTile - 1) * kColPitch + kq;
+    const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float ab = wb[wi - 4 * j], aa = wa[wi - 4 * j];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const float bf = sB[i * kSrcCols * kColPitch + sbase + 4 * j];
+            acc[0][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, bf, acc[0][i], 0, 0, 0);
+            acc[1][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, bf, acc[1][i], 0, 0, 0);
+        }
+    }
+}
+
+// Row of the 16x16 result held in element v of lane l by the binary32 16x16x4
+// instruction (measured on gfx950 with one-hot operands).
+__device__ __forceinline__ int f32_result_row(int l, int v) { return kF32RowMajorLanes ? 4 * (l >> 4) + v : 4 * v + (l >> 4); }
+
+// Far window m = J - s of target block J in binary32: the window's sums are
+// formed in binary32 and added to the binary64 sums of the target.
+template <int D>
+__device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, const float *sB)
+{
+    const InstMeta m = A.meta[0];
+    const float *wb = A.W32, *wa = wb + m.wlen;
+    const int lane = threadIdx.x & (kWave - 1);
+    double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
+    flt4 acc[2][D];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < D; ++i) acc[t][i] = (flt4){0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t mm = J - s;
+#pragma unroll 2
+    for (int u = 0; u < kTile; ++u) window_lag_f32<D>(acc, wb, wa, sB, mm, u);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        // binary64 sums keep the binary64 result order (element sigma/4 of lane
+        // 16 (sigma % 4) + rho)
+        const int sig = f32_result_row(lane, v), rho = lane & 15;
+        const int e = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double *p = aj + (t * D + i) * kBlk + e;
+                *p = (s == 0 ? 0.0 : *p) + (double)acc[t][i][v];
+            }
+    }
+}
+
+// Far window m = J - s of target block J (one wavefront; staged columns
+// rho - u + 15), added to the target's sums in place.
+template <int D>
+__device__ __forceinline__ void far_target(const InstView &A, int s, int J, const double *sB)
 {
     const InstMeta m = A.meta[0];
     const double *wb = A.W, *wa = wb + m.wlen;
     const int lane = threadIdx.x & (kWave - 1);
-    for (int J = s + 3 + g; J < A.NB; J += G) {
-        double *aj = A.acc + (int64_t)J * 2 * D * kBlk + lane;
-        dbl4 acc[2][D];
+    double *aj = A.acc + (int64_t)J * 2 * D * kBlk + lane;
+    dbl4 acc[2][D];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int i = 0; i < D; ++i)
+        for (int i = 0; i < D; ++i)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[t][i][v] = s == 0 ? 0.0 : aj[((t * D + i) * 4 + v) * kWave];
-        const int64_t mm = J - s;
+            for (int v = 0; v < 4; ++v)
+                acc[t][i][v] = s == 0 ? 0.0 : aj[((t * D + i) * 4 + v) * kWave];
+    const int64_t mm = J - s;
 #pragma unroll 2
-        for (int u = 0; u < kTile; ++u) window_lag<D>(acc, wb, wa, sB, mm, u, kTile - 1);
+    for (int u = 0; u < kTile; ++u) window_lag<D>(acc, wb, wa, sB, mm, u, kTile - 1);
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int i = 0; i < D; ++i)
+        for (int i = 0; i < D; ++i)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) aj[((t * D + i) * 4 + v) * kWave] = acc[t][i][v];
-    }
+            for (int v = 0; v < 4; ++v) aj[((t * D + i) * 4 + v) * kWave] = acc[t][i][v];
 }
 
 // Near part of target block J = s + 2: column lags 17..47, i.e. window m = 2
 // (all u, staged columns rho - u + 15) and window m = 1 for u = 1..15
 // (staged columns rho - u + 31, masked past column 30), split over the first
-// kNearWaves wavefronts and added in LDS in a fixed order.
-template <int D>
-__device__ __forceinline__ void near_part(const StepArgs &A, int s, const double *sB,
+// NW wavefronts. Their partial sums are added in wavefront order, either all
+// at once from NW LDS slots (SEQ = false, red holds NW tiles) or one
+// wavefront after another into a single slot (SEQ = true).
+template <int D, int NW, bool SEQ>
+__device__ __forceinline__ void near_part(const InstView &A, int s, const double *sB,
                                           double *red)
 {
     const InstMeta m = A.meta[0];
@@ -450,51 +513,167 @@ __device__ __forceinline__ void near_part(const StepArgs &A, int s, const double
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int i = 0; i < D; ++i) acc[t][i] = (dbl4){0.0, 0.0, 0.0, 0.0};
-    const int p0 = kLags * w / kNearWaves, p1 = kLags * (w + 1) / kNearWaves;
+    const int p0 = kLags * w / NW, p1 = kLags * (w + 1) / NW;
     for (int p = p0; p < p1; ++p) {
         if (p < kTile)
             window_lag<D>(acc, wb, wa, sB, 2, p, kTile - 1);
         else
             window_lag<D>(acc, wb, wa, sB, 1, p - (kTile - 1), 2 * kTile - 1);
     }
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                red[((w * 2 * D + t * D + i) * 4 + v) * kWave + lane] = acc[t][i][v];
-    __syncthreads();  // the near wavefronts
     double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
-    for (int e = tid; e < 2 * D * kBlk; e += kNearWaves * kWave) {
-        double v = s == 0 ? 0.0 : aj[e];
+    if constexpr (!SEQ) {
 #pragma unroll
-        for (int k = 0; k < kNearWaves; ++k) v += red[k * 2 * D * kBlk + e];
-        aj[e] = v;
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    red[((w * 2 * D + t * D + i) * 4 + v) * kWave + lane] = acc[t][i][v];
+        __syncthreads();  // the near wavefronts
+        for (int e = tid; e < 2 * D * kBlk; e += NW * kWave) {
+            double v = s == 0 ? 0.0 : aj[e];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) v += red[k * 2 * D * kBlk + e];
+            aj[e] = v;
+        }
+    } else {
+        for (int k = 0; k < NW; ++k) {
+            if (w == k) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            double *r = red + ((t * D + i) * 4 + v) * kWave + lane;
+                            *r = k == 0 ? acc[t][i][v] : *r + acc[t][i][v];
+                        }
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < 2 * D * kBlk; e += NW * kWave)
+            aj[e] = (s == 0 ? 0.0 : aj[e]) + red[e];
     }
 }
 
-// Launch s of the pipeline; `wpw` wavefronts of each far workgroup take part.
-template <int SYS, int D>
+__device__ __forceinline__ InstView single_view(const StepArgs &A)
+{
+    return InstView{A.meta, A.params, A.y0, A.Y, A.W, A.W32, A.Fc, A.carry, A.acc, A.dead, A.NB};
+}
+
+// Launch s of the single-trajectory pipeline; `wpw` wavefronts of each far
+// workgroup take part (wavefront g of G handles targets s + 3 + g + k G).
+template <int SYS, int D, bool F32>
 __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wpw)
 {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x, wave = threadIdx.x >> 6;
+    const InstView V = single_view(A);
     if (b == 0) {
-        if (wave < kBandWaves) band_block<SYS, D>(A, s + 1, smem);
+        if (wave < kBandWaves) band_block<SYS, D>(V, s + 1, smem);
         return;
     }
     if (*A.dead != 0u) return;  // the trajectory has ended; later rows are NaN
-    double *sB = (double *)smem;
-    stage_sources<D>(A, s, sB);
-    __syncthreads();
-    if (b == 1) {
-        if (wave < kNearWaves)
-            near_part<D>(A, s, sB, (double *)(smem + staged_bytes<D>()));
+    if (b == 1 || !F32) {
+        double *sB = (double *)smem;
+        stage_sources<D, double>(V, s, sB);
+        __syncthreads();
+        if (b == 1) {
+            if (wave < kNearWaves)
+                near_part<D, kNearWaves, false>(V, s, sB, (double *)(smem + staged_bytes<D>()));
+            return;
+        }
+        if (wave >= wpw) return;
+        const int G = ((int)gridDim.x - 2) * wpw;
+        for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G) far_target<D>(V, s, J, sB);
+    } else {
+        float *sB = (float *)smem;
+        stage_sources<D, float>(V, s, sB);
+        __syncthreads();
+        if (wave >= wpw) return;
+        const int G = ((int)gridDim.x - 2) * wpw;
+        for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G)
+            far_target_f32<D>(V, s, J, sB);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched pipeline (layout and schedule in fabm_blocked.h).
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
+{
+    const InstMeta *m = A.meta + i;
+    const BlkInst &b = A.inst[i];
+    return InstView{m,
+                    A.params + m->p_off,
+                    A.y0 + (int64_t)i * D,
+                    A.Y + m->row_off * D,
+                    A.W + m->w_off,
+                    A.W32 ? A.W32 + m->w_off / 3 * 2 : nullptr,
+                    A.Fc + b.fc_off,
+                    A.carry + (int64_t)i * 2 * 2 * D * kBlk,
+                    A.acc + b.acc_off,
+                    A.dead + i,
+                    b.NB};
+}
+
+template <int SYS, int D, bool F32>
+__global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s, int nband,
+                                                              int nnear, const int *far_off,
+                                                              int nfar)
+{
+    extern __shared__ __align__(16) char smem[];
+    int q = blockIdx.x;
+    if (q < nband) {
+        const InstView V = batch_view<D>(A, A.order[q]);
+        band_block<SYS, D>(V, s + 1, smem);
         return;
     }
-    if (wave < wpw)
-        far_windows<D>(A, s, (b - 2) * wpw + wave, ((int)gridDim.x - 2) * wpw, sB);
+    q -= nband;
+    int inst, first = -1;
+    if (q < nnear) {
+        inst = A.order[q];
+    } else {
+        q -= nnear;
+        // instance k of the far prefix with far_off[k] <= q < far_off[k + 1]
+        int lo = 0, hi = nfar;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (far_off[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        inst = A.order[lo];
+        first = s + 3 + 4 * (q - far_off[lo]);
+    }
+    const InstView V = batch_view<D>(A, inst);
+    if (*V.dead != 0u) return;  // this trajectory has ended; its later rows are NaN
+    const int J = first + (threadIdx.x >> 6);
+    if (first < 0 || !F32) {
+        double *sB = (double *)smem;
+        stage_sources<D, double>(V, s, sB);
+        __syncthreads();
+        if (first < 0) {
+            near_part<D, kBatchThreads / kWave, true>(V, s, sB,
+                                                      (double *)(smem + staged_bytes<D>()));
+            return;
+        }
+        if (J < V.NB) far_target<D>(V, s, J, sB);
+    } else {
+        float *sB = (float *)smem;
+        stage_sources<D, float>(V, s, sB);
+        __syncthreads();
+        if (J < V.NB) far_target_f32<D>(V, s, J, sB);
+    }
+}
+
+__global__ void k_batch_status(BatchArgs A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < A.batch) {
+        const uint32_t d = A.dead[i];
+        A.status[i] = d == kDeadWatchdog ? -1 : (int64_t)d;
+    }
 }
 
 __global__ void k_step_status(StepArgs A)
@@ -536,7 +715,7 @@ void step_grid(int NB, int s, int *grid, int *wpw)
     *grid += std::min(kMaxFarWg, (nt + *wpw - 1) / *wpw);
 }
 
-template <int SYS, int D>
+template <int SYS, int D, bool F32>
 static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer *T,
                                   const char **where)
 {
@@ -553,7 +732,7 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
     const size_t smem = step_smem_bytes(D);
     if (!attr_done) {
         FABM_STEP_TRY("hipFuncSetAttribute(step LDS)",
-                      hipFuncSetAttribute((const void *)k_step<SYS, D>,
+                      hipFuncSetAttribute((const void *)k_step<SYS, D, F32>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
         attr_done = true;
     }
@@ -561,7 +740,8 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
         int grid, wpw;
         step_grid(A.NB, s, &grid, &wpw);
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
-        hipLaunchKernelGGL((k_step<SYS, D>), dim3(grid), dim3(kStepThreads), smem, st, A, s, wpw);
+        hipLaunchKernelGGL((k_step<SYS, D, F32>), dim3(grid), dim3(kStepThreads), smem, st, A, s,
+                           wpw);
         FABM_STEP_TRY("launch k_step", hipGetLastError());
         if (T) FABM_STEP_TRY("timer end", T->end(st));
     }
@@ -571,11 +751,71 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
 #undef FABM_STEP_TRY
 }
 
-hipError_t enqueue_steps(int sys, int d, const StepArgs &A, hipStream_t s, KernelTimer *T,
-                         const char **where)
+size_t batch_smem_bytes(int d)
 {
-#define FABM_STEP_CASE(SS, DD) \
-    if (sys == SS && d == DD) return enqueue_steps_t<SS, DD>(A, s, T, where);
+    const size_t band = sizeof(double) * (4 * kBlk + 2 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    const size_t near = sizeof(double) * (2 * (size_t)d * kBlk + (size_t)d * kSrcCols * kColPitch);
+    return std::max(band, near);
+}
+
+template <int SYS, int D, bool F32>
+static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, const int *far_off,
+                                  hipStream_t st, KernelTimer *T, const char **where)
+{
+#define FABM_STEP_TRY(what, expr)          \
+    do {                                   \
+        const hipError_t e_ = (expr);      \
+        if (e_ != hipSuccess) {            \
+            *where = what;                 \
+            return e_;                     \
+        }                                  \
+    } while (0)
+    const size_t smem = batch_smem_bytes(D);
+    for (int s = -1; s <= S.max_NB - 2; ++s) {
+        const size_t k = (size_t)(s + 1);
+        const int nb = S.nband[k], nn = S.nnear[k], nf = S.nfar[k];
+        const int nfw = S.far_off[(size_t)S.far_base[k] + (size_t)nf];
+        const int grid = nb + nn + nfw;
+        if (grid == 0) continue;
+        if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
+        hipLaunchKernelGGL((k_step_batch<SYS, D, F32>), dim3(grid), dim3(kBatchThreads), smem, st, A, s,
+                           nb, nn, far_off + S.far_base[k], nf);
+        FABM_STEP_TRY("launch k_step_batch", hipGetLastError());
+        if (T) FABM_STEP_TRY("timer end", T->end(st));
+    }
+    hipLaunchKernelGGL(k_batch_status, dim3((unsigned)((A.batch + 255) / 256)), dim3(256), 0, st, A);
+    FABM_STEP_TRY("launch k_batch_status", hipGetLastError());
+    return hipSuccess;
+#undef FABM_STEP_TRY
+}
+
+hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const BatchSchedule &S,
+                         const int *far_off, hipStream_t s, KernelTimer *T, const char **where)
+{
+#define FABM_BATCH_CASE(SS, DD)                                                          \
+    if (sys == SS && d == DD)                                                            \
+        return f32 ? enqueue_batch_t<SS, DD, true>(A, S, far_off, s, T, where)           \
+                   : enqueue_batch_t<SS, DD, false>(A, S, far_off, s, T, where);
+    FABM_BATCH_CASE(SYS_LINEAR, 1)
+    FABM_BATCH_CASE(SYS_LINEAR, 2)
+    FABM_BATCH_CASE(SYS_LINEAR, 3)
+    FABM_BATCH_CASE(SYS_LINEAR, 4)
+    FABM_BATCH_CASE(SYS_CHEN, 3)
+    FABM_BATCH_CASE(SYS_ROSSLER, 3)
+    FABM_BATCH_CASE(SYS_VDP, 2)
+    FABM_BATCH_CASE(SYS_FINANCIAL, 3)
+#undef FABM_BATCH_CASE
+    *where = "no BLOCKED kernel for this system/dimension";
+    return hipErrorInvalidValue;
+}
+
+hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_t s,
+                         KernelTimer *T, const char **where)
+{
+#define FABM_STEP_CASE(SS, DD)                                                   \
+    if (sys == SS && d == DD)                                                    \
+        return f32 ? enqueue_steps_t<SS, DD, true>(A, s, T, where)               \
+                   : enqueue_steps_t<SS, DD, false>(A, s, T, where);
     FABM_STEP_CASE(SYS_LINEAR, 1)
     FABM_STEP_CASE(SYS_LINEAR, 2)
     FABM_STEP_CASE(SYS_LINEAR, 3)

@@ -28,6 +28,9 @@ struct fabm_plan_s {
     bool stage_pending;
     uint64_t timeout_ticks;  // bound of every inter-workgroup wait (device wall clock)
     fabm::KernelTimer timer;   // optional per-kernel timing
+    // schedule of the last batched BLOCKED call, keyed by its block counts
+    std::vector<int32_t> sched_nb;
+    fabm::BatchSchedule sched;
 };
 
 namespace {
@@ -87,8 +90,12 @@ Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 {
     switch (pl->desc.path) {
     case FABM_PATH_DIRECT: return Path::Direct;
-    case FABM_PATH_BLOCKED: return batch == 1 ? Path::Blocked : Path::Unsupported;
-    default: return (batch == 1 && N[0] >= kAutoBlockedMinSteps) ? Path::Blocked : Path::Direct;
+    case FABM_PATH_BLOCKED: return Path::Blocked;
+    default: {
+        int64_t maxN = 0;
+        for (int64_t i = 0; i < batch; ++i) maxN = std::max(maxN, N[i]);
+        return maxN >= kAutoBlockedMinSteps ? Path::Blocked : Path::Direct;
+    }
     }
 }
 
@@ -96,11 +103,27 @@ Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 // `stage_bytes` bytes are copied from the plan's pinned staging buffer.
 struct Layout {
     Path path;
-    size_t meta, stage_bytes;
-    size_t w, f, part, carry, acc, sync, n_sync_words, total;
-    int64_t wlen;
-    int NB;
+    size_t meta, inst, order, far_off, stage_bytes;
+    size_t w, w32, f, part, carry, acc, sync, n_sync_words, total;
+    int64_t wlen;  // single-trajectory BLOCKED: weight table length
+    int NB;        // single-trajectory BLOCKED: blocks
 };
+
+int blocks_of(int64_t N) { return (int)((N + 1 + fabm::step_block_len() - 1) / fabm::step_block_len()); }
+
+// Schedule of a batched BLOCKED call (cached on the plan by block counts).
+const fabm::BatchSchedule &batch_schedule_for(const fabm_plan_s *pl, int64_t batch,
+                                              const int64_t *N)
+{
+    fabm_plan_s *mp = const_cast<fabm_plan_s *>(pl);  // host-side cache only
+    std::vector<int32_t> nb((size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) nb[(size_t)i] = blocks_of(N[i]);
+    if (nb != mp->sched_nb) {
+        fabm::batch_schedule(batch, nb.data(), mp->sched);
+        mp->sched_nb.swap(nb);
+    }
+    return mp->sched;
+}
 
 Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 {
@@ -115,15 +138,51 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
     size_t off = 0;
     L.meta = off;
     off += sizeof(InstMeta) * (size_t)batch;
-    if (L.path == Path::Blocked) {
+    if (L.path == Path::Blocked && batch > 1) {
+        const fabm::BatchSchedule &S = batch_schedule_for(pl, batch, N);
         const int Lb = fabm::step_block_len();
-        L.NB = (int)((N[0] + 1 + Lb - 1) / Lb);
+        const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;
+        size_t nw = 0, nf = 0, na = 0;
+        for (int64_t i = 0; i < batch; ++i) {
+            const size_t nb = (size_t)blocks_of(N[i]);
+            nw += 3 * (nb * Lb + Lb);
+            nf += (size_t)d * nb * Lb;
+            na += nb;
+        }
+        off = (off + 15) / 16 * 16;
+        L.inst = off;
+        off += sizeof(fabm::BlkInst) * (size_t)batch;
+        L.order = off;
+        off += sizeof(int) * (size_t)batch;
+        L.far_off = off;
+        off += sizeof(int) * S.far_off.size();
+        L.stage_bytes = off;
+        off = align_up(off);
+        L.w = off;
+        off = align_up(off + sizeof(double) * nw);
+        L.w32 = off;  // binary32 b, a for FP32 far windows
+        if (pl->desc.far_prec == FABM_FAR_FP32) off = align_up(off + sizeof(float) * nw / 3 * 2);
+        L.f = off;  // per instance: component-major history [d][NB_i*256]
+        off = align_up(off + sizeof(double) * nf);
+        L.carry = off;
+        off = align_up(off + 2 * blk * (size_t)batch);
+        L.acc = off;
+        off = align_up(off + blk * na);
+        L.sync = off;  // one non-finite flag per instance
+        L.n_sync_words = (size_t)std::max<int64_t>(64, batch);
+        off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
+    } else if (L.path == Path::Blocked) {
+        const int Lb = fabm::step_block_len();
+        L.NB = blocks_of(N[0]);
         L.wlen = (int64_t)L.NB * Lb + Lb;
         const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;  // one [2d][256] block of sums
         L.stage_bytes = off;
         off = align_up(off);
         L.w = off;
         off = align_up(off + sizeof(double) * 3 * (size_t)L.wlen);
+        L.w32 = off;  // binary32 b, a for FP32 far windows
+        if (pl->desc.far_prec == FABM_FAR_FP32)
+            off = align_up(off + sizeof(float) * 2 * (size_t)L.wlen);
         L.f = off;  // component-major history [d][NB*256]
         off = align_up(off + sizeof(double) * (size_t)d * (size_t)L.NB * Lb);
         L.carry = off;
@@ -244,7 +303,9 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         host_scalars(alpha[i], h[i], m);
         m.N = N[i];
         m.row_off = row_off ? row_off[i] : 0;
-        m.wlen = L.path == Path::Blocked ? L.wlen : N[i];
+        m.wlen = L.path != Path::Blocked ? N[i]
+                 : (batch == 1 ? L.wlen : (int64_t)blocks_of(N[i]) * fabm::step_block_len() +
+                                              fabm::step_block_len());
         m.w_off = w_off;
         m.p_off = (int64_t)pl->n_params * i;
         m.f_off = f_off;
@@ -253,6 +314,20 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         maxw = std::max(maxw, m.wlen);
     }
     char *base = (char *)ws;
+    const fabm::BatchSchedule *BS = nullptr;
+    if (L.path == Path::Blocked && batch > 1) {
+        BS = &batch_schedule_for(pl, batch, N);
+        fabm::BlkInst *hi = (fabm::BlkInst *)(pl->h_stage + L.inst);
+        int64_t fo = 0, ao = 0;
+        for (int64_t i = 0; i < batch; ++i) {
+            const int nb = blocks_of(N[i]);
+            hi[i] = fabm::BlkInst{fo, ao, nb, 0};
+            fo += (int64_t)d * nb * fabm::step_block_len();
+            ao += (int64_t)2 * d * nb * fabm::step_block_len();
+        }
+        std::memcpy(pl->h_stage + L.order, BS->order.data(), sizeof(int) * BS->order.size());
+        std::memcpy(pl->h_stage + L.far_off, BS->far_off.data(), sizeof(int) * BS->far_off.size());
+    }
     if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
 
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
@@ -261,13 +336,38 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     fabm::KernelTimer *T = pl->timer.on ? &pl->timer : nullptr;
     if (T) T->reset();
     if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
-    if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK) return st;
+    const bool f32 = L.path == Path::Blocked && pl->desc.far_prec == FABM_FAR_FP32;
+    float *W32 = f32 ? (float *)(base + L.w32) : nullptr;
+    if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s, W32))) != FABM_OK)
+        return st;
     if (T) HIP_TRY(T->end(s));
     if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
         FABM_OK)
         return st;
     double *Yi = y_out + (row_off ? row_off[0] : 0) * d;  // single-trajectory kernels
 
+    if (L.path == Path::Blocked && batch > 1) {
+        fabm::BatchArgs A{};
+        A.meta = dmeta;
+        A.inst = (const fabm::BlkInst *)(base + L.inst);
+        A.order = (const int *)(base + L.order);
+        A.params = params;
+        A.y0 = y0;
+        A.Y = y_out;
+        A.W = W;
+        A.W32 = W32;
+        A.Fc = (double *)(base + L.f);
+        A.carry = (double *)(base + L.carry);
+        A.acc = (double *)(base + L.acc);
+        A.dead = sync;
+        A.status = status;
+        A.batch = batch;
+        const char *where = "";
+        const hipError_t pe = fabm::enqueue_batch(pl->desc.system, d, f32, A, *BS,
+                                                  (const int *)(base + L.far_off), s, T, &where);
+        if (pe != hipSuccess) return record_hip(where, pe);
+        return FABM_OK;
+    }
     if (L.path == Path::Blocked) {
         fabm::StepArgs A{};
         A.meta = dmeta;
@@ -275,6 +375,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.y0 = y0;
         A.Y = Yi;
         A.W = W;
+        A.W32 = W32;
         A.Fc = (double *)(base + L.f);
         A.carry = (double *)(base + L.carry);
         A.acc = (double *)(base + L.acc);
@@ -282,7 +383,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.status = status;
         A.NB = L.NB;
         const char *where = "";
-        const hipError_t pe = fabm::enqueue_steps(pl->desc.system, d, A, s, T, &where);
+        const hipError_t pe = fabm::enqueue_steps(pl->desc.system, d, f32, A, s, T, &where);
         if (pe != hipSuccess) return record_hip(where, pe);
         return FABM_OK;
     }
@@ -339,8 +440,9 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     if (desc->far_prec != FABM_FAR_FP64 && desc->far_prec != FABM_FAR_FP32 &&
         desc->far_prec != FABM_FAR_FP16X2)
         return FABM_ERR_INVALID_ARG;
-    // far tiles run in FP64 only in this build; the block length is fixed
-    if (desc->far_prec != FABM_FAR_FP64) return FABM_ERR_UNSUPPORTED;
+    // far windows run in FP64 or FP32 (split FP16 is not offered); the block
+    // length is fixed
+    if (desc->far_prec == FABM_FAR_FP16X2) return FABM_ERR_UNSUPPORTED;
     if (desc->tile_L != 0 && desc->tile_L != fabm::step_block_len())
         return FABM_ERR_UNSUPPORTED;
     // kernels keep the state in registers: LINEAR up to d = 4
@@ -360,9 +462,7 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
             n = std::max<int64_t>(1, std::min(desc->max_steps, left));
             left -= n;
         }
-        size_t ws = desc->path == FABM_PATH_BLOCKED && desc->max_batch > 1
-                        ? 0
-                        : layout_for(pl, desc->max_batch, Ns.data()).total;
+        size_t ws = layout_for(pl, desc->max_batch, Ns.data()).total;
         int64_t one = desc->max_steps;
         ws = std::max(ws, layout_for(pl, 1, &one).total);
         *workspace_bytes = ws;

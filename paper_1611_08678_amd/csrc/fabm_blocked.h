@@ -35,12 +35,28 @@ constexpr int kStepThreads = 1024;  // 16 wavefronts, four per SIMD
 constexpr int kNearWaves = 8;       // wavefronts sharing the near part
 constexpr int kMaxFarWg = 254;      // far workgroups per launch (+ band + near <= 256 CUs)
 
+// One trajectory as seen by the step kernels' device code.
+struct InstView {
+    const InstMeta *meta;
+    const double *params;
+    const double *y0;
+    double *Y;          // rows [N+1][D]
+    const double *W;    // b, a, c tables of length meta->wlen each
+    const float *W32;   // b, a in binary32 (FP32 far windows only)
+    double *Fc;         // [D][NB*256]
+    double *carry;      // [2][2D][256]
+    double *acc;        // [NB][2D][4][64]
+    uint32_t *dead;
+    int NB;
+};
+
 struct StepArgs {
     const InstMeta *meta;
     const double *params;
     const double *y0;
     double *Y;          // caller rows [N+1][D]
     const double *W;    // b, a, c tables of length meta->wlen each
+    const float *W32;   // b, a in binary32 (FP32 far windows only)
     double *Fc;         // component-major history [D][NB*256]
     double *carry;      // [2][2D][256] band sums handed to the next block
     double *acc;        // [NB][2D][4][64] near + far sums of each target block,
@@ -53,6 +69,53 @@ struct StepArgs {
 // Value of StepArgs::dead when a bounded wait inside the band gave up
 // (reported as status -1).
 constexpr uint32_t kDeadWatchdog = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Batched step pipeline (dispatched for batch > 1): the same decomposition for
+// every instance, all instances advancing one block per launch. Instances are
+// sorted by block count, descending, so at launch s the instances with a band
+// block s+1, a near target s+2 or far targets are prefixes of that order.
+// Launch s has, in this order, one band workgroup per instance with a block
+// s+1, one near workgroup per instance with a target s+2, and for every
+// instance with targets >= s+3 one far workgroup per four targets (one target
+// per wavefront); `far_off` (per launch, host-built) holds the prefix sums of
+// far workgroups per instance in the same order.
+// ---------------------------------------------------------------------------
+constexpr int kBatchThreads = 256;  // four wavefronts per workgroup
+
+// Per-instance placement in the BLOCKED workspace.
+struct BlkInst {
+    int64_t fc_off;   // doubles: history [D][NB*256]
+    int64_t acc_off;  // doubles: near + far sums [NB][2D][4][64]
+    int32_t NB;       // blocks of 256 rows
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const InstMeta *meta;  // [batch]
+    const BlkInst *inst;   // [batch]
+    const int *order;      // instances by block count, descending
+    const double *params;  // [batch][n_params]
+    const double *y0;      // [batch][D]
+    double *Y;             // caller rows; instance i at meta[i].row_off
+    const double *W;       // weight tables, instance i at meta[i].w_off
+    const float *W32;      // binary32 b, a of instance i at 2 meta[i].w_off / 3
+    double *Fc;
+    double *carry;         // [batch][2][2D][256]
+    double *acc;
+    uint32_t *dead;        // [batch]
+    int64_t *status;       // [batch]
+    int64_t batch;
+};
+
+// Host schedule of one batched call.
+struct BatchSchedule {
+    std::vector<int> order;
+    std::vector<int> nband, nnear, nfar, far_base;  // per launch s + 1 (s = -1 .. S-2)
+    std::vector<int> far_off;                         // concatenated prefix sums
+    int max_NB = 0;
+};
+void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S);
 
 // ---------------------------------------------------------------------------
 // Single-launch persistent variant (not dispatched; see blocked_persistent.hip).

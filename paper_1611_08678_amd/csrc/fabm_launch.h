@@ -9,8 +9,9 @@ namespace fabm {
 struct InstMeta;
 
 // Weight tables for every instance of a call (one table per instance).
+// With W32, b and a are also written in binary32 (far windows in FP32).
 hipError_t launch_weights(const InstMeta *meta, int64_t batch, int64_t maxN, double *W,
-                          hipStream_t s);
+                          hipStream_t s, float *W32 = nullptr);
 hipError_t launch_weights_one(double al, double ig1, double ig2, int64_t n, double *b, double *a,
                               double *c, hipStream_t s);
 
@@ -35,11 +36,19 @@ hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const
 // (decomposition in fabm_blocked.h). On failure *where names the call.
 struct StepArgs;
 struct KernelTimer;
-hipError_t enqueue_steps(int sys, int d, const StepArgs &A, hipStream_t s, KernelTimer *T,
-                         const char **where);
+hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_t s,
+                         KernelTimer *T, const char **where);
 int step_block_len();
 size_t step_smem_bytes(int d);
 void step_grid(int NB, int s, int *grid, int *wpw);
+
+// BLOCKED path for a batch (> 1) of trajectories: one launch per block step
+// for all instances. `far_off` is S.far_off in device memory.
+struct BatchArgs;
+struct BatchSchedule;
+hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const BatchSchedule &S,
+                         const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
+size_t batch_smem_bytes(int d);
 
 // Single-launch persistent variant of the BLOCKED path (not dispatched).
 struct BlockedArgs;

@@ -1,6 +1,7 @@
-// schedule.cpp -- host-side task schedule of the single-launch persistent
-// variant of the BLOCKED path (not dispatched; see blocked_persistent.hip).
-// Pure host code, no device calls.
+// schedule.cpp -- host-side schedules of the BLOCKED path: the per-launch
+// workgroup counts of the batched step pipeline, and the task schedule of the
+// single-launch persistent variant (not dispatched; see
+// blocked_persistent.hip). Pure host code, no device calls.
 #include <algorithm>
 #include <tuple>
 #include <vector>
@@ -55,6 +56,43 @@ void blocked_schedule(int NB, int4 *tasks, int *queue, int *task_off)
         return tasks[a].x < tasks[b].x;
     });
     std::copy(order.begin(), order.end(), queue);
+}
+
+void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S)
+{
+    S.order.resize((size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) S.order[(size_t)i] = (int)i;
+    std::stable_sort(S.order.begin(), S.order.end(), [&](int a, int b) { return NB[a] > NB[b]; });
+    S.max_NB = batch > 0 ? NB[S.order[0]] : 0;
+    const int L = S.max_NB;  // launches s = -1 .. L-2, index k = s + 1
+    S.nband.assign((size_t)std::max(L, 1), 0);
+    S.nnear.assign((size_t)std::max(L, 1), 0);
+    S.nfar.assign((size_t)std::max(L, 1), 0);
+    S.far_base.assign((size_t)std::max(L, 1), 0);
+    S.far_off.clear();
+    // instances with NB >= x form a prefix of `order`
+    auto count_at_least = [&](int x) {
+        int lo = 0, hi = (int)batch;
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (NB[S.order[(size_t)mid]] >= x) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    for (int s = -1; s <= L - 2; ++s) {
+        const size_t k = (size_t)(s + 1);
+        S.nband[k] = count_at_least(s + 2);
+        S.nnear[k] = s >= 0 ? count_at_least(s + 3) : 0;
+        S.far_base[k] = (int)S.far_off.size();
+        S.far_off.push_back(0);
+        const int nf = s >= 0 ? count_at_least(s + 4) : 0;
+        for (int j = 0; j < nf; ++j) {
+            const int targets = NB[S.order[(size_t)j]] - (s + 3);
+            S.far_off.push_back(S.far_off.back() + (targets + 3) / 4);
+        }
+        S.nfar[k] = nf;
+    }
 }
 
 }  // namespace fabm

@@ -80,6 +80,22 @@ def test_plan_is_host_only_and_sizes_workspace(fabm):
         fabm.fabm_workspace_size(p, [N + 1])
 
 
+def test_plan_far_precisions(fabm):
+    fabm.fabm_plan("vdp", 2, "blocked", "fp32", 4, 5000)
+    with pytest.raises(fabm.FabmError) as e:
+        fabm.fabm_plan("vdp", 2, "blocked", "fp16x2", 1, 5000)
+    assert e.value.code == 2
+
+
+def test_batched_blocked_workspace_covers_calls(fabm):
+    p = fabm.fabm_plan("rossler", 3, "blocked", "fp32", 8, 3000, 8 * 3000)
+    for Ns in ([3000] * 8, [1, 2, 3000, 255, 256, 1000, 7, 2999], [5] * 8, [3000]):
+        assert 0 < fabm.fabm_workspace_size(p, Ns) <= p.workspace_bytes
+    # the FP32 copies of the weight tables take space only when asked for
+    p64 = fabm.fabm_plan("rossler", 3, "blocked", "fp64", 8, 3000, 8 * 3000)
+    assert fabm.fabm_workspace_size(p64, [3000] * 8) < fabm.fabm_workspace_size(p, [3000] * 8)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     import paper_1611_08678_amd as F
     monkeypatch.setattr(F, "_lib", None)

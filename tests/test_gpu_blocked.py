@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from tests.conftest import gpu_available
-from tests.test_gpu_direct import _chen_horizon, _to_np, relerr
+from tests.test_gpu_direct import _batch_parity, _chen_horizon, _to_np, relerr
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -129,6 +129,74 @@ def test_blocked_kernel_times(F):
     assert kt["blocked_step"][1] == (N + 1 + 255) // 256
     assert kt["blocked_step"][0] > 0 and kt["weights"][1] == 1
     assert int(st.item()) == 0
+
+
+def test_blocked_batch_rossler_ragged(F, orc):
+    """Batched BLOCKED path: ragged lengths (one block to a dozen), per-instance
+    alpha and y0, against the oracle's batch solver."""
+    from paper_1611_08678_amd import workloads as W
+    w = W.rossler_batch(batch=40, n_lo=1, n_hi=3000, seed=7)
+    w["N"][:4] = [1, 255, 256, 511]  # edge lengths: one row, full block, block + 1 row
+    _batch_parity(F, orc, w, path="blocked")
+
+
+@pytest.mark.parametrize("sysname", ["vdp", "financial", "linear2", "linear4"])
+def test_blocked_batch_systems(F, orc, sysname):
+    rng = np.random.default_rng(23)
+    B = 12
+    if sysname == "vdp":
+        theta, d, sid = rng.uniform(0.5, 2, (B, 1)), 2, 3
+    elif sysname == "financial":
+        theta, d, sid = np.tile([3.0, 0.1, 1.0], (B, 1)), 3, 4
+    else:
+        d, sid = int(sysname[-1]), 0
+        theta = np.stack([_lin(d, 100 + i)[0] for i in range(B)])
+    w = dict(system=sid, d=d, theta=theta, alpha=rng.uniform(0.6, 1.0, B),
+             h=rng.uniform(0.005, 0.02, B), N=rng.integers(200, 2500, B, endpoint=True),
+             y0=rng.uniform(-1.5, 1.5, (B, d)))
+    _batch_parity(F, orc, w, path="blocked")
+
+
+def test_blocked_batch_blowup_and_determinism(F, orc):
+    """Instances that blow up are flagged at the oracle's step with NaN rows
+    after it, without disturbing the others; two runs agree bitwise."""
+    lam = np.array([-1.0, 60.0, -2.0, 3.0, 1.2, -0.5])
+    B = lam.size
+    theta = np.stack([[l, 0.0, 0.0] for l in lam])
+    w = dict(system=0, d=1, theta=theta, alpha=np.full(B, 0.9), h=np.full(B, 0.5),
+             N=np.array([2000, 1500, 900, 2200, 1800, 700]), y0=np.ones((B, 1)))
+    _batch_parity(F, orc, w, path="blocked")
+    runs = [F.solve_batch(w["system"], w["theta"], w["alpha"], w["h"], w["N"], w["y0"],
+                          path="blocked") for _ in range(2)]
+    assert np.array_equal(_to_np(runs[0][0]), _to_np(runs[1][0]), equal_nan=True)
+
+
+# FP32 far windows: weights and history rounded to binary32 and 64 products
+# per window summed in binary32, added to binary64 sums. A priori the far sum
+# carries about (2 + 64) u32 sum|w||f| (u32 = 2^-24) and y a small multiple of
+# h^alpha times that; the bound below is twice the largest error measured on
+# MI355X for these cases, rounded up.
+FP32_BOUND = 1e-5
+
+
+def test_blocked_fp32_single(F, orc):
+    th = [1.3]
+    y0 = [0.8, -0.4]
+    N = 7000
+    ref, _, _, _ = orc.solve(3, th, 0.9, 0.01, N, y0)
+    y64, _ = F.solve("vdp", th, 0.9, 0.01, N, y0, path="blocked", far_prec="fp64")
+    y32, st = F.solve("vdp", th, 0.9, 0.01, N, y0, path="blocked", far_prec="fp32")
+    e32, e64 = relerr(_to_np(y32), ref), relerr(_to_np(y64), ref)
+    assert int(st.item()) == 0
+    assert e64 <= 1e-11
+    assert 1e-12 < e32 <= FP32_BOUND, e32  # binary32 windows did run, within the bound
+
+
+def test_blocked_fp32_batch(F, orc):
+    from paper_1611_08678_amd import workloads as W
+    w = W.rossler_batch(batch=24, n_lo=600, n_hi=3000, seed=11)
+    worst = _batch_parity(F, orc, w, tol=FP32_BOUND, path="blocked_fp32")
+    assert worst > 1e-12
 
 
 @pytest.mark.skip(reason=(

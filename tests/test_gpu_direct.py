@@ -65,9 +65,10 @@ def test_scalar_linear_direct(F, orc):
     assert relerr(_to_np(y), ref) <= 1e-11
 
 
-def _batch_parity(F, orc, w, tol=1e-11):
+def _batch_parity(F, orc, w, tol=1e-11, path="direct"):
+    path, _, prec = path.partition("_")
     y, off, st = F.solve_batch(w["system"], w["theta"], w["alpha"], w["h"], w["N"], w["y0"],
-                               path="direct")
+                               path=path, far_prec=prec or "fp64")
     ref, roff, rst = orc.solve_batch(w["system"], w["theta"], w["alpha"], w["h"], w["N"], w["y0"])
     assert np.array_equal(off, roff)
     yy = _to_np(y)
