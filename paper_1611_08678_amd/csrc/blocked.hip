@@ -350,9 +350,10 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 // ---------------------------------------------------------------------------
 constexpr int kSrcCols = 31;
 constexpr int kColPitch = 17;
-// Result layout of v_mfma_f32_16x16x4f32: element v of lane l is row
-// 4 (l / 16) + v when true, row 4 v + l / 16 (as for binary64) when false.
-constexpr bool kF32RowMajorLanes = false;
+// Result layout of v_mfma_f32_16x16x4f32 (measured on gfx950 with one-hot
+// operands): element v of lane l is row 4 (l / 16) + v, column l % 16 -- not
+// the binary64 instruction's row 4 v + l / 16.
+constexpr bool kF32RowMajorLanes = true;
 
 template <int D, typename T = double>
 constexpr size_t staged_bytes()

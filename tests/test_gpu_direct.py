@@ -72,13 +72,23 @@ def _batch_parity(F, orc, w, tol=1e-11, path="direct"):
     ref, roff, rst = orc.solve_batch(w["system"], w["theta"], w["alpha"], w["h"], w["N"], w["y0"])
     assert np.array_equal(off, roff)
     yy = _to_np(y)
-    assert np.array_equal(_to_np(st), rst)
+    gst = _to_np(st)
     worst = 0.0
     for i in range(len(off)):
         sl = slice(off[i], off[i] + int(w["N"][i]) + 1)
-        if rst[i]:
-            k = int(rst[i])
-            assert np.all(np.isnan(yy[sl][k:]))
+        if gst[i] != rst[i]:
+            # The first non-finite step is decided at the top of the binary64
+            # range: the oracle rounds the whole corrector sum C_t to binary64,
+            # the GPU band adds the newest history term after scaling by h^alpha,
+            # so one side may overflow one step before the other. Accepted only
+            # when the last row both agree on is within 1e3 of the overflow.
+            k = int(min(gst[i], rst[i]))
+            assert k > 0 and abs(int(gst[i]) - int(rst[i])) == 1, (i, gst[i], rst[i])
+            assert np.abs(ref[sl][k - 1]).max() > np.finfo(np.float64).max / 1e3, (i, k)
+        if gst[i]:
+            assert np.all(np.isnan(yy[sl][int(gst[i]):]))
+        if rst[i] or gst[i]:
+            k = int(min(x for x in (gst[i], rst[i]) if x))
             worst = max(worst, relerr(yy[sl][:k], ref[sl][:k]))
         else:
             worst = max(worst, relerr(yy[sl], ref[sl]))
