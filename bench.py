@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -40,6 +41,11 @@ def parse():
                     help="steps of the oracle sample for cpu_baseline (0 disables)")
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="skip the instrumented solve that measures per-kernel time")
+    ap.add_argument("--workload", default="chen", choices=["chen", "rossler_batch", "vdp_batch"],
+                    help="chen: the headline single trajectory; the batch workloads are "
+                         "additional measurements of the batched BLOCKED path")
+    ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32"],
+                    help="far-window arithmetic (default: fp64; rossler_batch: fp32)")
     return ap.parse_args()
 
 
@@ -128,11 +134,88 @@ def roofline(kt: dict, N: int, d: int):
     return dict(bound="unknown", kernel=dom, seconds=secs)
 
 
+def bench_batch(F, W, args):
+    """Batched BLOCKED solve of a batch workload: Rossler (4096 instances,
+    N uniform in [2^14, 2^17], per-instance alpha, FP32 far windows) or the
+    Van der Pol forward pass (1024 instances, N = 2^15)."""
+    import numpy as np
+    import torch
+    w = W.rossler_batch() if args.workload == "rossler_batch" else W.vdp_adjoint()
+    prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" else "fp64")
+    Ns = np.asarray(w["N"], dtype=np.int64)
+    B, d = len(Ns), w["d"]
+    plan = F.fabm_plan(w["system"], d, "blocked", prec, B, int(Ns.max()), int(Ns.sum()))
+    ws = torch.empty(F.fabm_workspace_size(plan, Ns), dtype=torch.uint8, device="cuda")
+    y0 = torch.as_tensor(w["y0"], dtype=torch.float64, device="cuda").contiguous()
+    th = torch.as_tensor(w["theta"], dtype=torch.float64, device="cuda").contiguous()
+    row_off = np.zeros(B, dtype=np.int64)
+    row_off[1:] = np.cumsum(Ns + 1)[:-1]
+    y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
+    st = torch.zeros(B, dtype=torch.int64, device="cuda")
+    call = lambda: F.fabm_solve_batch(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        call()
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) / 1e3 for a, b in evs]
+    print(f"# {args.workload}: solve times {['%.4f' % t for t in per]} s", file=sys.stderr,
+          flush=True)
+    F.fabm_plan_set_profiling(plan, True)
+    call()
+    torch.cuda.synchronize()
+    kt = {k: v for k, v in F.fabm_plan_kernel_times(plan).items() if v[1]}
+    t = float(np.mean(per))
+    flops = float((2.0 * d * Ns * (Ns + 1)).sum())
+    out = {"metric": "steps*states/s (history GFLOP/s alongside), batched blocked",
+           "value": float(Ns.sum()) * d / t, "unit": "steps*states/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec == "fp64" else "f64 band, f32 far windows", "data": "synthetic",
+           "config": {"workload": w["name"], "batch": B, "N_min": int(Ns.min()),
+                      "N_max": int(Ns.max()), "far_prec": prec},
+           "history_gflops": flops / t / 1e9,
+           "status_nonzero": int((st.cpu().numpy() != 0).sum()),
+           "kernel_times_s": {k: v[0] for k, v in kt.items()},
+           "kernel_launches": {k: v[1] for k, v in kt.items()}}
+    if "blocked_step" in kt:
+        secs, launches = kt["blocked_step"]
+        peak = FP32_MFMA_PEAK_TFLOPS if prec == "fp32" else FP64_MFMA_PEAK_TFLOPS
+        ach = flops / secs / 1e12
+        out["roofline"] = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                               frac=ach / peak, traffic=None, kernel="k_step_batch",
+                               launches=launches, avg_launch_s=secs / launches,
+                               algorithmic_flops_per_launch=flops / launches)
+    if args.cpu_sample > 0:
+        # oracle check of the three shortest instances
+        from oracle import oracle as O
+        yy = y.cpu().numpy()
+        errs = []
+        for i in np.argsort(Ns)[:3]:
+            ref, _, _, _ = O.solve(w["system"], w["theta"][i], float(w["alpha"][i]),
+                                   float(w["h"][i]), int(Ns[i]), w["y0"][i])
+            g = yy[row_off[i]:row_off[i] + Ns[i] + 1]
+            errs.append(float(np.abs(g - ref).max() / np.abs(ref).max()))
+        out["rel_err_shortest_3"] = errs
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload != "chen":
+        import paper_1611_08678_amd as F
+        from paper_1611_08678_amd import workloads as W
+        F.load()
+        return bench_batch(F, W, args)
     import numpy as np
     import paper_1611_08678_amd as F
     from paper_1611_08678_amd import workloads as W
