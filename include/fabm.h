@@ -151,6 +151,32 @@ fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace
                              const int64_t *row_off, double *y_out, int64_t *status,
                              hipStream_t stream);
 
+/* Reverse-mode gradients (the discrete adjoint of the scheme above) of
+ *   L = sum_i sum_{n=0}^{N_i} < gy_i[n], y_i[n] >
+ * with respect to y0 and theta of every instance (batch = 1 for a single
+ * trajectory), where y_i is the trajectory fabm_solve_batch returns for the
+ * same inputs with far precision FP64. The forward trajectory and its
+ * predictor values are recomputed in the workspace (the same rows the BLOCKED
+ * path returns), then a reverse pass runs the blocked decomposition in
+ * reversed time (band plus FP64 MFMA windows of the transposed Toeplitz
+ * sums). The plan's path and far precision do not apply to this call.
+ *   alpha, h, N, row_off (host) [batch]        as in fabm_solve_batch
+ *   y0      (device) [batch][d];  params (device) [batch][n_params]
+ *   gy      (device) rows placed like y_out of fabm_solve_batch: dL/dy_i[n]
+ *   gy0     (device) [batch][d]          receives dL/dy0_i
+ *   gparams (device) [batch][n_params]   receives dL/dtheta_i
+ *   status  (device) [batch] int64       the forward status as in fabm_solve_batch;
+ *                                        an instance whose forward trajectory is not
+ *                                        finite gets NaN gradients
+ *   workspace_bytes >= fabm_adjoint_workspace_size(plan, batch, N). */
+fabm_status fabm_adjoint(fabm_plan_t plan, void *workspace, size_t workspace_bytes, int64_t batch,
+                         const double *alpha, const double *h, const int64_t *N,
+                         const double *y0, const double *params, const int64_t *row_off,
+                         const double *gy, double *gy0, double *gparams, int64_t *status,
+                         hipStream_t stream);
+fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *N,
+                                        size_t *bytes);
+
 /* Weight tables of Section 2 for one alpha, lags m = 0..n-1:
  *   b (device) [n], a (device) [n], c (device) [n]  (any may be NULL).
  * Computed in binary64 with cancellation-free rearrangements of the defining
@@ -167,7 +193,8 @@ typedef enum {
     FABM_KERNEL_BLOCKED_STEP = 3, /* BLOCKED step: one band block plus the MFMA
                                      near and far windows of one source block */
     FABM_KERNEL_HISTORY = 4,      /* fabm_history_sums contraction */
-    FABM_KERNEL_COUNT = 5
+    FABM_KERNEL_ADJOINT = 5,      /* reverse pass: band plus MFMA windows of one block */
+    FABM_KERNEL_COUNT = 6
 } fabm_kernel_class;
 
 /* Instrumentation. While enabled, every solve call of the plan records a pair

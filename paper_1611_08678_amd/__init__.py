@@ -31,8 +31,8 @@ FAR_PRECS = {"fp64": FABM_FAR_FP64, "fp32": FABM_FAR_FP32, "fp16x2": FABM_FAR_FP
 EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan", "fabm_plan_destroy",
            "fabm_workspace_size", "fabm_solve", "fabm_solve_batch", "fabm_weights",
            "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
-           "fabm_plan_kernel_times")
-KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history")
+           "fabm_plan_kernel_times", "fabm_adjoint", "fabm_adjoint_workspace_size")
+KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint")
 
 
 class FabmError(RuntimeError):
@@ -101,6 +101,11 @@ def load():
     L.fabm_plan_set_profiling.restype = C.c_int
     L.fabm_plan_kernel_times.argtypes = [_VP, _DP, _I64P]
     L.fabm_plan_kernel_times.restype = C.c_int
+    L.fabm_adjoint.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP, _VP, _I64P,
+                               _VP, _VP, _VP, _VP, _VP]
+    L.fabm_adjoint.restype = C.c_int
+    L.fabm_adjoint_workspace_size.argtypes = [_VP, C.c_int64, _I64P, C.POINTER(C.c_size_t)]
+    L.fabm_adjoint_workspace_size.restype = C.c_int
     _lib = L
     return L
 
@@ -201,6 +206,30 @@ def fabm_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_
                                    _stream(stream)), "fabm_solve_batch")
 
 
+def fabm_adjoint_workspace_size(plan: Plan, N) -> int:
+    import numpy as np
+    Ns = np.ascontiguousarray(np.atleast_1d(N), dtype=np.int64)
+    out = C.c_size_t()
+    _check(load().fabm_adjoint_workspace_size(plan.handle, Ns.size, Ns.ctypes.data_as(_I64P),
+                                              C.byref(out)), "fabm_adjoint_workspace_size")
+    return int(out.value)
+
+
+def fabm_adjoint(plan: Plan, workspace, alpha, h, N, y0, params, row_off, gy, gy0, gparams,
+                 status, stream=None):
+    import numpy as np
+    al = np.ascontiguousarray(np.atleast_1d(alpha), dtype=np.float64)
+    hh = np.ascontiguousarray(np.atleast_1d(h), dtype=np.float64)
+    Ns = np.ascontiguousarray(np.atleast_1d(N), dtype=np.int64)
+    ro = np.ascontiguousarray(np.atleast_1d(row_off), dtype=np.int64)
+    _check(load().fabm_adjoint(plan.handle, _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), al.size,
+                               al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
+                               Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
+                               ro.ctypes.data_as(_I64P), _ptr(gy), _ptr(gy0), _ptr(gparams),
+                               _ptr(status), _stream(stream)), "fabm_adjoint")
+
+
 def fabm_plan_set_profiling(plan: Plan, enable: bool):
     _check(load().fabm_plan_set_profiling(plan.handle, int(bool(enable))),
            "fabm_plan_set_profiling")
@@ -237,6 +266,15 @@ def fabm_history_sums(alpha: float, N: int, dim: int, f, P, Cs, path="auto", far
 # Convenience wrappers: allocate outputs and workspace with torch, then call
 # the ABI above. No arithmetic happens here.
 # ---------------------------------------------------------------------------
+def _dev(x):
+    """float64 device tensor of x (a tensor, array or nested list)."""
+    import numpy as np
+    import torch
+    if not isinstance(x, torch.Tensor):
+        x = np.asarray(x, dtype=np.float64)
+    return torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+
+
 def _workspace(nbytes: int):
     import torch
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
@@ -246,8 +284,8 @@ def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_pr
           plan: Plan | None = None):
     """One trajectory; returns (y [N+1, d] float64 device tensor, status int)."""
     import torch
-    y0 = torch.as_tensor(y0, dtype=torch.float64, device="cuda").contiguous().reshape(-1)
-    th = torch.as_tensor(theta, dtype=torch.float64, device="cuda").contiguous().reshape(-1)
+    y0 = _dev(y0).reshape(-1)
+    th = _dev(theta).reshape(-1)
     d = y0.numel()
     if plan is None:
         plan = fabm_plan(system, d, path, far_prec, 1, N)
@@ -263,9 +301,9 @@ def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64
     """Ragged batch; returns (y_rows [sum(N+1), d], row_off numpy, status tensor)."""
     import numpy as np
     import torch
-    y0s = torch.as_tensor(y0s, dtype=torch.float64, device="cuda").contiguous()
+    y0s = _dev(y0s)
     B, d = y0s.shape
-    th = torch.as_tensor(thetas, dtype=torch.float64, device="cuda").contiguous().reshape(B, -1)
+    th = _dev(thetas).reshape(B, -1)
     Ns = np.ascontiguousarray(Ns, dtype=np.int64)
     row_off = np.zeros(B, dtype=np.int64)
     row_off[1:] = np.cumsum(Ns + 1)[:-1]
@@ -276,3 +314,59 @@ def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64
     st = torch.zeros(B, dtype=torch.int64, device="cuda")
     fabm_solve_batch(plan, ws, alphas, hs, Ns, y0s, th, row_off, y, st)
     return y, row_off, st
+
+
+def adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, plan: Plan | None = None):
+    """Gradients of sum <gy, y> for a ragged batch (gy rows placed as solve_batch
+    returns y); returns (gy0 [B, d], gtheta [B, n_params], status) device tensors."""
+    import numpy as np
+    import torch
+    y0s = _dev(y0s)
+    B, d = y0s.shape
+    th = _dev(thetas).reshape(B, -1)
+    gy = _dev(gy)
+    Ns = np.ascontiguousarray(Ns, dtype=np.int64)
+    row_off = np.zeros(B, dtype=np.int64)
+    row_off[1:] = np.cumsum(Ns + 1)[:-1]
+    if plan is None:
+        plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()))
+    ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
+    gy0 = torch.empty((B, d), dtype=torch.float64, device="cuda")
+    gth = torch.empty_like(th)
+    st = torch.zeros(B, dtype=torch.int64, device="cuda")
+    fabm_adjoint(plan, ws, alphas, hs, Ns, y0s, th, row_off, gy, gy0, gth, st)
+    return gy0, gth, st
+
+
+def _solve_function():
+    import torch
+
+    class FabmSolveBatch(torch.autograd.Function):
+        """y = solve_batch(...) as a differentiable function of y0 [B, d] and
+        theta [B, n_params]; backward runs fabm_adjoint (blocked reverse pass).
+        Rows of y are the instances' trajectories concatenated (row_off as in
+        solve_batch)."""
+
+        @staticmethod
+        def forward(ctx, y0s, thetas, system, alphas, hs, Ns):
+            import numpy as np
+            y, _, st = solve_batch(system, thetas.detach(), alphas, hs, Ns, y0s.detach(),
+                                   path="blocked", far_prec="fp64")
+            ctx.save_for_backward(y0s.detach(), thetas.detach())
+            ctx.meta = (system, np.asarray(alphas, dtype=np.float64),
+                        np.asarray(hs, dtype=np.float64), np.asarray(Ns, dtype=np.int64))
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            y0s, thetas = ctx.saved_tensors
+            system, alphas, hs, Ns = ctx.meta
+            gy0, gth, _ = adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy)
+            return gy0, gth, None, None, None, None
+
+    return FabmSolveBatch
+
+
+def solve_batch_autograd(y0s, thetas, system, alphas, hs, Ns):
+    """Differentiable batched solve (torch autograd; see FabmSolveBatch)."""
+    return _solve_function().apply(y0s, thetas, system, alphas, hs, Ns)

@@ -103,7 +103,8 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     double *sa = sb + 2 * kBlk;   // a lags 0..511
     double *sF = sa + 2 * kBlk;   // [256][D] f of this block's rows
     double *sY = sF + kBlk * D;   // [256][D] y of this block's rows
-    double *sTh = sY + kBlk * D;  // theta, for systems with many parameters
+    double *sYP = sY + kBlk * D;  // [256][D] predictor values (when A.YP is set)
+    double *sTh = sYP + kBlk * D; // theta, for systems with many parameters
     int *s_cnt = (int *)(sTh + NP);  // rows of this block published so far (> 256: stop)
     int *s_dead = s_cnt + 1;         // first non-finite row (block-relative), -1, or -2
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
@@ -117,7 +118,10 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 
     // a non-finite state in an earlier block ends the trajectory
     if (*A.dead != 0u) {
-        for (int e = tid; e < nrows * D; e += nthr) A.Y[t0 * D + e] = __builtin_nan("");
+        for (int e = tid; e < nrows * D; e += nthr) {
+            A.Y[t0 * D + e] = __builtin_nan("");
+            if (A.YP) A.YP[t0 * D + e] = __builtin_nan("");
+        }
         return;
     }
     // theta in registers when short; a linear system's matrix is read from LDS
@@ -152,6 +156,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             for (int i = 0; i < D; ++i) {
                 sF[i] = f0[i];
                 sY[i] = y0[i];
+                sYP[i] = y0[i];
             }
         }
     }
@@ -275,6 +280,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             for (int i = 0; i < D; ++i) {
                 sF[t * D + i] = f[i];
                 sY[t * D + i] = y[i];
+                sYP[t * D + i] = yp[i];
             }
         }
         if ((t + 1) % kPublishEvery == 0 || t + 1 == hi) {
@@ -325,6 +331,10 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     const int valid = dead == -1 ? nrows : (dead < 0 ? 0 : dead);
     for (int e = tid; e < nrows * D; e += nthr)
         A.Y[t0 * D + e] = e / D < valid ? sY[e] : __builtin_nan("");
+    if (A.YP) {
+        for (int e = tid; e < nrows * D; e += nthr)
+            A.YP[t0 * D + e] = e / D < valid ? sYP[e] : __builtin_nan("");
+    }
     for (int e = tid; e < valid; e += nthr) {
 #pragma unroll
         for (int i = 0; i < D; ++i) A.Fc[i * pitch + t0 + e] = sF[e * D + i];
@@ -559,7 +569,7 @@ __device__ __forceinline__ void near_part(const InstView &A, int s, const double
 
 __device__ __forceinline__ InstView single_view(const StepArgs &A)
 {
-    return InstView{A.meta, A.params, A.y0, A.Y, A.W, A.W32, A.Fc, A.carry, A.acc, A.dead, A.NB};
+    return InstView{A.meta, A.params, A.y0, A.Y, nullptr, A.W, A.W32, A.Fc, A.carry, A.acc, A.dead, A.NB};
 }
 
 // Launch s of the single-trajectory pipeline; `wpw` wavefronts of each far
@@ -610,6 +620,7 @@ __device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
                     A.params + m->p_off,
                     A.y0 + (int64_t)i * D,
                     A.Y + m->row_off * D,
+                    A.YP ? A.YP + m->row_off * D : nullptr,
                     A.W + m->w_off,
                     A.W32 ? A.W32 + m->w_off / 3 * 2 : nullptr,
                     A.Fc + b.fc_off,
@@ -693,7 +704,7 @@ __global__ void k_step_status(StepArgs A)
 // itself and each far workgroup owns four SIMDs.
 size_t step_smem_bytes(int d)
 {
-    const size_t band = sizeof(double) * (4 * kBlk + 2 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    const size_t band = sizeof(double) * (4 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
     const size_t near = sizeof(double) * (kNearWaves * 2 * (size_t)d * kBlk +
                                           (size_t)d * kSrcCols * kColPitch);
     const size_t exclusive = 81 * 1024;
@@ -754,7 +765,7 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
 
 size_t batch_smem_bytes(int d)
 {
-    const size_t band = sizeof(double) * (4 * kBlk + 2 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    const size_t band = sizeof(double) * (4 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
     const size_t near = sizeof(double) * (2 * (size_t)d * kBlk + (size_t)d * kSrcCols * kColPitch);
     return std::max(band, near);
 }

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "fabm.h"
+#include "fabm_adjoint.h"
 #include "fabm_blocked.h"
 #include "fabm_device.h"
 #include "fabm_launch.h"
@@ -103,8 +104,11 @@ Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 // `stage_bytes` bytes are copied from the plan's pinned staging buffer.
 struct Layout {
     Path path;
-    size_t meta, inst, order, far_off, stage_bytes;
-    size_t w, w32, f, part, carry, acc, sync, n_sync_words, total;
+    size_t meta, inst, order, far_off, meta_adj, stage_bytes;
+    size_t w, w32, f, part, carry, acc, sync, n_sync_words;
+    // reverse pass only: forward rows, reversed sources and sums, partials
+    size_t yw, ypw, uv, acc_a, carry_a, part_a, fbar0;
+    size_t total;
     int64_t wlen;  // single-trajectory BLOCKED: weight table length
     int NB;        // single-trajectory BLOCKED: blocks
 };
@@ -125,10 +129,12 @@ const fabm::BatchSchedule &batch_schedule_for(const fabm_plan_s *pl, int64_t bat
     return mp->sched;
 }
 
-Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
+// adjoint: the reverse pass (always the batched BLOCKED layout, FP64, with the
+// extra regions of the reverse pipeline).
+Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool adjoint = false)
 {
     Layout L{};
-    L.path = choose_path(pl, batch, N);
+    L.path = adjoint ? Path::Blocked : choose_path(pl, batch, N);
     const int d = pl->desc.dim;
     int64_t sumN = 0, sumRows = 0;
     for (int64_t i = 0; i < batch; ++i) {
@@ -138,7 +144,7 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
     size_t off = 0;
     L.meta = off;
     off += sizeof(InstMeta) * (size_t)batch;
-    if (L.path == Path::Blocked && batch > 1) {
+    if (L.path == Path::Blocked && (batch > 1 || adjoint)) {
         const fabm::BatchSchedule &S = batch_schedule_for(pl, batch, N);
         const int Lb = fabm::step_block_len();
         const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;
@@ -156,12 +162,18 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
         off += sizeof(int) * (size_t)batch;
         L.far_off = off;
         off += sizeof(int) * S.far_off.size();
+        if (adjoint) {
+            off = (off + 15) / 16 * 16;
+            L.meta_adj = off;
+            off += sizeof(InstMeta) * (size_t)batch;
+        }
         L.stage_bytes = off;
         off = align_up(off);
         L.w = off;
         off = align_up(off + sizeof(double) * nw);
         L.w32 = off;  // binary32 b, a for FP32 far windows
-        if (pl->desc.far_prec == FABM_FAR_FP32) off = align_up(off + sizeof(float) * nw / 3 * 2);
+        if (pl->desc.far_prec == FABM_FAR_FP32 && !adjoint)
+            off = align_up(off + sizeof(float) * nw / 3 * 2);
         L.f = off;  // per instance: component-major history [d][NB_i*256]
         off = align_up(off + sizeof(double) * nf);
         L.carry = off;
@@ -171,6 +183,24 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
         L.sync = off;  // one non-finite flag per instance
         L.n_sync_words = (size_t)std::max<int64_t>(64, batch);
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
+        if (adjoint) {
+            size_t rows = 0;
+            for (int64_t i = 0; i < batch; ++i) rows += (size_t)N[i] + 1;
+            L.yw = off;
+            off = align_up(off + sizeof(double) * d * rows);
+            L.ypw = off;
+            off = align_up(off + sizeof(double) * d * rows);
+            L.uv = off;
+            off = align_up(off + sizeof(double) * 2 * nf);
+            L.acc_a = off;
+            off = align_up(off + blk / 2 * na);
+            L.carry_a = off;
+            off = align_up(off + blk * (size_t)batch);
+            L.part_a = off;
+            off = align_up(off + sizeof(double) * ((size_t)pl->n_params + d) * na);
+            L.fbar0 = off;
+            off = align_up(off + sizeof(double) * d * (size_t)batch);
+        }
     } else if (L.path == Path::Blocked) {
         const int Lb = fabm::step_block_len();
         L.NB = blocks_of(N[0]);
@@ -283,6 +313,26 @@ fabm_status stage_copy(fabm_plan_s *pl, size_t bytes, void *dst, hipStream_t s)
     return FABM_OK;
 }
 
+// Per-instance placement, order and far-workgroup table of a batched BLOCKED
+// call, written into the staging buffer.
+const fabm::BatchSchedule &stage_batch(fabm_plan_s *pl, const Layout &L, int64_t batch,
+                                       const int64_t *N)
+{
+    const int d = pl->desc.dim;
+    const fabm::BatchSchedule &BS = batch_schedule_for(pl, batch, N);
+    fabm::BlkInst *hi = (fabm::BlkInst *)(pl->h_stage + L.inst);
+    int64_t fo = 0, ao = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        const int nb = blocks_of(N[i]);
+        hi[i] = fabm::BlkInst{fo, ao, nb, 0};
+        fo += (int64_t)d * nb * fabm::step_block_len();
+        ao += (int64_t)2 * d * nb * fabm::step_block_len();
+    }
+    std::memcpy(pl->h_stage + L.order, BS.order.data(), sizeof(int) * BS.order.size());
+    std::memcpy(pl->h_stage + L.far_off, BS.far_off.data(), sizeof(int) * BS.far_off.size());
+    return BS;
+}
+
 // Shared body of fabm_solve and fabm_solve_batch after validation.
 fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *alpha,
                       const double *h, const int64_t *N, const double *y0, const double *params,
@@ -315,19 +365,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     }
     char *base = (char *)ws;
     const fabm::BatchSchedule *BS = nullptr;
-    if (L.path == Path::Blocked && batch > 1) {
-        BS = &batch_schedule_for(pl, batch, N);
-        fabm::BlkInst *hi = (fabm::BlkInst *)(pl->h_stage + L.inst);
-        int64_t fo = 0, ao = 0;
-        for (int64_t i = 0; i < batch; ++i) {
-            const int nb = blocks_of(N[i]);
-            hi[i] = fabm::BlkInst{fo, ao, nb, 0};
-            fo += (int64_t)d * nb * fabm::step_block_len();
-            ao += (int64_t)2 * d * nb * fabm::step_block_len();
-        }
-        std::memcpy(pl->h_stage + L.order, BS->order.data(), sizeof(int) * BS->order.size());
-        std::memcpy(pl->h_stage + L.far_off, BS->far_off.data(), sizeof(int) * BS->far_off.size());
-    }
+    if (L.path == Path::Blocked && batch > 1) BS = &stage_batch(pl, L, batch, N);
     if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
 
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
@@ -402,6 +440,120 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
                                              y_out, status, s));
     if (T) HIP_TRY(T->end(s));
     return st;
+}
+
+// Body of fabm_adjoint after validation: forward pass (batched BLOCKED, FP64)
+// into the workspace with predictor rows, then the reverse pipeline.
+fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *alpha,
+                        const double *h, const int64_t *N, const double *y0,
+                        const double *params, const int64_t *row_off, const double *gy,
+                        double *gy0, double *gparams, int64_t *status, hipStream_t s)
+{
+    const int d = pl->desc.dim;
+    const Layout L = layout_for(pl, batch, N, true);
+    fabm_status st = ensure_device(pl);
+    if (st != FABM_OK) return st;
+    if ((st = wait_staging(pl)) != FABM_OK) return st;
+    if ((st = ensure_stage(pl, L.stage_bytes)) != FABM_OK) return st;
+    InstMeta *hm = (InstMeta *)(pl->h_stage + L.meta);
+    InstMeta *ham = (InstMeta *)(pl->h_stage + L.meta_adj);
+    int64_t w_off = 0, f_off = 0, maxw = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        InstMeta &m = hm[i];
+        host_scalars(alpha[i], h[i], m);
+        m.N = N[i];
+        m.wlen = (int64_t)blocks_of(N[i]) * fabm::step_block_len() + fabm::step_block_len();
+        m.w_off = w_off;
+        m.p_off = (int64_t)pl->n_params * i;
+        m.f_off = f_off;
+        m.row_off = f_off;  // the forward rows go to the workspace, packed
+        ham[i] = m;
+        ham[i].row_off = row_off[i];  // dL/dy rows are the caller's
+        w_off += 3 * m.wlen;
+        f_off += N[i] + 1;
+        maxw = std::max(maxw, m.wlen);
+    }
+    const fabm::BatchSchedule &BS = stage_batch(pl, L, batch, N);
+    char *base = (char *)ws;
+    if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
+    InstMeta *dmeta = (InstMeta *)(base + L.meta);
+    double *W = (double *)(base + L.w);
+    uint32_t *sync = (uint32_t *)(base + L.sync);
+    fabm::KernelTimer *T = pl->timer.on ? &pl->timer : nullptr;
+    if (T) T->reset();
+    if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
+    if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK) return st;
+    if (T) HIP_TRY(T->end(s));
+    if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
+        FABM_OK)
+        return st;
+    fabm::BatchArgs A{};
+    A.meta = dmeta;
+    A.inst = (const fabm::BlkInst *)(base + L.inst);
+    A.order = (const int *)(base + L.order);
+    A.params = params;
+    A.y0 = y0;
+    A.Y = (double *)(base + L.yw);
+    A.YP = (double *)(base + L.ypw);
+    A.W = W;
+    A.Fc = (double *)(base + L.f);
+    A.carry = (double *)(base + L.carry);
+    A.acc = (double *)(base + L.acc);
+    A.dead = sync;
+    A.status = status;
+    A.batch = batch;
+    const int *far_off = (const int *)(base + L.far_off);
+    const char *where = "";
+    hipError_t pe = fabm::enqueue_batch(pl->desc.system, d, false, A, BS, far_off, s, T, &where);
+    if (pe != hipSuccess) return record_hip(where, pe);
+    fabm::AdjArgs R{};
+    R.meta = (const InstMeta *)(base + L.meta_adj);
+    R.inst = A.inst;
+    R.order = A.order;
+    R.params = params;
+    R.y0 = y0;
+    R.Y = A.Y;
+    R.YP = A.YP;
+    R.G = gy;
+    R.W = W;
+    R.UV = (double *)(base + L.uv);
+    R.carry = (double *)(base + L.carry_a);
+    R.acc = (double *)(base + L.acc_a);
+    R.part = (double *)(base + L.part_a);
+    R.fbar0 = (double *)(base + L.fbar0);
+    R.dead = sync;
+    R.gy0 = gy0;
+    R.gparams = gparams;
+    R.batch = batch;
+    pe = fabm::enqueue_adjoint(pl->desc.system, d, R, BS, far_off, s, T, &where);
+    if (pe != hipSuccess) return record_hip(where, pe);
+    return FABM_OK;
+}
+
+// Checks shared by the batched entry points.
+fabm_status check_batch(const fabm_plan_s *plan, int64_t batch, const double *alpha,
+                        const double *h, const int64_t *N, const int64_t *row_off)
+{
+    if (!plan || !alpha || !h || !N || !row_off) return FABM_ERR_INVALID_ARG;
+    if (batch < 1 || batch > plan->desc.max_batch) return FABM_ERR_INVALID_ARG;
+    const int64_t total_cap = plan->desc.max_total_steps
+                                  ? plan->desc.max_total_steps
+                                  : plan->desc.max_batch * plan->desc.max_steps;
+    int64_t sumN = 0;
+    std::vector<std::pair<int64_t, int64_t>> spans((size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) {
+        fabm_status st = check_alpha_h(alpha[i], h[i]);
+        if (st != FABM_OK) return st;
+        if (N[i] < 1 || N[i] > plan->desc.max_steps || row_off[i] < 0)
+            return FABM_ERR_INVALID_ARG;
+        sumN += N[i];
+        spans[(size_t)i] = {row_off[i], row_off[i] + N[i] + 1};
+    }
+    if (sumN > total_cap) return FABM_ERR_INVALID_ARG;
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return FABM_ERR_INVALID_ARG;
+    return FABM_OK;
 }
 
 }  // namespace
@@ -516,25 +668,8 @@ fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace
                              const int64_t *row_off, double *y_out, int64_t *status,
                              hipStream_t stream)
 {
-    if (!plan || !alpha || !h || !N || !row_off) return FABM_ERR_INVALID_ARG;
-    if (batch < 1 || batch > plan->desc.max_batch) return FABM_ERR_INVALID_ARG;
-    const int64_t total_cap = plan->desc.max_total_steps
-                                  ? plan->desc.max_total_steps
-                                  : plan->desc.max_batch * plan->desc.max_steps;
-    int64_t sumN = 0;
-    std::vector<std::pair<int64_t, int64_t>> spans((size_t)batch);
-    for (int64_t i = 0; i < batch; ++i) {
-        fabm_status st = check_alpha_h(alpha[i], h[i]);
-        if (st != FABM_OK) return st;
-        if (N[i] < 1 || N[i] > plan->desc.max_steps || row_off[i] < 0)
-            return FABM_ERR_INVALID_ARG;
-        sumN += N[i];
-        spans[(size_t)i] = {row_off[i], row_off[i] + N[i] + 1};
-    }
-    if (sumN > total_cap) return FABM_ERR_INVALID_ARG;
-    std::sort(spans.begin(), spans.end());
-    for (size_t i = 1; i < spans.size(); ++i)
-        if (spans[i].first < spans[i - 1].second) return FABM_ERR_INVALID_ARG;
+    fabm_status cst = check_batch(plan, batch, alpha, h, N, row_off);
+    if (cst != FABM_OK) return cst;
     if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
     if (plan->n_params > 0 && !aligned8(params)) return FABM_ERR_INVALID_ARG;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
@@ -543,6 +678,38 @@ fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace
     if (workspace_bytes < L.total) return FABM_ERR_WORKSPACE;
     return run_solve(plan, workspace, batch, alpha, h, N, y0, params, row_off, y_out, status,
                      stream);
+}
+
+fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *N,
+                                        size_t *bytes)
+{
+    if (!plan || !N || !bytes || batch < 1 || batch > plan->desc.max_batch)
+        return FABM_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < batch; ++i)
+        if (N[i] < 1 || N[i] > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
+    if (plan->desc.system == FABM_SYS_LINEAR && plan->desc.dim > 4) return FABM_ERR_UNSUPPORTED;
+    *bytes = layout_for(plan, batch, N, true).total;
+    return FABM_OK;
+}
+
+fabm_status fabm_adjoint(fabm_plan_t plan, void *workspace, size_t workspace_bytes, int64_t batch,
+                         const double *alpha, const double *h, const int64_t *N,
+                         const double *y0, const double *params, const int64_t *row_off,
+                         const double *gy, double *gy0, double *gparams, int64_t *status,
+                         hipStream_t stream)
+{
+    fabm_status st = check_batch(plan, batch, alpha, h, N, row_off);
+    if (st != FABM_OK) return st;
+    if (!aligned8(y0) || !aligned8(gy) || !aligned8(gy0) || !aligned8(status))
+        return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && (!aligned8(params) || !aligned8(gparams)))
+        return FABM_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
+    size_t need = 0;
+    if ((st = fabm_adjoint_workspace_size(plan, batch, N, &need)) != FABM_OK) return st;
+    if (workspace_bytes < need) return FABM_ERR_WORKSPACE;
+    return run_adjoint(plan, workspace, batch, alpha, h, N, y0, params, row_off, gy, gy0, gparams,
+                       status, stream);
 }
 
 fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *c,

@@ -1,0 +1,42 @@
+// fabm_adjoint.h -- argument block of the reverse (adjoint) pipeline
+// (internal; kernels in adjoint.hip, layout in capi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fabm_blocked.h"
+#include "fabm_device.h"
+
+namespace fabm {
+
+// Placement per instance i: forward rows Y, YP at meta[i].f_off (packed),
+// dL/dy rows G at meta[i].row_off (the caller's), reversed sources UV at
+// 2 inst[i].fc_off, sums acc at inst[i].acc_off / 2, block partials at
+// inst[i].acc_off / (2 D 256) * (n_params + D).
+struct AdjArgs {
+    const InstMeta *meta;   // [batch]
+    const BlkInst *inst;    // [batch] (same as the forward batch)
+    const int *order;       // instances by block count, descending
+    const double *params;   // [batch][n_params]
+    const double *y0;       // [batch][D]
+    const double *Y, *YP;   // recomputed forward rows
+    const double *G;        // caller's dL/dy rows
+    const double *W;        // weight tables (b, a, c)
+    double *UV;             // reversed sources [2D][NB*256] per instance
+    double *carry;          // [batch][2][D][256]
+    double *acc;            // [NB][D][4][64] per instance
+    double *part;           // [NB][n_params + D] per instance
+    double *fbar0;          // [batch][D]
+    const uint32_t *dead;   // forward non-finite flags [batch]
+    double *gy0;            // [batch][D]
+    double *gparams;        // [batch][n_params] (at meta[i].p_off)
+    int64_t batch;
+};
+
+struct KernelTimer;
+hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule &S,
+                           const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
+size_t adj_smem_bytes(int d);
+
+}  // namespace fabm

@@ -41,6 +41,7 @@ struct InstView {
     const double *params;
     const double *y0;
     double *Y;          // rows [N+1][D]
+    double *YP;         // predictor rows [N+1][D] (row 0 = y0), or null
     const double *W;    // b, a, c tables of length meta->wlen each
     const float *W32;   // b, a in binary32 (FP32 far windows only)
     double *Fc;         // [D][NB*256]
@@ -98,6 +99,7 @@ struct BatchArgs {
     const double *params;  // [batch][n_params]
     const double *y0;      // [batch][D]
     double *Y;             // caller rows; instance i at meta[i].row_off
+    double *YP;            // predictor rows placed like Y, or null
     const double *W;       // weight tables, instance i at meta[i].w_off
     const float *W32;      // binary32 b, a of instance i at 2 meta[i].w_off / 3
     double *Fc;

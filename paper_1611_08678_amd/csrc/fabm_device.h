@@ -66,6 +66,61 @@ __device__ __forceinline__ void rhs(double t, const double (&y)[D], double (&f)[
     }
 }
 
+// Transposed Jacobian products of f for the reverse pass: gy += (df/dy)^T w
+// and gth += (df/dtheta)^T w at (t, y). Derivatives of the forms in rhs().
+template <int SYS, int D>
+__device__ __forceinline__ void rhs_vjp(double t, const double (&y)[D], const double (&w)[D],
+                                        const double *__restrict__ p, double (&gy)[D],
+                                        double *gth)
+{
+    if constexpr (SYS == SYS_LINEAR) {
+        // f_i = sum_j A_ij y_j + b0_i + b1_i t
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double s = gy[j];
+#pragma unroll
+            for (int i = 0; i < D; ++i) s = fma(p[i * D + j], w[i], s);
+            gy[j] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) gth[i * D + j] = fma(w[i], y[j], gth[i * D + j]);
+            gth[D * D + i] += w[i];
+            gth[D * D + D + i] = fma(w[i], t, gth[D * D + D + i]);
+        }
+    } else if constexpr (SYS == SYS_CHEN) {
+        const double a = p[0], b = p[1], c = p[2];
+        gy[0] += -a * w[0] + (c - a - y[2]) * w[1] + y[1] * w[2];
+        gy[1] += a * w[0] + c * w[1] + y[0] * w[2];
+        gy[2] += -y[0] * w[1] - b * w[2];
+        gth[0] += (y[1] - y[0]) * w[0] - y[0] * w[1];
+        gth[1] += -y[2] * w[2];
+        gth[2] += (y[0] + y[1]) * w[1];
+    } else if constexpr (SYS == SYS_ROSSLER) {
+        const double a = p[0], c = p[2];
+        gy[0] += w[1] + y[2] * w[2];
+        gy[1] += -w[0] + a * w[1];
+        gy[2] += -w[0] + (y[0] - c) * w[2];
+        gth[0] += y[1] * w[1];
+        gth[1] += w[2];
+        gth[2] += -y[2] * w[2];
+    } else if constexpr (SYS == SYS_VDP) {
+        const double mu = p[0];
+        gy[0] += (-2.0 * mu * y[0] * y[1] - 1.0) * w[1];
+        gy[1] += w[0] + mu * (1.0 - y[0] * y[0]) * w[1];
+        gth[0] += (1.0 - y[0] * y[0]) * y[1] * w[1];
+    } else if constexpr (SYS == SYS_FINANCIAL) {
+        const double a = p[0], b = p[1], c = p[2];
+        gy[0] += (y[1] - a) * w[0] - 2.0 * y[0] * w[1] - w[2];
+        gy[1] += y[0] * w[0] - b * w[1];
+        gy[2] += w[0] - c * w[2];
+        gth[0] += -y[0] * w[0];
+        gth[1] += -y[1] * w[1];
+        gth[2] += -y[2] * w[2];
+    }
+}
+
 // One corrector step from the two history sums (Section 2): returns y_t and
 // f_t, given P_t, C_t, y0 and the step scalars.
 template <int SYS, int D>

@@ -16,7 +16,8 @@ enum : int {
     KC_DIRECT_GRID = 2,
     KC_BLOCKED_STEP = 3,
     KC_HISTORY = 4,
-    KC_COUNT = 5
+    KC_ADJOINT = 5,
+    KC_COUNT = 6
 };
 
 struct KernelTimer {

@@ -1,0 +1,136 @@
+"""GPU parity of fabm_adjoint (the discrete adjoint on the blocked reverse pass)
+against the oracle's hand-derived reverse mode, against central differences
+of the GPU forward pass, and through torch autograd. Gradients of
+L = sum_n <gy[n], y[n]> with respect to y0 and theta."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.test_gpu_direct import _to_np
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+SID = {"linear": 0, "chen": 1, "rossler": 2, "vdp": 3, "financial": 4}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1611_08678_amd as F
+    F.load()
+    return F
+
+
+def _offsets(Ns):
+    off = np.zeros(len(Ns), dtype=np.int64)
+    off[1:] = np.cumsum(np.asarray(Ns) + 1)[:-1]
+    return off
+
+
+def _grad_parity(F, orc, system, thetas, alphas, hs, Ns, y0s, seed=0, tol=1e-10):
+    thetas, y0s, Ns = np.asarray(thetas, float), np.asarray(y0s, float), np.asarray(Ns)
+    B, d = y0s.shape
+    rng = np.random.default_rng(seed)
+    gy = rng.standard_normal((int((Ns + 1).sum()), d))
+    gy0, gth, st = F.adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy)
+    gy0, gth, st = _to_np(gy0), _to_np(gth), _to_np(st)
+    off = _offsets(Ns)
+    worst = 0.0
+    for i in range(B):
+        rg0, rgt, rst = orc.adjoint(SID[system], thetas[i], alphas[i], hs[i], int(Ns[i]), y0s[i],
+                                    gy[off[i]:off[i] + Ns[i] + 1])
+        assert st[i] == rst, (i, st[i], rst)
+        if rst:
+            assert np.all(np.isnan(gy0[i])) and np.all(np.isnan(gth[i]))
+            continue
+        ref = np.concatenate([rg0, rgt])
+        got = np.concatenate([gy0[i], gth[i]])
+        worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    assert worst <= tol, worst
+    return worst
+
+
+def test_adjoint_vdp_ragged_batch(F, orc):
+    """Van der Pol batch (the adjoint workload's system) with ragged lengths,
+    one to a dozen blocks, including the edge lengths 1, 255, 256, 511."""
+    rng = np.random.default_rng(4)
+    B = 12
+    Ns = rng.integers(100, 3000, B, endpoint=True)
+    Ns[:4] = [1, 255, 256, 511]
+    _grad_parity(F, orc, "vdp", rng.uniform(0.5, 2.0, (B, 1)), np.full(B, 0.9), np.full(B, 0.01),
+                 Ns, rng.uniform(-2, 2, (B, 2)), seed=1)
+
+
+@pytest.mark.parametrize("system,d,theta,alpha,h,N", [
+    ("chen", 3, [35.0, 3.0, 28.0], 0.95, 0.001, 1500),
+    ("rossler", 3, [0.2, 0.2, 5.7], 0.93, 0.005, 2600),
+    ("financial", 3, [3.0, 0.1, 1.0], 0.85, 0.01, 2200),
+    ("linear", 1, None, 0.5, 0.005, 2000),
+    ("linear", 3, None, 0.8, 0.01, 1800),
+    ("linear", 4, None, 0.95, 0.01, 1300),
+])
+def test_adjoint_systems(F, orc, system, d, theta, alpha, h, N):
+    rng = np.random.default_rng(8)
+    if theta is None:
+        A = -(2 * np.eye(d) + rng.standard_normal((d, d)) / 8)
+        theta = np.concatenate([A.ravel(), rng.standard_normal(d), 0.05 * rng.standard_normal(d)])
+    y0 = rng.uniform(-1, 1, d) if system != "chen" else np.array([-9.0, -5.0, 14.0])
+    _grad_parity(F, orc, system, [theta], [alpha], [h], [N], [y0], seed=2)
+
+
+def test_adjoint_against_finite_differences(F):
+    """Central differences of the GPU forward pass (two step sizes, showing the
+    O(delta^2) convergence) against the GPU adjoint."""
+    mu, y0, N, alpha, h = 1.3, np.array([0.8, -0.4]), 1500, 0.9, 0.01
+    rng = np.random.default_rng(3)
+    gy = rng.standard_normal((N + 1, 2))
+
+    def loss(mu_, y0_):
+        y, _ = F.solve("vdp", [mu_], alpha, h, N, y0_, path="blocked")
+        return float((_to_np(y) * gy).sum())
+
+    gy0, gth, st = F.adjoint_batch("vdp", [[mu]], [alpha], [h], [N], [y0], gy)
+    assert int(_to_np(st)[0]) == 0
+    grad = np.concatenate([_to_np(gy0)[0], _to_np(gth)[0]])
+    errs = []
+    for delta in (1e-4, 1e-5):
+        fd = []
+        for k in range(2):
+            e = np.zeros(2)
+            e[k] = delta
+            fd.append((loss(mu, y0 + e) - loss(mu, y0 - e)) / (2 * delta))
+        dm = delta * max(1.0, abs(mu))
+        fd.append((loss(mu + dm, y0) - loss(mu - dm, y0)) / (2 * dm))
+        errs.append(np.abs(np.array(fd) - grad).max() / np.abs(grad).max())
+    assert errs[1] <= 1e-6, errs
+    assert errs[1] <= errs[0] * 1.5  # no worse at the smaller step
+
+
+def test_autograd_function_matches_adjoint(F):
+    import torch
+    rng = np.random.default_rng(6)
+    B, Ns = 3, np.array([700, 1200, 300])
+    th = torch.tensor(rng.uniform(0.5, 2.0, (B, 1)), device="cuda", requires_grad=True)
+    y0 = torch.tensor(rng.uniform(-2, 2, (B, 2)), device="cuda", requires_grad=True)
+    al, hs = np.full(B, 0.9), np.full(B, 0.01)
+    y = F.solve_batch_autograd(y0, th, "vdp", al, hs, Ns)
+    gy = torch.tensor(rng.standard_normal(tuple(y.shape)), device="cuda")
+    (y * gy).sum().backward()
+    gy0, gth, _ = F.adjoint_batch("vdp", th.detach(), al, hs, Ns, y0.detach(), gy)
+    assert torch.equal(y0.grad, gy0) and torch.equal(th.grad, gth)
+
+
+def test_adjoint_blowup_gives_nan_and_status(F, orc):
+    lam = np.array([-1.0, 60.0, -2.0])
+    thetas = np.stack([[l, 0.0, 0.0] for l in lam])
+    _grad_parity(F, orc, "linear", thetas, np.full(3, 0.9), np.full(3, 0.5),
+                 np.array([900, 700, 600]), np.ones((3, 1)), seed=4)
+
+
+def test_adjoint_deterministic(F):
+    rng = np.random.default_rng(9)
+    B, Ns = 4, np.array([900, 2000, 1200, 256])
+    args = ("vdp", rng.uniform(0.5, 2.0, (B, 1)), np.full(B, 0.9), np.full(B, 0.01), Ns,
+            rng.uniform(-2, 2, (B, 2)), rng.standard_normal((int((Ns + 1).sum()), 2)))
+    r1, r2 = F.adjoint_batch(*args), F.adjoint_batch(*args)
+    assert all(np.array_equal(_to_np(a), _to_np(b)) for a, b in zip(r1, r2))
