@@ -24,6 +24,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
+# reference copy kernel (profiles/k_step_chen_N2p20_pmc.md), valid only for
+# the kernel source it was measured on (sha256 prefix of blocked.hip).
+MEASURED_TRAFFIC = {"k_step": (59.13e6, "91e44c8a7d9f45a9")}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
@@ -41,9 +45,13 @@ def parse():
                     help="steps of the oracle sample for cpu_baseline (0 disables)")
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="skip the instrumented solve that measures per-kernel time")
-    ap.add_argument("--workload", default="chen", choices=["chen", "rossler_batch", "vdp_batch"],
+    ap.add_argument("--workload", default="chen",
+                    choices=["chen", "rossler_batch", "vdp_batch", "vdp_adjoint"],
                     help="chen: the headline single trajectory; the batch workloads are "
                          "additional measurements of the batched BLOCKED path")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before the benchmark "
+                         "(untimed; a reference kernel of known traffic for hardware counters)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32"],
                     help="far-window arithmetic (default: fp64; rossler_batch: fp32)")
     return ap.parse_args()
@@ -108,6 +116,19 @@ def cpu_baseline(w, n_sample: int, N: int):
                       sample_seconds=dt)
 
 
+def measured_traffic(kernel: str):
+    """Counter-measured HBM bytes per launch, or None if the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    val, sha = MEASURED_TRAFFIC.get(kernel, (None, None))
+    if val is None:
+        return None
+    src = os.path.join(ROOT, "paper_1611_08678_amd", "csrc", "blocked.hip")
+    with open(src, "rb") as f:
+        cur = hashlib.sha256(f.read()).hexdigest()[:16]
+    return val if cur == sha else None
+
+
 def roofline(kt: dict, N: int, d: int):
     """Roofline object of the dominant kernel of the headline path, from the
     library's per-launch HIP events (recorded on the kernel's own stream)."""
@@ -121,7 +142,8 @@ def roofline(kt: dict, N: int, d: int):
         # kernels (MFMA near/far windows plus the sequential band)
         ach = flops / secs / 1e12
         return dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=None, kernel="k_step",
+                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=measured_traffic("k_step"),
+                    kernel="k_step",
                     launches=launches, avg_launch_s=secs / launches,
                     algorithmic_flops_per_launch=flops / launches)
     if dom == "direct_grid":
@@ -167,10 +189,12 @@ def bench_batch(F, W, args):
     per = [a.elapsed_time(b) / 1e3 for a, b in evs]
     print(f"# {args.workload}: solve times {['%.4f' % t for t in per]} s", file=sys.stderr,
           flush=True)
-    F.fabm_plan_set_profiling(plan, True)
-    call()
-    torch.cuda.synchronize()
-    kt = {k: v for k, v in F.fabm_plan_kernel_times(plan).items() if v[1]}
+    kt = {}
+    if not args.no_kernel_times:
+        F.fabm_plan_set_profiling(plan, True)
+        call()
+        torch.cuda.synchronize()
+        kt = {k: v for k, v in F.fabm_plan_kernel_times(plan).items() if v[1]}
     t = float(np.mean(per))
     flops = float((2.0 * d * Ns * (Ns + 1)).sum())
     out = {"metric": "steps*states/s (history GFLOP/s alongside), batched blocked",
@@ -206,15 +230,106 @@ def bench_batch(F, W, args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(F, W, args):
+    """Van der Pol x1024, N = 2^15: forward solve, MSE loss against targets from
+    mu + N(0, 0.05) (computed once by the same forward pass, untimed) and the
+    adjoint for d/dmu and d/dy0. Timed: forward + backward."""
+    import numpy as np
+    import torch
+    w = W.vdp_adjoint()
+    Ns = np.asarray(w["N"], dtype=np.int64)
+    B, d = len(Ns), w["d"]
+    plan = F.fabm_plan(w["system"], d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()))
+    ws = torch.empty(max(F.fabm_workspace_size(plan, Ns), F.fabm_adjoint_workspace_size(plan, Ns)),
+                     dtype=torch.uint8, device="cuda")
+    y0 = torch.as_tensor(w["y0"], dtype=torch.float64, device="cuda").contiguous()
+    th = torch.as_tensor(w["theta"], dtype=torch.float64, device="cuda").contiguous()
+    tht = torch.as_tensor(w["theta_target"], dtype=torch.float64, device="cuda").contiguous()
+    row_off = np.zeros(B, dtype=np.int64)
+    row_off[1:] = np.cumsum(Ns + 1)[:-1]
+    rows = int((Ns + 1).sum())
+    y = torch.empty((rows, d), dtype=torch.float64, device="cuda")
+    yt = torch.empty_like(y)
+    st = torch.zeros(B, dtype=torch.int64, device="cuda")
+    gy0 = torch.empty((B, d), dtype=torch.float64, device="cuda")
+    gth = torch.empty_like(th)
+    F.fabm_solve_batch(plan, ws, w["alpha"], w["h"], Ns, y0, tht, row_off, yt, st)
+    scale = 2.0 / (rows * d)  # d/dy of the mean of squared differences
+
+    def step():
+        F.fabm_solve_batch(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
+        gy = (y - yt) * scale
+        F.fabm_adjoint(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, gy, gy0, gth, st)
+        return gy
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record(stream)
+        gy = step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) / 1e3 for a, b in evs]
+    print(f"# vdp_adjoint: forward+backward times {['%.4f' % t for t in per]} s", file=sys.stderr,
+          flush=True)
+    F.fabm_plan_set_profiling(plan, True)
+    F.fabm_adjoint(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, gy, gy0, gth, st)
+    torch.cuda.synchronize()
+    kt = {k: v for k, v in F.fabm_plan_kernel_times(plan).items() if v[1]}
+    t = float(np.mean(per))
+    flops = float((2.0 * d * Ns * (Ns + 1)).sum())
+    out = {"metric": "forward + backward (adjoint) time of a batched solve, d/dmu and d/dy0",
+           "value": t, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": w["name"], "batch": B, "N": int(Ns.max())},
+           "history_gflops_fwd_plus_bwd": 2.0 * flops / t / 1e9,
+           "adjoint_kernel_times_s": {k: v[0] for k, v in kt.items()},
+           "adjoint_kernel_launches": {k: v[1] for k, v in kt.items()}}
+    if args.cpu_sample > 0:
+        from oracle import oracle as O
+        i = 0
+        g = gy.cpu().numpy()[row_off[i]:row_off[i] + Ns[i] + 1]
+        t0 = time.perf_counter()
+        rg0, rgt, _ = O.adjoint(w["system"], w["theta"][i], float(w["alpha"][i]), float(w["h"][i]),
+                                int(Ns[i]), w["y0"][i], g)
+        dt = time.perf_counter() - t0
+        ref = np.concatenate([rg0, rgt])
+        got = np.concatenate([gy0.cpu().numpy()[i], gth.cpu().numpy()[i]])
+        out["grad_rel_err_vs_oracle_instance0"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+        out["oracle_adjoint_seconds_one_instance"] = dt
+    print(json.dumps(out), flush=True)
+
+
+def copy_reference(mib: int):
+    """One device-to-device copy of `mib` MiB (reads and writes that many bytes)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"# copy reference: {mib} MiB read + {mib} MiB written", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_mib > 0:
+        copy_reference(args.copy_mib)
     if args.workload != "chen":
         import paper_1611_08678_amd as F
         from paper_1611_08678_amd import workloads as W
         F.load()
+        if args.workload == "vdp_adjoint":
+            return bench_adjoint(F, W, args)
         return bench_batch(F, W, args)
     import numpy as np
     import paper_1611_08678_amd as F
