@@ -95,19 +95,22 @@ __device__ __forceinline__ int band_wait_rows(int *s_cnt, int *s_dead, int need)
     }
 }
 
-template <int SYS, int D>
+template <int SYS, int D, bool YPOUT>
 __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
-    double *sb = (double *)smem;  // b lags 0..511
-    double *sa = sb + 2 * kBlk;   // a lags 0..511
-    double *sF = sa + 2 * kBlk;   // [256][D] f of this block's rows
-    double *sY = sF + kBlk * D;   // [256][D] y of this block's rows
-    double *sYP = sY + kBlk * D;  // [256][D] predictor values (when A.YP is set)
-    double *sTh = sYP + kBlk * D; // theta, for systems with many parameters
+    double *sb = (double *)smem;   // b lags 0..511 (next block's sums)
+    double *sa = sb + 2 * kBlk;    // a lags 0..511
+    double *sbh = sa + 2 * kBlk;   // h^a b lags 0..255 (this block's sums)
+    double *sah = sbh + kBlk;      // h^a a lags 0..255
+    double *sF = sah + kBlk;       // [256][D] f of this block's rows
+    double *sY = sF + kBlk * D;    // [256][D] y of this block's rows
+    double *sYP = sY + kBlk * D;   // [256][D] predictor values (YPOUT)
+    double *sTh = sYP + (YPOUT ? kBlk * D : 0);  // theta, for systems with many parameters
     int *s_cnt = (int *)(sTh + NP);  // rows of this block published so far (> 256: stop)
     int *s_dead = s_cnt + 1;         // first non-finite row (block-relative), -1, or -2
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const InstMeta m = A.meta[0];
     const int64_t N = m.N;
     const int64_t pitch = (int64_t)A.NB * kBlk;
@@ -120,7 +123,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     if (*A.dead != 0u) {
         for (int e = tid; e < nrows * D; e += nthr) {
             A.Y[t0 * D + e] = __builtin_nan("");
-            if (A.YP) A.YP[t0 * D + e] = __builtin_nan("");
+            if constexpr (YPOUT) A.YP[t0 * D + e] = __builtin_nan("");
         }
         return;
     }
@@ -140,6 +143,10 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         sb[j] = wb[j];
         sa[j] = wa[j];
     }
+    for (int j = tid; j < kBlk; j += nthr) {
+        sbh[j] = m.ha * wb[j];
+        sah[j] = m.ha * wa[j];
+    }
     // f_0 (block 0 forms row 0 here; later blocks need it for the c - a fix)
     double f0[D];
     if (J == 0) {
@@ -156,11 +163,13 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             for (int i = 0; i < D; ++i) {
                 sF[i] = f0[i];
                 sY[i] = y0[i];
-                sYP[i] = y0[i];
+                if constexpr (YPOUT) sYP[i] = y0[i];
             }
         }
     }
-    // sums of target row `row` of block J (pc, cc) and of block J+1 (pn, cn)
+    // Sums of target row `row`: of this block in the form y0 + h^a P and
+    // y0 + h^a C (what the predictor and corrector add the newest term to),
+    // of the next block as plain P and C (handed over through `carry`).
     const int row = 64 * wave + lane;
     const int64_t T = t0 + row;
     double pc[D], cc[D], pn[D], cn[D];
@@ -168,17 +177,18 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         // source row 0 takes b_{T-1} and c_{T-1}
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = T >= 1 ? wb[T - 1] * f0[i] : 0.0;
-            cc[i] = T >= 1 ? wc[T - 1] * f0[i] : 0.0;
+            pc[i] = fma(m.ha, T >= 1 ? wb[T - 1] * f0[i] : 0.0, y0[i]);
+            cc[i] = fma(m.ha, T >= 1 ? wc[T - 1] * f0[i] : 0.0, y0[i]);
             pn[i] = wb[kBlk + row - 1] * f0[i];
             cn[i] = wc[kBlk + row - 1] * f0[i];
         }
     } else {
         const double *cin = A.carry + (int64_t)(J & 1) * 2 * D * kBlk;
+        double P[D], Cs[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = cin[i * kBlk + row];
-            cc[i] = cin[(D + i) * kBlk + row];
+            P[i] = cin[i * kBlk + row];
+            Cs[i] = cin[(D + i) * kBlk + row];
             pn[i] = cn[i] = 0.0;
         }
         if (J >= 2) {
@@ -190,28 +200,34 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             const double dca = wc[T - 1] - wa[T - 1];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                pc[i] += aj[i * kBlk + e];
+                P[i] += aj[i * kBlk + e];
                 // source row 0 takes c_{T-1} where the tiles used a_{T-1}
-                cc[i] = fma(dca, f0[i], cc[i] + aj[(D + i) * kBlk + e]);
+                Cs[i] = fma(dca, f0[i], Cs[i] + aj[(D + i) * kBlk + e]);
             }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            pc[i] = fma(m.ha, P[i], y0[i]);
+            cc[i] = fma(m.ha, Cs[i], y0[i]);
         }
     }
     __syncthreads();
 
-    const int lo = 64 * wave < nrows ? 64 * wave : nrows;  // rows this wavefront forms:
-    const int hi = 64 * wave + 64 < nrows ? 64 * wave + 64 : nrows;  // [lo, hi)
+    // rows this wavefront forms: [lo, hi)
+    const int lo = 64 * wave < nrows ? 64 * wave : nrows;
+    const int hi = 64 * wave + 64 < nrows ? 64 * wave + 64 : nrows;
     int done = J == 0 ? 1 : 0;  // rows already in this wavefront's sums
     bool go = true;
     // rows formed by earlier wavefronts: both blocks' sums
     while (go && done < lo) {
-        const int c = band_wait_rows(s_cnt, s_dead, done + 1);
+        const int c = __builtin_amdgcn_readfirstlane(band_wait_rows(s_cnt, s_dead, done + 1));
         if (c < 0) {
             go = false;
             break;
         }
         const int upto = c < lo ? c : lo;
         for (; done < upto; ++done) {
-            const double bw = sb[row - done - 1], aw = sa[row - done - 1];
+            const double bw = sbh[row - done - 1], aw = sah[row - done - 1];
             const double bn = sb[kBlk + row - done - 1], an = sa[kBlk + row - done - 1];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -223,76 +239,82 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             }
         }
     }
-    // this wavefront's rows. The sums read out for row t leave out row t-1,
+    // This wavefront's rows. The sums read out for row t leave out row t-1,
     // whose contribution enters the predictor and the corrector directly:
-    //   yP_t = y0 + h^a P'_t + (h^a b_0) f_{t-1},
-    //   y_t  = y0 + h^a C'_t + (h^a a_0) f_{t-1} + (h^a / Gamma(a+2)) f(t, yP_t),
+    //   yP_t = (y0 + h^a P'_t) + (h^a b_0) f_{t-1},
+    //   y_t  = (y0 + h^a C'_t) + (h^a a_0) f_{t-1} + (h^a / Gamma(a+2)) f(t, yP_t),
     // so the dependent chain of a step is the two evaluations of f; adding
     // row t-1 to the other sums and reading out those of row t+1 overlap it.
+    // Rows are checked for non-finite values when they are published.
     const int first = done;
-    const double hb0 = m.ha * sb[0], ha0 = m.ha * sa[0], hig2 = m.ha * m.ig2;
+    const double hb0 = sbh[0], ha0 = sah[0], hig2 = m.ha * m.ig2;
     double fprev[D], ypb[D], ycb[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        // the first row's sums are complete
+    {
         const int l0 = first - lo < 63 ? first - lo : 63;
-        ypb[i] = fma(m.ha, readlane_f64(pc[i], l0), y0[i]);
-        ycb[i] = fma(m.ha, readlane_f64(cc[i], l0), y0[i]);
-        fprev[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            ypb[i] = readlane_f64(pc[i], l0);
+            ycb[i] = readlane_f64(cc[i], l0);
+            fprev[i] = 0.0;
+        }
     }
-    int bad = -1;  // first non-finite row formed by this wavefront
+    int checked = first;  // rows before this one have been checked
     for (int t = first; go && t < hi; ++t) {
         const double tt = (double)(t0 + t) * m.h;
-        double yp[D], fp[D], yc[D], y[D], f[D];
+        double yp[D], fp[D], y[D], f[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) yp[i] = fma(hb0, fprev[i], ypb[i]);
         rhs<SYS, D>(tt, yp, fp, th);
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            yc[i] = fma(ha0, fprev[i], ycb[i]);
-            y[i] = fma(hig2, fp[i], yc[i]);
-        }
+        for (int i = 0; i < D; ++i) y[i] = fma(hig2, fp[i], fma(ha0, fprev[i], ycb[i]));
         rhs<SYS, D>(tt, y, f, th);
         // off the chain: row t-1 into the sums of the later rows (lags of
         // rows <= t-1 are clamped; those sums are no longer read), then the
         // sums of row t+1
         const int lag = row - t;
         const int lc = lag > 0 ? lag : 0;
-        const double bw = sb[lc], aw = sa[lc];
+        const double bw = sbh[lc], aw = sah[lc];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             pc[i] = fma(bw, fprev[i], pc[i]);
             cc[i] = fma(aw, fprev[i], cc[i]);
         }
         const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
-        bool nf = false;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            ypb[i] = fma(m.ha, readlane_f64(pc[i], ln), y0[i]);
-            ycb[i] = fma(m.ha, readlane_f64(cc[i], ln), y0[i]);
-            nf |= !isfinite(y[i]);
-            nf |= !isfinite(f[i]);
+            ypb[i] = readlane_f64(pc[i], ln);
+            ycb[i] = readlane_f64(cc[i], ln);
             fprev[i] = f[i];
         }
-        if (nf && bad < 0) bad = t;
         if (lane == 0) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 sF[t * D + i] = f[i];
                 sY[t * D + i] = y[i];
-                sYP[t * D + i] = yp[i];
+                if constexpr (YPOUT) sYP[t * D + i] = yp[i];
             }
         }
         if ((t + 1) % kPublishEvery == 0 || t + 1 == hi) {
-            if (bad >= 0) {
+            // check rows [checked, t] (at most 8 rows of 2D values) before
+            // publishing them: one value per lane
+            __builtin_amdgcn_wave_barrier();
+            const int nv = (t + 1 - checked) * 2 * D;
+            bool bad = false;
+            if (lane < nv) {
+                const int r = checked + lane / (2 * D), k = lane % (2 * D);
+                bad = !isfinite(k < D ? sF[r * D + k] : sY[r * D + k - D]);
+            }
+            const uint64_t mask = __ballot(bad);
+            if (mask) {
                 if (lane == 0) {
-                    *s_dead = bad;
+                    *s_dead = checked + __builtin_ctzll(mask) / (2 * D);
                     __hip_atomic_store(s_cnt, kBlk + 1, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
                 go = false;
                 break;
             }
+            checked = t + 1;
             if (lane == 0)
                 __hip_atomic_store(s_cnt, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
@@ -312,7 +334,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             }
         }
         while (done < nrows) {
-            const int c = band_wait_rows(s_cnt, s_dead, done + 1);
+            const int c = __builtin_amdgcn_readfirstlane(band_wait_rows(s_cnt, s_dead, done + 1));
             if (c < 0) break;
             for (; done < c; ++done) {
                 const double bn = sb[kBlk + row - done - 1], an = sa[kBlk + row - done - 1];
@@ -331,7 +353,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     const int valid = dead == -1 ? nrows : (dead < 0 ? 0 : dead);
     for (int e = tid; e < nrows * D; e += nthr)
         A.Y[t0 * D + e] = e / D < valid ? sY[e] : __builtin_nan("");
-    if (A.YP) {
+    if constexpr (YPOUT) {
         for (int e = tid; e < nrows * D; e += nthr)
             A.YP[t0 * D + e] = e / D < valid ? sYP[e] : __builtin_nan("");
     }
@@ -581,7 +603,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
     const int b = blockIdx.x, wave = threadIdx.x >> 6;
     const InstView V = single_view(A);
     if (b == 0) {
-        if (wave < kBandWaves) band_block<SYS, D>(V, s + 1, smem);
+        if (wave < kBandWaves) band_block<SYS, D, false>(V, s + 1, smem);
         return;
     }
     if (*A.dead != 0u) return;  // the trajectory has ended; later rows are NaN
@@ -630,7 +652,7 @@ __device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
                     b.NB};
 }
 
-template <int SYS, int D, bool F32>
+template <int SYS, int D, bool F32, bool YPOUT>
 __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s, int nband,
                                                               int nnear, const int *far_off,
                                                               int nfar)
@@ -639,7 +661,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
     int q = blockIdx.x;
     if (q < nband) {
         const InstView V = batch_view<D>(A, A.order[q]);
-        band_block<SYS, D>(V, s + 1, smem);
+        band_block<SYS, D, YPOUT>(V, s + 1, smem);
         return;
     }
     q -= nband;
@@ -704,7 +726,7 @@ __global__ void k_step_status(StepArgs A)
 // itself and each far workgroup owns four SIMDs.
 size_t step_smem_bytes(int d)
 {
-    const size_t band = sizeof(double) * (4 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    const size_t band = sizeof(double) * (6 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
     const size_t near = sizeof(double) * (kNearWaves * 2 * (size_t)d * kBlk +
                                           (size_t)d * kSrcCols * kColPitch);
     const size_t exclusive = 81 * 1024;
@@ -765,12 +787,12 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
 
 size_t batch_smem_bytes(int d)
 {
-    const size_t band = sizeof(double) * (4 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    const size_t band = sizeof(double) * (6 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
     const size_t near = sizeof(double) * (2 * (size_t)d * kBlk + (size_t)d * kSrcCols * kColPitch);
     return std::max(band, near);
 }
 
-template <int SYS, int D, bool F32>
+template <int SYS, int D, bool F32, bool YPOUT>
 static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, const int *far_off,
                                   hipStream_t st, KernelTimer *T, const char **where)
 {
@@ -790,7 +812,8 @@ static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, co
         const int grid = nb + nn + nfw;
         if (grid == 0) continue;
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
-        hipLaunchKernelGGL((k_step_batch<SYS, D, F32>), dim3(grid), dim3(kBatchThreads), smem, st, A, s,
+        hipLaunchKernelGGL((k_step_batch<SYS, D, F32, YPOUT>), dim3(grid), dim3(kBatchThreads), smem,
+                           st, A, s,
                            nb, nn, far_off + S.far_base[k], nf);
         FABM_STEP_TRY("launch k_step_batch", hipGetLastError());
         if (T) FABM_STEP_TRY("timer end", T->end(st));
@@ -804,10 +827,12 @@ static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, co
 hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const BatchSchedule &S,
                          const int *far_off, hipStream_t s, KernelTimer *T, const char **where)
 {
+    // predictor rows are written when A.YP is set (FP64 far windows only)
 #define FABM_BATCH_CASE(SS, DD)                                                          \
     if (sys == SS && d == DD)                                                            \
-        return f32 ? enqueue_batch_t<SS, DD, true>(A, S, far_off, s, T, where)           \
-                   : enqueue_batch_t<SS, DD, false>(A, S, far_off, s, T, where);
+        return A.YP  ? enqueue_batch_t<SS, DD, false, true>(A, S, far_off, s, T, where)  \
+               : f32 ? enqueue_batch_t<SS, DD, true, false>(A, S, far_off, s, T, where)  \
+                     : enqueue_batch_t<SS, DD, false, false>(A, S, far_off, s, T, where);
     FABM_BATCH_CASE(SYS_LINEAR, 1)
     FABM_BATCH_CASE(SYS_LINEAR, 2)
     FABM_BATCH_CASE(SYS_LINEAR, 3)
