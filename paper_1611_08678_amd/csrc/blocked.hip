@@ -259,50 +259,57 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         }
     }
     int checked = first;  // rows before this one have been checked
-    for (int t = first; go && t < hi; ++t) {
-        const double tt = (double)(t0 + t) * m.h;
-        double yp[D], fp[D], y[D], f[D];
+    // rows in groups of kPublishEvery (aligned to the block), unrolled, so the
+    // publish check runs once per group; the weights of the next step are
+    // loaded one step ahead
+    int lc0 = row - first;
+    double bw = sbh[lc0 > 0 ? lc0 : 0], aw = sah[lc0 > 0 ? lc0 : 0];
+    for (int g0 = first & ~(kPublishEvery - 1); go && g0 < hi; g0 += kPublishEvery) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) yp[i] = fma(hb0, fprev[i], ypb[i]);
-        rhs<SYS, D>(tt, yp, fp, th);
+        for (int k = 0; k < kPublishEvery; ++k) {
+            const int t = g0 + k;
+            if (t < first || t >= hi) continue;
+            const int lagn = row - t - 1;
+            const double bwn = sbh[lagn > 0 ? lagn : 0], awn = sah[lagn > 0 ? lagn : 0];
+            const double tt = (double)(t0 + t) * m.h;
+            double yp[D], fp[D], y[D], f[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) y[i] = fma(hig2, fp[i], fma(ha0, fprev[i], ycb[i]));
-        rhs<SYS, D>(tt, y, f, th);
-        // off the chain: row t-1 into the sums of the later rows (lags of
-        // rows <= t-1 are clamped; those sums are no longer read), then the
-        // sums of row t+1
-        const int lag = row - t;
-        const int lc = lag > 0 ? lag : 0;
-        const double bw = sbh[lc], aw = sah[lc];
+            for (int i = 0; i < D; ++i) yp[i] = fma(hb0, fprev[i], ypb[i]);
+            rhs<SYS, D>(tt, yp, fp, th);
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            pc[i] = fma(bw, fprev[i], pc[i]);
-            cc[i] = fma(aw, fprev[i], cc[i]);
-        }
-        const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            ypb[i] = readlane_f64(pc[i], ln);
-            ycb[i] = readlane_f64(cc[i], ln);
-            fprev[i] = f[i];
-        }
-        if (lane == 0) {
+            for (int i = 0; i < D; ++i) y[i] = fma(hig2, fp[i], fma(ha0, fprev[i], ycb[i]));
+            rhs<SYS, D>(tt, y, f, th);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                sF[t * D + i] = f[i];
-                sY[t * D + i] = y[i];
-                if constexpr (YPOUT) sYP[t * D + i] = yp[i];
+                pc[i] = fma(bw, fprev[i], pc[i]);
+                cc[i] = fma(aw, fprev[i], cc[i]);
             }
+            const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                ypb[i] = readlane_f64(pc[i], ln);
+                ycb[i] = readlane_f64(cc[i], ln);
+                fprev[i] = f[i];
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    sF[t * D + i] = f[i];
+                    sY[t * D + i] = y[i];
+                    if constexpr (YPOUT) sYP[t * D + i] = yp[i];
+                }
+            }
+            bw = bwn;
+            aw = awn;
         }
-        if ((t + 1) % kPublishEvery == 0 || t + 1 == hi) {
-            // check rows [checked, t] (at most 8 rows of 2D values) before
-            // publishing them: one value per lane
+        const int tl = g0 + kPublishEvery < hi ? g0 + kPublishEvery : hi;  // rows formed: < tl
+        {
             __builtin_amdgcn_wave_barrier();
-            const int nv = (t + 1 - checked) * 2 * D;
+            const int nv = (tl - checked) * 2 * D;
             bool bad = false;
             if (lane < nv) {
-                const int r = checked + lane / (2 * D), k = lane % (2 * D);
-                bad = !isfinite(k < D ? sF[r * D + k] : sY[r * D + k - D]);
+                const int r = checked + lane / (2 * D), kk = lane % (2 * D);
+                bad = !isfinite(kk < D ? sF[r * D + kk] : sY[r * D + kk - D]);
             }
             const uint64_t mask = __ballot(bad);
             if (mask) {
@@ -314,11 +321,11 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
                 go = false;
                 break;
             }
-            checked = t + 1;
+            checked = tl;
             if (lane == 0)
-                __hip_atomic_store(s_cnt, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(s_cnt, tl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        done = t + 1;
+        done = tl;
     }
     if (go) {
         // own rows into block J+1 (f_t was written to LDS by lane 0 of this
