@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {"k_step": (59.13e6, "91e44c8a7d9f45a9")}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense binary16 matrix rate
 
 
 def parse():
@@ -46,14 +47,16 @@ def parse():
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="skip the instrumented solve that measures per-kernel time")
     ap.add_argument("--workload", default="chen",
-                    choices=["chen", "rossler_batch", "vdp_batch", "vdp_adjoint"],
+                    choices=["chen", "rossler_batch", "vdp_batch", "vdp_adjoint",
+                             "linear64_batch"],
                     help="chen: the headline single trajectory; the batch workloads are "
                          "additional measurements of the batched BLOCKED path")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the benchmark "
                          "(untimed; a reference kernel of known traffic for hardware counters)")
-    ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32"],
-                    help="far-window arithmetic (default: fp64; rossler_batch: fp32)")
+    ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
+                    help="far-window arithmetic (default: fp64; rossler_batch: fp32; "
+                         "fp16x2 only for linear64_batch)")
     return ap.parse_args()
 
 
@@ -158,11 +161,14 @@ def roofline(kt: dict, N: int, d: int):
 
 def bench_batch(F, W, args):
     """Batched BLOCKED solve of a batch workload: Rossler (4096 instances,
-    N uniform in [2^14, 2^17], per-instance alpha, FP32 far windows) or the
-    Van der Pol forward pass (1024 instances, N = 2^15)."""
+    N uniform in [2^14, 2^17], per-instance alpha, FP32 far windows), the
+    Van der Pol forward pass (1024 instances, N = 2^15), or the linear d = 64
+    batch (512 instances sharing alpha = 0.8, h = 0.01, N = 2^16: the
+    shared-grid form, far tiles FP64, FP32 or FP16X2)."""
     import numpy as np
     import torch
-    w = W.rossler_batch() if args.workload == "rossler_batch" else W.vdp_adjoint()
+    w = {"rossler_batch": W.rossler_batch, "linear64_batch": W.linear64_batch}.get(
+        args.workload, W.vdp_adjoint)()
     prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" else "fp64")
     Ns = np.asarray(w["N"], dtype=np.int64)
     B, d = len(Ns), w["d"]
@@ -201,7 +207,9 @@ def bench_batch(F, W, args):
            "value": float(Ns.sum()) * d / t, "unit": "steps*states/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == "fp64" else "f64 band, f32 far windows", "data": "synthetic",
+           "dtype": {"fp64": "f64", "fp32": "f64 band, f32 far windows",
+                     "fp16x2": "f64 band, fp16 hi+lo far tiles (f32 sums)"}[prec],
+           "data": "synthetic",
            "config": {"workload": w["name"], "batch": B, "N_min": int(Ns.min()),
                       "N_max": int(Ns.max()), "far_prec": prec},
            "history_gflops": flops / t / 1e9,
@@ -216,7 +224,32 @@ def bench_batch(F, W, args):
                                frac=ach / peak, traffic=None, kernel="k_step_batch",
                                launches=launches, avg_launch_s=secs / launches,
                                algorithmic_flops_per_launch=flops / launches)
-    if args.cpu_sample > 0:
+    if "wide_far" in kt:
+        # far sums of the shared grid: every target row t takes the 64 * (t // 64)
+        # source rows of earlier blocks, both tables, every column
+        secs, launches = kt["wide_far"]
+        t_rows = np.arange(int(Ns[0]) + 1, dtype=np.float64)
+        far_flops = float((4.0 * B * d * 64.0 * np.floor(t_rows / 64.0)).sum())
+        hw = 3.0 if prec == "fp16x2" else 1.0  # hi*hi + hi*lo + lo*hi products
+        peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
+                "fp16x2": FP16_MFMA_PEAK_TFLOPS}[prec]
+        ach = hw * far_flops / secs / 1e12
+        out["roofline"] = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                               frac=ach / peak, traffic=None, kernel="k_wide_far",
+                               launches=launches, avg_launch_s=secs / launches,
+                               algorithmic_flops_per_launch=far_flops / launches,
+                               mfma_flops_per_algorithmic_flop=hw)
+    if args.cpu_sample > 0 and args.workload == "linear64_batch":
+        # oracle check of the first 1000 steps of the first and last instance
+        from oracle import oracle as O
+        errs = []
+        for i in (0, B - 1):
+            ref, _, _, _ = O.solve(w["system"], w["theta"][i], float(w["alpha"][i]),
+                                   float(w["h"][i]), 1000, w["y0"][i])
+            g = y[int(row_off[i]):int(row_off[i]) + 1001].cpu().numpy()
+            errs.append(float(np.abs(g - ref).max() / np.abs(ref).max()))
+        out["rel_err_first_1000_steps"] = errs
+    elif args.cpu_sample > 0:
         # oracle check of the three shortest instances
         from oracle import oracle as O
         yy = y.cpu().numpy()

@@ -79,7 +79,26 @@ typedef enum {
 typedef enum { FABM_PATH_AUTO = 0, FABM_PATH_DIRECT = 1, FABM_PATH_BLOCKED = 2 } fabm_path;
 
 /* Arithmetic of the far-history tiles of the BLOCKED path. The weights, the
- * near-diagonal band and the corrector update are always binary64. */
+ * near-diagonal band and the corrector update are always binary64.
+ *   FP64:   binary64 operands and sums.
+ *   FP32:   binary32 operands, binary32 sums over at most one block of
+ *           sources, added into binary64.
+ *   FP16X2: each operand x stored as 2^e (hi + lo), hi and lo binary16 and e
+ *           shared by a lag window or by one block of one history column;
+ *           products hi*hi + hi*lo + lo*hi in binary32 over one block of
+ *           sources, scaled and added into binary64 (shared-grid form only).
+ *
+ * BLOCKED comes in two forms.
+ *   Per trajectory (tile_L 256): each instance's history is cut into blocks
+ *     of 256 rows; every system, LINEAR up to d = 4; far tiles FP64 or FP32.
+ *   Shared grid (tile_L 64): all instances of a call have the same alpha, h
+ *     and N, so the weight tables are shared and the histories of all
+ *     instances form one matrix with a column per (instance, component);
+ *     each block of 64 rows takes its far sums from one Toeplitz-times-history
+ *     product. LINEAR only, any d up to 64; far tiles FP64, FP32 or FP16X2.
+ * The planner takes the shared-grid form for LINEAR plans with d > 4 or
+ * FP16X2; a call to such a plan whose instances differ in alpha, h or N
+ * returns UNSUPPORTED. */
 typedef enum { FABM_FAR_FP64 = 0, FABM_FAR_FP32 = 1, FABM_FAR_FP16X2 = 2 } fabm_far_prec;
 
 typedef struct {
@@ -90,7 +109,9 @@ typedef struct {
     int64_t max_batch;       /* largest batch a call will pass (>= 1) */
     int64_t max_steps;       /* largest N of any instance (>= 1) */
     int64_t max_total_steps; /* largest sum of N over a batch; 0 means max_batch*max_steps */
-    int32_t tile_L;          /* BLOCKED block length, multiple of 64; 0 lets the planner choose */
+    int32_t tile_L;          /* BLOCKED block length: 0 (planner's choice), 256 (per
+                              * trajectory) or 64 (shared grid); other multiples of 64
+                              * are UNSUPPORTED */
     int32_t flags;           /* reserved, must be 0 */
 } fabm_plan_desc;
 
@@ -111,7 +132,8 @@ int32_t fabm_n_params(fabm_system system, int32_t dim);
  * handle and *workspace_bytes (may be NULL) the device workspace size that
  * covers any call within the described maxima. Errors: INVALID_ARG for a
  * null pointer, unknown system, dim out of range, max_* < 1, bad tile_L or
- * nonzero flags; UNSUPPORTED for a far precision the path does not offer. */
+ * nonzero flags; UNSUPPORTED for a far precision, block length or path the
+ * system does not offer (FP16X2 outside LINEAR, DIRECT for LINEAR d > 4). */
 fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *workspace_bytes);
 
 /* Release a plan (host memory only). NULL is ignored. */
@@ -150,6 +172,31 @@ fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace
                              const int64_t *N, const double *y0, const double *params,
                              const int64_t *row_off, double *y_out, int64_t *status,
                              hipStream_t stream);
+
+/* Captured solves (HIP graphs) for callers that replay one solve many times
+ * (serving loops, inner iterations): the launch sequence of one
+ * fabm_solve_batch call (same arguments and checks) is recorded once into a
+ * graph instead of running. Each fabm_graph_launch then runs the whole solve
+ * on `stream`, reading the current contents of y0 and params and overwriting
+ * y_out and status; alpha, h, N, row_off and every device address are fixed
+ * at capture. The graph owns a pinned copy of the per-instance table; the
+ * plan's other calls do not disturb it. The workspace, y0, params, y_out and
+ * status must stay allocated while the graph exists, and no other call may
+ * use that workspace while a launch of the graph is in flight (two launches
+ * in flight on different streams race on it). Captured paths: every path
+ * the plan runs eagerly. Errors: as fabm_solve_batch; DEVICE if capture or
+ * instantiation fails (fabm_last_error names the call). Nothing is
+ * enqueued by fabm_graph_solve_batch itself. */
+typedef struct fabm_graph_s *fabm_graph_t;
+fabm_status fabm_graph_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                                   int64_t batch, const double *alpha, const double *h,
+                                   const int64_t *N, const double *y0, const double *params,
+                                   const int64_t *row_off, double *y_out, int64_t *status,
+                                   fabm_graph_t *out);
+/* Enqueue one run of a captured solve on `stream`. */
+fabm_status fabm_graph_launch(fabm_graph_t graph, hipStream_t stream);
+/* Release a captured solve (after its launches have completed). NULL is ignored. */
+void fabm_graph_destroy(fabm_graph_t graph);
 
 /* Reverse-mode gradients (the discrete adjoint of the scheme above) of
  *   L = sum_i sum_{n=0}^{N_i} < gy_i[n], y_i[n] >
@@ -194,7 +241,9 @@ typedef enum {
                                      near and far windows of one source block */
     FABM_KERNEL_HISTORY = 4,      /* fabm_history_sums contraction */
     FABM_KERNEL_ADJOINT = 5,      /* reverse pass: band plus MFMA windows of one block */
-    FABM_KERNEL_COUNT = 6
+    FABM_KERNEL_WIDE_FAR = 6,     /* shared-grid batch: far sums of one block (matrix cores) */
+    FABM_KERNEL_WIDE_BAND = 7,    /* shared-grid batch: rows of one block, all instances */
+    FABM_KERNEL_COUNT = 8
 } fabm_kernel_class;
 
 /* Instrumentation. While enabled, every solve call of the plan records a pair

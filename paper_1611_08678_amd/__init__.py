@@ -31,8 +31,10 @@ FAR_PRECS = {"fp64": FABM_FAR_FP64, "fp32": FABM_FAR_FP32, "fp16x2": FABM_FAR_FP
 EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan", "fabm_plan_destroy",
            "fabm_workspace_size", "fabm_solve", "fabm_solve_batch", "fabm_weights",
            "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
-           "fabm_plan_kernel_times", "fabm_adjoint", "fabm_adjoint_workspace_size")
-KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint")
+           "fabm_plan_kernel_times", "fabm_adjoint", "fabm_adjoint_workspace_size",
+           "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy")
+KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint",
+                  "wide_far", "wide_band")
 
 
 class FabmError(RuntimeError):
@@ -106,6 +108,13 @@ def load():
     L.fabm_adjoint.restype = C.c_int
     L.fabm_adjoint_workspace_size.argtypes = [_VP, C.c_int64, _I64P, C.POINTER(C.c_size_t)]
     L.fabm_adjoint_workspace_size.restype = C.c_int
+    L.fabm_graph_solve_batch.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP,
+                                         _VP, _I64P, _VP, _VP, C.POINTER(_VP)]
+    L.fabm_graph_solve_batch.restype = C.c_int
+    L.fabm_graph_launch.argtypes = [_VP, _VP]
+    L.fabm_graph_launch.restype = C.c_int
+    L.fabm_graph_destroy.argtypes = [_VP]
+    L.fabm_graph_destroy.restype = None
     _lib = L
     return L
 
@@ -206,6 +215,39 @@ def fabm_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_
                                    _stream(stream)), "fabm_solve_batch")
 
 
+class Graph:
+    """A captured solve (fabm_graph_solve_batch); `launch(stream)` runs it."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep  # the device buffers the graph reads and writes
+
+    def launch(self, stream=None):
+        _check(load().fabm_graph_launch(self.handle, _stream(stream)), "fabm_graph_launch")
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.fabm_graph_destroy(self.handle)
+            self.handle = None
+
+
+def fabm_graph_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out,
+                           status) -> Graph:
+    import numpy as np
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    hh = np.ascontiguousarray(h, dtype=np.float64)
+    Ns = np.ascontiguousarray(N, dtype=np.int64)
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    g = C.c_void_p()
+    _check(load().fabm_graph_solve_batch(plan.handle, _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(), al.size,
+                                         al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
+                                         Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
+                                         ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
+                                         C.byref(g)), "fabm_graph_solve_batch")
+    return Graph(g, (plan, workspace, y0, params, y_out, status))
+
+
 def fabm_adjoint_workspace_size(plan: Plan, N) -> int:
     import numpy as np
     Ns = np.ascontiguousarray(np.atleast_1d(N), dtype=np.int64)
@@ -281,14 +323,14 @@ def _workspace(nbytes: int):
 
 
 def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_prec="fp64",
-          plan: Plan | None = None):
+          plan: Plan | None = None, tile_L: int = 0):
     """One trajectory; returns (y [N+1, d] float64 device tensor, status int)."""
     import torch
     y0 = _dev(y0).reshape(-1)
     th = _dev(theta).reshape(-1)
     d = y0.numel()
     if plan is None:
-        plan = fabm_plan(system, d, path, far_prec, 1, N)
+        plan = fabm_plan(system, d, path, far_prec, 1, N, tile_L=tile_L)
     ws = _workspace(fabm_workspace_size(plan, [N]))
     y = torch.empty((N + 1, d), dtype=torch.float64, device="cuda")
     st = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -297,7 +339,7 @@ def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_pr
 
 
 def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64",
-                plan: Plan | None = None):
+                plan: Plan | None = None, tile_L: int = 0):
     """Ragged batch; returns (y_rows [sum(N+1), d], row_off numpy, status tensor)."""
     import numpy as np
     import torch
@@ -308,7 +350,8 @@ def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64
     row_off = np.zeros(B, dtype=np.int64)
     row_off[1:] = np.cumsum(Ns + 1)[:-1]
     if plan is None:
-        plan = fabm_plan(system, d, path, far_prec, B, int(Ns.max()), int(Ns.sum()))
+        plan = fabm_plan(system, d, path, far_prec, B, int(Ns.max()), int(Ns.sum()),
+                         tile_L=tile_L)
     ws = _workspace(fabm_workspace_size(plan, Ns))
     y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
     st = torch.zeros(B, dtype=torch.int64, device="cuda")

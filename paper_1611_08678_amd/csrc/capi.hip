@@ -15,6 +15,7 @@
 #include "fabm_device.h"
 #include "fabm_launch.h"
 #include "fabm_timer.h"
+#include "fabm_wide.h"
 
 using fabm::InstMeta;
 
@@ -32,6 +33,14 @@ struct fabm_plan_s {
     // schedule of the last batched BLOCKED call, keyed by its block counts
     std::vector<int32_t> sched_nb;
     fabm::BatchSchedule sched;
+};
+
+// A captured solve: its instance table lives in its own pinned buffer, copied
+// by the graph's first node at every launch.
+struct fabm_graph_s {
+    char *stage = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -85,10 +94,20 @@ fabm_status check_alpha_h(double alpha, double h)
     return FABM_OK;
 }
 
-enum class Path { Direct, Blocked, Unsupported };
+enum class Path { Direct, Blocked, Wide, Unsupported };
+
+// LINEAR plans that need the shared-grid form: states wider than the
+// per-trajectory kernels hold in registers, split binary16 far tiles, or its
+// block length asked for explicitly.
+bool wide_plan(const fabm_plan_desc &d)
+{
+    return d.system == FABM_SYS_LINEAR &&
+           (d.dim > 4 || d.far_prec == FABM_FAR_FP16X2 || d.tile_L == fabm::kWideBlk);
+}
 
 Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 {
+    if (wide_plan(pl->desc)) return Path::Wide;
     switch (pl->desc.path) {
     case FABM_PATH_DIRECT: return Path::Direct;
     case FABM_PATH_BLOCKED: return Path::Blocked;
@@ -108,6 +127,9 @@ struct Layout {
     size_t w, w32, f, part, carry, acc, sync, n_sync_words;
     // reverse pass only: forward rows, reversed sources and sums, partials
     size_t yw, ypw, uv, acc_a, carry_a, part_a, fbar0;
+    // shared grid: low binary16 parts, their scales, Toeplitz operand table
+    size_t flo, fexp, t16, t16exp;
+    int64_t cp;    // shared grid: padded history columns
     size_t total;
     int64_t wlen;  // single-trajectory BLOCKED: weight table length
     int NB;        // single-trajectory BLOCKED: blocks
@@ -201,6 +223,40 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
             L.fbar0 = off;
             off = align_up(off + sizeof(double) * d * (size_t)batch);
         }
+    } else if (L.path == Path::Wide) {
+        int64_t maxN = 1;
+        for (int64_t i = 0; i < batch; ++i) maxN = std::max(maxN, N[i]);
+        const int Lb = fabm::kWideBlk;
+        L.NB = (int)((maxN + 1 + Lb - 1) / Lb);
+        L.wlen = (int64_t)L.NB * Lb + Lb;
+        L.cp = (batch * d + fabm::kWideColAlign - 1) / fabm::kWideColAlign * fabm::kWideColAlign;
+        const size_t cells = (size_t)L.NB * Lb * (size_t)L.cp;  // history rows x columns
+        const fabm_far_prec fp = pl->desc.far_prec;
+        L.stage_bytes = off;
+        off = align_up(off);
+        L.w = off;
+        off = align_up(off + sizeof(double) * 3 * (size_t)L.wlen);
+        L.w32 = off;
+        if (fp == FABM_FAR_FP32) off = align_up(off + sizeof(float) * 2 * (size_t)L.wlen);
+        L.f = off;  // the history copy the far product reads: [rows][cp]
+        off = align_up(off + (fp == FABM_FAR_FP64 ? 8 : fp == FABM_FAR_FP32 ? 4 : 2) * cells);
+        L.flo = L.fexp = L.t16 = L.t16exp = off;
+        if (fp == FABM_FAR_FP16X2) {
+            L.flo = off;
+            off = align_up(off + 2 * cells);
+            L.fexp = off;
+            off = align_up(off + sizeof(int32_t) * (size_t)L.NB * (size_t)L.cp);
+            L.t16 = off;
+            off = align_up(off + fabm::wide_t16_bytes(L.NB));
+            L.t16exp = off;
+            off = align_up(off + sizeof(int32_t) * 2 * (size_t)L.NB);
+        }
+        L.part = off;  // far sums of one block, per split
+        off = align_up(off + sizeof(double) * (size_t)fabm::wide_max_splits((int)L.cp, L.NB) * 2 *
+                                 Lb * (size_t)L.cp);
+        L.sync = off;  // first non-finite row of each instance
+        L.n_sync_words = (size_t)std::max<int64_t>(64, batch);
+        off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
     } else if (L.path == Path::Blocked) {
         const int Lb = fabm::step_block_len();
         L.NB = blocks_of(N[0]);
@@ -315,12 +371,12 @@ fabm_status stage_copy(fabm_plan_s *pl, size_t bytes, void *dst, hipStream_t s)
 
 // Per-instance placement, order and far-workgroup table of a batched BLOCKED
 // call, written into the staging buffer.
-const fabm::BatchSchedule &stage_batch(fabm_plan_s *pl, const Layout &L, int64_t batch,
-                                       const int64_t *N)
+const fabm::BatchSchedule &stage_batch(fabm_plan_s *pl, char *stage, const Layout &L,
+                                       int64_t batch, const int64_t *N)
 {
     const int d = pl->desc.dim;
     const fabm::BatchSchedule &BS = batch_schedule_for(pl, batch, N);
-    fabm::BlkInst *hi = (fabm::BlkInst *)(pl->h_stage + L.inst);
+    fabm::BlkInst *hi = (fabm::BlkInst *)(stage + L.inst);
     int64_t fo = 0, ao = 0;
     for (int64_t i = 0; i < batch; ++i) {
         const int nb = blocks_of(N[i]);
@@ -328,34 +384,47 @@ const fabm::BatchSchedule &stage_batch(fabm_plan_s *pl, const Layout &L, int64_t
         fo += (int64_t)d * nb * fabm::step_block_len();
         ao += (int64_t)2 * d * nb * fabm::step_block_len();
     }
-    std::memcpy(pl->h_stage + L.order, BS.order.data(), sizeof(int) * BS.order.size());
-    std::memcpy(pl->h_stage + L.far_off, BS.far_off.data(), sizeof(int) * BS.far_off.size());
+    std::memcpy(stage + L.order, BS.order.data(), sizeof(int) * BS.order.size());
+    std::memcpy(stage + L.far_off, BS.far_off.data(), sizeof(int) * BS.far_off.size());
     return BS;
 }
 
-// Shared body of fabm_solve and fabm_solve_batch after validation.
+// Shared body of fabm_solve, fabm_solve_batch and fabm_graph_solve_batch after
+// validation. `graph_stage` (graph builds only) is a pinned buffer owned by the
+// graph: the instance table is written there and its copy becomes a node of
+// the graph; otherwise the plan's staging buffer is used and guarded by an
+// event.
 fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *alpha,
                       const double *h, const int64_t *N, const double *y0, const double *params,
-                      const int64_t *row_off, double *y_out, int64_t *status, hipStream_t s)
+                      const int64_t *row_off, double *y_out, int64_t *status, hipStream_t s,
+                      char *graph_stage = nullptr)
 {
     const int d = pl->desc.dim;
     const Layout L = layout_for(pl, batch, N);
     if (L.path == Path::Unsupported) return FABM_ERR_UNSUPPORTED;
+    if (L.path == Path::Wide)
+        for (int64_t i = 1; i < batch; ++i)
+            if (alpha[i] != alpha[0] || h[i] != h[0] || N[i] != N[0]) return FABM_ERR_UNSUPPORTED;
     fabm_status st = ensure_device(pl);
     if (st != FABM_OK) return st;
-    if ((st = wait_staging(pl)) != FABM_OK) return st;
-    if ((st = ensure_stage(pl, L.stage_bytes)) != FABM_OK) return st;
+    if (!graph_stage) {
+        if ((st = wait_staging(pl)) != FABM_OK) return st;
+        if ((st = ensure_stage(pl, L.stage_bytes)) != FABM_OK) return st;
+    }
+    char *stage = graph_stage ? graph_stage : pl->h_stage;
 
-    InstMeta *hm = (InstMeta *)(pl->h_stage + L.meta);
+    InstMeta *hm = (InstMeta *)(stage + L.meta);
     int64_t w_off = 0, f_off = 0, maxw = 0;
     for (int64_t i = 0; i < batch; ++i) {
         InstMeta &m = hm[i];
         host_scalars(alpha[i], h[i], m);
         m.N = N[i];
         m.row_off = row_off ? row_off[i] : 0;
-        m.wlen = L.path != Path::Blocked ? N[i]
-                 : (batch == 1 ? L.wlen : (int64_t)blocks_of(N[i]) * fabm::step_block_len() +
-                                              fabm::step_block_len());
+        m.wlen = L.path == Path::Wide ? L.wlen
+                 : L.path != Path::Blocked
+                     ? N[i]
+                     : (batch == 1 ? L.wlen : (int64_t)blocks_of(N[i]) * fabm::step_block_len() +
+                                                  fabm::step_block_len());
         m.w_off = w_off;
         m.p_off = (int64_t)pl->n_params * i;
         m.f_off = f_off;
@@ -365,24 +434,64 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     }
     char *base = (char *)ws;
     const fabm::BatchSchedule *BS = nullptr;
-    if (L.path == Path::Blocked && batch > 1) BS = &stage_batch(pl, L, batch, N);
-    if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
+    if (L.path == Path::Blocked && batch > 1) BS = &stage_batch(pl, stage, L, batch, N);
+    if (graph_stage)
+        HIP_TRY(hipMemcpyAsync(base, graph_stage, L.stage_bytes, hipMemcpyHostToDevice, s));
+    else if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK)
+        return st;
 
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
     double *W = (double *)(base + L.w);
     uint32_t *sync = (uint32_t *)(base + L.sync);
-    fabm::KernelTimer *T = pl->timer.on ? &pl->timer : nullptr;
+    fabm::KernelTimer *T = pl->timer.on && !graph_stage ? &pl->timer : nullptr;
     if (T) T->reset();
     if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
-    const bool f32 = L.path == Path::Blocked && pl->desc.far_prec == FABM_FAR_FP32;
+    const bool f32 = (L.path == Path::Blocked || L.path == Path::Wide) &&
+                     pl->desc.far_prec == FABM_FAR_FP32;
     float *W32 = f32 ? (float *)(base + L.w32) : nullptr;
-    if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s, W32))) != FABM_OK)
+    // the shared grid has one weight table, that of instance 0
+    if ((st = ok_or_device(fabm::launch_weights(dmeta, L.path == Path::Wide ? 1 : batch, maxw, W,
+                                                s, W32))) != FABM_OK)
         return st;
     if (T) HIP_TRY(T->end(s));
     if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
         FABM_OK)
         return st;
     double *Yi = y_out + (row_off ? row_off[0] : 0) * d;  // single-trajectory kernels
+
+    if (L.path == Path::Wide) {
+        fabm::WideArgs A{};
+        A.meta = dmeta;
+        A.params = params;
+        A.y0 = y0;
+        A.Y = y_out;
+        A.W = W;
+        A.W32 = W32;
+        const fabm_far_prec fp = pl->desc.far_prec;
+        A.prec = fp == FABM_FAR_FP64 ? fabm::WIDE_F64
+                 : fp == FABM_FAR_FP32 ? fabm::WIDE_F32 : fabm::WIDE_F16X2;
+        if (A.prec == fabm::WIDE_F64) A.F = (double *)(base + L.f);
+        if (A.prec == fabm::WIDE_F32) A.F32 = (float *)(base + L.f);
+        if (A.prec == fabm::WIDE_F16X2) {
+            A.Fhi = (_Float16 *)(base + L.f);
+            A.Flo = (_Float16 *)(base + L.flo);
+            A.Fexp = (int32_t *)(base + L.fexp);
+            A.T16 = (const _Float16 *)(base + L.t16);
+            A.T16exp = (const int32_t *)(base + L.t16exp);
+        }
+        A.part = (double *)(base + L.part);
+        A.dead = sync;
+        A.status = status;
+        A.batch = batch;
+        A.wlen = L.wlen;
+        A.d = d;
+        A.cp = (int)L.cp;
+        A.NB = L.NB;
+        const char *where = "";
+        const hipError_t pe = fabm::enqueue_wide(A, s, T, &where);
+        if (pe != hipSuccess) return record_hip(where, pe);
+        return FABM_OK;
+    }
 
     if (L.path == Path::Blocked && batch > 1) {
         fabm::BatchArgs A{};
@@ -473,7 +582,7 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
         f_off += N[i] + 1;
         maxw = std::max(maxw, m.wlen);
     }
-    const fabm::BatchSchedule &BS = stage_batch(pl, L, batch, N);
+    const fabm::BatchSchedule &BS = stage_batch(pl, pl->h_stage, L, batch, N);
     char *base = (char *)ws;
     if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
@@ -592,13 +701,15 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     if (desc->far_prec != FABM_FAR_FP64 && desc->far_prec != FABM_FAR_FP32 &&
         desc->far_prec != FABM_FAR_FP16X2)
         return FABM_ERR_INVALID_ARG;
-    // far windows run in FP64 or FP32 (split FP16 is not offered); the block
-    // length is fixed
-    if (desc->far_prec == FABM_FAR_FP16X2) return FABM_ERR_UNSUPPORTED;
-    if (desc->tile_L != 0 && desc->tile_L != fabm::step_block_len())
+    // split binary16 far tiles and the 64-row blocks exist in the shared-grid
+    // form only (LINEAR); the per-trajectory kernels keep the state in
+    // registers (LINEAR up to d = 4) and use 256-row blocks
+    const bool wide = wide_plan(*desc);
+    if (desc->far_prec == FABM_FAR_FP16X2 && desc->system != FABM_SYS_LINEAR)
         return FABM_ERR_UNSUPPORTED;
-    // kernels keep the state in registers: LINEAR up to d = 4
-    if (desc->system == FABM_SYS_LINEAR && desc->dim > 4) return FABM_ERR_UNSUPPORTED;
+    if (desc->tile_L != 0 && desc->tile_L != (wide ? fabm::kWideBlk : fabm::step_block_len()))
+        return FABM_ERR_UNSUPPORTED;
+    if (wide && desc->path == FABM_PATH_DIRECT) return FABM_ERR_UNSUPPORTED;
 
     fabm_plan_s *pl = new (std::nothrow) fabm_plan_s();
     if (!pl) return FABM_ERR_INVALID_ARG;
@@ -678,6 +789,74 @@ fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace
     if (workspace_bytes < L.total) return FABM_ERR_WORKSPACE;
     return run_solve(plan, workspace, batch, alpha, h, N, y0, params, row_off, y_out, status,
                      stream);
+}
+
+fabm_status fabm_graph_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                                   int64_t batch, const double *alpha, const double *h,
+                                   const int64_t *N, const double *y0, const double *params,
+                                   const int64_t *row_off, double *y_out, int64_t *status,
+                                   fabm_graph_t *out)
+{
+    if (!out) return FABM_ERR_INVALID_ARG;
+    *out = nullptr;
+    fabm_status st = check_batch(plan, batch, alpha, h, N, row_off);
+    if (st != FABM_OK) return st;
+    if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && !aligned8(params)) return FABM_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
+    const Layout L = layout_for(plan, batch, N);
+    if (L.path == Path::Unsupported) return FABM_ERR_UNSUPPORTED;
+    if (workspace_bytes < L.total) return FABM_ERR_WORKSPACE;
+    if (L.path == Path::Wide)
+        for (int64_t i = 1; i < batch; ++i)
+            if (alpha[i] != alpha[0] || h[i] != h[0] || N[i] != N[0]) return FABM_ERR_UNSUPPORTED;
+    if ((st = ensure_device(plan)) != FABM_OK) return st;
+
+    fabm_graph_s *g = new (std::nothrow) fabm_graph_s();
+    if (!g) return FABM_ERR_DEVICE;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipHostMalloc((void **)&g->stage, std::max<size_t>(L.stage_bytes, 64),
+                                 hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        st = record_hip("fabm_graph_solve_batch: staging or stream", e);
+    } else if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+        st = record_hip("hipStreamBeginCapture", e);
+    } else {
+        st = run_solve(plan, workspace, batch, alpha, h, N, y0, params, row_off, y_out, status,
+                       cs, g->stage);
+        // the capture is ended whatever happened inside it
+        e = hipStreamEndCapture(cs, &graph);
+        if (st == FABM_OK && e != hipSuccess) st = record_hip("hipStreamEndCapture", e);
+        if (st == FABM_OK) {
+            e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) st = record_hip("hipGraphInstantiate", e);
+        }
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    g->graph = graph;
+    if (st != FABM_OK) {
+        fabm_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return FABM_OK;
+}
+
+fabm_status fabm_graph_launch(fabm_graph_t graph, hipStream_t stream)
+{
+    if (!graph || !graph->exec) return FABM_ERR_INVALID_ARG;
+    return record_hip("hipGraphLaunch", hipGraphLaunch(graph->exec, stream));
+}
+
+void fabm_graph_destroy(fabm_graph_t graph)
+{
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    if (graph->stage) (void)hipHostFree(graph->stage);
+    delete graph;
 }
 
 fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *N,

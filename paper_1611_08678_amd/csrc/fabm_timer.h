@@ -17,7 +17,9 @@ enum : int {
     KC_BLOCKED_STEP = 3,
     KC_HISTORY = 4,
     KC_ADJOINT = 5,
-    KC_COUNT = 6
+    KC_WIDE_FAR = 6,
+    KC_WIDE_BAND = 7,
+    KC_COUNT = 8
 };
 
 struct KernelTimer {

@@ -102,3 +102,52 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(F, "SO", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         F.load()
+
+
+def test_plan_shared_grid_rules(fabm):
+    fabm.fabm_plan("linear", 64, "blocked", "fp64", 512, 1 << 16)
+    fabm.fabm_plan("linear", 64, "auto", "fp16x2", 512, 1 << 16)
+    fabm.fabm_plan("linear", 3, "blocked", "fp64", 4, 1000, tile_L=64)
+    for kw in (dict(system="chen", dim=3, far_prec="fp16x2"),
+               dict(system="linear", dim=64, path="direct"),
+               dict(system="chen", dim=3, tile_L=64),
+               dict(system="linear", dim=64, tile_L=256),
+               dict(system="linear", dim=3, tile_L=128)):
+        with pytest.raises(fabm.FabmError) as e:
+            fabm.fabm_plan(**kw)
+        assert e.value.code == 2, kw
+
+
+def test_shared_grid_workspace(fabm):
+    N = 1 << 16
+    sizes = {}
+    for prec in ("fp64", "fp32", "fp16x2"):
+        p = fabm.fabm_plan("linear", 64, "blocked", prec, 512, N, 512 * N)
+        sizes[prec] = fabm.fabm_workspace_size(p, [N] * 512)
+        assert sizes[prec] <= p.workspace_bytes
+    # one history copy of ceil((N+1)/64)*64 rows x 32768 columns: binary64,
+    # binary32, or two binary16 parts
+    cells = 1025 * 64 * 32768
+    assert sizes["fp64"] >= 8 * cells and sizes["fp32"] >= 4 * cells
+    assert sizes["fp16x2"] >= 4 * cells and sizes["fp32"] < sizes["fp64"]
+
+
+def test_shared_grid_needs_shared_alpha_h_N(fabm):
+    """Checked on the host before any device work (placeholder device
+    addresses are never touched)."""
+    import ctypes as C
+    import numpy as np
+    p = fabm.fabm_plan("linear", 8, "blocked", "fp64", 3, 100, 300)
+    ws = p.workspace_bytes
+    fake = C.c_void_p(1 << 40)  # 256-byte aligned placeholder
+    for al, hh, Ns in (([0.8, 0.7, 0.8], [0.01] * 3, [100] * 3),
+                       ([0.8] * 3, [0.01, 0.01, 0.02], [100] * 3),
+                       ([0.8] * 3, [0.01] * 3, [100, 99, 100])):
+        al, hh = np.asarray(al, float), np.asarray(hh, float)
+        Ns = np.asarray(Ns, np.int64)
+        ro = np.concatenate([[0], np.cumsum(Ns + 1)[:-1]]).astype(np.int64)
+        lib = fabm.load()
+        code = lib.fabm_solve_batch(p.handle, fake, ws, 3, al.ctypes.data_as(fabm._DP),
+                                    hh.ctypes.data_as(fabm._DP), Ns.ctypes.data_as(fabm._I64P),
+                                    fake, fake, ro.ctypes.data_as(fabm._I64P), fake, fake, None)
+        assert code == 2
