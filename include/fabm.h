@@ -184,9 +184,11 @@ fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace
  * status must stay allocated while the graph exists, and no other call may
  * use that workspace while a launch of the graph is in flight (two launches
  * in flight on different streams race on it). Captured paths: every path
- * the plan runs eagerly. Errors: as fabm_solve_batch; DEVICE if capture or
- * instantiation fails (fabm_last_error names the call). Nothing is
- * enqueued by fabm_graph_solve_batch itself. */
+ * the plan runs eagerly except the whole-GPU DIRECT kernel of a single
+ * trajectory with N >= 8192 (a cooperative launch: UNSUPPORTED). Errors: as
+ * fabm_solve_batch; DEVICE if capture or instantiation fails
+ * (fabm_last_error names the call). Nothing is enqueued by
+ * fabm_graph_solve_batch itself. */
 typedef struct fabm_graph_s *fabm_graph_t;
 fabm_status fabm_graph_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
                                    int64_t batch, const double *alpha, const double *h,

@@ -810,6 +810,10 @@ fabm_status fabm_graph_solve_batch(fabm_plan_t plan, void *workspace, size_t wor
     if (L.path == Path::Wide)
         for (int64_t i = 1; i < batch; ++i)
             if (alpha[i] != alpha[0] || h[i] != h[0] || N[i] != N[0]) return FABM_ERR_UNSUPPORTED;
+    // the whole-GPU DIRECT kernel relies on a cooperative launch (all
+    // workgroups resident at once), which is not recorded into graphs here
+    if (L.path == Path::Direct && batch == 1 && N[0] >= kGridDirectMinSteps)
+        return FABM_ERR_UNSUPPORTED;
     if ((st = ensure_device(plan)) != FABM_OK) return st;
 
     fabm_graph_s *g = new (std::nothrow) fabm_graph_s();

@@ -1,0 +1,82 @@
+"""Captured solves (fabm_graph_solve_batch / fabm_graph_launch): one graph per
+path replays the whole solve. Between replays the program does its own eager
+work (new y0 written in place) and synchronises; every replay must equal an
+eager solve of the same inputs bitwise (the kernels are deterministic)."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.test_gpu_direct import _to_np
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1611_08678_amd as F
+    F.load()
+    return F
+
+
+def _case(name):
+    rng = np.random.default_rng(21)
+    if name == "batch_blocked_fp32":  # per-trajectory blocks, ragged, per-instance alpha
+        B = 6
+        Ns = np.array([100, 1500, 1, 256, 700, 999])
+        return ("rossler", np.tile([0.2, 0.2, 5.7], (B, 1)), rng.uniform(0.9, 1.0, B),
+                np.full(B, 0.005), Ns, rng.uniform(-5, 5, (B, 3)), "blocked", "fp32")
+    if name == "single_blocked":
+        return ("chen", np.array([[35.0, 3.0, 28.0]]), np.array([0.95]), np.array([0.001]),
+                np.array([3000]), np.array([[-9.0, -5.0, 14.0]]), "blocked", "fp64")
+    if name == "batch_direct":
+        B = 4
+        return ("vdp", rng.uniform(0.5, 2, (B, 1)), np.full(B, 0.9), np.full(B, 0.01),
+                np.array([500, 20, 333, 800]), rng.uniform(-2, 2, (B, 2)), "direct", "fp64")
+    B, d = 4, 16  # shared grid, split binary16 far tiles
+    A = -(2 * np.eye(d)[None] + rng.standard_normal((B, d, d)) / 8)
+    th = np.concatenate([A.reshape(B, -1), 0.1 * rng.standard_normal((B, 2 * d))], axis=1)
+    return ("linear", th, np.full(B, 0.8), np.full(B, 0.01), np.full(B, 600),
+            rng.standard_normal((B, d)), "blocked", "fp16x2")
+
+
+@pytest.mark.parametrize("name", ["batch_blocked_fp32", "single_blocked", "batch_direct",
+                                  "shared_grid_fp16x2"])
+def test_graph_replays_match_eager(F, name):
+    import torch
+    system, th, al, hs, Ns, y0s, path, prec = _case(name)
+    B, d = y0s.shape
+    plan = F.fabm_plan(system, d, path, prec, B, int(Ns.max()), int(Ns.sum()))
+    ws = F._workspace(F.fabm_workspace_size(plan, Ns))
+    row_off = np.concatenate([[0], np.cumsum(Ns + 1)[:-1]]).astype(np.int64)
+    y0 = torch.tensor(y0s, device="cuda")
+    thd = torch.tensor(th, device="cuda")
+    y = torch.full((int((Ns + 1).sum()), d), -7.0, dtype=torch.float64, device="cuda")
+    st = torch.full((B,), -3, dtype=torch.int64, device="cuda")
+    g = F.fabm_graph_solve_batch(plan, ws, al, hs, Ns, y0, thd, row_off, y, st)
+    torch.cuda.synchronize()
+    assert torch.all(y == -7.0)  # building the graph runs nothing
+    for rep in range(3):
+        y0.copy_(torch.tensor(y0s * (1.0 + 0.03 * rep), device="cuda"))
+        g.launch()
+        torch.cuda.synchronize()
+        got, gst = y.clone(), st.clone()
+        ref, _, rst = F.solve_batch(system, thd, al, hs, Ns, y0, path=path, far_prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(gst, rst), (rep, _to_np(gst), _to_np(rst))
+        assert torch.equal(got, ref), rep
+    del g
+    torch.cuda.synchronize()
+
+
+def test_graph_refuses_cooperative_direct(F):
+    plan = F.fabm_plan("vdp", 2, "direct", "fp64", 1, 10000)
+    import torch
+    ws = F._workspace(F.fabm_workspace_size(plan, [10000]))
+    y0 = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    th = torch.ones((1, 1), dtype=torch.float64, device="cuda")
+    y = torch.empty((10001, 2), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(F.FabmError) as e:
+        F.fabm_graph_solve_batch(plan, ws, [0.9], [0.01], [10000], y0, th, [0], y, st)
+    assert e.value.code == 2
