@@ -4,9 +4,9 @@
 // source block I (lag block q = s - I >= 1) the 64 x 64 Toeplitz tile has
 // entries w[q*64 + r - 1 - k], r the target row and k the source row inside
 // their blocks: every entry comes from the 127-lag window
-// w[(q-1)*64 .. (q+1)*64 - 2]. A workgroup owns 64 (FP64, FP32) or 128
-// (FP16X2) history columns and all 64 target rows; wavefront w owns 16 or 32
-// of those columns and accumulates four 16-row tiles per weight table. The
+// w[(q-1)*64 .. (q+1)*64 - 2]. A workgroup owns 64 history columns and all 64
+// target rows; wavefront w owns 16 of those columns and accumulates four
+// 16-row tiles per weight table. The
 // Toeplitz tile is the A operand (read out of the window staged in LDS), the
 // history the B operand (read straight from HBM, each value once per
 // workgroup).
@@ -238,6 +238,12 @@ __global__ __launch_bounds__(256) void k_wide_t16(WideArgs A, _Float16 *T16, int
     }
 }
 
+// One wavefront: 16 columns, four 16-row tiles per table. Within a source
+// block the A operand of row tile rt and k-slice ks depends on rt - 2 ks only
+// (the window start moves by 16 per row tile and by 32 per k-slice), so six
+// operand pairs serve the eight (rt, ks) tiles; consecutive products go to
+// different accumulators. The next block's history operands are loaded while
+// the current block is multiplied.
 __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int splits)
 {
     __shared__ half8 sT[2][kT16Q / 8];  // [buffer][table, part, copy, entry / 8]
@@ -246,22 +252,34 @@ __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int spl
     int I0, I1;
     split_range(s, blockIdx.y, splits, I0, I1);
     const int64_t cp = A.cp;
-    const int64_t c0 = (int64_t)blockIdx.x * 128 + wave * 32 + sig;  // column of ct = 0
+    const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + sig;
     const int shift = (7 - sig) & 7;  // copy holding this lane's operands aligned
 
-    dbl4 acc[2][2][4];  // [ct][table][rt]
+    dbl4 acc[2][4];  // [table][rt]
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+    for (int tb = 0; tb < 2; ++tb)
 #pragma unroll
-        for (int tb = 0; tb < 2; ++tb)
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) acc[ct][tb][rt] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int rt = 0; rt < 4; ++rt) acc[tb][rt] = dbl4{0.0, 0.0, 0.0, 0.0};
 
     const half8 *T16 = (const half8 *)A.T16;
     const half8 *Fh = (const half8 *)A.Fhi, *Fl = (const half8 *)A.Flo;
+    // history operands of one block: rows 32 ks + 8 (l/16) .. +7 of this column
+    half8 bh[2], bl[2], nh[2], nl[2];
+    int ef = 0, nef = 0;
+    auto load_b = [&](int I, half8 (&h)[2], half8 (&l)[2], int &e) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int64_t o = ((int64_t)I * (LW / 8) + 4 * ks + g) * cp + col;
+            h[ks] = Fh[o];
+            l[ks] = Fl[o];
+        }
+        e = A.Fexp[(int64_t)I * cp + col];
+    };
     if (I0 < I1) {
         const half8 *src = T16 + (int64_t)(s - I0) * (kT16Q / 8);
-        for (int e = tid; e < kT16Q / 8; e += 256) sT[0][e] = src[e];
+        sT[0][tid] = src[tid];
+        sT[0][tid + 256] = src[tid + 256];
+        load_b(I0, bh, bl, ef);
     }
     __syncthreads();
     for (int I = I0; I < I1; ++I) {
@@ -273,69 +291,61 @@ __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int spl
             const half8 *src = T16 + (int64_t)(q - 1) * (kT16Q / 8);
             tnext[0] = src[tid];
             tnext[1] = src[tid + 256];
+            load_b(I + 1, nh, nl, nef);
         }
-        // history operands of this block: 8 consecutive rows of one column
-        half8 bh[2][2], bl[2][2];  // [ks][ct]
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-                const int64_t e = ((int64_t)I * (LW / 8) + 4 * ks + g) * cp + c0 + 16 * ct;
-                bh[ks][ct] = Fh[e];
-                bl[ks][ct] = Fl[e];
-            }
-        int ef[2];
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) ef[ct] = A.Fexp[(int64_t)I * cp + c0 + 16 * ct];
         const int ew0 = A.T16exp[q * 2 + 0], ew1 = A.T16exp[q * 2 + 1];
-        flt4 c32[2][2][4];
+        flt4 c32[2][4];
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int tb = 0; tb < 2; ++tb)
 #pragma unroll
-            for (int tb = 0; tb < 2; ++tb)
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt) c32[ct][tb][rt] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int rt = 0; rt < 4; ++rt) c32[tb][rt] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
         const half8 *tw = sT[buf];
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const int u0 = LW - 1 - 16 * rt - sig + 32 * ks + 8 * g;
-                const int m8 = (u0 - shift) >> 3;
-#pragma unroll
-                for (int tb = 0; tb < 2; ++tb) {
-                    const half8 ah = tw[((tb * 2 + 0) * 8 + shift) * (kT16Row / 8) + m8];
-                    const half8 al = tw[((tb * 2 + 1) * 8 + shift) * (kT16Row / 8) + m8];
-#pragma unroll
-                    for (int ct = 0; ct < 2; ++ct) {
-                        flt4 c = c32[ct][tb][rt];
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[ks][ct], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[ks][ct], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[ks][ct], c, 0, 0, 0);
-                        c32[ct][tb][rt] = c;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int j = -2; j <= 3; ++j) {  // j = rt - 2 ks
+            const int u0 = LW - 1 - 16 * j - sig + 8 * g;
+            const int m8 = (u0 - shift) >> 3;
+            half8 ah[2], al[2];
 #pragma unroll
             for (int tb = 0; tb < 2; ++tb) {
-                const double sc = ldexp(1.0, (tb ? ew1 : ew0) + ef[ct]);
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        acc[ct][tb][rt][v] = fma((double)c32[ct][tb][rt][v], sc, acc[ct][tb][rt][v]);
+                ah[tb] = tw[((tb * 2 + 0) * 8 + shift) * (kT16Row / 8) + m8];
+                al[tb] = tw[((tb * 2 + 1) * 8 + shift) * (kT16Row / 8) + m8];
             }
+#pragma unroll
+            for (int prod = 0; prod < 3; ++prod)
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int rt = j + 2 * ks;
+                    if (rt < 0 || rt > 3) continue;
+#pragma unroll
+                    for (int tb = 0; tb < 2; ++tb) {
+                        const half8 a = prod == 2 ? al[tb] : ah[tb];
+                        const half8 b = prod == 1 ? bl[ks] : bh[ks];
+                        c32[tb][rt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c32[tb][rt], 0, 0, 0);
+                    }
+                }
+        }
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+            const double sc = ldexp(1.0, (tb ? ew1 : ew0) + ef);
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[tb][rt][v] = fma((double)c32[tb][rt][v], sc, acc[tb][rt][v]);
+        }
         if (more) {
             sT[buf ^ 1][tid] = tnext[0];
             sT[buf ^ 1][tid + 256] = tnext[1];
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                bh[ks] = nh[ks];
+                bl[ks] = nl[ks];
+            }
+            ef = nef;
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) store_tiles<true>(A, blockIdx.y, c0 + 16 * ct, acc[ct]);
+    store_tiles<true>(A, blockIdx.y, col, acc);
 }
 
 // Split partials summed into split 0, in split order.
@@ -491,7 +501,7 @@ __global__ void k_wide_status(const uint32_t *dead, int64_t *status, int64_t bat
     if (i < batch) status[i] = (int64_t)dead[i];
 }
 
-int cols_per_wg(int prec) { return prec == WIDE_F16X2 ? 128 : 64; }
+int cols_per_wg(int) { return 64; }
 
 int splits_for(int cp, int prec, int s)
 {
