@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the benchmark "
                          "(untimed; a reference kernel of known traffic for hardware counters)")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch workloads: run fabm_tune on the plan before timing (untimed)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
                     help="far-window arithmetic (default: fp64; rossler_batch: fp32; "
                          "fp16x2 only for linear64_batch)")
@@ -181,6 +183,10 @@ def bench_batch(F, W, args):
     y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
     st = torch.zeros(B, dtype=torch.int64, device="cuda")
     call = lambda: F.fabm_solve_batch(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
+    tune = None
+    if args.tune:
+        tune = F.fabm_tune(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
+        print(f"# tune: {tune}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         call()
     torch.cuda.synchronize()
@@ -214,6 +220,7 @@ def bench_batch(F, W, args):
                       "N_max": int(Ns.max()), "far_prec": prec},
            "history_gflops": flops / t / 1e9,
            "status_nonzero": int((st.cpu().numpy() != 0).sum()),
+           "tune": tune,
            "kernel_times_s": {k: v[0] for k, v in kt.items()},
            "kernel_launches": {k: v[1] for k, v in kt.items()}}
     if "blocked_step" in kt:

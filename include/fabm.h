@@ -200,6 +200,33 @@ fabm_status fabm_graph_launch(fabm_graph_t graph, hipStream_t stream);
 /* Release a captured solve (after its launches have completed). NULL is ignored. */
 void fabm_graph_destroy(fabm_graph_t graph);
 
+/* Autotuner. Runs the solve described by the arguments (same arguments and
+ * checks as fabm_solve_batch; y_out and status receive a valid result) once
+ * untimed and then once per candidate launch shape of the plan's path, times
+ * each with events on `stream`, and keeps the fastest in the plan for its
+ * later calls. Blocks the host until the runs end. Results of a plan differ
+ * between launch shapes by rounding only (the summation order of the far
+ * sums changes); a tuned plan is bitwise deterministic.
+ *   single-trajectory BLOCKED: far workgroups per step launch {32, 64, 128, 254}
+ *   shared grid: far workgroups a launch aims for {256, 512, 1024, 2048, 4096}
+ *                (the source range of a block is split until the column tiles
+ *                times the splits reach it, at most 64 splits)
+ *   other paths: nothing to choose (knob NONE).
+ * report (host, may be NULL) receives the candidates, their times and the
+ * index chosen. */
+typedef enum { FABM_TUNE_NONE = 0, FABM_TUNE_FAR_WORKGROUPS = 1, FABM_TUNE_SPLIT_TARGET = 2 } fabm_tune_knob;
+typedef struct {
+    int32_t knob;       /* fabm_tune_knob */
+    int32_t n;          /* candidates timed */
+    int32_t value[8];   /* candidate values */
+    double seconds[8];  /* solve time of each candidate */
+    int32_t chosen;     /* index of the value kept */
+} fabm_tune_report;
+fabm_status fabm_tune(fabm_plan_t plan, void *workspace, size_t workspace_bytes, int64_t batch,
+                      const double *alpha, const double *h, const int64_t *N, const double *y0,
+                      const double *params, const int64_t *row_off, double *y_out,
+                      int64_t *status, hipStream_t stream, fabm_tune_report *report);
+
 /* Reverse-mode gradients (the discrete adjoint of the scheme above) of
  *   L = sum_i sum_{n=0}^{N_i} < gy_i[n], y_i[n] >
  * with respect to y0 and theta of every instance (batch = 1 for a single

@@ -32,7 +32,7 @@ EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan"
            "fabm_workspace_size", "fabm_solve", "fabm_solve_batch", "fabm_weights",
            "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
            "fabm_plan_kernel_times", "fabm_adjoint", "fabm_adjoint_workspace_size",
-           "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy")
+           "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy", "fabm_tune")
 KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint",
                   "wide_far", "wide_band")
 
@@ -115,6 +115,9 @@ def load():
     L.fabm_graph_launch.restype = C.c_int
     L.fabm_graph_destroy.argtypes = [_VP]
     L.fabm_graph_destroy.restype = None
+    L.fabm_tune.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP, _VP, _I64P,
+                            _VP, _VP, _VP, C.POINTER(_TuneReport)]
+    L.fabm_tune.restype = C.c_int
     _lib = L
     return L
 
@@ -213,6 +216,34 @@ def fabm_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_
                                    Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                                    ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
                                    _stream(stream)), "fabm_solve_batch")
+
+
+class _TuneReport(C.Structure):
+    _fields_ = [("knob", C.c_int32), ("n", C.c_int32), ("value", C.c_int32 * 8),
+                ("seconds", C.c_double * 8), ("chosen", C.c_int32)]
+
+
+TUNE_KNOBS = ("none", "far_workgroups", "split_target")
+
+
+def fabm_tune(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out, status,
+              stream=None) -> dict:
+    """Autotune the plan's launch shape on these inputs (see fabm.h); returns
+    {"knob", "candidates", "seconds", "chosen"}."""
+    import numpy as np
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    hh = np.ascontiguousarray(h, dtype=np.float64)
+    Ns = np.ascontiguousarray(N, dtype=np.int64)
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    rep = _TuneReport()
+    _check(load().fabm_tune(plan.handle, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                            al.size, al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
+                            Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
+                            ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status), _stream(stream),
+                            C.byref(rep)), "fabm_tune")
+    n = rep.n
+    return {"knob": TUNE_KNOBS[rep.knob], "candidates": list(rep.value[:n]),
+            "seconds": list(rep.seconds[:n]), "chosen": rep.chosen if n else None}
 
 
 class Graph:

@@ -742,7 +742,10 @@ size_t step_smem_bytes(int d)
 
 // Grid of launch s: band, near and far workgroups, and the number of active
 // wavefronts per far workgroup (one target each, four per round of SIMDs).
-void step_grid(int NB, int s, int *grid, int *wpw)
+// Launch shape of step s: band and near workgroups plus up to far_cap far
+// workgroups of wpw wavefronts (the far loop strides over the targets, so any
+// cap covers all of them).
+void step_grid(int NB, int s, int *grid, int *wpw, int far_cap)
 {
     *grid = 1;
     *wpw = 0;
@@ -750,10 +753,11 @@ void step_grid(int NB, int s, int *grid, int *wpw)
     *grid = 2;
     const int nt = NB - (s + 3);  // far targets
     if (nt <= 0) return;
-    const int per_round = 4 * kMaxFarWg;
+    const int cap = std::max(1, std::min(far_cap > 0 ? far_cap : kMaxFarWg, kMaxFarWg));
+    const int per_round = 4 * cap;
     const int rounds = std::min((nt + per_round - 1) / per_round, kStepThreads / kWave / 4);
     *wpw = 4 * rounds;
-    *grid += std::min(kMaxFarWg, (nt + *wpw - 1) / *wpw);
+    *grid += std::min(cap, (nt + *wpw - 1) / *wpw);
 }
 
 template <int SYS, int D, bool F32>
@@ -779,7 +783,7 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
     }
     for (int s = -1; s <= A.NB - 2; ++s) {
         int grid, wpw;
-        step_grid(A.NB, s, &grid, &wpw);
+        step_grid(A.NB, s, &grid, &wpw, A.far_cap);
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
         hipLaunchKernelGGL((k_step<SYS, D, F32>), dim3(grid), dim3(kStepThreads), smem, st, A, s,
                            wpw);

@@ -33,6 +33,9 @@ struct fabm_plan_s {
     // schedule of the last batched BLOCKED call, keyed by its block counts
     std::vector<int32_t> sched_nb;
     fabm::BatchSchedule sched;
+    // launch shapes (defaults, or the fastest found by fabm_tune)
+    int far_cap = fabm::kMaxFarWg;               // single-trajectory BLOCKED
+    int split_target = fabm::kWideSplitTarget;  // shared grid
 };
 
 // A captured solve: its instance table lives in its own pinned buffer, copied
@@ -487,6 +490,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.d = d;
         A.cp = (int)L.cp;
         A.NB = L.NB;
+        A.split_target = pl->split_target;
         const char *where = "";
         const hipError_t pe = fabm::enqueue_wide(A, s, T, &where);
         if (pe != hipSuccess) return record_hip(where, pe);
@@ -529,6 +533,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.dead = sync;
         A.status = status;
         A.NB = L.NB;
+        A.far_cap = pl->far_cap;
         const char *where = "";
         const hipError_t pe = fabm::enqueue_steps(pl->desc.system, d, f32, A, s, T, &where);
         if (pe != hipSuccess) return record_hip(where, pe);
@@ -861,6 +866,82 @@ void fabm_graph_destroy(fabm_graph_t graph)
     if (graph->graph) (void)hipGraphDestroy(graph->graph);
     if (graph->stage) (void)hipHostFree(graph->stage);
     delete graph;
+}
+
+fabm_status fabm_tune(fabm_plan_t plan, void *workspace, size_t workspace_bytes, int64_t batch,
+                      const double *alpha, const double *h, const int64_t *N, const double *y0,
+                      const double *params, const int64_t *row_off, double *y_out,
+                      int64_t *status, hipStream_t stream, fabm_tune_report *report)
+{
+    fabm_status st = check_batch(plan, batch, alpha, h, N, row_off);
+    if (st != FABM_OK) return st;
+    if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && !aligned8(params)) return FABM_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
+    const Layout L = layout_for(plan, batch, N);
+    if (L.path == Path::Unsupported) return FABM_ERR_UNSUPPORTED;
+    if (workspace_bytes < L.total) return FABM_ERR_WORKSPACE;
+
+    fabm_tune_report rep{};
+    int *knob = nullptr;
+    static const int kCaps[] = {32, 64, 128, fabm::kMaxFarWg};
+    static const int kTargets[] = {256, 512, 1024, 2048, fabm::kWideMaxSplitTarget};
+    const int *cand = nullptr;
+    if (L.path == Path::Blocked && batch == 1) {
+        rep.knob = FABM_TUNE_FAR_WORKGROUPS;
+        knob = &plan->far_cap;
+        cand = kCaps;
+        rep.n = (int32_t)(sizeof kCaps / sizeof kCaps[0]);
+    } else if (L.path == Path::Wide) {
+        rep.knob = FABM_TUNE_SPLIT_TARGET;
+        knob = &plan->split_target;
+        cand = kTargets;
+        rep.n = (int32_t)(sizeof kTargets / sizeof kTargets[0]);
+    }
+    if (!knob) {  // nothing to choose on this path
+        rep.knob = FABM_TUNE_NONE;
+        if (report) *report = rep;
+        return FABM_OK;
+    }
+    const int keep = *knob;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return record_hip("hipEventCreate", he);
+    }
+    const bool prof = plan->timer.on;
+    plan->timer.on = false;
+    // one untimed run first (first-touch of the workspace, code objects)
+    st = run_solve(plan, workspace, batch, alpha, h, N, y0, params, row_off, y_out, status, stream);
+    int best = -1;
+    for (int c = 0; st == FABM_OK && c < rep.n; ++c) {
+        *knob = cand[c];
+        rep.value[c] = cand[c];
+        if ((st = record_hip("hipEventRecord", hipEventRecord(e0, stream))) != FABM_OK) break;
+        st = run_solve(plan, workspace, batch, alpha, h, N, y0, params, row_off, y_out, status,
+                       stream);
+        if (st != FABM_OK) break;
+        if ((st = record_hip("hipEventRecord", hipEventRecord(e1, stream))) != FABM_OK) break;
+        if ((st = record_hip("hipEventSynchronize", hipEventSynchronize(e1))) != FABM_OK) break;
+        float ms = 0.0f;
+        if ((st = record_hip("hipEventElapsedTime", hipEventElapsedTime(&ms, e0, e1))) != FABM_OK)
+            break;
+        rep.seconds[c] = 1e-3 * (double)ms;
+        if (best < 0 || rep.seconds[c] < rep.seconds[best]) best = c;
+    }
+    plan->timer.on = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FABM_OK || best < 0) {
+        *knob = keep;
+        return st != FABM_OK ? st : FABM_ERR_DEVICE;
+    }
+    *knob = cand[best];
+    rep.chosen = best;
+    if (report) *report = rep;
+    return FABM_OK;
 }
 
 fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *N,

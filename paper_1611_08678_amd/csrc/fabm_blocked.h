@@ -65,6 +65,7 @@ struct StepArgs {
     uint32_t *dead;     // [0]: first non-finite step (0 while finite), or kDeadWatchdog
     int64_t *status;
     int NB;
+    int far_cap;        // far workgroups per launch (host side: launch shape only)
 };
 
 // Value of StepArgs::dead when a bounded wait inside the band gave up

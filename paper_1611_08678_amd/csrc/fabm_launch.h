@@ -40,7 +40,7 @@ hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_
                          KernelTimer *T, const char **where);
 int step_block_len();
 size_t step_smem_bytes(int d);
-void step_grid(int NB, int s, int *grid, int *wpw);
+void step_grid(int NB, int s, int *grid, int *wpw, int far_cap);
 
 // BLOCKED path for a batch (> 1) of trajectories: one launch per block step
 // for all instances. `far_off` is S.far_off in device memory.

@@ -30,6 +30,8 @@ struct KernelTimer;
 constexpr int kWideBlk = 64;       // rows per block
 constexpr int kWideColAlign = 128; // column padding of the history copies
 constexpr int kWideMaxSplits = 64; // source-range splits of one far launch
+constexpr int kWideSplitTarget = 1024;     // default far workgroups per launch
+constexpr int kWideMaxSplitTarget = 4096;  // largest target the tuner tries
 
 enum : int { WIDE_F64 = 0, WIDE_F32 = 1, WIDE_F16X2 = 2 };
 
@@ -52,13 +54,15 @@ struct WideArgs {
     int64_t batch;
     int64_t wlen;
     int d, cp, NB, prec;
+    int split_target;       // far workgroups a launch aims for (source-range splits)
 };
 
 // Enqueue the whole shared-grid solve after the weights exist.
 hipError_t enqueue_wide(const WideArgs &A, hipStream_t s, KernelTimer *T, const char **where);
 // Bytes of the FP16X2 Toeplitz operand table for NB blocks.
 size_t wide_t16_bytes(int NB);
-// Far-launch splits for a given column count (upper bound over all blocks).
+// Far-launch splits for a given column count (upper bound over all blocks and
+// split targets up to kWideMaxSplitTarget).
 int wide_max_splits(int cp, int NB);
 
 }  // namespace fabm

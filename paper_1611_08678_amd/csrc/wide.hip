@@ -503,10 +503,10 @@ __global__ void k_wide_status(const uint32_t *dead, int64_t *status, int64_t bat
 
 int cols_per_wg(int) { return 64; }
 
-int splits_for(int cp, int prec, int s)
+int splits_for(int cp, int prec, int s, int target)
 {
     const int tiles = cp / cols_per_wg(prec);
-    int sp = (1024 + tiles - 1) / tiles;
+    int sp = (std::max(target, 1) + tiles - 1) / tiles;
     sp = std::min(sp, kWideMaxSplits);
     return std::max(1, std::min(sp, s));
 }
@@ -518,7 +518,8 @@ size_t wide_t16_bytes(int NB) { return sizeof(_Float16) * (size_t)kT16Q * (size_
 int wide_max_splits(int cp, int NB)
 {
     int mx = 1;
-    for (int prec = 0; prec < 3; ++prec) mx = std::max(mx, splits_for(cp, prec, NB));
+    for (int prec = 0; prec < 3; ++prec)
+        mx = std::max(mx, splits_for(cp, prec, NB, kWideMaxSplitTarget));
     return mx;
 }
 
@@ -540,7 +541,8 @@ hipError_t enqueue_wide(const WideArgs &A, hipStream_t st, KernelTimer *T, const
     const int tiles = A.cp / cols_per_wg(A.prec);
     for (int s = 0; s < A.NB; ++s) {
         if (s > 0) {
-            const int sp = splits_for(A.cp, A.prec, s);
+            const int sp =
+                splits_for(A.cp, A.prec, s, std::min(A.split_target, kWideMaxSplitTarget));
             if (T && (e = T->begin(KC_WIDE_FAR, st)) != hipSuccess) {
                 *where = "timer";
                 return e;
