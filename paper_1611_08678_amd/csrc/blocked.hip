@@ -388,6 +388,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 // distinct even bank pairs.
 // ---------------------------------------------------------------------------
 constexpr int kSrcCols = 31;
+constexpr int kPairCols = 47;  // blocks s - 2 .. s: the windows of sources s - 1 and s
 constexpr int kColPitch = 17;
 // Result layout of v_mfma_f32_16x16x4f32 (measured on gfx950 with one-hot
 // operands): element v of lane l is row 4 (l / 16) + v, column l % 16 -- not
@@ -400,16 +401,18 @@ constexpr size_t staged_bytes()
     return sizeof(T) * D * kSrcCols * kColPitch;
 }
 
-template <int D, typename T>
+// NC = kSrcCols: columns 16 s - 15 .. 16 s + 15; NC = kPairCols: the 16 columns
+// before those as well (the window of source block s - 1 too).
+template <int D, typename T, int NC = kSrcCols>
 __device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB)
 {
     const int64_t pitch = (int64_t)A.NB * kBlk;
-    const int64_t r0 = (int64_t)kBlk * s - kTile * (kSrcCols - kTile);  // row of column 16 s - 15
-    for (int e = threadIdx.x; e < D * kSrcCols * kTile; e += blockDim.x) {
-        const int i = e / (kSrcCols * kTile), rem = e - i * (kSrcCols * kTile);
+    const int64_t r0 = (int64_t)kBlk * s - kTile * (NC - kTile);  // row of staged column 0
+    for (int e = threadIdx.x; e < D * NC * kTile; e += blockDim.x) {
+        const int i = e / (NC * kTile), rem = e - i * (NC * kTile);
         const int c = rem / kTile, tau = rem - c * kTile;
         const int64_t row = r0 + kTile * c + tau;
-        sB[(i * kSrcCols + c) * kColPitch + tau] = row >= 0 ? (T)A.Fc[i * pitch + row] : (T)0;
+        sB[(i * NC + c) * kColPitch + tau] = row >= 0 ? (T)A.Fc[i * pitch + row] : (T)0;
     }
 }
 
@@ -417,7 +420,7 @@ __device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB)
 // all components, added into `acc` (one wavefront). The history column of
 // lane rho is staged column rho - u + coff; columns past the staged range
 // (coff > 15 only) belong to blocks not yet formed and are masked to zero.
-template <int D>
+template <int D, int NC = kSrcCols>
 __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__restrict__ wb,
                                            const double *__restrict__ wa, const double *sB,
                                            int64_t m, int u, int coff)
@@ -425,7 +428,7 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
     const int lane = threadIdx.x & (kWave - 1);
     const int r16 = lane & 15, kq = lane >> 4;  // A row sigma / B column rho; K slot
     const int c = r16 - u + coff;
-    const bool ok = c < kSrcCols;
+    const bool ok = c < NC;
     const int sbase = (ok ? c : 0) * kColPitch + kq;
     const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
 #pragma unroll
@@ -434,7 +437,7 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
         double bf[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double v = sB[i * kSrcCols * kColPitch + sbase + 4 * j];
+            const double v = sB[i * NC * kColPitch + sbase + 4 * j];
             bf[i] = ok ? v : 0.0;
         }
 #pragma unroll
@@ -447,21 +450,21 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
 
 // The same column lag on the binary32 matrix cores (v_mfma_f32_16x16x4f32):
 // weights and history rounded to binary32, products summed in binary32.
-template <int D>
+template <int D, int NC = kSrcCols>
 __device__ __forceinline__ void window_lag_f32(flt4 (&acc)[2][D], const float *__restrict__ wb,
                                                const float *__restrict__ wa, const float *sB,
-                                               int64_t m, int u)
+                                               int64_t m, int u, int coff = kTile - 1)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int r16 = lane & 15, kq = lane >> 4;
-    const int sbase = (r16 - u + kTile - 1) * kColPitch + kq;
+    const int sbase = (r16 - u + coff) * kColPitch + kq;
     const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const float ab = wb[wi - 4 * j], aa = wa[wi - 4 * j];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const float bf = sB[i * kSrcCols * kColPitch + sbase + 4 * j];
+            const float bf = sB[i * NC * kColPitch + sbase + 4 * j];
             acc[0][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, bf, acc[0][i], 0, 0, 0);
             acc[1][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, bf, acc[1][i], 0, 0, 0);
         }
@@ -474,21 +477,36 @@ __device__ __forceinline__ int f32_result_row(int l, int v) { return kF32RowMajo
 
 // Far window m = J - s of target block J in binary32: the window's sums are
 // formed in binary32 and added to the binary64 sums of the target.
-template <int D>
-__device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, const float *sB)
+// PAIR: the windows of sources s - 1 (staged columns from 0) and s (from 16),
+// out of kPairCols staged columns; each window is summed in binary32 and added
+// to the binary64 sums in source order. `first`: no earlier window has
+// written the target's sums.
+template <int D, bool PAIR = false>
+__device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, const float *sB,
+                                               bool first)
 {
+    constexpr int NC = PAIR ? kPairCols : kSrcCols;
     const InstMeta m = A.meta[0];
     const float *wb = A.W32, *wa = wb + m.wlen;
     const int lane = threadIdx.x & (kWave - 1);
     double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
-    flt4 acc[2][D];
+    flt4 acc[2][D], acc2[2][D];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int i = 0; i < D; ++i) acc[t][i] = (flt4){0.0f, 0.0f, 0.0f, 0.0f};
+        for (int i = 0; i < D; ++i) acc[t][i] = acc2[t][i] = (flt4){0.0f, 0.0f, 0.0f, 0.0f};
     const int64_t mm = J - s;
+    if constexpr (PAIR) {
 #pragma unroll 2
-    for (int u = 0; u < kTile; ++u) window_lag_f32<D>(acc, wb, wa, sB, mm, u);
+        for (int u = 0; u < kTile; ++u)
+            window_lag_f32<D, NC>(acc, wb, wa, sB, mm + 1, u, kTile - 1);
+#pragma unroll 2
+        for (int u = 0; u < kTile; ++u)
+            window_lag_f32<D, NC>(acc2, wb, wa, sB, mm, u, 2 * kTile - 1);
+    } else {
+#pragma unroll 2
+        for (int u = 0; u < kTile; ++u) window_lag_f32<D, NC>(acc, wb, wa, sB, mm, u);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         // binary64 sums keep the binary64 result order (element sigma/4 of lane
@@ -500,16 +518,20 @@ __device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, 
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 double *p = aj + (t * D + i) * kBlk + e;
-                *p = (s == 0 ? 0.0 : *p) + (double)acc[t][i][v];
+                double x = (first ? 0.0 : *p) + (double)acc[t][i][v];
+                if constexpr (PAIR) x += (double)acc2[t][i][v];
+                *p = x;
             }
     }
 }
 
 // Far window m = J - s of target block J (one wavefront; staged columns
 // rho - u + 15), added to the target's sums in place.
-template <int D>
-__device__ __forceinline__ void far_target(const InstView &A, int s, int J, const double *sB)
+template <int D, bool PAIR = false>
+__device__ __forceinline__ void far_target(const InstView &A, int s, int J, const double *sB,
+                                           bool first)
 {
+    constexpr int NC = PAIR ? kPairCols : kSrcCols;
     const InstMeta m = A.meta[0];
     const double *wb = A.W, *wa = wb + m.wlen;
     const int lane = threadIdx.x & (kWave - 1);
@@ -521,10 +543,16 @@ __device__ __forceinline__ void far_target(const InstView &A, int s, int J, cons
         for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                acc[t][i][v] = s == 0 ? 0.0 : aj[((t * D + i) * 4 + v) * kWave];
+                acc[t][i][v] = first ? 0.0 : aj[((t * D + i) * 4 + v) * kWave];
     const int64_t mm = J - s;
+    if constexpr (PAIR) {
+        // source block s - 1 first: the order of the one-window launches
 #pragma unroll 2
-    for (int u = 0; u < kTile; ++u) window_lag<D>(acc, wb, wa, sB, mm, u, kTile - 1);
+        for (int u = 0; u < kTile; ++u) window_lag<D, NC>(acc, wb, wa, sB, mm + 1, u, kTile - 1);
+    }
+#pragma unroll 2
+    for (int u = 0; u < kTile; ++u)
+        window_lag<D, NC>(acc, wb, wa, sB, mm, u, PAIR ? 2 * kTile - 1 : kTile - 1);
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -625,7 +653,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         }
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
-        for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G) far_target<D>(V, s, J, sB);
+        for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G)
+            far_target<D>(V, s, J, sB, s == 0);
     } else {
         float *sB = (float *)smem;
         stage_sources<D, float>(V, s, sB);
@@ -633,7 +662,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
         for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G)
-            far_target_f32<D>(V, s, J, sB);
+            far_target_f32<D>(V, s, J, sB, s == 0);
     }
 }
 
@@ -689,22 +718,45 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
     }
     const InstView V = batch_view<D>(A, inst);
     if (*V.dead != 0u) return;  // this trajectory has ended; its later rows are NaN
+    // Far windows in pairs of source blocks: an odd launch s adds the windows of
+    // sources s - 1 and s to every target J >= s + 3 with one read and write of
+    // its sums; an even launch adds source s to target s + 3 only (the one
+    // target whose band comes before the next odd launch). Every target gets
+    // every source block in the same order as one window per launch.
+    const bool pair = s > 0 && (s & 1) != 0;
     const int J = first + (threadIdx.x >> 6);
+    const bool mine = first >= 0 && J < V.NB && (pair || J == s + 3);
     if (first < 0 || !F32) {
         double *sB = (double *)smem;
-        stage_sources<D, double>(V, s, sB);
+        if (first >= 0 && pair)
+            stage_sources<D, double, kPairCols>(V, s, sB);
+        else
+            stage_sources<D, double>(V, s, sB);
         __syncthreads();
         if (first < 0) {
             near_part<D, kBatchThreads / kWave, true>(V, s, sB,
                                                       (double *)(smem + staged_bytes<D>()));
             return;
         }
-        if (J < V.NB) far_target<D>(V, s, J, sB);
+        if (mine) {
+            if (pair)
+                far_target<D, true>(V, s, J, sB, s <= 1);
+            else
+                far_target<D>(V, s, J, sB, s <= 1);
+        }
     } else {
         float *sB = (float *)smem;
-        stage_sources<D, float>(V, s, sB);
+        if (pair)
+            stage_sources<D, float, kPairCols>(V, s, sB);
+        else
+            stage_sources<D, float>(V, s, sB);
         __syncthreads();
-        if (J < V.NB) far_target_f32<D>(V, s, J, sB);
+        if (mine) {
+            if (pair)
+                far_target_f32<D, true>(V, s, J, sB, s <= 1);
+            else
+                far_target_f32<D>(V, s, J, sB, s <= 1);
+        }
     }
 }
 
@@ -800,7 +852,8 @@ size_t batch_smem_bytes(int d)
 {
     const size_t band = sizeof(double) * (6 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
     const size_t near = sizeof(double) * (2 * (size_t)d * kBlk + (size_t)d * kSrcCols * kColPitch);
-    return std::max(band, near);
+    const size_t pair = sizeof(double) * (size_t)d * kPairCols * kColPitch;
+    return std::max(std::max(band, near), pair);
 }
 
 template <int SYS, int D, bool F32, bool YPOUT>

@@ -126,7 +126,7 @@ Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 // `stage_bytes` bytes are copied from the plan's pinned staging buffer.
 struct Layout {
     Path path;
-    size_t meta, inst, order, far_off, meta_adj, stage_bytes;
+    size_t meta, inst, order, far_off, far_off_rev, meta_adj, stage_bytes;
     size_t w, w32, f, part, carry, acc, sync, n_sync_words;
     // reverse pass only: forward rows, reversed sources and sums, partials
     size_t yw, ypw, uv, acc_a, carry_a, part_a, fbar0;
@@ -188,6 +188,9 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         L.far_off = off;
         off += sizeof(int) * S.far_off.size();
         if (adjoint) {
+            // the reverse pass takes one source block per launch
+            L.far_off_rev = off;
+            off += sizeof(int) * S.far_off_single.size();
             off = (off + 15) / 16 * 16;
             L.meta_adj = off;
             off += sizeof(InstMeta) * (size_t)batch;
@@ -389,6 +392,9 @@ const fabm::BatchSchedule &stage_batch(fabm_plan_s *pl, char *stage, const Layou
     }
     std::memcpy(stage + L.order, BS.order.data(), sizeof(int) * BS.order.size());
     std::memcpy(stage + L.far_off, BS.far_off.data(), sizeof(int) * BS.far_off.size());
+    if (L.far_off_rev)
+        std::memcpy(stage + L.far_off_rev, BS.far_off_single.data(),
+                    sizeof(int) * BS.far_off_single.size());
     return BS;
 }
 
@@ -639,7 +645,10 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     R.gy0 = gy0;
     R.gparams = gparams;
     R.batch = batch;
-    pe = fabm::enqueue_adjoint(pl->desc.system, d, R, BS, far_off, s, T, &where);
+    fabm::BatchSchedule Sr = BS;  // one source block per launch
+    Sr.far_off = BS.far_off_single;
+    pe = fabm::enqueue_adjoint(pl->desc.system, d, R, Sr, (const int *)(base + L.far_off_rev), s,
+                               T, &where);
     if (pe != hipSuccess) return record_hip(where, pe);
     return FABM_OK;
 }

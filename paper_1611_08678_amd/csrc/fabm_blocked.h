@@ -115,7 +115,8 @@ struct BatchArgs {
 struct BatchSchedule {
     std::vector<int> order;
     std::vector<int> nband, nnear, nfar, far_base;  // per launch s + 1 (s = -1 .. S-2)
-    std::vector<int> far_off;                         // concatenated prefix sums
+    std::vector<int> far_off;         // concatenated prefix sums (source blocks in pairs)
+    std::vector<int> far_off_single;  // the same with one source block per launch (reverse pass)
     int max_NB = 0;
 };
 void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S);

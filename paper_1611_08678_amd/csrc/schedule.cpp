@@ -70,6 +70,7 @@ void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S)
     S.nfar.assign((size_t)std::max(L, 1), 0);
     S.far_base.assign((size_t)std::max(L, 1), 0);
     S.far_off.clear();
+    S.far_off_single.clear();
     // instances with NB >= x form a prefix of `order`
     auto count_at_least = [&](int x) {
         int lo = 0, hi = (int)batch;
@@ -86,10 +87,16 @@ void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S)
         S.nnear[k] = s >= 0 ? count_at_least(s + 3) : 0;
         S.far_base[k] = (int)S.far_off.size();
         S.far_off.push_back(0);
+        S.far_off_single.push_back(0);
+        // far windows go in pairs of source blocks: odd launches take every
+        // target J >= s + 3, even launches target s + 3 only (k_step_batch)
         const int nf = s >= 0 ? count_at_least(s + 4) : 0;
+        const bool pair = s > 0 && (s & 1) != 0;
         for (int j = 0; j < nf; ++j) {
-            const int targets = NB[S.order[(size_t)j]] - (s + 3);
+            const int all = NB[S.order[(size_t)j]] - (s + 3);
+            const int targets = pair ? all : 1;
             S.far_off.push_back(S.far_off.back() + (targets + 3) / 4);
+            S.far_off_single.push_back(S.far_off_single.back() + (all + 3) / 4);
         }
         S.nfar[k] = nf;
     }
