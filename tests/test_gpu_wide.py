@@ -157,3 +157,17 @@ def test_wide_linear64_full_size(F, orc, prec):
             assert np.all(np.abs(yi[t] - yt) <= tol), (i, t, np.abs(yi[t] - yt).max(), mag.max())
     del y, st
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "fp32"])
+def test_wide_instances_of_very_different_magnitude(F, orc, prec):
+    """Scaling y0, b0 and b1 of a linear system by k scales its solution by k.
+    Instances 1e-8 .. 1e12 apart share the far product; each history column
+    carries its own power-of-two scale (FP16X2), so every instance keeps its
+    own relative accuracy (normwise per instance)."""
+    w = _linear_batch(4, 12, 600, seed=13)
+    d = 12
+    for i, k in enumerate([1e-8, 1.0, 1e5, 1e12]):
+        w["y0"][i] *= k
+        w["theta"][i, d * d:] *= k
+    _parity(F, orc, w, prec, REDUCED_BOUND)
