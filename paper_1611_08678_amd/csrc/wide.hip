@@ -360,22 +360,31 @@ __global__ __launch_bounds__(256) void k_wide_reduce(double *part, int64_t n, in
 }
 
 // ---------------------------------------------------------------------------
-// Band: one wavefront per instance, lane c holds component c (d <= 64), row c
-// of the system matrix in registers. Rows of block s in order:
+// Band: one workgroup of four wavefronts per instance. Lane c holds component
+// c (d <= 64); wavefront w holds columns 16 w .. 16 w + 15 of row c of the
+// system matrix. Rows of block s in order:
 //   P = far P + sum_{t0 <= k < T} b[T-1-k] f_k,
 //   C = far C + sum_{t0 <= k < T} a[T-1-k] f_k + (c[T-1] - a[T-1]) f_0,
 //   yP = y0 + h^a P, y = y0 + h^a (C + f(yP) / Gamma(a+2)), f_T = f(y),
-// with f(v) = A v + b0 + b1 t formed from v broadcast through LDS. The far
-// sums of the block are read into LDS first; the slot of row r holds far P
-// until row r is formed and f_r after.
+// with f(v) = A v + b0 + b1 t. Wavefront w forms the in-block terms of rows
+// k = w, w + 4, ... and its quarter of every matrix-vector product; the four
+// partials meet in LDS and every wavefront adds them in the same order, so all
+// four hold identical rows. The newest row's terms are added from registers.
+// The far sums of the block are read into LDS first; the slot of row r holds
+// far P until row r is formed and f_r after.
 // ---------------------------------------------------------------------------
+constexpr int kWideBandWaves = 4;
+constexpr int kWideBandCols = 64 / kWideBandWaves;  // matrix columns per wavefront
+
 template <int PREC>
-__global__ __launch_bounds__(64) void k_wide_band(WideArgs A, int s)
+__global__ __launch_bounds__(256) void k_wide_band(WideArgs A, int s)
 {
     __shared__ double sX[LW][64];  // far P of row r, then f_r
     __shared__ double sC[LW][64];  // far C of row r
     __shared__ double sWb[LW], sWa[LW], sDca[LW], sV[64];
-    const int lane = threadIdx.x;
+    __shared__ double sRed[2][kWideBandWaves][64];  // matrix-vector partials (two slots)
+    __shared__ double sPC[2][kWideBandWaves][64];   // in-block partials of P and C
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t i = blockIdx.x;
     const int d = A.d;
     const bool act = lane < d;
@@ -386,49 +395,54 @@ __global__ __launch_bounds__(64) void k_wide_band(WideArgs A, int s)
     double *Yi = A.Y + m.row_off * d;
 
     if (A.dead[i] != 0u) {
-        if (act)
+        if (act && w == 0)
             for (int r = 0; r < nrows; ++r) Yi[(t0 + r) * d + lane] = __builtin_nan("");
         return;
     }
     const double *p = A.params + m.p_off;
-    double arow[64];
+    double acol[kWideBandCols];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) arow[j] = (act && j < d) ? p[lane * d + j] : 0.0;
+    for (int jj = 0; jj < kWideBandCols; ++jj) {
+        const int j = kWideBandCols * w + jj;
+        acol[jj] = (act && j < d) ? p[lane * d + j] : 0.0;
+    }
     const double b0 = act ? p[d * d + lane] : 0.0, b1 = act ? p[d * d + d + lane] : 0.0;
     const double y0 = act ? A.y0[i * d + lane] : 0.0;
 
     const double *wb = A.W, *wa = wb + A.wlen, *wc = wa + A.wlen;
-    sWb[lane] = wb[lane];
-    sWa[lane] = wa[lane];
-    {
+    if (w == 0) {
+        sWb[lane] = wb[lane];
+        sWa[lane] = wa[lane];
         const int64_t T = t0 + lane;
         sDca[lane] = (T >= 1 && T <= N) ? wc[T - 1] - wa[T - 1] : 0.0;
     }
     const double *fp0 = A.part, *fc0 = A.part + (int64_t)LW * cp;
-    for (int r = 0; r < nrows; ++r) {
+    for (int r = w; r < nrows; r += kWideBandWaves) {
         sX[r][lane] = (s > 0 && act) ? fp0[r * cp + col] : 0.0;
         sC[r][lane] = (s > 0 && act) ? fc0[r * cp + col] : 0.0;
     }
 
-    // f(v) at time t for this lane's component: v broadcast through LDS
+    // f(v) at time t for this lane's component (identical in all wavefronts)
+    int slot = 0;
     auto fval = [&](double v, double t) -> double {
+        if (w == 0) sV[lane] = act ? v : 0.0;
         __syncthreads();
-        sV[lane] = act ? v : 0.0;
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int jj = 0; jj < kWideBandCols; ++jj)
+            c[jj & 3] = fma(acol[jj], sV[kWideBandCols * w + jj], c[jj & 3]);
+        sRed[slot][w][lane] = (c[0] + c[1]) + (c[2] + c[3]);
         __syncthreads();
-        double c[8];
-        c[0] = fma(b1, t, b0);
-#pragma unroll
-        for (int k = 1; k < 8; ++k) c[k] = 0.0;
-#pragma unroll
-        for (int j = 0; j < 64; j += 8)
-#pragma unroll
-            for (int k = 0; k < 8; ++k) c[k] = fma(arow[j + k], sV[j + k], c[k]);
-        return ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+        const double mv = (sRed[slot][0][lane] + sRed[slot][1][lane]) +
+                          (sRed[slot][2][lane] + sRed[slot][3][lane]);
+        slot ^= 1;
+        return fma(b1, t, b0) + mv;
     };
     const double f0 = fval(y0, 0.0);
-    __syncthreads();
 
     const double ha = m.ha, ig2 = m.ig2, h = m.h;
+    const double b0w = sWb[0], a0w = sWa[0];
+    double fprev = 0.0;  // f of row r - 1 (all wavefronts)
     for (int r = 0; r < nrows; ++r) {
         const int64_t T = t0 + r;
         double y, f;
@@ -436,48 +450,58 @@ __global__ __launch_bounds__(64) void k_wide_band(WideArgs A, int s)
             y = y0;
             f = f0;
         } else {
-            double P0 = sX[r][lane], C0 = fma(sDca[r], f0, sC[r][lane]), P1 = 0.0, C1 = 0.0;
-            int k = 0;
-            for (; k + 1 < r; k += 2) {
-                const double fa = sX[k][lane], fb = sX[k + 1][lane];
-                P0 = fma(sWb[r - 1 - k], fa, P0);
-                C0 = fma(sWa[r - 1 - k], fa, C0);
-                P1 = fma(sWb[r - 2 - k], fb, P1);
-                C1 = fma(sWa[r - 2 - k], fb, C1);
+            // this wavefront's in-block terms: rows k = w, w + 4, ... <= r - 2
+            double pp = 0.0, cc = 0.0;
+            for (int k = w; k < r - 1; k += kWideBandWaves) {
+                const double fk = sX[k][lane];
+                pp = fma(sWb[r - 1 - k], fk, pp);
+                cc = fma(sWa[r - 1 - k], fk, cc);
             }
-            if (k < r) {
-                const double fa = sX[k][lane];
-                P0 = fma(sWb[r - 1 - k], fa, P0);
-                C0 = fma(sWa[r - 1 - k], fa, C0);
+            sPC[0][w][lane] = pp;
+            sPC[1][w][lane] = cc;
+            const double farP = sX[r][lane], farC = fma(sDca[r], f0, sC[r][lane]);
+            __syncthreads();
+            double P = farP + ((sPC[0][0][lane] + sPC[0][1][lane]) +
+                               (sPC[0][2][lane] + sPC[0][3][lane]));
+            double C = farC + ((sPC[1][0][lane] + sPC[1][1][lane]) +
+                               (sPC[1][2][lane] + sPC[1][3][lane]));
+            if (r > 0) {  // the newest row of the block
+                P = fma(b0w, fprev, P);
+                C = fma(a0w, fprev, C);
             }
             const double t = (double)T * h;
-            const double yp = fma(ha, P0 + P1, y0);
+            const double yp = fma(ha, P, y0);
             const double fp = fval(yp, t);
-            y = fma(ha, fma(fp, ig2, C0 + C1), y0);
+            y = fma(ha, fma(fp, ig2, C), y0);
             f = fval(y, t);
             if (__ballot(act && !(isfinite(y) && isfinite(f)))) {
-                if (act)
+                if (act && w == 0) {
                     for (int rr = r; rr < nrows; ++rr) Yi[(t0 + rr) * d + lane] = __builtin_nan("");
-                if (lane == 0) A.dead[i] = (uint32_t)T;
+                    if (lane == 0) A.dead[i] = (uint32_t)T;
+                }
                 return;
             }
         }
-        sX[r][lane] = f;
-        if (act) {
-            Yi[T * d + lane] = y;
-            if constexpr (PREC == WIDE_F64) A.F[T * cp + col] = f;
-            if constexpr (PREC == WIDE_F32) A.F32[T * cp + col] = (float)f;
+        fprev = f;
+        if (w == 0) {
+            sX[r][lane] = f;
+            if (act) {
+                Yi[T * d + lane] = y;
+                if constexpr (PREC == WIDE_F64) A.F[T * cp + col] = f;
+                if constexpr (PREC == WIDE_F32) A.F32[T * cp + col] = (float)f;
+            }
         }
     }
     if constexpr (PREC == WIDE_F16X2) {
+        __syncthreads();  // every f_r in LDS
         if (act && s + 1 < A.NB) {
             double mx = 0.0;
             for (int r = 0; r < nrows; ++r) mx = fmax(mx, fabs(sX[r][lane]));
             int e = 0;
             if (mx > 0.0) (void)frexp(mx, &e);
-            A.Fexp[(int64_t)s * cp + col] = e;
+            if (w == 0) A.Fexp[(int64_t)s * cp + col] = e;
             half8 *Fh = (half8 *)A.Fhi, *Fl = (half8 *)A.Flo;
-            for (int r8 = 0; r8 < LW / 8; ++r8) {
+            for (int r8 = w; r8 < LW / 8; r8 += kWideBandWaves) {
                 half8 vh, vl;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -573,11 +597,11 @@ hipError_t enqueue_wide(const WideArgs &A, hipStream_t st, KernelTimer *T, const
         }
         const dim3 grid((unsigned)A.batch);
         if (A.prec == WIDE_F64)
-            hipLaunchKernelGGL(k_wide_band<WIDE_F64>, grid, dim3(64), 0, st, A, s);
+            hipLaunchKernelGGL(k_wide_band<WIDE_F64>, grid, dim3(256), 0, st, A, s);
         else if (A.prec == WIDE_F32)
-            hipLaunchKernelGGL(k_wide_band<WIDE_F32>, grid, dim3(64), 0, st, A, s);
+            hipLaunchKernelGGL(k_wide_band<WIDE_F32>, grid, dim3(256), 0, st, A, s);
         else
-            hipLaunchKernelGGL(k_wide_band<WIDE_F16X2>, grid, dim3(64), 0, st, A, s);
+            hipLaunchKernelGGL(k_wide_band<WIDE_F16X2>, grid, dim3(256), 0, st, A, s);
         WIDE_CHECK("k_wide_band");
         if (T && (e = T->end(st)) != hipSuccess) {
             *where = "timer";
