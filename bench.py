@@ -31,12 +31,13 @@ MEASURED_TRAFFIC = {"k_step": (59.12e6, "1edb6a50aebf275b")}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense binary16 matrix rate
+HBM_PEAK_GBPS = 8000.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=1 << 20)
     ap.add_argument("--paths", default="blocked,direct", help="comma list of blocked,direct")
@@ -54,6 +55,9 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the benchmark "
                          "(untimed; a reference kernel of known traffic for hardware counters)")
+    ap.add_argument("--batch-path", default="blocked", choices=["blocked", "direct"],
+                    help="batch workloads: the path to time (direct: one workgroup per "
+                         "instance, HBM-bound)")
     ap.add_argument("--tune", action="store_true",
                     help="batch workloads: run fabm_tune on the plan before timing (untimed)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
@@ -174,7 +178,7 @@ def bench_batch(F, W, args):
     prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" else "fp64")
     Ns = np.asarray(w["N"], dtype=np.int64)
     B, d = len(Ns), w["d"]
-    plan = F.fabm_plan(w["system"], d, "blocked", prec, B, int(Ns.max()), int(Ns.sum()))
+    plan = F.fabm_plan(w["system"], d, args.batch_path, prec, B, int(Ns.max()), int(Ns.sum()))
     ws = torch.empty(F.fabm_workspace_size(plan, Ns), dtype=torch.uint8, device="cuda")
     y0 = torch.as_tensor(w["y0"], dtype=torch.float64, device="cuda").contiguous()
     th = torch.as_tensor(w["theta"], dtype=torch.float64, device="cuda").contiguous()
@@ -217,7 +221,8 @@ def bench_batch(F, W, args):
                      "fp16x2": "f64 band, fp16 hi+lo far tiles (f32 sums)"}[prec],
            "data": "synthetic",
            "config": {"workload": w["name"], "batch": B, "N_min": int(Ns.min()),
-                      "N_max": int(Ns.max()), "far_prec": prec},
+                      "N_max": int(Ns.max()), "path": args.batch_path,
+                      "far_prec": prec if args.batch_path == "blocked" else None},
            "history_gflops": flops / t / 1e9,
            "status_nonzero": int((st.cpu().numpy() != 0).sum()),
            "tune": tune,
@@ -231,6 +236,13 @@ def bench_batch(F, W, args):
                                frac=ach / peak, traffic=None, kernel="k_step_batch",
                                launches=launches, avg_launch_s=secs / launches,
                                algorithmic_flops_per_launch=flops / launches)
+    if "direct_wg" in kt:
+        secs, launches = kt["direct_wg"]
+        by = float((4.0 * Ns * (Ns + 1) * (d + 2)).sum())  # weights + history per step
+        out["roofline"] = dict(bound="hbm", achieved=by / secs / 1e9, peak=HBM_PEAK_GBPS,
+                               unit="GB/s", frac=by / secs / 1e9 / HBM_PEAK_GBPS, traffic=None,
+                               kernel="k_direct_wg", launches=launches,
+                               avg_launch_s=secs / launches, algorithmic_bytes_per_launch=by)
     if "wide_far" in kt:
         # far sums of the shared grid: every target row t takes the 64 * (t // 64)
         # source rows of earlier blocks, both tables, every column
@@ -241,11 +253,27 @@ def bench_batch(F, W, args):
         peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
                 "fp16x2": FP16_MFMA_PEAK_TFLOPS}[prec]
         ach = hw * far_flops / secs / 1e12
-        out["roofline"] = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
-                               frac=ach / peak, traffic=None, kernel="k_wide_far",
-                               launches=launches, avg_launch_s=secs / launches,
-                               algorithmic_flops_per_launch=far_flops / launches,
-                               mfma_flops_per_algorithmic_flop=hw)
+        # history read by the far launches: every earlier row, every column,
+        # once per workgroup column tile (8, 4 or 2 + 2 bytes per value)
+        eb = {"fp64": 8.0, "fp32": 4.0, "fp16x2": 4.0}[prec]
+        hist = float((64.0 * np.floor(t_rows[::64] / 64.0)).sum()) * B * d * eb
+        if prec == "fp16x2":
+            # 64 flop per history byte: 512 TFLOP/s at 8 TB/s, below the
+            # 833 TFLOP/s of algorithmic work the binary16 matrix cores give at
+            # three products per term, so HBM bounds this kernel
+            out["roofline"] = dict(bound="hbm", achieved=hist / secs / 1e9, peak=HBM_PEAK_GBPS,
+                                   unit="GB/s", frac=hist / secs / 1e9 / HBM_PEAK_GBPS,
+                                   traffic=None, kernel="k_wide_far", launches=launches,
+                                   avg_launch_s=secs / launches,
+                                   algorithmic_bytes_per_launch=hist / launches,
+                                   mfma_tflops=ach, mfma_frac=ach / peak,
+                                   mfma_flops_per_algorithmic_flop=hw)
+        else:
+            out["roofline"] = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
+                                   frac=ach / peak, traffic=None, kernel="k_wide_far",
+                                   launches=launches, avg_launch_s=secs / launches,
+                                   algorithmic_flops_per_launch=far_flops / launches,
+                                   history_gbps=hist / secs / 1e9)
     if args.cpu_sample > 0 and args.workload == "linear64_batch":
         # oracle check of the first 1000 steps of the first and last instance
         from oracle import oracle as O
@@ -413,6 +441,13 @@ def main():
         out["kernel_times_s"] = {k: v[0] for k, v in kt.items() if v[1]}
         out["kernel_launches"] = {k: v[1] for k, v in kt.items() if v[1]}
     out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, d)
+    if "direct" in results:
+        # DIRECT reads both weight rows and the history at every step:
+        # sum_t 8 t (d + 2) B = 4 N (N + 1) (d + 2) B (algorithmic)
+        by = 4.0 * N * (N + 1) * (d + 2)
+        td = float(np.mean(results["direct"]["solve_s"]))
+        out["paths"]["direct"]["algorithmic_hbm_gbps"] = by / td / 1e9
+        out["paths"]["direct"]["hbm_frac"] = by / td / 1e9 / HBM_PEAK_GBPS
     if "direct" in results and "blocked" in results:
         out["blocked_speedup_over_direct"] = (np.mean(results["direct"]["solve_s"]) /
                                               np.mean(results["blocked"]["solve_s"]))
