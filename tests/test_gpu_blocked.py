@@ -206,3 +206,28 @@ def test_blocked_fp32_batch(F, orc):
     "BLOCKED path is the step-kernel pipeline tested above."))
 def test_blocked_persistent_variant_far_tasks():
     pass
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.3, 1.0])
+def test_blocked_alpha_range(F, orc, alpha):
+    """Orders near the ends of (0, 1]: slowly decaying weights (alpha = 0.05)
+    and the classical case (alpha = 1), over several blocks and a ragged tail."""
+    th, y0 = _lin(3, 77)
+    th[:9] *= 0.1  # eigenvalues near -0.2: the explicit predictor is stable at alpha = 0.05
+    N = 1300
+    y, st = F.solve("linear", th, alpha, 0.01, N, y0, path="blocked")
+    ref, _, _, rst = orc.solve(0, th, alpha, 0.01, N, y0)
+    assert int(st.item()) == rst == 0
+    assert relerr(_to_np(y), ref) <= 1e-11
+
+
+def test_blocked_batch_alpha_range(F, orc):
+    """One batch, per-instance alpha from 0.05 to 1, ragged lengths."""
+    rng = np.random.default_rng(71)
+    al = np.array([0.05, 0.2, 0.5, 0.75, 0.99, 1.0])
+    B, d = len(al), 2
+    A = -(0.2 * np.eye(d)[None] + rng.standard_normal((B, d, d)) / 80)
+    th = np.concatenate([A.reshape(B, -1), 0.1 * rng.standard_normal((B, 2 * d))], axis=1)
+    w = dict(system=0, theta=th, alpha=al, h=np.full(B, 0.01),
+             N=np.array([1200, 700, 2049, 256, 1, 900]), y0=rng.uniform(-1, 1, (B, d)))
+    _batch_parity(F, orc, w, path="blocked")

@@ -28,9 +28,9 @@ def F():
     return F
 
 
-def _linear_batch(B, d, N, seed, blow=None, alpha=0.8, h=0.01):
+def _linear_batch(B, d, N, seed, blow=None, alpha=0.8, h=0.01, scale=1.0):
     rng = np.random.default_rng(seed)
-    A = -(2 * np.eye(d)[None] + rng.standard_normal((B, d, d)) / 8)
+    A = -scale * (2 * np.eye(d)[None] + rng.standard_normal((B, d, d)) / 8)
     if blow is not None:
         for i, g in blow.items():
             A[i] += g * np.eye(d)
@@ -171,3 +171,12 @@ def test_wide_instances_of_very_different_magnitude(F, orc, prec):
         w["y0"][i] *= k
         w["theta"][i, d * d:] *= k
     _parity(F, orc, w, prec, REDUCED_BOUND)
+
+
+@pytest.mark.parametrize("alpha", [0.05, 1.0])
+def test_wide_alpha_range(F, orc, alpha):
+    # eigenvalues near -0.2: the explicit predictor is stable at alpha = 0.05
+    w = _linear_batch(3, 9, 700, seed=17, alpha=alpha, scale=0.1)
+    assert np.all(orc.solve_batch(0, w["theta"], w["alpha"], w["h"], w["N"], w["y0"])[2] == 0)
+    _parity(F, orc, w, "fp64", 1e-11)
+    _parity(F, orc, w, "fp16x2", REDUCED_BOUND)
