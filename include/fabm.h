@@ -253,6 +253,27 @@ fabm_status fabm_adjoint(fabm_plan_t plan, void *workspace, size_t workspace_byt
 fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *N,
                                         size_t *bytes);
 
+/* The adjoint in two calls, for callers that need the trajectory before its
+ * gradient (a training step: forward, loss, backward) and would otherwise
+ * solve twice. fabm_adjoint_forward runs the forward pass of fabm_adjoint
+ * into the workspace (trajectory, predictor rows, history) and writes the
+ * trajectory to y_out (rows placed as in fabm_solve_batch) and the status;
+ * fabm_adjoint_reverse then runs only the reverse pass on what the workspace
+ * holds and writes gy0 and gparams. The two calls give bitwise the gradients
+ * fabm_adjoint gives for the same arguments. Between them the workspace must
+ * not be used by any other call, and alpha, h, N, row_off, y0 and params must
+ * be unchanged. workspace_bytes >= fabm_adjoint_workspace_size(plan, batch, N). */
+fabm_status fabm_adjoint_forward(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                                 int64_t batch, const double *alpha, const double *h,
+                                 const int64_t *N, const double *y0, const double *params,
+                                 const int64_t *row_off, double *y_out, int64_t *status,
+                                 hipStream_t stream);
+fabm_status fabm_adjoint_reverse(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                                 int64_t batch, const double *alpha, const double *h,
+                                 const int64_t *N, const double *y0, const double *params,
+                                 const int64_t *row_off, const double *gy, double *gy0,
+                                 double *gparams, hipStream_t stream);
+
 /* Weight tables of Section 2 for one alpha, lags m = 0..n-1:
  *   b (device) [n], a (device) [n], c (device) [n]  (any may be NULL).
  * Computed in binary64 with cancellation-free rearrangements of the defining

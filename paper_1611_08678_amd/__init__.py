@@ -32,7 +32,8 @@ EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan"
            "fabm_workspace_size", "fabm_solve", "fabm_solve_batch", "fabm_weights",
            "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
            "fabm_plan_kernel_times", "fabm_adjoint", "fabm_adjoint_workspace_size",
-           "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy", "fabm_tune")
+           "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy", "fabm_tune",
+           "fabm_adjoint_forward", "fabm_adjoint_reverse")
 KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint",
                   "wide_far", "wide_band")
 
@@ -106,6 +107,12 @@ def load():
     L.fabm_adjoint.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP, _VP, _I64P,
                                _VP, _VP, _VP, _VP, _VP]
     L.fabm_adjoint.restype = C.c_int
+    L.fabm_adjoint_forward.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP,
+                                       _VP, _I64P, _VP, _VP, _VP]
+    L.fabm_adjoint_forward.restype = C.c_int
+    L.fabm_adjoint_reverse.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP,
+                                       _VP, _I64P, _VP, _VP, _VP, _VP]
+    L.fabm_adjoint_reverse.restype = C.c_int
     L.fabm_adjoint_workspace_size.argtypes = [_VP, C.c_int64, _I64P, C.POINTER(C.c_size_t)]
     L.fabm_adjoint_workspace_size.restype = C.c_int
     L.fabm_graph_solve_batch.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP,
@@ -303,6 +310,36 @@ def fabm_adjoint(plan: Plan, workspace, alpha, h, N, y0, params, row_off, gy, gy
                                _ptr(status), _stream(stream)), "fabm_adjoint")
 
 
+def _host_arrays(alpha, h, N, row_off):
+    import numpy as np
+    return (np.ascontiguousarray(np.atleast_1d(alpha), dtype=np.float64),
+            np.ascontiguousarray(np.atleast_1d(h), dtype=np.float64),
+            np.ascontiguousarray(np.atleast_1d(N), dtype=np.int64),
+            np.ascontiguousarray(np.atleast_1d(row_off), dtype=np.int64))
+
+
+def fabm_adjoint_forward(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out, status,
+                         stream=None):
+    al, hh, Ns, ro = _host_arrays(alpha, h, N, row_off)
+    _check(load().fabm_adjoint_forward(plan.handle, _ptr(workspace),
+                                       workspace.numel() * workspace.element_size(), al.size,
+                                       al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
+                                       Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
+                                       ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
+                                       _stream(stream)), "fabm_adjoint_forward")
+
+
+def fabm_adjoint_reverse(plan: Plan, workspace, alpha, h, N, y0, params, row_off, gy, gy0,
+                         gparams, stream=None):
+    al, hh, Ns, ro = _host_arrays(alpha, h, N, row_off)
+    _check(load().fabm_adjoint_reverse(plan.handle, _ptr(workspace),
+                                       workspace.numel() * workspace.element_size(), al.size,
+                                       al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
+                                       Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
+                                       ro.ctypes.data_as(_I64P), _ptr(gy), _ptr(gy0),
+                                       _ptr(gparams), _stream(stream)), "fabm_adjoint_reverse")
+
+
 def fabm_plan_set_profiling(plan: Plan, enable: bool):
     _check(load().fabm_plan_set_profiling(plan.handle, int(bool(enable))),
            "fabm_plan_set_profiling")
@@ -423,19 +460,37 @@ def _solve_function():
 
         @staticmethod
         def forward(ctx, y0s, thetas, system, alphas, hs, Ns):
+            # the forward pass of the adjoint: the workspace it leaves (rows,
+            # predictor rows, history) is kept for the backward pass
             import numpy as np
-            y, _, st = solve_batch(system, thetas.detach(), alphas, hs, Ns, y0s.detach(),
-                                   path="blocked", far_prec="fp64")
-            ctx.save_for_backward(y0s.detach(), thetas.detach())
-            ctx.meta = (system, np.asarray(alphas, dtype=np.float64),
-                        np.asarray(hs, dtype=np.float64), np.asarray(Ns, dtype=np.int64))
+            import torch
+            y0d = _dev(y0s.detach()).contiguous()
+            B, d = y0d.shape
+            th = _dev(thetas.detach()).reshape(B, -1).contiguous()
+            al = np.asarray(alphas, dtype=np.float64)
+            hh = np.asarray(hs, dtype=np.float64)
+            Ns = np.ascontiguousarray(Ns, dtype=np.int64)
+            row_off = np.zeros(B, dtype=np.int64)
+            row_off[1:] = np.cumsum(Ns + 1)[:-1]
+            plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()))
+            ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
+            y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
+            st = torch.zeros(B, dtype=torch.int64, device="cuda")
+            fabm_adjoint_forward(plan, ws, al, hh, Ns, y0d, th, row_off, y, st)
+            ctx.save_for_backward(y0d, th)
+            ctx.meta = (plan, ws, al, hh, Ns, row_off)
             return y
 
         @staticmethod
         def backward(ctx, gy):
-            y0s, thetas = ctx.saved_tensors
-            system, alphas, hs, Ns = ctx.meta
-            gy0, gth, _ = adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy)
+            import torch
+            y0d, th = ctx.saved_tensors
+            plan, ws, al, hh, Ns, row_off = ctx.meta
+            gy0 = torch.empty_like(y0d)
+            gth = torch.empty_like(th)
+            fabm_adjoint_reverse(plan, ws, al, hh, Ns, y0d, th, row_off,
+                                 _dev(gy).contiguous(), gy0, gth)
+            ctx.meta = None  # release the workspace
             return gy0, gth, None, None, None, None
 
     return FabmSolveBatch

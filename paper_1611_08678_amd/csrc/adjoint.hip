@@ -482,4 +482,32 @@ hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule
     return hipErrorInvalidValue;
 }
 
+__global__ __launch_bounds__(256) void k_copy_rows(const InstMeta *__restrict__ src_meta,
+                                                   const InstMeta *__restrict__ dst_meta,
+                                                   int64_t batch, int d,
+                                                   const double *__restrict__ src,
+                                                   double *__restrict__ dst)
+{
+    for (int64_t i = blockIdx.y; i < batch; i += gridDim.y) {
+        const int64_t n = (src_meta[i].N + 1) * d;
+        const double *a = src + src_meta[i].f_off * d;
+        double *b = dst + dst_meta[i].row_off * d;
+        for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n;
+             e += (int64_t)gridDim.x * 256)
+            b[e] = a[e];
+    }
+}
+
+hipError_t launch_copy_rows(const InstMeta *src_meta, const InstMeta *dst_meta, int64_t batch,
+                            int64_t max_rows, int d, const double *src, double *dst,
+                            hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((max_rows * d + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_copy_rows,
+                       dim3((unsigned)std::max<int64_t>(blocks, 1),
+                            (unsigned)std::min<int64_t>(batch, 65535)),
+                       dim3(256), 0, s, src_meta, dst_meta, batch, d, src, dst);
+    return hipGetLastError();
+}
+
 }  // namespace fabm

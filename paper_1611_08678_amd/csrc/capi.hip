@@ -564,10 +564,16 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
 
 // Body of fabm_adjoint after validation: forward pass (batched BLOCKED, FP64)
 // into the workspace with predictor rows, then the reverse pipeline.
+// Phases of the adjoint: both passes, the forward pass only (trajectory also
+// copied to the caller's rows), or the reverse pass on the workspace a forward
+// phase left.
+enum class AdjPhase { Both, Forward, Reverse };
+
 fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *alpha,
                         const double *h, const int64_t *N, const double *y0,
                         const double *params, const int64_t *row_off, const double *gy,
-                        double *gy0, double *gparams, int64_t *status, hipStream_t s)
+                        double *gy0, double *gparams, int64_t *status, hipStream_t s,
+                        AdjPhase phase = AdjPhase::Both, double *y_out = nullptr)
 {
     const int d = pl->desc.dim;
     const Layout L = layout_for(pl, batch, N, true);
@@ -601,12 +607,15 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     uint32_t *sync = (uint32_t *)(base + L.sync);
     fabm::KernelTimer *T = pl->timer.on ? &pl->timer : nullptr;
     if (T) T->reset();
-    if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
-    if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK) return st;
-    if (T) HIP_TRY(T->end(s));
-    if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
-        FABM_OK)
-        return st;
+    if (phase != AdjPhase::Reverse) {
+        if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
+        if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK)
+            return st;
+        if (T) HIP_TRY(T->end(s));
+        if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
+            FABM_OK)
+            return st;
+    }
     fabm::BatchArgs A{};
     A.meta = dmeta;
     A.inst = (const fabm::BlkInst *)(base + L.inst);
@@ -624,8 +633,17 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     A.batch = batch;
     const int *far_off = (const int *)(base + L.far_off);
     const char *where = "";
-    hipError_t pe = fabm::enqueue_batch(pl->desc.system, d, false, A, BS, far_off, s, T, &where);
-    if (pe != hipSuccess) return record_hip(where, pe);
+    hipError_t pe = hipSuccess;
+    if (phase != AdjPhase::Reverse) {
+        pe = fabm::enqueue_batch(pl->desc.system, d, false, A, BS, far_off, s, T, &where);
+        if (pe != hipSuccess) return record_hip(where, pe);
+    }
+    if (phase == AdjPhase::Forward) {
+        int64_t maxr = 0;
+        for (int64_t i = 0; i < batch; ++i) maxr = std::max(maxr, N[i] + 1);
+        return ok_or_device(fabm::launch_copy_rows(dmeta, (const InstMeta *)(base + L.meta_adj),
+                                                   batch, maxr, d, A.Y, y_out, s));
+    }
     fabm::AdjArgs R{};
     R.meta = (const InstMeta *)(base + L.meta_adj);
     R.inst = A.inst;
@@ -983,6 +1001,43 @@ fabm_status fabm_adjoint(fabm_plan_t plan, void *workspace, size_t workspace_byt
     if (workspace_bytes < need) return FABM_ERR_WORKSPACE;
     return run_adjoint(plan, workspace, batch, alpha, h, N, y0, params, row_off, gy, gy0, gparams,
                        status, stream);
+}
+
+fabm_status fabm_adjoint_forward(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                                 int64_t batch, const double *alpha, const double *h,
+                                 const int64_t *N, const double *y0, const double *params,
+                                 const int64_t *row_off, double *y_out, int64_t *status,
+                                 hipStream_t stream)
+{
+    fabm_status st = check_batch(plan, batch, alpha, h, N, row_off);
+    if (st != FABM_OK) return st;
+    if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && !aligned8(params)) return FABM_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
+    size_t need = 0;
+    if ((st = fabm_adjoint_workspace_size(plan, batch, N, &need)) != FABM_OK) return st;
+    if (workspace_bytes < need) return FABM_ERR_WORKSPACE;
+    return run_adjoint(plan, workspace, batch, alpha, h, N, y0, params, row_off, nullptr,
+                       nullptr, nullptr, status, stream, AdjPhase::Forward, y_out);
+}
+
+fabm_status fabm_adjoint_reverse(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
+                                 int64_t batch, const double *alpha, const double *h,
+                                 const int64_t *N, const double *y0, const double *params,
+                                 const int64_t *row_off, const double *gy, double *gy0,
+                                 double *gparams, hipStream_t stream)
+{
+    fabm_status st = check_batch(plan, batch, alpha, h, N, row_off);
+    if (st != FABM_OK) return st;
+    if (!aligned8(y0) || !aligned8(gy) || !aligned8(gy0)) return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && (!aligned8(params) || !aligned8(gparams)))
+        return FABM_ERR_INVALID_ARG;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return FABM_ERR_WORKSPACE;
+    size_t need = 0;
+    if ((st = fabm_adjoint_workspace_size(plan, batch, N, &need)) != FABM_OK) return st;
+    if (workspace_bytes < need) return FABM_ERR_WORKSPACE;
+    return run_adjoint(plan, workspace, batch, alpha, h, N, y0, params, row_off, gy, gy0,
+                       gparams, nullptr, stream, AdjPhase::Reverse);
 }
 
 fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *c,

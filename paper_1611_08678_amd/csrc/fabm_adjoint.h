@@ -39,4 +39,10 @@ hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule
                            const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
 size_t adj_smem_bytes(int d);
 
+// Rows 0..N_i of every instance from src (placed by src_meta[i].f_off) to dst
+// (placed by dst_meta[i].row_off), d doubles per row.
+hipError_t launch_copy_rows(const InstMeta *src_meta, const InstMeta *dst_meta, int64_t batch,
+                            int64_t max_rows, int d, const double *src, double *dst,
+                            hipStream_t s);
+
 }  // namespace fabm

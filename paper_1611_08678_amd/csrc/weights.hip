@@ -72,20 +72,21 @@ __device__ __forceinline__ double weight_c(double al, double ig1, double ig2, in
 __global__ __launch_bounds__(256) void k_weights(const InstMeta *__restrict__ meta, int64_t batch,
                                                  double *__restrict__ W, float *__restrict__ W32)
 {
-    const int64_t i = blockIdx.y;
-    if (i >= batch) return;
-    const InstMeta m = meta[i];
-    double *b = W + m.w_off, *a = b + m.wlen, *c = a + m.wlen;
-    float *b32 = W32 ? W32 + m.w_off / 3 * 2 : nullptr, *a32 = b32 ? b32 + m.wlen : nullptr;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m.wlen;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const double bj = weight_b(m.alpha, m.ig1, j), aj = weight_a(m.alpha, m.ig1, m.ig2, j);
-        b[j] = bj;
-        a[j] = aj;
-        c[j] = weight_c(m.alpha, m.ig1, m.ig2, j);
-        if (b32) {
-            b32[j] = (float)bj;
-            a32[j] = (float)aj;
+    // instances stride over the second grid dimension (at most 65535)
+    for (int64_t i = blockIdx.y; i < batch; i += gridDim.y) {
+        const InstMeta m = meta[i];
+        double *b = W + m.w_off, *a = b + m.wlen, *c = a + m.wlen;
+        float *b32 = W32 ? W32 + m.w_off / 3 * 2 : nullptr, *a32 = b32 ? b32 + m.wlen : nullptr;
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m.wlen;
+             j += (int64_t)gridDim.x * blockDim.x) {
+            const double bj = weight_b(m.alpha, m.ig1, j), aj = weight_a(m.alpha, m.ig1, m.ig2, j);
+            b[j] = bj;
+            a[j] = aj;
+            c[j] = weight_c(m.alpha, m.ig1, m.ig2, j);
+            if (b32) {
+                b32[j] = (float)bj;
+                a32[j] = (float)aj;
+            }
         }
     }
 }
@@ -107,7 +108,7 @@ hipError_t launch_weights(const InstMeta *meta, int64_t batch, int64_t maxN, dou
                           hipStream_t s, float *W32)
 {
     const int64_t blocks = (maxN + 255) / 256;
-    dim3 grid((unsigned)(blocks < 4096 ? blocks : 4096), (unsigned)batch);
+    dim3 grid((unsigned)(blocks < 4096 ? blocks : 4096), (unsigned)(batch < 65535 ? batch : 65535));
     hipLaunchKernelGGL(k_weights, grid, dim3(256), 0, s, meta, batch, W, W32);
     return hipGetLastError();
 }

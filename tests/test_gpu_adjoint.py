@@ -134,3 +134,39 @@ def test_adjoint_deterministic(F):
             rng.uniform(-2, 2, (B, 2)), rng.standard_normal((int((Ns + 1).sum()), 2)))
     r1, r2 = F.adjoint_batch(*args), F.adjoint_batch(*args)
     assert all(np.array_equal(_to_np(a), _to_np(b)) for a, b in zip(r1, r2))
+
+
+def test_adjoint_in_two_calls_matches_one_call(F):
+    """fabm_adjoint_forward + fabm_adjoint_reverse: the trajectory equals the
+    solve's (bitwise: the same batched pipeline), the status is the forward's,
+    and the gradients equal fabm_adjoint's bitwise; a blowing-up instance gets
+    its status and NaN gradients."""
+    import torch
+    rng = np.random.default_rng(12)
+    B = 5
+    Ns = np.array([1300, 2, 700, 2600, 256])
+    th = rng.uniform(0.5, 2.0, (B, 1))
+    y0 = rng.uniform(-2, 2, (B, 2))
+    al, hs = np.full(B, 0.9), np.full(B, 0.01)
+    hs[3] = 1.0  # Van der Pol with a large step: this instance blows up (step 12)
+    plan = F.fabm_plan("vdp", 2, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()))
+    ws = F._workspace(F.fabm_adjoint_workspace_size(plan, Ns))
+    row_off = _offsets(Ns)
+    y0d, thd = torch.tensor(y0, device="cuda"), torch.tensor(th, device="cuda")
+    y = torch.full((int((Ns + 1).sum()), 2), -5.0, dtype=torch.float64, device="cuda")
+    st = torch.full((B,), -9, dtype=torch.int64, device="cuda")
+    F.fabm_adjoint_forward(plan, ws, al, hs, Ns, y0d, thd, row_off, y, st)
+    ys, _, sts = F.solve_batch("vdp", th, al, hs, Ns, y0, path="blocked")
+    assert torch.equal(st, sts) and int(st[3].item()) > 0
+    ok = ~torch.isnan(ys)
+    assert torch.equal(y[ok], ys[ok]) and torch.equal(torch.isnan(y), ~ok)
+    gy = torch.tensor(rng.standard_normal((int((Ns + 1).sum()), 2)), device="cuda")
+    gy0 = torch.empty((B, 2), dtype=torch.float64, device="cuda")
+    gth = torch.empty((B, 1), dtype=torch.float64, device="cuda")
+    F.fabm_adjoint_reverse(plan, ws, al, hs, Ns, y0d, thd, row_off, gy, gy0, gth)
+    r0, rt, rst = F.adjoint_batch("vdp", th, al, hs, Ns, y0, gy)
+    assert torch.equal(rst, st)
+    for a, b in ((gy0, r0), (gth, rt)):
+        assert torch.equal(torch.isnan(a), torch.isnan(b))
+        assert torch.equal(a[~torch.isnan(a)], b[~torch.isnan(b)])
+    assert torch.all(torch.isnan(gy0[3])) and not torch.any(torch.isnan(gy0[[0, 1, 2, 4]]))
