@@ -115,6 +115,9 @@ typedef struct {
     int32_t flags;           /* reserved, must be 0 */
 } fabm_plan_desc;
 
+/* A plan is used by one host thread at a time: calls that share a plan share
+ * its pinned staging buffer and schedule cache. Different plans are
+ * independent. */
 typedef struct fabm_plan_s *fabm_plan_t;
 
 /* Description of the last HIP failure behind a FABM_ERR_DEVICE returned to
@@ -133,7 +136,8 @@ int32_t fabm_n_params(fabm_system system, int32_t dim);
  * covers any call within the described maxima. Errors: INVALID_ARG for a
  * null pointer, unknown system, dim out of range, max_* < 1, bad tile_L or
  * nonzero flags; UNSUPPORTED for a far precision, block length or path the
- * system does not offer (FP16X2 outside LINEAR, DIRECT for LINEAR d > 4). */
+ * system does not offer (FP16X2 outside LINEAR, DIRECT for LINEAR d > 4), or
+ * a shared-grid plan with max_batch * dim above 2^30 history columns. */
 fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *workspace_bytes);
 
 /* Release a plan (host memory only). NULL is ignored. */

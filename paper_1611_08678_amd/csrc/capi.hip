@@ -71,6 +71,7 @@ constexpr int64_t kGridDirectMinSteps = 8192;  // single trajectories this long 
 constexpr int kGridMax = 256;                  // MI355X compute units
 constexpr int64_t kAutoBlockedMinSteps = 1024;
 constexpr uint64_t kWaitTimeoutSeconds = 10;  // no legitimate wait comes near this
+constexpr int64_t kWideMaxCols = (int64_t)1 << 30;  // shared grid: instances x d
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -236,6 +237,10 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         L.NB = (int)((maxN + 1 + Lb - 1) / Lb);
         L.wlen = (int64_t)L.NB * Lb + Lb;
         L.cp = (batch * d + fabm::kWideColAlign - 1) / fabm::kWideColAlign * fabm::kWideColAlign;
+        if (L.cp > kWideMaxCols) {  // column indices and launch shapes are 32-bit
+            L.path = Path::Unsupported;
+            return L;
+        }
         const size_t cells = (size_t)L.NB * Lb * (size_t)L.cp;  // history rows x columns
         const fabm_far_prec fp = pl->desc.far_prec;
         L.stage_bytes = off;
@@ -742,6 +747,7 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     if (desc->tile_L != 0 && desc->tile_L != (wide ? fabm::kWideBlk : fabm::step_block_len()))
         return FABM_ERR_UNSUPPORTED;
     if (wide && desc->path == FABM_PATH_DIRECT) return FABM_ERR_UNSUPPORTED;
+    if (wide && desc->max_batch > kWideMaxCols / desc->dim) return FABM_ERR_UNSUPPORTED;
 
     fabm_plan_s *pl = new (std::nothrow) fabm_plan_s();
     if (!pl) return FABM_ERR_INVALID_ARG;

@@ -112,7 +112,8 @@ def test_plan_shared_grid_rules(fabm):
                dict(system="linear", dim=64, path="direct"),
                dict(system="chen", dim=3, tile_L=64),
                dict(system="linear", dim=64, tile_L=256),
-               dict(system="linear", dim=3, tile_L=128)):
+               dict(system="linear", dim=3, tile_L=128),
+               dict(system="linear", dim=64, max_batch=(1 << 24) + 1)):
         with pytest.raises(fabm.FabmError) as e:
             fabm.fabm_plan(**kw)
         assert e.value.code == 2, kw
