@@ -49,9 +49,11 @@ def parse():
                     help="skip the instrumented solve that measures per-kernel time")
     ap.add_argument("--workload", default="chen",
                     choices=["chen", "rossler_batch", "vdp_batch", "vdp_adjoint",
-                             "linear64_batch"],
+                             "linear64_batch", "hr_table2"],
                     help="chen: the headline single trajectory; the batch workloads are "
-                         "additional measurements of the batched BLOCKED path")
+                         "additional measurements of the batched BLOCKED path; hr_table2: "
+                         "one Hindmarsh-Rose trajectory swept over the step counts of the "
+                         "paper's Section 4 timing table")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the benchmark "
                          "(untimed; a reference kernel of known traffic for hardware counters)")
@@ -60,6 +62,8 @@ def parse():
                          "instance, HBM-bound)")
     ap.add_argument("--tune", action="store_true",
                     help="batch workloads: run fabm_tune on the plan before timing (untimed)")
+    ap.add_argument("--sweep-N", default=None,
+                    help="hr_table2: comma list of step counts (default: all of the table's)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
                     help="far-window arithmetic (default: fp64; rossler_batch: fp32; "
                          "fp16x2 only for linear64_batch)")
@@ -391,6 +395,76 @@ def bench_adjoint(F, W, args):
     print(json.dumps(out), flush=True)
 
 
+# Average seconds the paper reports for its Hindmarsh-Rose runs (Section 4,
+# Table 2) on a BlueGene/P partition and on a CUDA GPU, neither named further;
+# model parameters, alpha, h and precision of those runs are not given, so
+# these are context for the shape of the sweep, not a baseline of this workload.
+PAPER_TABLE2_S = {100_000: (170.75, 169.06), 500_000: (1592.66, 1276.42),
+                  1_000_000: (4621.25, 2670.56), 1_500_000: (9162.33, 4450.09),
+                  2_000_000: (14931.16, 6639.45), 2_500_000: (22697.66, 9229.66),
+                  3_000_000: (31659.66, 12226.39)}
+
+
+def bench_table2(F, W, args):
+    """One Hindmarsh-Rose trajectory (d = 3) solved by the BLOCKED path at each
+    step count of the paper's timing table. `value` is the whole sweep's
+    steps*states over its summed solve time; each N is also reported alone."""
+    import numpy as np
+    rows, tot_states, tot_t = [], 0.0, 0.0
+    head = None
+    Ns = [int(n) for n in args.sweep_N.split(",")] if args.sweep_N else list(W.TABLE2_N)
+    for N in Ns:
+        w = W.hindmarsh_rose(N=N)
+        print(f"# hr_table2: N={N} blocked, {args.warmup} warmup + {args.steps} timed",
+              file=sys.stderr, flush=True)
+        r = time_path(F, w, "blocked", args.steps, args.warmup,
+                      kernel_times=not args.no_kernel_times)
+        t = float(np.mean(r["solve_s"]))
+        y = r["y"]
+        hpc, cuda = PAPER_TABLE2_S.get(N, (None, None))
+        rows.append(dict(N=N, solve_s=t, steps_states_per_s=N * 3 / t,
+                         history_gflops=2.0 * 3 * N * (N + 1) / t / 1e9, status=r["status"],
+                         finite=bool(np.all(np.isfinite(y))),
+                         x_range=[float(y[:, 0].min()), float(y[:, 0].max())],
+                         paper_cuda_s=cuda, paper_hpc_s=hpc,
+                         ratio_paper_cuda_over_this=cuda / t if cuda else None))
+        print(f"# hr_table2: N={N} solve {t:.4f} s", file=sys.stderr, flush=True)
+        tot_states += N * 3
+        tot_t += t
+        head = (N, r)
+    N, r = head
+    value = tot_states / tot_t
+    out = {
+        "metric": "steps*states/s (history GFLOP/s alongside), blocked path, N sweep",
+        "value": value, "unit": "steps*states/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": tot_t * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": ("fractional Hindmarsh-Rose (a,b,c,d,r,s,xr,I)=(1,3,1,5,0.006,4,"
+                                "-1.6,3.25), alpha=0.95, h=0.01, y0=(-1.6,-10,2), d=3, one "
+                                "trajectory per N, N in " + ",".join(str(n) for n in Ns)),
+                   "path": "blocked", "far_prec": "fp64"},
+        "sweep": rows,
+        "paper_context": ("paper Table 2: average seconds on a BlueGene/P partition and an "
+                          "unnamed CUDA GPU for Hindmarsh-Rose runs of unstated parameters, "
+                          "step size and precision; ratios are context, not a baseline"),
+    }
+    kt = r.get("kernel_times")
+    if kt:
+        out["kernel_times_s_at_largest_N"] = {k: v[0] for k, v in kt.items() if v[1]}
+    out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, 3)
+    if out["roofline"]:
+        out["roofline"]["at_N"] = N
+    if args.cpu_sample > 0:
+        w = W.hindmarsh_rose(N=N)
+        yref, cpu = cpu_baseline(w, min(args.cpu_sample, N), N)
+        n = yref.shape[0]
+        out["cpu_baseline"] = cpu
+        scale = np.abs(yref).max()
+        out["rel_err_sample_prefix"] = float((np.abs(r["y"][:n] - yref).max(axis=1) /
+                                              scale).max())
+    print(json.dumps(out), flush=True)
+
+
 def copy_reference(mib: int):
     """One device-to-device copy of `mib` MiB (reads and writes that many bytes)."""
     import torch
@@ -416,6 +490,8 @@ def main():
         F.load()
         if args.workload == "vdp_adjoint":
             return bench_adjoint(F, W, args)
+        if args.workload == "hr_table2":
+            return bench_table2(F, W, args)
         return bench_batch(F, W, args)
     import numpy as np
     import paper_1611_08678_amd as F

@@ -61,13 +61,17 @@ typedef enum {
  *   CHEN       (a(y-x), (c-a)x - xz + cy, xy - bz);  theta = (a, b, c), d = 3
  *   ROSSLER    (-y-z, x + a y, b + z(x-c));          theta = (a, b, c), d = 3
  *   VDP        (v, mu(1-x^2)v - x);                  theta = (mu),      d = 2
- *   FINANCIAL  (z + (y-a)x, 1 - b y - x^2, -x - cz); theta = (a, b, c), d = 3 */
+ *   FINANCIAL  (z + (y-a)x, 1 - b y - x^2, -x - cz); theta = (a, b, c), d = 3
+ *   HINDMARSH_ROSE (y - a x^3 + b x^2 - z + I, c - d x^2 - y, r (s (x - xr) - z));
+ *              theta = (a, b, c, d, r, s, xr, I), d = 3 (the neuron model the
+ *              paper's experiments simulate) */
 typedef enum {
     FABM_SYS_LINEAR = 0,
     FABM_SYS_CHEN = 1,
     FABM_SYS_ROSSLER = 2,
     FABM_SYS_VDP = 3,
-    FABM_SYS_FINANCIAL = 4
+    FABM_SYS_FINANCIAL = 4,
+    FABM_SYS_HINDMARSH_ROSE = 5
 } fabm_system;
 
 /* How the history sums P_t, C_t are contracted.

@@ -45,6 +45,8 @@ enum {
     ORC_ROSSLER = 2,   /* (-y-z, x + a y, b + z(x-c)),          theta = (a,b,c) */
     ORC_VDP = 3,       /* (v, mu(1-x^2)v - x),                  theta = (mu)    */
     ORC_FINANCIAL = 4, /* (z + (y-a)x, 1 - b y - x^2, -x - c z), theta = (a,b,c) */
+    ORC_HINDMARSH_ROSE = 5, /* (y - a x^3 + b x^2 - z + I, c - d x^2 - y, r (s (x - xr) - z)),
+                               theta = (a, b, c, d, r, s, xr, I) */
     ORC_CALLBACK = 99  /* user function pointer (oracle-only test problems) */
 };
 
@@ -95,6 +97,13 @@ static void rhs_eval(const orc_rhs *r, double t, const double *y, double *f)
         f[1] = 1.0 - p[1] * y[1] - y[0] * y[0];
         f[2] = -y[0] - p[2] * y[2];
         break;
+    case ORC_HINDMARSH_ROSE: {
+        const double x = y[0];
+        f[0] = y[1] - p[0] * x * x * x + p[1] * x * x - y[2] + p[7];
+        f[1] = p[2] - p[3] * x * x - y[1];
+        f[2] = p[4] * (p[5] * (x - p[6]) - y[2]);
+        break;
+    }
     case ORC_CALLBACK:
         r->cb(t, y, f, r->user);
         break;
@@ -110,6 +119,7 @@ int oracle_n_params(int system, int d)
     case ORC_LINEAR: return d * d + 2 * d;
     case ORC_CHEN: case ORC_ROSSLER: case ORC_FINANCIAL: return 3;
     case ORC_VDP: return 1;
+    case ORC_HINDMARSH_ROSE: return 8;
     default: return 0;
     }
 }
@@ -118,7 +128,7 @@ int oracle_dim(int system, int d_linear)
 {
     switch (system) {
     case ORC_LINEAR: return d_linear;
-    case ORC_CHEN: case ORC_ROSSLER: case ORC_FINANCIAL: return 3;
+    case ORC_CHEN: case ORC_ROSSLER: case ORC_FINANCIAL: case ORC_HINDMARSH_ROSE: return 3;
     case ORC_VDP: return 2;
     default: return -1;
     }
@@ -182,6 +192,23 @@ static void rhs_vjp(const orc_rhs *r, double t, const double *y,
         gth[0] += fbar[0] * (-x);
         gth[1] += fbar[1] * (-yy);
         gth[2] += fbar[2] * (-z);
+        break;
+    }
+    case ORC_HINDMARSH_ROSE: {
+        double a = p[0], b = p[1], d = p[3], r = p[4], sg = p[5], xr = p[6];
+        double x = y[0], z = y[2];
+        gy[0] += fbar[0] * (-3.0 * a * x * x + 2.0 * b * x) + fbar[1] * (-2.0 * d * x) +
+                 fbar[2] * (r * sg);
+        gy[1] += fbar[0] - fbar[1];
+        gy[2] += -fbar[0] - fbar[2] * r;
+        gth[0] += fbar[0] * (-x * x * x);
+        gth[1] += fbar[0] * (x * x);
+        gth[2] += fbar[1];
+        gth[3] += fbar[1] * (-x * x);
+        gth[4] += fbar[2] * (sg * (x - xr) - z);
+        gth[5] += fbar[2] * (r * (x - xr));
+        gth[6] += fbar[2] * (-r * sg);
+        gth[7] += fbar[0];
         break;
     }
     default:

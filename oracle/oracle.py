@@ -22,7 +22,7 @@ SRC = os.path.join(HERE, "fabm_oracle.c")
 SO = os.path.join(HERE, "liboracle.so")
 
 # Own numbering of the right-hand sides (see fabm_oracle.c).
-LINEAR, CHEN, ROSSLER, VDP, FINANCIAL = 0, 1, 2, 3, 4
+LINEAR, CHEN, ROSSLER, VDP, FINANCIAL, HINDMARSH_ROSE = 0, 1, 2, 3, 4, 5
 
 _lib = None
 

@@ -18,12 +18,14 @@ SO = os.path.join(HERE, "libfabm.so")
 
 # enums of fabm.h
 FABM_OK, FABM_ERR_INVALID_ARG, FABM_ERR_UNSUPPORTED, FABM_ERR_WORKSPACE, FABM_ERR_DEVICE = range(5)
-FABM_SYS_LINEAR, FABM_SYS_CHEN, FABM_SYS_ROSSLER, FABM_SYS_VDP, FABM_SYS_FINANCIAL = range(5)
+(FABM_SYS_LINEAR, FABM_SYS_CHEN, FABM_SYS_ROSSLER, FABM_SYS_VDP, FABM_SYS_FINANCIAL,
+ FABM_SYS_HINDMARSH_ROSE) = range(6)
 FABM_PATH_AUTO, FABM_PATH_DIRECT, FABM_PATH_BLOCKED = range(3)
 FABM_FAR_FP64, FABM_FAR_FP32, FABM_FAR_FP16X2 = range(3)
 
 SYSTEMS = {"linear": FABM_SYS_LINEAR, "chen": FABM_SYS_CHEN, "rossler": FABM_SYS_ROSSLER,
-           "vdp": FABM_SYS_VDP, "financial": FABM_SYS_FINANCIAL}
+           "vdp": FABM_SYS_VDP, "financial": FABM_SYS_FINANCIAL,
+           "hindmarsh_rose": FABM_SYS_HINDMARSH_ROSE}
 PATHS = {"auto": FABM_PATH_AUTO, "direct": FABM_PATH_DIRECT, "blocked": FABM_PATH_BLOCKED}
 FAR_PRECS = {"fp64": FABM_FAR_FP64, "fp32": FABM_FAR_FP32, "fp16x2": FABM_FAR_FP16X2}
 

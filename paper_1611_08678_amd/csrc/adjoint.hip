@@ -38,10 +38,6 @@ constexpr int kColPitch = 17;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int n_params_of_sys(int sys, int d)
-{
-    return sys == SYS_LINEAR ? d * d + 2 * d : (sys == SYS_VDP ? 1 : 3);
-}
 
 }  // namespace
 
@@ -477,6 +473,7 @@ hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule
     FABM_ADJ_CASE(SYS_ROSSLER, 3)
     FABM_ADJ_CASE(SYS_VDP, 2)
     FABM_ADJ_CASE(SYS_FINANCIAL, 3)
+    FABM_ADJ_CASE(SYS_HINDMARSH_ROSE, 3)
 #undef FABM_ADJ_CASE
     *where = "no adjoint kernel for this system/dimension";
     return hipErrorInvalidValue;

@@ -43,10 +43,6 @@ constexpr int kTile = 16;  // polyphase factor = MFMA edge
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-constexpr int n_params_of_sys(int sys, int d)
-{
-    return sys == SYS_LINEAR ? d * d + 2 * d : (sys == SYS_VDP ? 1 : 3);
-}
 
 }  // namespace
 
@@ -905,6 +901,7 @@ hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const Bat
     FABM_BATCH_CASE(SYS_ROSSLER, 3)
     FABM_BATCH_CASE(SYS_VDP, 2)
     FABM_BATCH_CASE(SYS_FINANCIAL, 3)
+    FABM_BATCH_CASE(SYS_HINDMARSH_ROSE, 3)
 #undef FABM_BATCH_CASE
     *where = "no BLOCKED kernel for this system/dimension";
     return hipErrorInvalidValue;
@@ -925,6 +922,7 @@ hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_
     FABM_STEP_CASE(SYS_ROSSLER, 3)
     FABM_STEP_CASE(SYS_VDP, 2)
     FABM_STEP_CASE(SYS_FINANCIAL, 3)
+    FABM_STEP_CASE(SYS_HINDMARSH_ROSE, 3)
 #undef FABM_STEP_CASE
     *where = "no BLOCKED kernel for this system/dimension";
     return hipErrorInvalidValue;

@@ -333,6 +333,7 @@ hipError_t launch_blocked_single(int sys, int d, int G, const BlockedArgs &A, hi
     FABM_BLK_CASE(SYS_ROSSLER, 3)
     FABM_BLK_CASE(SYS_VDP, 2)
     FABM_BLK_CASE(SYS_FINANCIAL, 3)
+    FABM_BLK_CASE(SYS_HINDMARSH_ROSE, 3)
 #undef FABM_BLK_CASE
     return hipErrorInvalidValue;
 }

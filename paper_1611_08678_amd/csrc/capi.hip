@@ -85,6 +85,7 @@ int32_t n_params_of(int sys, int d)
     case FABM_SYS_ROSSLER:
     case FABM_SYS_FINANCIAL: return d == 3 ? 3 : -1;
     case FABM_SYS_VDP: return d == 2 ? 1 : -1;
+    case FABM_SYS_HINDMARSH_ROSE: return d == 3 ? 8 : -1;
     default: return -1;
     }
 }

@@ -321,7 +321,7 @@ struct Dispatch;
 #define FABM_DIRECT_CASES(MACRO)                                   \
     MACRO(SYS_LINEAR, 1) MACRO(SYS_LINEAR, 2) MACRO(SYS_LINEAR, 3) \
     MACRO(SYS_LINEAR, 4) MACRO(SYS_CHEN, 3) MACRO(SYS_ROSSLER, 3)  \
-    MACRO(SYS_VDP, 2) MACRO(SYS_FINANCIAL, 3)
+    MACRO(SYS_VDP, 2) MACRO(SYS_FINANCIAL, 3) MACRO(SYS_HINDMARSH_ROSE, 3)
 
 hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
                             const double *params, const double *y0, double *F, const double *W,

@@ -28,7 +28,23 @@ struct InstMeta {
 };
 static_assert(sizeof(InstMeta) == 88, "InstMeta layout");
 
-enum : int { SYS_LINEAR = 0, SYS_CHEN = 1, SYS_ROSSLER = 2, SYS_VDP = 3, SYS_FINANCIAL = 4 };
+enum : int {
+    SYS_LINEAR = 0,
+    SYS_CHEN = 1,
+    SYS_ROSSLER = 2,
+    SYS_VDP = 3,
+    SYS_FINANCIAL = 4,
+    SYS_HINDMARSH_ROSE = 5
+};
+
+// Entries of theta of each system (LINEAR: A, b0, b1).
+constexpr int n_params_of_sys(int sys, int d)
+{
+    return sys == SYS_LINEAR ? d * d + 2 * d
+           : sys == SYS_VDP ? 1
+           : sys == SYS_HINDMARSH_ROSE ? 8
+                                       : 3;
+}
 
 // f(t, y; theta) for the fixed set of systems (textbook forms; parameter
 // layout as documented in fabm.h). D is the state dimension.
@@ -63,6 +79,12 @@ __device__ __forceinline__ void rhs(double t, const double (&y)[D], double (&f)[
         f[0] = fma(y[1] - a, y[0], y[2]);
         f[1] = 1.0 - b * y[1] - y[0] * y[0];
         f[2] = -y[0] - c * y[2];
+    } else if constexpr (SYS == SYS_HINDMARSH_ROSE) {
+        // theta = (a, b, c, d, r, s, xr, I)
+        const double x = y[0], x2 = x * x;
+        f[0] = fma(x2, fma(-p[0], x, p[1]), y[1] - y[2] + p[7]);
+        f[1] = fma(-p[3], x2, p[2] - y[1]);
+        f[2] = p[4] * fma(p[5], x - p[6], -y[2]);
     }
 }
 
@@ -118,6 +140,20 @@ __device__ __forceinline__ void rhs_vjp(double t, const double (&y)[D], const do
         gth[0] += -y[0] * w[0];
         gth[1] += -y[1] * w[1];
         gth[2] += -y[2] * w[2];
+    } else if constexpr (SYS == SYS_HINDMARSH_ROSE) {
+        const double a = p[0], b = p[1], d = p[3], r = p[4], s = p[5], xr = p[6];
+        const double x = y[0], x2 = x * x;
+        gy[0] += (-3.0 * a * x2 + 2.0 * b * x) * w[0] - 2.0 * d * x * w[1] + r * s * w[2];
+        gy[1] += w[0] - w[1];
+        gy[2] += -w[0] - r * w[2];
+        gth[0] += -x2 * x * w[0];
+        gth[1] += x2 * w[0];
+        gth[2] += w[1];
+        gth[3] += -x2 * w[1];
+        gth[4] += (s * (x - xr) - y[2]) * w[2];
+        gth[5] += r * (x - xr) * w[2];
+        gth[6] += -r * s * w[2];
+        gth[7] += w[0];
     }
 }
 

@@ -1,6 +1,6 @@
 """Seeded synthetic workloads (inputs only).
 
-This module draws the inputs of the five benchmark/parity workloads with
+This module draws the inputs of the benchmark/parity workloads with
 numpy's PCG64 generator and holds no arithmetic of the method itself; the
 oracle and the HIP library both take their inputs from here. Each workload is
 a dict with keys: system, theta [B, n_params], alpha [B], h [B], N [B],
@@ -16,12 +16,16 @@ y0 [B, d] (B = 1 for single trajectories) plus descriptive fields.
   vdp_adjoint    1024 Van der Pol, mu ~ U[0.5, 2], y0 ~ U[-2, 2]^2,
                  target mu_hat = mu + N(0, 0.05^2), alpha 0.9, h = 0.01,
                  N = 2^15 (seed 4)
+  hindmarsh_rose Hindmarsh-Rose neuron (a, b, c, d, r, s, xr, I) =
+                 (1, 3, 1, 5, 0.006, 4, -1.6, 3.25), alpha 0.95, h = 0.01,
+                 y0 = (-1.6, -10, 2); N from the step counts of the paper's
+                 Section 4 timing table (TABLE2_N)
 """
 from __future__ import annotations
 
 import numpy as np
 
-LINEAR, CHEN, ROSSLER, VDP, FINANCIAL = 0, 1, 2, 3, 4
+LINEAR, CHEN, ROSSLER, VDP, FINANCIAL, HINDMARSH_ROSE = 0, 1, 2, 3, 4, 5
 
 
 def _linear_theta(A, b0=None, b1=None):
@@ -75,6 +79,21 @@ def vdp_adjoint(batch: int = 1024, N: int = 1 << 15, seed: int = 4, h: float = 0
     return dict(name="vdp_adjoint", system=VDP, d=2, theta=mu[:, None].copy(),
                 theta_target=(mu + eps)[:, None].copy(), alpha=np.full(batch, alpha),
                 h=np.full(batch, h), N=np.full(batch, N, dtype=np.int64), y0=y0)
+
+
+# Step counts of the paper's Section 4 comparison of cluster and GPU run times
+# (Table 2); the model parameters, alpha and h of those runs are not given.
+TABLE2_N = (100_000, 500_000, 1_000_000, 1_500_000, 2_000_000, 2_500_000, 3_000_000)
+HR_THETA = (1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25)
+
+
+def hindmarsh_rose(N: int = 1_000_000, h: float = 0.01, alpha: float = 0.95):
+    """One Hindmarsh-Rose trajectory in the bursting regime of the integer-order
+    model (the parameter set most used in the literature); theta follows the
+    layout of the device system (a, b, c, d, r, s, xr, I)."""
+    return dict(name="hindmarsh_rose", system=HINDMARSH_ROSE, d=3,
+                theta=np.array([HR_THETA]), alpha=np.array([alpha]), h=np.array([h]),
+                N=np.array([N], dtype=np.int64), y0=np.array([[-1.6, -10.0, 2.0]]))
 
 
 def random_history(N: int, d: int, seed: int = 0):

@@ -35,8 +35,9 @@ def test_library_exports_every_declared_symbol(fabm):
 def test_enums_match_oracle_numbering(fabm):
     from oracle import oracle as O
     assert (fabm.FABM_SYS_LINEAR, fabm.FABM_SYS_CHEN, fabm.FABM_SYS_ROSSLER, fabm.FABM_SYS_VDP,
-            fabm.FABM_SYS_FINANCIAL) == (O.LINEAR, O.CHEN, O.ROSSLER, O.VDP, O.FINANCIAL)
-    for sysid, d in [(0, 1), (0, 7), (1, 3), (2, 3), (3, 2), (4, 3)]:
+            fabm.FABM_SYS_FINANCIAL, fabm.FABM_SYS_HINDMARSH_ROSE) == (
+        O.LINEAR, O.CHEN, O.ROSSLER, O.VDP, O.FINANCIAL, O.HINDMARSH_ROSE)
+    for sysid, d in [(0, 1), (0, 7), (1, 3), (2, 3), (3, 2), (4, 3), (5, 3)]:
         assert fabm.fabm_n_params(sysid, d) == O.n_params(sysid, d)
     assert fabm.fabm_n_params(fabm.FABM_SYS_CHEN, 2) == -1
     assert fabm.fabm_n_params(fabm.FABM_SYS_LINEAR, 65) == -1

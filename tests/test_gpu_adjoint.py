@@ -11,7 +11,7 @@ from tests.test_gpu_direct import _to_np
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
-SID = {"linear": 0, "chen": 1, "rossler": 2, "vdp": 3, "financial": 4}
+SID = {"linear": 0, "chen": 1, "rossler": 2, "vdp": 3, "financial": 4, "hindmarsh_rose": 5}
 
 
 @pytest.fixture(scope="module")
@@ -65,6 +65,7 @@ def test_adjoint_vdp_ragged_batch(F, orc):
     ("chen", 3, [35.0, 3.0, 28.0], 0.95, 0.001, 1500),
     ("rossler", 3, [0.2, 0.2, 5.7], 0.93, 0.005, 2600),
     ("financial", 3, [3.0, 0.1, 1.0], 0.85, 0.01, 2200),
+    ("hindmarsh_rose", 3, [1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25], 0.95, 0.01, 3000),
     ("linear", 1, None, 0.5, 0.005, 2000),
     ("linear", 3, None, 0.8, 0.01, 1800),
     ("linear", 4, None, 0.95, 0.01, 1300),

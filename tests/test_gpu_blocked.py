@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from tests.conftest import gpu_available
-from tests.test_gpu_direct import _batch_parity, _chen_horizon, _to_np, relerr
+from tests.test_gpu_direct import _batch_parity, _chen_horizon, _hr_theta, _to_np, relerr
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -110,6 +110,57 @@ def test_blocked_chen_full_size(F, orc):
         assert np.all(np.abs(yy[t] - yt) <= tol), (t, yy[t], yt, mag)
 
 
+@pytest.mark.parametrize("far_prec", ["fp64", "fp32"])
+def test_blocked_hindmarsh_rose(F, orc, far_prec):
+    """Hindmarsh-Rose over 20000 steps, every row against the oracle (its
+    one-ulp sensitivity horizon spans the trajectory): 1e-11 for FP64 windows.
+    The bursts amplify perturbations (a single relative change of 2^-24 in y0
+    grows about 200-fold in the oracle itself), so the FP32 windows, which
+    round every far sum to binary32, are held to 30 times the oracle's own
+    response to that single perturbation rather than to the bound of the
+    non-spiking systems."""
+    from paper_1611_08678_amd import workloads as W
+    N = 20000
+    w = W.hindmarsh_rose(N=N)
+    th, a, h, y0 = w["theta"][0], w["alpha"][0], w["h"][0], w["y0"][0]
+    y, st = F.solve("hindmarsh_rose", th, a, h, N, y0, path="blocked", far_prec=far_prec)
+    ref, _, _, rst = orc.solve(w["system"], th, a, h, N, y0)
+    assert int(st.item()) == rst == 0
+    err = relerr(_to_np(y), ref)
+    if far_prec == "fp64":
+        assert err <= 1e-11
+        return
+    alt, _, _, _ = orc.solve(w["system"], th, a, h, N, y0 * (1 + 2.0 ** -24))
+    assert 1e-12 < err <= 30 * relerr(alt, ref), (err, relerr(alt, ref))
+
+
+def test_blocked_hindmarsh_rose_longest_table_size(F, orc):
+    """The longest run of the paper's timing table (N = 3e6, T = 30000) in the
+    launch configuration of the N sweep: status 0, finite and inside the
+    attractor's box, the first 4096 rows against the oracle, and sampled rows
+    anywhere re-formed by the oracle from the GPU's own history with the
+    recursive-summation bound used for Chen at full size."""
+    from paper_1611_08678_amd import workloads as W
+    N = W.TABLE2_N[-1]
+    w = W.hindmarsh_rose(N=N)
+    th, a, h, y0 = w["theta"][0], w["alpha"][0], w["h"][0], w["y0"][0]
+    y, st = F.solve("hindmarsh_rose", th, a, h, N, y0, path="blocked")
+    yy = _to_np(y)
+    assert int(st.item()) == 0
+    assert np.all(np.isfinite(yy))
+    assert np.all(np.abs(yy[:, 0]) < 3) and np.all(np.abs(yy[:, 1]) < 20)
+    assert np.all(np.abs(yy[:, 2]) < 6)
+    ref, _, _, _ = orc.solve(w["system"], th, a, h, 4096, y0)
+    assert relerr(yy[:4097], ref) <= 1e-11
+    u = np.finfo(np.float64).eps / 2
+    wts = orc.weights(a, N)
+    f = orc.rhs_rows(w["system"], th, h, yy)
+    for t in (4097, 100_000, 1_000_000, 2_000_003, N - 255, N):
+        yt, mag = orc.step_from_history(w["system"], th, a, h, t, y0, f, wts)
+        tol = 10.0 * np.sqrt(t) * u * mag + 4 * u * np.abs(yt)
+        assert np.all(np.abs(yy[t] - yt) <= tol), (t, yy[t], yt, mag)
+
+
 def test_blocked_kernel_times(F):
     """The profiling interface reports one step launch per 256-row block."""
     import torch
@@ -140,7 +191,8 @@ def test_blocked_batch_rossler_ragged(F, orc):
     _batch_parity(F, orc, w, path="blocked")
 
 
-@pytest.mark.parametrize("sysname", ["vdp", "financial", "linear2", "linear4"])
+@pytest.mark.parametrize("sysname", ["vdp", "financial", "hindmarsh_rose", "linear2",
+                                     "linear4"])
 def test_blocked_batch_systems(F, orc, sysname):
     rng = np.random.default_rng(23)
     B = 12
@@ -148,6 +200,8 @@ def test_blocked_batch_systems(F, orc, sysname):
         theta, d, sid = rng.uniform(0.5, 2, (B, 1)), 2, 3
     elif sysname == "financial":
         theta, d, sid = np.tile([3.0, 0.1, 1.0], (B, 1)), 3, 4
+    elif sysname == "hindmarsh_rose":
+        theta, d, sid = _hr_theta(rng, B), 3, 5
     else:
         d, sid = int(sysname[-1]), 0
         theta = np.stack([_lin(d, 100 + i)[0] for i in range(B)])

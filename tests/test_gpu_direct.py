@@ -102,8 +102,17 @@ def test_rossler_ragged_batch_direct(F, orc):
     _batch_parity(F, orc, w)
 
 
-@pytest.mark.parametrize("sysname", ["vdp", "financial", "linear1", "linear2", "linear3",
-                                     "linear4"])
+def _hr_theta(rng, B):
+    """Hindmarsh-Rose parameters of the bursting set with the applied current I
+    drawn from [2.5, 3.5] per instance."""
+    from paper_1611_08678_amd import workloads as W
+    theta = np.tile(W.HR_THETA, (B, 1))
+    theta[:, 7] = rng.uniform(2.5, 3.5, B)
+    return theta
+
+
+@pytest.mark.parametrize("sysname", ["vdp", "financial", "hindmarsh_rose", "linear1", "linear2",
+                                     "linear3", "linear4"])
 def test_systems_direct(F, orc, sysname):
     rng = np.random.default_rng(17)
     B = 6
@@ -111,6 +120,8 @@ def test_systems_direct(F, orc, sysname):
         theta, d, sid = rng.uniform(0.5, 2, (B, 1)), 2, 3
     elif sysname == "financial":
         theta, d, sid = np.tile([3.0, 0.1, 1.0], (B, 1)), 3, 4
+    elif sysname == "hindmarsh_rose":
+        theta, d, sid = _hr_theta(rng, B), 3, 5
     else:
         d, sid = int(sysname[-1]), 0
         A = -(2 * np.eye(d) + rng.standard_normal((B, d, d)) / 8)
@@ -119,6 +130,20 @@ def test_systems_direct(F, orc, sysname):
     w = dict(system=sid, theta=theta, alpha=rng.uniform(0.6, 1.0, B), h=np.full(B, 0.01),
              N=rng.integers(50, 900, B), y0=rng.uniform(-1.5, 1.5, (B, d)))
     _batch_parity(F, orc, w)
+
+
+def test_hindmarsh_rose_direct(F, orc):
+    """The Hindmarsh-Rose neuron over 20000 steps (T = 200, several bursts):
+    the oracle's own one-ulp sensitivity horizon spans the whole trajectory, so
+    every row is compared."""
+    from paper_1611_08678_amd import workloads as W
+    w = W.hindmarsh_rose(N=20000)
+    y, st = F.solve("hindmarsh_rose", w["theta"][0], w["alpha"][0], w["h"][0], 20000,
+                    w["y0"][0], path="direct")
+    ref, _, _, rst = orc.solve(w["system"], w["theta"][0], w["alpha"][0], w["h"][0], 20000,
+                               w["y0"][0])
+    assert int(st.item()) == rst == 0
+    assert relerr(_to_np(y), ref) <= 1e-11
 
 
 def test_blow_up_status_matches_oracle(F, orc):

@@ -16,6 +16,8 @@ SYSTEMS = {
     "chen": (1, [35.0, 3.0, 28.0], [-9.0, -5.0, 14.0], 0.95, 0.001, 200),
     "rossler": (2, [0.2, 0.2, 5.7], [1.0, -2.0, 0.5], 0.93, 0.005, 250),
     "financial": (4, [3.0, 0.1, 1.0], [0.5, 1.0, -0.3], 0.85, 0.01, 200),
+    "hindmarsh_rose": (5, [1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25], [-1.2, -7.0, 2.5], 0.95,
+                       0.01, 200),
     "linear": (0, None, [0.4, -1.2], 0.8, 0.01, 250),
 }
 

@@ -193,6 +193,16 @@ def test_system_equilibria(orc):
     assert np.abs(orc.rhs(orc.VDP, [1.7], 0.0, [0.0, 0.0])).max() == 0.0
     # financial system (a, b, c): equilibrium (0, 1/b, 0)
     assert np.abs(orc.rhs(orc.FINANCIAL, [3.0, 0.1, 1.0], 0.0, [0.0, 10.0, 0.0])).max() < 1e-12
+    # Hindmarsh-Rose: with y* = c - d x*^2 and z* = s (x* - xr), x* is a real root
+    # of -a x^3 + (b - d) x^2 - s x + (c + s xr + I) (numpy's polynomial roots)
+    th = [1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25]
+    a, b, c, d, r, sg, xr, I = th
+    roots = np.roots([-a, b - d, -sg, c + sg * xr + I])
+    xs = [z.real for z in roots if abs(z.imag) < 1e-12]
+    assert xs
+    for x in xs:
+        y = [x, c - d * x * x, sg * (x - xr)]
+        assert np.abs(orc.rhs(orc.HINDMARSH_ROSE, th, 0.0, y)).max() < 1e-12
     # linear: A y* + b0 = 0
     A = np.array([[-2.0, 0.3], [0.1, -1.0]])
     b0 = np.array([0.4, -0.2])
