@@ -24,7 +24,10 @@
  *   - the predictor weight is b_m = ((m+1)^a - m^a)/Gamma(a+1), with a minus
  *     sign; the printed "+" would not reproduce a constant right-hand side
  *     and gives b_m = 2m+1 at a = 1;
- *   - alpha lies in (0, 1]; only y(0) is needed (ceil(alpha) = 1);
+ *   - alpha lies in (0, 2]; the ceil(alpha) initial values y(0) and, for
+ *     alpha > 1, y'(0) enter every step through the Taylor polynomial
+ *     sum_{k < ceil(alpha)} t^k / k! y^(k)(0) of eq. (1) (y0 + t y'(0)); the
+ *     weights keep their formulas, which hold for any alpha > 0;
  *   - history values f_k are evaluated at the corrected y_k; t_n = n*h;
  *   - a non-finite state freezes the trajectory: the step index where it
  *     first appears is returned and every later row is NaN.
@@ -254,13 +257,27 @@ static int all_finite(const double *v, int d)
     return 1;
 }
 
+/* Number of initial values eq. (1) needs: ceil(alpha) (1 or 2 here). */
+static int n_init_of(double alpha) { return alpha > 1.0 ? 2 : 1; }
+
+/* The Taylor polynomial of the initial values at t (the term that stands
+ * before the history integral in eq. (1)): T(t) = y(0) + t y'(0) for
+ * 1 < alpha <= 2, y(0) otherwise. init is [ceil(alpha)][d]. */
+static void taylor_base(double alpha, double t, const double *init, int d, double *out)
+{
+    for (int i = 0; i < d; ++i) out[i] = init[i];
+    if (n_init_of(alpha) == 2)
+        for (int i = 0; i < d; ++i) out[i] += t * init[d + i];
+}
+
 /* ------------------------------------------------------------------------ */
 /* One trajectory of the PECE scheme, Section 2 (eq. (2) and the corrector). */
 /* For n = 0 .. N-1:                                                         */
 /*   P    = sum_{k=0}^{n}  b_{n-k} f_k                                       */
 /*   C    = c_n f_0 + sum_{k=1}^{n} a_{n-k} f_k                              */
-/*   yP   = y0 + h^a P,               fP = f(t_{n+1}, yP)                    */
-/*   y    = y0 + h^a (C + fP / Gamma(a+2)),  f_{n+1} = f(t_{n+1}, y)         */
+/*   yP   = T(t_{n+1}) + h^a P,       fP = f(t_{n+1}, yP)                    */
+/*   y    = T(t_{n+1}) + h^a (C + fP / Gamma(a+2)),  f_{n+1} = f(t_{n+1}, y) */
+/* with T the Taylor polynomial of the initial values y0 ([ceil(a)][d]).     */
 /* Outputs (row-major [N+1][d]): y (required), yP (row 0 = y0), f.           */
 /* b, a, c: caller-provided weight tables of length >= N (may be NULL, then  */
 /* they are computed here). Returns 0, or the first step with a non-finite   */
@@ -284,6 +301,7 @@ static int64_t solve_one(const orc_rhs *r, double alpha, double h, int64_t N,
     }
     double *F = f ? f : malloc(sizeof(double) * (N + 1) * d);
     double *ypr = malloc(sizeof(double) * d), *fp = malloc(sizeof(double) * d);
+    double *T = malloc(sizeof(double) * d);
     long double *SP = malloc(sizeof(long double) * d), *SC = malloc(sizeof(long double) * d);
 
     memcpy(y, y0, sizeof(double) * d);
@@ -315,9 +333,10 @@ static int64_t solve_one(const orc_rhs *r, double alpha, double h, int64_t N,
                 for (int i = 0; i < d; ++i) SC[i] += wak * fk[i];
             }
         }
-        for (int i = 0; i < d; ++i) ypr[i] = y0[i] + ha * (double)SP[i];
+        taylor_base(alpha, t1, y0, d, T);
+        for (int i = 0; i < d; ++i) ypr[i] = T[i] + ha * (double)SP[i];
         rhs_eval(r, t1, ypr, fp);
-        for (int i = 0; i < d; ++i) yn1[i] = y0[i] + ha * ((double)SC[i] + fp[i] * ig2);
+        for (int i = 0; i < d; ++i) yn1[i] = T[i] + ha * ((double)SC[i] + fp[i] * ig2);
         rhs_eval(r, t1, yn1, F + (n + 1) * d);
         if (yp) memcpy(yp + (n + 1) * d, ypr, sizeof(double) * d);
         if (!all_finite(yn1, d) || !all_finite(F + (n + 1) * d, d)) {
@@ -336,6 +355,7 @@ static int64_t solve_one(const orc_rhs *r, double alpha, double h, int64_t N,
     if (!f) free(F);
     free(ypr);
     free(fp);
+    free(T);
     free(SP);
     free(SC);
     return status;
@@ -368,6 +388,8 @@ void oracle_step_from_history(int system, int d, const double *theta, double alp
     long double *SP = malloc(sizeof(long double) * d), *SC = malloc(sizeof(long double) * d);
     long double *MG = malloc(sizeof(long double) * d);
     double *ypr = malloc(sizeof(double) * d), *fp = malloc(sizeof(double) * d);
+    double *T = malloc(sizeof(double) * d);
+    taylor_base(alpha, (double)t * h, y0, d, T);
     for (int i = 0; i < d; ++i) {
         SP[i] = 0.0L;
         SC[i] = (long double)wc[n] * f_hist[i];
@@ -388,12 +410,13 @@ void oracle_step_from_history(int system, int d, const double *theta, double alp
             }
         }
     }
-    for (int i = 0; i < d; ++i) ypr[i] = y0[i] + ha * (double)SP[i];
+    for (int i = 0; i < d; ++i) ypr[i] = T[i] + ha * (double)SP[i];
     rhs_eval(&r, (double)t * h, ypr, fp);
     for (int i = 0; i < d; ++i) {
-        y_out[i] = y0[i] + ha * ((double)SC[i] + fp[i] * ig2);
+        y_out[i] = T[i] + ha * ((double)SC[i] + fp[i] * ig2);
         mag_out[i] = ha * (double)MG[i];
     }
+    free(T);
     free(SP);
     free(SC);
     free(MG);
@@ -419,12 +442,13 @@ int64_t oracle_solve_cb(orc_rhs_cb cb, void *user, int d, double alpha, double h
 }
 
 /* A batch of independent trajectories: instance i has its own alpha, h, N,
- * y0 (row i of [batch][d]) and theta (row i of [batch][n_theta]); its rows
+ * initial values (block i of [batch][n_init][d]; an instance uses the first
+ * ceil(alpha_i) rows of its block) and theta (row i of [batch][n_theta]); its rows
  * start at row_off[i] of y (and of yp / f when given). Instances run in
  * parallel over OpenMP threads; each instance's arithmetic is the
  * single-trajectory scheme above, so results do not depend on the thread
  * count. status[i] receives the per-instance status. */
-void oracle_solve_batch(int system, int d, int n_theta, int64_t batch,
+void oracle_solve_batch(int system, int d, int n_theta, int n_init, int64_t batch,
                         const double *alpha, const double *h, const int64_t *N,
                         const double *y0, const double *theta, const int64_t *row_off,
                         double *y, double *yp, double *f, int64_t *status)
@@ -433,7 +457,7 @@ void oracle_solve_batch(int system, int d, int n_theta, int64_t batch,
     for (int64_t i = 0; i < batch; ++i) {
         orc_rhs r = {system, d, theta + i * n_theta, 0, 0};
         int64_t o = row_off[i] * d;
-        status[i] = solve_one(&r, alpha[i], h[i], N[i], y0 + i * d, 0, 0, 0, y + o,
+        status[i] = solve_one(&r, alpha[i], h[i], N[i], y0 + i * n_init * d, 0, 0, 0, y + o,
                               yp ? yp + o : 0, f ? f + o : 0);
     }
 }
@@ -483,12 +507,15 @@ void oracle_history_sums(double alpha, int64_t N, int d, const double *f, double
 /*   ybar_0 starts at g_0, thetabar at 0, fbar_k at 0. For n = N .. 1:       */
 /*     ybar_n   = g_n + J_y(t_n, y_n)^T fbar_n;  thetabar += J_th^T fbar_n   */
 /*     ybar_0  += ybar_n;  u = h^a ybar_n                                    */
+/*     (for 1 < a <= 2 also y'bar_0 += t_n (ybar_n + ypbar_n): both y_n and  */
+/*      yP_n contain t_n y'(0) through the Taylor polynomial)                */
 /*     ypbar    = J_y(t_n, yP_n)^T (u / Gamma(a+2)); thetabar likewise       */
 /*     ybar_0  += ypbar;   v = h^a ypbar                                     */
 /*     fbar_0  += c_{n-1} u;  fbar_k += a_{n-1-k} u  (1 <= k <= n-1)         */
 /*     fbar_k  += b_{n-1-k} v                        (0 <= k <= n-1)         */
 /*   finally ybar_0 += J_y(0, y0)^T fbar_0 and thetabar += J_th^T fbar_0.    */
-/* gy is [N+1][d]; outputs gy0 [d] and gtheta [n_theta]. Returns the forward */
+/* gy is [N+1][d]; outputs gy0 [ceil(a)][d] (the gradient with respect to   */
+/* y(0), then y'(0) for a > 1) and gtheta [n_theta]. Returns the forward     */
 /* status (gradients are NaN when the forward blew up).                      */
 /* ------------------------------------------------------------------------ */
 int64_t oracle_adjoint(int system, int d, const double *theta, double alpha, double h,
@@ -508,7 +535,9 @@ int64_t oracle_adjoint(int system, int d, const double *theta, double alpha, dou
     step_scalars(alpha, h, &ha, &ig2);
 
     long double *fbar = calloc((size_t)(N + 1) * d, sizeof(long double));
+    const int ni = n_init_of(alpha);
     long double *gy0l = calloc(d, sizeof(long double));
+    long double *gy1l = calloc(d, sizeof(long double));
     long double *gthl = calloc(nth > 0 ? nth : 1, sizeof(long double));
     long double *ybar = calloc(d, sizeof(long double));
     long double *u = calloc(d, sizeof(long double)), *v = calloc(d, sizeof(long double));
@@ -529,6 +558,7 @@ int64_t oracle_adjoint(int system, int d, const double *theta, double alpha, dou
         rhs_vjp(&r, tn, YP + n * d, tmp, ypbar, gthl);
         for (int i = 0; i < d; ++i) {
             gy0l[i] += ypbar[i];
+            if (ni == 2) gy1l[i] += (long double)tn * (ybar[i] + ypbar[i]);
             v[i] = (long double)ha * ypbar[i];
         }
         for (int i = 0; i < d; ++i) fbar[i] += (long double)cc[n - 1] * u[i];
@@ -539,12 +569,14 @@ int64_t oracle_adjoint(int system, int d, const double *theta, double alpha, dou
     }
     rhs_vjp(&r, 0.0, y0, fbar, gy0l, gthl);
     for (int i = 0; i < d; ++i) gy0[i] = (double)gy0l[i];
+    if (ni == 2)
+        for (int i = 0; i < d; ++i) gy0[d + i] = (double)gy1l[i];
     for (int q = 0; q < nth; ++q) gtheta[q] = (double)gthl[q];
     if (st) {
-        for (int i = 0; i < d; ++i) gy0[i] = NAN;
+        for (int i = 0; i < ni * d; ++i) gy0[i] = NAN;
         for (int q = 0; q < nth; ++q) gtheta[q] = NAN;
     }
-    free(bb); free(aa); free(cc); free(Y); free(YP); free(fbar); free(gy0l);
+    free(bb); free(aa); free(cc); free(Y); free(YP); free(fbar); free(gy0l); free(gy1l);
     free(gthl); free(ybar); free(u); free(v); free(tmp); free(ypbar);
     return st;
 }

@@ -56,7 +56,8 @@ def lib():
         L.oracle_solve_cb.argtypes = [RHS_CB, C.c_void_p, C.c_int, C.c_double, C.c_double,
                                       C.c_int64, _D, _D, _D, _D]
         L.oracle_solve_cb.restype = C.c_int64
-        L.oracle_solve_batch.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, _D, _D, _I64,
+        L.oracle_solve_batch.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64, _D, _D,
+                                         _I64,
                                          _D, _D, _I64, _D, _D, _D, _I64]
         L.oracle_history_sums.argtypes = [C.c_double, C.c_int64, C.c_int, _D, _D, _D, _D, _D]
         L.oracle_adjoint.argtypes = [C.c_int, C.c_int, _D, C.c_double, C.c_double, C.c_int64,
@@ -114,13 +115,22 @@ def rhs_rows(system: int, theta, h: float, y):
     return f
 
 
+def _init(y0, alpha):
+    """Initial values as [ceil(alpha)][d] rows (y(0), then y'(0) for alpha > 1):
+    y0 is [d] or [1|2][d]. Returns (flat array, d, rows given)."""
+    y0 = _f64(y0)
+    rows = 1 if y0.ndim == 1 else y0.shape[0]
+    d = y0.shape[-1]
+    assert rows in (1, 2) and (alpha <= 1.0 or rows == 2), "alpha > 1 needs y(0) and y'(0)"
+    return np.ascontiguousarray(y0.reshape(rows * d)), d, rows
+
+
 def step_from_history(system: int, theta, alpha: float, h: float, t: int, y0, f_hist,
                       weights_bac):
     """Teacher-forced step: y_t from the history rows f_0..f_{t-1} (f_hist has
     at least t rows), with weight tables of length >= t. Returns (y_t, mag)
     where mag is h^alpha times the sum of the magnitudes of the history terms."""
-    y0 = _f64(y0).ravel()
-    d = y0.size
+    y0, d, _ = _init(y0, alpha)
     f = _f64(f_hist)
     assert f.shape[0] >= t and f.shape[1] == d
     wb, wa, wc = (_f64(w) for w in weights_bac)
@@ -132,9 +142,9 @@ def step_from_history(system: int, theta, alpha: float, h: float, t: int, y0, f_
 
 
 def solve(system: int, theta, alpha: float, h: float, N: int, y0, weights_bac=None):
-    """One trajectory. Returns (y [N+1,d], yP [N+1,d], f [N+1,d], status)."""
-    y0 = _f64(y0).ravel()
-    d = y0.size
+    """One trajectory. y0 is y(0) [d], or [2][d] holding y(0) and y'(0) (needed
+    for 1 < alpha <= 2). Returns (y [N+1,d], yP [N+1,d], f [N+1,d], status)."""
+    y0, d, _ = _init(y0, alpha)
     th = _f64(theta).ravel()
     y = np.empty((N + 1, d))
     yp = np.empty((N + 1, d))
@@ -148,9 +158,9 @@ def solve(system: int, theta, alpha: float, h: float, N: int, y0, weights_bac=No
 
 
 def solve_callback(fn, alpha: float, h: float, N: int, y0):
-    """One trajectory with a Python right-hand side fn(t, y) -> f (small N only)."""
-    y0 = _f64(y0).ravel()
-    d = y0.size
+    """One trajectory with a Python right-hand side fn(t, y) -> f (small N only);
+    y0 as in solve()."""
+    y0, d, _ = _init(y0, alpha)
 
     def _cb(t, yptr, fptr, _user):
         yy = np.ctypeslib.as_array(yptr, shape=(d,)).copy()
@@ -168,10 +178,14 @@ def solve_callback(fn, alpha: float, h: float, N: int, y0):
 
 
 def solve_batch(system: int, thetas, alphas, hs, Ns, y0s, want_f: bool = False):
-    """Ragged batch. Returns (y_rows, row_off, status[, f_rows]); instance i
-    occupies rows row_off[i] .. row_off[i] + N_i of y_rows."""
+    """Ragged batch. y0s is [B][d], or [B][2][d] with y'(0) as the second row
+    (used by instances with alpha > 1). Returns (y_rows, row_off, status[,
+    f_rows]); instance i occupies rows row_off[i] .. row_off[i] + N_i of y_rows."""
     y0s = _f64(y0s)
-    B, d = y0s.shape
+    B, d = y0s.shape[0], y0s.shape[-1]
+    n_init = 1 if y0s.ndim == 2 else y0s.shape[1]
+    assert n_init in (1, 2) and (n_init == 2 or np.all(_f64(alphas) <= 1.0))
+    y0s = np.ascontiguousarray(y0s.reshape(B * n_init * d))
     th = _f64(thetas).reshape(B, -1)
     al = _f64(alphas).ravel()
     hh = _f64(hs).ravel()
@@ -182,7 +196,7 @@ def solve_batch(system: int, thetas, alphas, hs, Ns, y0s, want_f: bool = False):
     y = np.empty((rows, d))
     f = np.empty((rows, d)) if want_f else None
     st = np.zeros(B, dtype=np.int64)
-    lib().oracle_solve_batch(system, d, th.shape[1], B, _p(al), _p(hh),
+    lib().oracle_solve_batch(system, d, th.shape[1], n_init, B, _p(al), _p(hh),
                              Nn.ctypes.data_as(_I64), _p(y0s), _p(th),
                              off.ctypes.data_as(_I64), _p(y), None, _p(f),
                              st.ctypes.data_as(_I64))
@@ -204,13 +218,15 @@ def history_sums(alpha: float, f_hist):
 
 
 def adjoint(system: int, theta, alpha: float, h: float, N: int, y0, gy):
-    """Discrete adjoint for L = sum_n <gy[n], y[n]>. Returns (gy0, gtheta, status)."""
-    y0 = _f64(y0).ravel()
-    d = y0.size
+    """Discrete adjoint for L = sum_n <gy[n], y[n]>. Returns (gy0, gtheta, status);
+    gy0 has the shape of y0 ([d], or [2][d] with the gradient with respect to
+    y'(0) in the second row, zero for alpha <= 1)."""
+    shape = np.shape(y0)
+    y0, d, rows = _init(y0, alpha)
     th = _f64(theta).ravel()
     g = _f64(gy).reshape(N + 1, d)
-    gy0 = np.empty(d)
+    gy0 = np.zeros(rows * d)
     gth = np.empty(max(th.size, 1))
     st = lib().oracle_adjoint(system, d, _p(th), float(alpha), float(h), int(N), _p(y0), _p(g),
                               _p(gy0), _p(gth))
-    return gy0, gth[: th.size], int(st)
+    return gy0.reshape(shape), gth[: th.size], int(st)

@@ -19,6 +19,9 @@ SYSTEMS = {
     "hindmarsh_rose": (5, [1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25], [-1.2, -7.0, 2.5], 0.95,
                        0.01, 200),
     "linear": (0, None, [0.4, -1.2], 0.8, 0.01, 250),
+    # 1 < alpha <= 2: y(0) and y'(0); the gradient has a row for each
+    "vdp_slope": (3, [1.3], [[1.1, -0.7], [0.4, 0.9]], 1.5, 0.01, 300),
+    "linear_alpha2": (0, None, [[0.4, -1.2], [-0.3, 0.5]], 2.0, 0.01, 250),
 }
 
 
@@ -40,9 +43,11 @@ def _loss(orc, sid, th, alpha, h, N, y0, g):
 def test_adjoint_vs_central_differences(orc, name):
     sid, th, y0, alpha, h, N = _theta(name)
     rng = np.random.default_rng(3)
-    g = rng.standard_normal((N + 1, y0.size))
+    g = rng.standard_normal((N + 1, y0.shape[-1]))
     gy0, gth, st = orc.adjoint(sid, th, alpha, h, N, y0, g)
     assert st == 0
+    shape = y0.shape
+    y0, gy0 = y0.ravel(), gy0.ravel()
     params = [("y0", y0, gy0), ("theta", th, gth)]
     for label, base, grad in params:
         for i in range(base.size):
@@ -53,9 +58,11 @@ def test_adjoint_vs_central_differences(orc, name):
                 p[i] += dlt
                 m[i] -= dlt
                 if label == "y0":
+                    p, m = p.reshape(shape), m.reshape(shape)
                     fd = (_loss(orc, sid, th, alpha, h, N, p, g) - _loss(orc, sid, th, alpha, h, N, m, g)) / (2 * dlt)
                 else:
-                    fd = (_loss(orc, sid, p, alpha, h, N, y0, g) - _loss(orc, sid, m, alpha, h, N, y0, g)) / (2 * dlt)
+                    y0s = y0.reshape(shape)
+                    fd = (_loss(orc, sid, p, alpha, h, N, y0s, g) - _loss(orc, sid, m, alpha, h, N, y0s, g)) / (2 * dlt)
                 errs.append(abs(fd - grad[i]))
             scale = max(abs(grad[i]), 1e-3 * np.abs(grad).max(), 1e-12)
             assert min(errs) <= 2e-6 * scale, (label, i, grad[i], errs)
@@ -113,7 +120,7 @@ def test_adjoint_vs_torch_autograd(orc, name):
     sid, th, y0, alpha, h, N = _theta(name)
     N = min(N, 120)
     rng = np.random.default_rng(9)
-    g = rng.standard_normal((N + 1, y0.size))
+    g = rng.standard_normal((N + 1, y0.shape[-1]))
     tth = torch.tensor(th, dtype=torch.float64, requires_grad=True)
     ty0 = torch.tensor(y0, dtype=torch.float64, requires_grad=True)
     Y = _torch_forward(torch, sid, tth, ty0, alpha, h, N)

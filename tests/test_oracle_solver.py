@@ -139,8 +139,10 @@ def test_alpha_one_second_order(orc):
     assert abs(orders[-1] - 2.0) < 0.1, orders
 
 
-def _mp_pece(system_rhs, alpha, h, N, y0, dps=50):
-    """Brute-force PECE straight from the paper's weight formulas in mpmath."""
+def _mp_pece(system_rhs, alpha, h, N, y0, dps=50, y1=None):
+    """Brute-force PECE straight from the paper's weight formulas in mpmath;
+    with y1 (= y'(0), for 1 < alpha <= 2) the initial part of every step is
+    y0 + t y1."""
     import mpmath
     mpmath.mp.dps = dps
     al = mpmath.mpf(alpha)
@@ -150,6 +152,7 @@ def _mp_pece(system_rhs, alpha, h, N, y0, dps=50):
     aw = lambda m: ((m + 2) ** (al + 1) - 2 * (m + 1) ** (al + 1) + mpmath.mpf(m) ** (al + 1)) / g2
     cw = lambda n: (mpmath.mpf(n) ** (al + 1) - (n - al) * (n + 1) ** al) / g2
     Y0 = [mpmath.mpf(v) for v in y0]
+    Y1 = [mpmath.mpf(v) for v in (y1 if y1 is not None else [0.0] * len(y0))]
     ys, fs = [Y0], [system_rhs(mpmath.mpf(0), Y0)]
     ha = hh ** al
     for n in range(N):
@@ -157,9 +160,10 @@ def _mp_pece(system_rhs, alpha, h, N, y0, dps=50):
         P = [sum(bw(n - k) * fs[k][i] for k in range(n + 1)) for i in range(len(y0))]
         Cc = [cw(n) * fs[0][i] + sum(aw(n - k) * fs[k][i] for k in range(1, n + 1))
               for i in range(len(y0))]
-        yp = [Y0[i] + ha * P[i] for i in range(len(y0))]
+        base = [Y0[i] + t1 * Y1[i] for i in range(len(y0))]
+        yp = [base[i] + ha * P[i] for i in range(len(y0))]
         fp = system_rhs(t1, yp)
-        yn = [Y0[i] + ha * (Cc[i] + fp[i] / g2) for i in range(len(y0))]
+        yn = [base[i] + ha * (Cc[i] + fp[i] / g2) for i in range(len(y0))]
         ys.append(yn)
         fs.append(system_rhs(t1, yn))
     return np.array([[float(v) for v in row] for row in ys])
