@@ -4,15 +4,19 @@
  * Section 2 of Baban, Bonchis, Fikl, Rosu, "Parallel simulations for
  * Fractional-Order Systems" (arXiv:1611.08678).
  *
- * Problem (Section 2, eq. (1)): D_*^alpha y(t) = f(t, y(t)) on [0, T], with
- * 0 < alpha <= 1 and y(0) = y0 (for alpha <= 1 no higher initial derivative
- * enters). The grid is t_n = n h, n = 0..N, T = N h. One step of the scheme
- * (eq. (2) predictor, then the corrector) is, for target t = n + 1:
+ * Problem (Section 2, eq. (1)): D_*^alpha y(t) = f(t, y(t)) on [0, T] with
+ * the ceil(alpha) initial values y^(k)(0): y(0) = y0 for 0 < alpha <= 1, and
+ * y(0), y'(0) for 1 < alpha <= 2 (plans with FABM_PLAN_INITIAL_SLOPE). The
+ * grid is t_n = n h, n = 0..N, T = N h. One step of the scheme (eq. (2)
+ * predictor, then the corrector) is, for target t = n + 1:
  *
  *   P_t  = sum_{k=0}^{t-1} b_{t-1-k} f_k
  *   C_t  = c_{t-1} f_0 + sum_{k=1}^{t-1} a_{t-1-k} f_k
- *   yP_t = y0 + h^alpha P_t,            fP_t = f(t_t, yP_t)
- *   y_t  = y0 + h^alpha (C_t + fP_t / Gamma(alpha + 2)),  f_t = f(t_t, y_t)
+ *   yP_t = T_t + h^alpha P_t,            fP_t = f(t_t, yP_t)
+ *   y_t  = T_t + h^alpha (C_t + fP_t / Gamma(alpha + 2)),  f_t = f(t_t, y_t)
+ *
+ * with T_t = y(0) for alpha <= 1 and T_t = y(0) + t_t y'(0) for
+ * 1 < alpha <= 2 (the Taylor polynomial of the initial values in eq. (1)),
  *
  * with b_m = ((m+1)^a - m^a)/Gamma(a+1),
  *      a_m = ((m+2)^(a+1) - 2(m+1)^(a+1) + m^(a+1))/Gamma(a+2),
@@ -116,8 +120,16 @@ typedef struct {
     int32_t tile_L;          /* BLOCKED block length: 0 (planner's choice), 256 (per
                               * trajectory) or 64 (shared grid); other multiples of 64
                               * are UNSUPPORTED */
-    int32_t flags;           /* reserved, must be 0 */
+    int32_t flags;           /* 0 or FABM_PLAN_INITIAL_SLOPE; other bits INVALID_ARG */
 } fabm_plan_desc;
+
+/* Plan flag: the calls of the plan pass two initial values per instance, y0
+ * as [batch][2][d] (y(0), then y'(0)), which orders 1 < alpha <= 2 need
+ * (eq. (1)); instances with alpha <= 1 ignore their y'(0) row. The adjoint
+ * calls of such a plan return gy0 as [batch][2][d] (dL/dy(0), then
+ * dL/dy'(0), zero for alpha <= 1). Without the flag, 1 < alpha <= 2 is
+ * UNSUPPORTED. */
+#define FABM_PLAN_INITIAL_SLOPE 1
 
 /* A plan is used by one host thread at a time: calls that share a plan share
  * its pinned staging buffer and schedule cache. Different plans are
@@ -139,7 +151,7 @@ int32_t fabm_n_params(fabm_system system, int32_t dim);
  * handle and *workspace_bytes (may be NULL) the device workspace size that
  * covers any call within the described maxima. Errors: INVALID_ARG for a
  * null pointer, unknown system, dim out of range, max_* < 1, bad tile_L or
- * nonzero flags; UNSUPPORTED for a far precision, block length or path the
+ * unknown flags; UNSUPPORTED for a far precision, block length or path the
  * system does not offer (FP16X2 outside LINEAR, DIRECT for LINEAR d > 4), or
  * a shared-grid plan with max_batch * dim above 2^30 history columns. */
 fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *workspace_bytes);
@@ -153,9 +165,11 @@ fabm_status fabm_workspace_size(fabm_plan_t plan, int64_t batch, const int64_t *
                                 size_t *bytes);
 
 /* One trajectory (Section 2, eq. (1)-(2) and the corrector).
- *   alpha  in (0, 1]  (1 < alpha < 2: UNSUPPORTED; else INVALID_ARG)
+ *   alpha  in (0, 1]; in (1, 2] with FABM_PLAN_INITIAL_SLOPE (without it
+ *          UNSUPPORTED); otherwise INVALID_ARG
  *   h      > 0, finite;   N >= 1, N <= plan max_steps
- *   y0     (device) [d]           initial state y(0)
+ *   y0     (device) [d]           initial state y(0); [2][d] (y(0), y'(0)) for
+ *                                 plans with FABM_PLAN_INITIAL_SLOPE
  *   params (device) [n_params]    theta of the plan's system (may be NULL if n_params == 0)
  *   y_out  (device) [N+1][d]      receives y_0 .. y_N
  *   status (device) [1] int64     0, or the first step index whose state is not
@@ -171,7 +185,8 @@ fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes
 /* A batch of independent trajectories of one system, each with its own
  * alpha, h, N, y0 and theta (ragged lengths), in one enqueue.
  *   alpha, h (host) [batch];  N (host) [batch]
- *   y0      (device) [batch][d];  params (device) [batch][n_params]
+ *   y0      (device) [batch][d] ([batch][2][d] with FABM_PLAN_INITIAL_SLOPE);
+ *   params  (device) [batch][n_params]
  *   row_off (host) [batch]  first row of instance i in y_out; the rows
  *           row_off[i] .. row_off[i] + N[i] must not overlap another instance's
  *   y_out   (device) [total rows][d];  status (device) [batch] int64 as in fabm_solve. */
@@ -237,7 +252,8 @@ fabm_status fabm_tune(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
 
 /* Reverse-mode gradients (the discrete adjoint of the scheme above) of
  *   L = sum_i sum_{n=0}^{N_i} < gy_i[n], y_i[n] >
- * with respect to y0 and theta of every instance (batch = 1 for a single
+ * with respect to y0 (and y'(0) for orders above one) and theta of every
+ * instance (batch = 1 for a single
  * trajectory), where y_i is the trajectory fabm_solve_batch returns for the
  * same inputs with far precision FP64. The forward trajectory and its
  * predictor values are recomputed in the workspace (the same rows the BLOCKED
@@ -245,9 +261,11 @@ fabm_status fabm_tune(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
  * reversed time (band plus FP64 MFMA windows of the transposed Toeplitz
  * sums). The plan's path and far precision do not apply to this call.
  *   alpha, h, N, row_off (host) [batch]        as in fabm_solve_batch
- *   y0      (device) [batch][d];  params (device) [batch][n_params]
+ *   y0      (device) [batch][d] ([batch][2][d] with FABM_PLAN_INITIAL_SLOPE);
+ *   params  (device) [batch][n_params]
  *   gy      (device) rows placed like y_out of fabm_solve_batch: dL/dy_i[n]
- *   gy0     (device) [batch][d]          receives dL/dy0_i
+ *   gy0     (device) [batch][d]          receives dL/dy0_i; [batch][2][d]
+ *                                        (dL/dy(0), dL/dy'(0)) with the flag
  *   gparams (device) [batch][n_params]   receives dL/dtheta_i
  *   status  (device) [batch] int64       the forward status as in fabm_solve_batch;
  *                                        an instance whose forward trajectory is not
@@ -284,9 +302,9 @@ fabm_status fabm_adjoint_reverse(fabm_plan_t plan, void *workspace, size_t works
 
 /* Weight tables of Section 2 for one alpha, lags m = 0..n-1:
  *   b (device) [n], a (device) [n], c (device) [n]  (any may be NULL).
- * Computed in binary64 with cancellation-free rearrangements of the defining
- * power differences (expm1/log1p for b, an all-positive binomial series for
- * the second difference in a, a short series for c). */
+ * alpha in (0, 2]. Computed in binary64 with cancellation-free rearrangements
+ * of the defining power differences (expm1/log1p for b, the even binomial
+ * series of the second difference in a, a short series for c). */
 fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *c,
                          hipStream_t stream);
 

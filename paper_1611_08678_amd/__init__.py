@@ -176,6 +176,7 @@ class Plan:
     dim: int
     n_params: int
     path: int
+    initial_slope: bool = False  # calls pass y0 as [batch][2][d] (y(0), y'(0))
 
     def __del__(self):
         if self.handle and _lib is not None:
@@ -183,17 +184,22 @@ class Plan:
             self.handle = None
 
 
+FABM_PLAN_INITIAL_SLOPE = 1
+
+
 def fabm_plan(system, dim: int, path="auto", far_prec="fp64", max_batch: int = 1,
-              max_steps: int = 1, max_total_steps: int = 0, tile_L: int = 0) -> Plan:
+              max_steps: int = 1, max_total_steps: int = 0, tile_L: int = 0,
+              initial_slope: bool = False) -> Plan:
     L = load()
     desc = _PlanDesc(_enum(system, SYSTEMS), int(dim), _enum(path, PATHS),
                      _enum(far_prec, FAR_PRECS), int(max_batch), int(max_steps),
-                     int(max_total_steps), int(tile_L), 0)
+                     int(max_total_steps), int(tile_L),
+                     FABM_PLAN_INITIAL_SLOPE if initial_slope else 0)
     h = C.c_void_p()
     ws = C.c_size_t()
     _check(L.fabm_plan(C.byref(desc), C.byref(h), C.byref(ws)), "fabm_plan")
     return Plan(h, int(ws.value), desc.system, desc.dim, fabm_n_params(desc.system, desc.dim),
-                desc.path)
+                desc.path, bool(initial_slope))
 
 
 def fabm_workspace_size(plan: Plan, N) -> int:
@@ -392,15 +398,25 @@ def _workspace(nbytes: int):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
 
 
+def _init_rows(y0, lead: int):
+    """Initial values with `lead` leading dimensions: [..., d] (y(0)) or
+    [..., 2, d] (y(0), y'(0)). Returns (device tensor, d, two_rows)."""
+    y0 = _dev(y0)
+    two = y0.dim() == lead + 2
+    if two and y0.shape[-2] != 2:
+        raise ValueError("initial values must be [..., d] or [..., 2, d]")
+    return y0, int(y0.shape[-1]), two
+
+
 def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_prec="fp64",
           plan: Plan | None = None, tile_L: int = 0):
-    """One trajectory; returns (y [N+1, d] float64 device tensor, status int)."""
+    """One trajectory; returns (y [N+1, d] float64 device tensor, status int).
+    y0 is y(0) [d], or [2, d] holding y(0) and y'(0) (orders 1 < alpha <= 2)."""
     import torch
-    y0 = _dev(y0).reshape(-1)
+    y0, d, two = _init_rows(y0, 0)
     th = _dev(theta).reshape(-1)
-    d = y0.numel()
     if plan is None:
-        plan = fabm_plan(system, d, path, far_prec, 1, N, tile_L=tile_L)
+        plan = fabm_plan(system, d, path, far_prec, 1, N, tile_L=tile_L, initial_slope=two)
     ws = _workspace(fabm_workspace_size(plan, [N]))
     y = torch.empty((N + 1, d), dtype=torch.float64, device="cuda")
     st = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -410,18 +426,19 @@ def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_pr
 
 def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64",
                 plan: Plan | None = None, tile_L: int = 0):
-    """Ragged batch; returns (y_rows [sum(N+1), d], row_off numpy, status tensor)."""
+    """Ragged batch; returns (y_rows [sum(N+1), d], row_off numpy, status tensor).
+    y0s is [B, d], or [B, 2, d] with y'(0) as the second row (orders above one)."""
     import numpy as np
     import torch
-    y0s = _dev(y0s)
-    B, d = y0s.shape
+    y0s, d, two = _init_rows(y0s, 1)
+    B = int(y0s.shape[0])
     th = _dev(thetas).reshape(B, -1)
     Ns = np.ascontiguousarray(Ns, dtype=np.int64)
     row_off = np.zeros(B, dtype=np.int64)
     row_off[1:] = np.cumsum(Ns + 1)[:-1]
     if plan is None:
         plan = fabm_plan(system, d, path, far_prec, B, int(Ns.max()), int(Ns.sum()),
-                         tile_L=tile_L)
+                         tile_L=tile_L, initial_slope=two)
     ws = _workspace(fabm_workspace_size(plan, Ns))
     y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
     st = torch.zeros(B, dtype=torch.int64, device="cuda")
@@ -431,20 +448,22 @@ def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64
 
 def adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, plan: Plan | None = None):
     """Gradients of sum <gy, y> for a ragged batch (gy rows placed as solve_batch
-    returns y); returns (gy0 [B, d], gtheta [B, n_params], status) device tensors."""
+    returns y); returns (gy0 shaped like y0s, gtheta [B, n_params], status)
+    device tensors (with [B, 2, d] initial values gy0 holds dL/dy(0), dL/dy'(0))."""
     import numpy as np
     import torch
-    y0s = _dev(y0s)
-    B, d = y0s.shape
+    y0s, d, two = _init_rows(y0s, 1)
+    B = int(y0s.shape[0])
     th = _dev(thetas).reshape(B, -1)
     gy = _dev(gy)
     Ns = np.ascontiguousarray(Ns, dtype=np.int64)
     row_off = np.zeros(B, dtype=np.int64)
     row_off[1:] = np.cumsum(Ns + 1)[:-1]
     if plan is None:
-        plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()))
+        plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
+                         initial_slope=two)
     ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
-    gy0 = torch.empty((B, d), dtype=torch.float64, device="cuda")
+    gy0 = torch.empty_like(y0s)
     gth = torch.empty_like(th)
     st = torch.zeros(B, dtype=torch.int64, device="cuda")
     fabm_adjoint(plan, ws, alphas, hs, Ns, y0s, th, row_off, gy, gy0, gth, st)
@@ -455,8 +474,9 @@ def _solve_function():
     import torch
 
     class FabmSolveBatch(torch.autograd.Function):
-        """y = solve_batch(...) as a differentiable function of y0 [B, d] and
-        theta [B, n_params]; backward runs fabm_adjoint (blocked reverse pass).
+        """y = solve_batch(...) as a differentiable function of y0 [B, d] (or
+        [B, 2, d] with y'(0), orders above one) and theta [B, n_params];
+        backward runs the blocked reverse pass.
         Rows of y are the instances' trajectories concatenated (row_off as in
         solve_batch)."""
 
@@ -466,15 +486,16 @@ def _solve_function():
             # predictor rows, history) is kept for the backward pass
             import numpy as np
             import torch
-            y0d = _dev(y0s.detach()).contiguous()
-            B, d = y0d.shape
+            y0d, d, two = _init_rows(y0s.detach(), 1)
+            B = int(y0d.shape[0])
             th = _dev(thetas.detach()).reshape(B, -1).contiguous()
             al = np.asarray(alphas, dtype=np.float64)
             hh = np.asarray(hs, dtype=np.float64)
             Ns = np.ascontiguousarray(Ns, dtype=np.int64)
             row_off = np.zeros(B, dtype=np.int64)
             row_off[1:] = np.cumsum(Ns + 1)[:-1]
-            plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()))
+            plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
+                             initial_slope=two)
             ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
             y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
             st = torch.zeros(B, dtype=torch.int64, device="cuda")

@@ -51,10 +51,11 @@ struct AdjView {
     double *UV;            // reversed sources [2D][NB*256]: U then V
     double *carry;         // [2][D][256]
     double *acc;           // [NB][D][4][64]
-    double *part;          // [NB][NP + D] per-block gradient partials
+    double *part;          // [NB][NP + 2D] per-block gradient partials
     double *fbar0;         // [D] band sums of reversed row N
     const uint32_t *dead;  // forward non-finite flag
     int NB;
+    int slope;             // y'(0) partials wanted
 };
 
 template <int D>
@@ -71,10 +72,11 @@ __device__ __forceinline__ AdjView adj_view(const AdjArgs &A, int i, int np)
                    A.UV + 2 * b.fc_off,
                    A.carry + (int64_t)i * 2 * D * kBlk,
                    A.acc + b.acc_off / 2,
-                   A.part + b.acc_off / (2 * D * kBlk) * (np + D),
+                   A.part + b.acc_off / (2 * D * kBlk) * (np + 2 * D),
                    A.fbar0 + (int64_t)i * D,
                    A.dead + i,
-                   b.NB};
+                   b.NB,
+                   A.slope};
 }
 
 // ---------------------------------------------------------------------------
@@ -88,7 +90,9 @@ template <int SYS, int D>
 __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
-    constexpr int NG = NP + D;  // gradient partials: theta, then y0
+    // gradient partials: theta, y(0), then y'(0) (orders above one: every
+    // row's initial part is y(0) + t_n y'(0))
+    constexpr int NG = NP + 2 * D;
     double *sa = (double *)smem;  // a lags 0..511
     double *sb = sa + 2 * kBlk;   // b lags 0..511
     double *sU = sb + 2 * kBlk;   // [256][D]
@@ -160,6 +164,7 @@ __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 gpart[NP + i] += ybar[i] + ypbar[i];
+                gpart[NP + D + i] = fma(tn, ybar[i] + ypbar[i], gpart[NP + D + i]);
                 sU[r * D + i] = m.ha * ybar[i];
                 sV[r * D + i] = m.ha * ypbar[i];
             }
@@ -200,7 +205,8 @@ __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
     for (int i = 0; i < D; ++i) cout[i * kBlk + tid] = Sn[i];
     // gradient partials of the block: fixed-order tree over the 256 rows
     double *pj = A.part + (int64_t)J * NG;
-    for (int k = 0; k < NG; ++k) {
+    const int ng = A.slope ? NG : NP + D;
+    for (int k = 0; k < ng; ++k) {
         __syncthreads();
         sRed[tid] = gpart[k];
         __syncthreads();
@@ -360,16 +366,18 @@ template <int SYS, int D>
 __global__ __launch_bounds__(kBatchThreads) void k_adj_final(AdjArgs A)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
-    constexpr int NG = NP + D;
+    constexpr int NG = NP + 2 * D;
+    const bool slope = A.slope != 0;
     __shared__ double red[kBatchThreads];
     __shared__ double fb0[D];
     const int i = blockIdx.x, tid = threadIdx.x;
     const AdjView V = adj_view<D>(A, i, NP);
     const InstMeta m = V.meta[0];
     const int64_t N = m.N;
-    double *gy0 = A.gy0 + (int64_t)i * D, *gth = A.gparams + m.p_off;
+    double *gy0 = A.gy0 + (int64_t)i * (slope ? 2 : 1) * D, *gth = A.gparams + m.p_off;
+    const int ng = slope ? NG : NP + D;
     if (*V.dead != 0u) {
-        for (int k = tid; k < NG; k += kBatchThreads) {
+        for (int k = tid; k < ng; k += kBatchThreads) {
             if (k < NP) gth[k] = __builtin_nan("");
             else gy0[k - NP] = __builtin_nan("");
         }
@@ -391,7 +399,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_adj_final(AdjArgs A)
         __syncthreads();
     }
     if (tid == 0) {
-        double th[NP], y0[D], w[D], gy[D], gt[NP];
+        double th[NP], y0[D], w[D], gy[D], gy1[D], gt[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             th[k] = V.params[k];
@@ -402,19 +410,27 @@ __global__ __launch_bounds__(kBatchThreads) void k_adj_final(AdjArgs A)
             y0[c] = A.y0[(int64_t)i * D + c];
             w[c] = fb0[c];
             gy[c] = V.G[c];  // g_0
+            gy1[c] = 0.0;
         }
         for (int J = 0; J < V.NB; ++J) {
             const double *pj = V.part + (int64_t)J * NG;
 #pragma unroll
             for (int k = 0; k < NP; ++k) gt[k] += pj[k];
 #pragma unroll
-            for (int c = 0; c < D; ++c) gy[c] += pj[NP + c];
+            for (int c = 0; c < D; ++c) {
+                gy[c] += pj[NP + c];
+                gy1[c] += pj[NP + D + c];
+            }
         }
         rhs_vjp<SYS, D>(0.0, y0, w, th, gy, gt);
 #pragma unroll
         for (int k = 0; k < NP; ++k) gth[k] = gt[k];
 #pragma unroll
         for (int c = 0; c < D; ++c) gy0[c] = gy[c];
+        // y'(0) enters only for orders above one
+        if (slope)
+#pragma unroll
+            for (int c = 0; c < D; ++c) gy0[D + c] = m.alpha > 1.0 ? gy1[c] : 0.0;
     }
 }
 

@@ -164,17 +164,24 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         }
     }
     // Sums of target row `row`: of this block in the form y0 + h^a P and
-    // y0 + h^a C (what the predictor and corrector add the newest term to),
-    // of the next block as plain P and C (handed over through `carry`).
+    // y0 + h^a C (what the predictor and corrector add the newest term to;
+    // for orders above one y0 + t_T y'(0) in place of y0), of the next block
+    // as plain P and C (handed over through `carry`).
     const int row = 64 * wave + lane;
     const int64_t T = t0 + row;
+    double base[D];
+    {
+        double y1[D];
+        load_slope<D>(m, A.y1, y1);
+        taylor_base<D>((double)T * m.h, y0, y1, base);
+    }
     double pc[D], cc[D], pn[D], cn[D];
     if (J == 0) {
         // source row 0 takes b_{T-1} and c_{T-1}
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = fma(m.ha, T >= 1 ? wb[T - 1] * f0[i] : 0.0, y0[i]);
-            cc[i] = fma(m.ha, T >= 1 ? wc[T - 1] * f0[i] : 0.0, y0[i]);
+            pc[i] = fma(m.ha, T >= 1 ? wb[T - 1] * f0[i] : 0.0, base[i]);
+            cc[i] = fma(m.ha, T >= 1 ? wc[T - 1] * f0[i] : 0.0, base[i]);
             pn[i] = wb[kBlk + row - 1] * f0[i];
             cn[i] = wc[kBlk + row - 1] * f0[i];
         }
@@ -203,8 +210,8 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = fma(m.ha, P[i], y0[i]);
-            cc[i] = fma(m.ha, Cs[i], y0[i]);
+            pc[i] = fma(m.ha, P[i], base[i]);
+            cc[i] = fma(m.ha, Cs[i], base[i]);
         }
     }
     __syncthreads();
@@ -622,7 +629,8 @@ __device__ __forceinline__ void near_part(const InstView &A, int s, const double
 
 __device__ __forceinline__ InstView single_view(const StepArgs &A)
 {
-    return InstView{A.meta, A.params, A.y0, A.Y, nullptr, A.W, A.W32, A.Fc, A.carry, A.acc, A.dead, A.NB};
+    return InstView{A.meta, A.params, A.y0, A.y1, A.Y, nullptr, A.W, A.W32, A.Fc, A.carry, A.acc,
+                    A.dead, A.NB};
 }
 
 // Launch s of the single-trajectory pipeline; `wpw` wavefronts of each far
@@ -673,6 +681,7 @@ __device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
     return InstView{m,
                     A.params + m->p_off,
                     A.y0 + (int64_t)i * D,
+                    A.y1 ? A.y1 + (int64_t)i * D : nullptr,
                     A.Y + m->row_off * D,
                     A.YP ? A.YP + m->row_off * D : nullptr,
                     A.W + m->w_off,

@@ -90,14 +90,18 @@ int32_t n_params_of(int sys, int d)
     }
 }
 
-fabm_status check_alpha_h(double alpha, double h)
+// Orders up to one need y(0) only; 1 < alpha <= 2 needs y'(0) as well, which
+// calls pass when the plan has FABM_PLAN_INITIAL_SLOPE (`two_init`).
+fabm_status check_alpha_h(double alpha, double h, bool two_init)
 {
     if (!std::isfinite(alpha) || !std::isfinite(h) || h <= 0.0 || alpha <= 0.0)
         return FABM_ERR_INVALID_ARG;
-    if (alpha > 1.0 && alpha < 2.0) return FABM_ERR_UNSUPPORTED;
-    if (alpha > 1.0) return FABM_ERR_INVALID_ARG;
+    if (alpha > 2.0) return FABM_ERR_INVALID_ARG;
+    if (alpha > 1.0 && !two_init) return FABM_ERR_UNSUPPORTED;
     return FABM_OK;
 }
+
+bool has_slope(const fabm_plan_s *pl) { return (pl->desc.flags & FABM_PLAN_INITIAL_SLOPE) != 0; }
 
 enum class Path { Direct, Blocked, Wide, Unsupported };
 
@@ -134,6 +138,7 @@ struct Layout {
     size_t yw, ypw, uv, acc_a, carry_a, part_a, fbar0;
     // shared grid: low binary16 parts, their scales, Toeplitz operand table
     size_t flo, fexp, t16, t16exp;
+    size_t init;   // initial values split into y0 [batch][d] and y'(0) [batch][d]
     int64_t cp;    // shared grid: padded history columns
     size_t total;
     int64_t wlen;  // single-trajectory BLOCKED: weight table length
@@ -226,8 +231,8 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
             off = align_up(off + blk / 2 * na);
             L.carry_a = off;
             off = align_up(off + blk * (size_t)batch);
-            L.part_a = off;
-            off = align_up(off + sizeof(double) * ((size_t)pl->n_params + d) * na);
+            L.part_a = off;  // per block: theta, y(0) and y'(0) partials
+            off = align_up(off + sizeof(double) * ((size_t)pl->n_params + 2 * d) * na);
             L.fbar0 = off;
             off = align_up(off + sizeof(double) * d * (size_t)batch);
         }
@@ -304,9 +309,14 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         L.n_sync_words = 64;
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
     }
+    if (has_slope(pl)) {
+        L.init = off;
+        off = align_up(off + sizeof(double) * 2 * (size_t)d * (size_t)batch);
+    }
     L.total = off;
     return L;
 }
+
 
 void host_scalars(double alpha, double h, InstMeta &m)
 {
@@ -320,6 +330,23 @@ void host_scalars(double alpha, double h, InstMeta &m)
 }
 
 fabm_status ok_or_device(hipError_t e) { return record_hip("kernel launch", e); }
+
+// With FABM_PLAN_INITIAL_SLOPE the caller's initial values are [batch][2][d];
+// the kernels read y(0) and y'(0) as separate [batch][d] arrays in the
+// workspace. Returns the arrays to pass (y1 null without the flag).
+fabm_status split_init(const fabm_plan_s *pl, const Layout &L, char *base, int64_t batch,
+                       const double *&y0, const double *&y1, hipStream_t s)
+{
+    y1 = nullptr;
+    if (!has_slope(pl)) return FABM_OK;
+    const int d = pl->desc.dim;
+    double *a = (double *)(base + L.init), *b = a + (size_t)batch * d;
+    fabm_status st = ok_or_device(fabm::launch_split_init(y0, batch, d, a, b, s));
+    if (st != FABM_OK) return st;
+    y0 = a;
+    y1 = b;
+    return FABM_OK;
+}
 
 // Device-side resources of a plan, created at its first solve so that
 // fabm_plan itself touches no device.
@@ -454,6 +481,8 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         HIP_TRY(hipMemcpyAsync(base, graph_stage, L.stage_bytes, hipMemcpyHostToDevice, s));
     else if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK)
         return st;
+    const double *y1 = nullptr;
+    if ((st = split_init(pl, L, base, batch, y0, y1, s)) != FABM_OK) return st;
 
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
     double *W = (double *)(base + L.w);
@@ -479,6 +508,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.meta = dmeta;
         A.params = params;
         A.y0 = y0;
+        A.y1 = y1;
         A.Y = y_out;
         A.W = W;
         A.W32 = W32;
@@ -516,6 +546,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.order = (const int *)(base + L.order);
         A.params = params;
         A.y0 = y0;
+        A.y1 = y1;
         A.Y = y_out;
         A.W = W;
         A.W32 = W32;
@@ -536,6 +567,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.meta = dmeta;
         A.params = params;
         A.y0 = y0;
+        A.y1 = y1;
         A.Y = Yi;
         A.W = W;
         A.W32 = W32;
@@ -556,14 +588,14 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         double *part = (double *)(base + L.part);
         if (T) HIP_TRY(T->begin(fabm::KC_DIRECT_GRID, s));
         st = ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta, params,
-                                                   y0, F, W, Yi, status, part, sync,
+                                                   y0, y1, F, W, Yi, status, part, sync,
                                                    pl->timeout_ticks, s));
         if (T) HIP_TRY(T->end(s));
         return st;
     }
     if (T) HIP_TRY(T->begin(fabm::KC_DIRECT_WG, s));
-    st = ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, batch, params, y0, F, W,
-                                             y_out, status, s));
+    st = ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, batch, params, y0, y1, F,
+                                             W, y_out, status, s));
     if (T) HIP_TRY(T->end(s));
     return st;
 }
@@ -608,6 +640,8 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     const fabm::BatchSchedule &BS = stage_batch(pl, pl->h_stage, L, batch, N);
     char *base = (char *)ws;
     if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) return st;
+    const double *y1 = nullptr;
+    if ((st = split_init(pl, L, base, batch, y0, y1, s)) != FABM_OK) return st;
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
     double *W = (double *)(base + L.w);
     uint32_t *sync = (uint32_t *)(base + L.sync);
@@ -628,6 +662,7 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     A.order = (const int *)(base + L.order);
     A.params = params;
     A.y0 = y0;
+    A.y1 = y1;
     A.Y = (double *)(base + L.yw);
     A.YP = (double *)(base + L.ypw);
     A.W = W;
@@ -667,6 +702,7 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     R.fbar0 = (double *)(base + L.fbar0);
     R.dead = sync;
     R.gy0 = gy0;
+    R.slope = y1 != nullptr;
     R.gparams = gparams;
     R.batch = batch;
     fabm::BatchSchedule Sr = BS;  // one source block per launch
@@ -689,7 +725,7 @@ fabm_status check_batch(const fabm_plan_s *plan, int64_t batch, const double *al
     int64_t sumN = 0;
     std::vector<std::pair<int64_t, int64_t>> spans((size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
-        fabm_status st = check_alpha_h(alpha[i], h[i]);
+        fabm_status st = check_alpha_h(alpha[i], h[i], has_slope(plan));
         if (st != FABM_OK) return st;
         if (N[i] < 1 || N[i] > plan->desc.max_steps || row_off[i] < 0)
             return FABM_ERR_INVALID_ARG;
@@ -730,7 +766,7 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     const int32_t np = n_params_of(desc->system, desc->dim);
     if (np < 0) return FABM_ERR_INVALID_ARG;
     if (desc->max_batch < 1 || desc->max_steps < 1 || desc->max_total_steps < 0 ||
-        desc->flags != 0 || desc->max_steps > ((int64_t)1 << 30))
+        (desc->flags & ~FABM_PLAN_INITIAL_SLOPE) != 0 || desc->max_steps > ((int64_t)1 << 30))
         return FABM_ERR_INVALID_ARG;
     if (desc->tile_L < 0 || desc->tile_L % 64 != 0) return FABM_ERR_INVALID_ARG;
     if (desc->path != FABM_PATH_AUTO && desc->path != FABM_PATH_DIRECT &&
@@ -801,7 +837,7 @@ fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes
                        double *y_out, int64_t *status, hipStream_t stream)
 {
     if (!plan) return FABM_ERR_INVALID_ARG;
-    fabm_status st = check_alpha_h(alpha, h);
+    fabm_status st = check_alpha_h(alpha, h, has_slope(plan));
     if (st != FABM_OK) return st;
     if (N < 1 || N > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
     if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
@@ -1050,7 +1086,7 @@ fabm_status fabm_adjoint_reverse(fabm_plan_t plan, void *workspace, size_t works
 fabm_status fabm_weights(double alpha, int64_t n, double *b, double *a, double *c,
                          hipStream_t stream)
 {
-    fabm_status st = check_alpha_h(alpha, 1.0);
+    fabm_status st = check_alpha_h(alpha, 1.0, true);
     if (st != FABM_OK) return st;
     if (n < 1) return FABM_ERR_INVALID_ARG;
     if ((b && !aligned8(b)) || (a && !aligned8(a)) || (c && !aligned8(c)))
@@ -1084,7 +1120,7 @@ fabm_status fabm_history_sums(double alpha, int64_t N, int32_t dim, const double
                               double *C, fabm_path path, fabm_far_prec far_prec,
                               void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
-    fabm_status st = check_alpha_h(alpha, 1.0);
+    fabm_status st = check_alpha_h(alpha, 1.0, true);
     if (st != FABM_OK) return st;
     if (N < 1 || dim < 1) return FABM_ERR_INVALID_ARG;
     if (dim > 4) return FABM_ERR_UNSUPPORTED;

@@ -80,6 +80,7 @@ template <int SYS, int D>
 __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict__ meta,
                                                       const double *__restrict__ params,
                                                       const double *__restrict__ y0g,
+                                                      const double *__restrict__ y1g,
                                                       double *__restrict__ F,
                                                       const double *__restrict__ W,
                                                       double *__restrict__ Y,
@@ -93,9 +94,10 @@ __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict
     const double *wb = W + m.w_off, *wa = wb + m.wlen, *wc = wa + m.wlen;
     double *Fh = F + m.f_off * D, *Yh = Y + m.row_off * D;
     const double *p = params + m.p_off;
-    double y0[D];
+    double y0[D], y1[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = y0g[(int64_t)inst * D + i];
+    load_slope<D>(m, y1g ? y1g + (int64_t)inst * D : nullptr, y1);
 
     if (tid == 0) {
         double f0[D];
@@ -115,8 +117,10 @@ __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict
         partial_sums<D>(Fh, wb, wa, wc, t, 0, t, tid, sp, sc);
         block_sum2<D>(sp, sc, red, tid);
         if (tid == 0) {
-            double y[D], f[D];
-            pece_update<SYS, D>(m, (double)t * m.h, y0, sp, sc, p, y, f);
+            double y[D], f[D], base[D];
+            const double tt = (double)t * m.h;
+            taylor_base<D>(tt, y0, y1, base);
+            pece_update<SYS, D>(m, tt, base, sp, sc, p, y, f);
             if (!finite_all(y) || !finite_all(f)) {
                 s_dead = t;
             } else {
@@ -145,6 +149,7 @@ template <int SYS, int D>
 __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restrict__ meta,
                                                         const double *__restrict__ params,
                                                         const double *__restrict__ y0g,
+                                                        const double *__restrict__ y1g,
                                                         double *__restrict__ F,
                                                         const double *__restrict__ W,
                                                         double *__restrict__ Y,
@@ -160,9 +165,10 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
     const int64_t N = m.N;
     const double *wb = W + m.w_off, *wa = wb + m.wlen, *wc = wa + m.wlen;
     const double *p = params;
-    double y0[D];
+    double y0[D], y1[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = y0g[i];
+    load_slope<D>(m, y1g, y1);
 
     if (g == 0 && tid == 0) {
         double f0[D];
@@ -210,8 +216,10 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
             __syncthreads();  // red[] is reused by the combine below
             block_sum2<D>(qp, qc, red, tid);
             if (tid == 0) {
-                double y[D], f[D];
-                pece_update<SYS, D>(m, (double)t * m.h, y0, qp, qc, p, y, f);
+                double y[D], f[D], base[D];
+                const double tt = (double)t * m.h;
+                taylor_base<D>(tt, y0, y1, base);
+                pece_update<SYS, D>(m, tt, base, qp, qc, p, y, f);
                 if (!finite_all(y) || !finite_all(f)) {
                     flag_max(&sync[2], (uint32_t)t);
                 } else {
@@ -311,6 +319,30 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+// init [batch][2][d] -> y0 [batch][d], y1 [batch][d]
+__global__ void k_split_init(const double *__restrict__ init, int64_t batch, int d,
+                             double *__restrict__ y0, double *__restrict__ y1)
+{
+    const int64_t n = batch * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / d, c = e - i * d;
+        y0[e] = init[(2 * i) * d + c];
+        y1[e] = init[(2 * i + 1) * d + c];
+    }
+}
+
+hipError_t launch_split_init(const double *init, int64_t batch, int d, double *y0, double *y1,
+                             hipStream_t s)
+{
+    const int64_t n = batch * d;
+    if (n <= 0) return hipSuccess;
+    const int64_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_split_init, dim3((unsigned)(b < 1024 ? b : 1024)), dim3(256), 0, s, init,
+                       batch, d, y0, y1);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch over (system, dimension). LINEAR is instantiated for the small
 // dimensions the direct kernels keep in registers.
@@ -324,13 +356,13 @@ struct Dispatch;
     MACRO(SYS_VDP, 2) MACRO(SYS_FINANCIAL, 3) MACRO(SYS_HINDMARSH_ROSE, 3)
 
 hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
-                            const double *params, const double *y0, double *F, const double *W,
-                            double *Y, int64_t *status, hipStream_t s)
+                            const double *params, const double *y0, const double *y1, double *F,
+                            const double *W, double *Y, int64_t *status, hipStream_t s)
 {
 #define FABM_WG_CASE(S, DD)                                                                   \
     if (sys == S && d == DD) {                                                                \
         hipLaunchKernelGGL((k_direct_wg<S, DD>), dim3((unsigned)batch), dim3(kBlock), 0, s, \
-                           meta, params, y0, F, W, Y, status);                               \
+                           meta, params, y0, y1, F, W, Y, status);                           \
         return hipGetLastError();                                                             \
     }
     FABM_DIRECT_CASES(FABM_WG_CASE)
@@ -339,13 +371,13 @@ hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
 }
 
 hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const double *params,
-                              const double *y0, double *F, const double *W, double *Y,
-                              int64_t *status, double *part, uint32_t *sync,
+                              const double *y0, const double *y1, double *F, const double *W,
+                              double *Y, int64_t *status, double *part, uint32_t *sync,
                               uint64_t timeout_ticks, hipStream_t s)
 {
-    void *args[] = {(void *)&meta, (void *)&params, (void *)&y0,     (void *)&F,
-                    (void *)&W,    (void *)&Y,      (void *)&status, (void *)&part,
-                    (void *)&sync, (void *)&timeout_ticks};
+    void *args[] = {(void *)&meta, (void *)&params, (void *)&y0,     (void *)&y1,
+                    (void *)&F,    (void *)&W,      (void *)&Y,      (void *)&status,
+                    (void *)&part, (void *)&sync,   (void *)&timeout_ticks};
 #define FABM_GRID_CASE(S, DD)                                                                \
     if (sys == S && d == DD)                                                                 \
         return hipLaunchCooperativeKernel((const void *)k_direct_grid<S, DD>, dim3(G),     \

@@ -13,7 +13,7 @@ namespace fabm {
 // Placement per instance i: forward rows Y, YP at meta[i].f_off (packed),
 // dL/dy rows G at meta[i].row_off (the caller's), reversed sources UV at
 // 2 inst[i].fc_off, sums acc at inst[i].acc_off / 2, block partials at
-// inst[i].acc_off / (2 D 256) * (n_params + D).
+// inst[i].acc_off / (2 D 256) * (n_params + 2 D).
 struct AdjArgs {
     const InstMeta *meta;   // [batch]
     const BlkInst *inst;    // [batch] (same as the forward batch)
@@ -26,10 +26,11 @@ struct AdjArgs {
     double *UV;             // reversed sources [2D][NB*256] per instance
     double *carry;          // [batch][2][D][256]
     double *acc;            // [NB][D][4][64] per instance
-    double *part;           // [NB][n_params + D] per instance
+    double *part;           // [NB][n_params + 2D] per instance: theta, y(0), y'(0)
     double *fbar0;          // [batch][D]
     const uint32_t *dead;   // forward non-finite flags [batch]
-    double *gy0;            // [batch][D]
+    double *gy0;            // [batch][D], or [batch][2][D] with `slope`
+    int slope;              // initial values include y'(0): gradients [batch][2][D]
     double *gparams;        // [batch][n_params] (at meta[i].p_off)
     int64_t batch;
 };

@@ -40,6 +40,7 @@ struct InstView {
     const InstMeta *meta;
     const double *params;
     const double *y0;
+    const double *y1;   // y'(0) [D] (orders above one), or null
     double *Y;          // rows [N+1][D]
     double *YP;         // predictor rows [N+1][D] (row 0 = y0), or null
     const double *W;    // b, a, c tables of length meta->wlen each
@@ -55,6 +56,7 @@ struct StepArgs {
     const InstMeta *meta;
     const double *params;
     const double *y0;
+    const double *y1;   // y'(0) [D] (orders above one), or null
     double *Y;          // caller rows [N+1][D]
     const double *W;    // b, a, c tables of length meta->wlen each
     const float *W32;   // b, a in binary32 (FP32 far windows only)
@@ -99,6 +101,7 @@ struct BatchArgs {
     const int *order;      // instances by block count, descending
     const double *params;  // [batch][n_params]
     const double *y0;      // [batch][D]
+    const double *y1;      // [batch][D] y'(0) (orders above one), or null
     double *Y;             // caller rows; instance i at meta[i].row_off
     double *YP;            // predictor rows placed like Y, or null
     const double *W;       // weight tables, instance i at meta[i].w_off

@@ -157,20 +157,41 @@ __device__ __forceinline__ void rhs_vjp(double t, const double (&y)[D], const do
     }
 }
 
+// Initial values (eq. (1)): an order above one needs y'(0) besides y(0), and
+// every step starts from the Taylor polynomial y(0) + t y'(0). `slope` loads
+// y'(0), or zeros for orders up to one or when none is given.
+template <int D>
+__device__ __forceinline__ void load_slope(const InstMeta &m, const double *y1, double (&v)[D])
+{
+    const bool on = y1 != nullptr && m.alpha > 1.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = on ? y1[i] : 0.0;
+}
+
+// Initial part of the step at time tt: y(0) + tt y'(0).
+template <int D>
+__device__ __forceinline__ void taylor_base(double tt, const double (&y0)[D],
+                                            const double (&y1)[D], double (&base)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) base[i] = fma(tt, y1[i], y0[i]);
+}
+
 // One corrector step from the two history sums (Section 2): returns y_t and
-// f_t, given P_t, C_t, y0 and the step scalars.
+// f_t, given P_t, C_t, the initial part of the step (y0, or its Taylor
+// polynomial at t_t for orders above one) and the step scalars.
 template <int SYS, int D>
-__device__ __forceinline__ void pece_update(const InstMeta &m, double tt, const double (&y0)[D],
+__device__ __forceinline__ void pece_update(const InstMeta &m, double tt, const double (&base)[D],
                                             const double (&P)[D], const double (&Cs)[D],
                                             const double *__restrict__ p, double (&y)[D],
                                             double (&f)[D])
 {
     double yp[D], fp[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) yp[i] = fma(m.ha, P[i], y0[i]);
+    for (int i = 0; i < D; ++i) yp[i] = fma(m.ha, P[i], base[i]);
     rhs<SYS, D>(tt, yp, fp, p);
 #pragma unroll
-    for (int i = 0; i < D; ++i) y[i] = fma(m.ha, fma(fp[i], m.ig2, Cs[i]), y0[i]);
+    for (int i = 0; i < D; ++i) y[i] = fma(m.ha, fma(fp[i], m.ig2, Cs[i]), base[i]);
     rhs<SYS, D>(tt, y, f, p);
 }
 

@@ -18,18 +18,24 @@ hipError_t launch_weights_one(double al, double ig1, double ig2, int64_t n, doub
 // Zero-fill of 32-bit words (a kernel, so it is safe inside captured graphs).
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
-// DIRECT path, one workgroup per instance.
+// Split of the initial values [batch][2][d] (y(0), then y'(0)) into y0 and
+// y1, each [batch][d] (a kernel, so it is safe inside captured graphs).
+hipError_t launch_split_init(const double *init, int64_t batch, int d, double *y0, double *y1,
+                             hipStream_t s);
+
+// DIRECT path, one workgroup per instance. y1 (y'(0) per instance, used for
+// orders above one) may be null.
 hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
-                            const double *params, const double *y0, double *F, const double *W,
-                            double *Y, int64_t *status, hipStream_t s);
+                            const double *params, const double *y0, const double *y1, double *F,
+                            const double *W, double *Y, int64_t *status, hipStream_t s);
 
 // DIRECT path, one trajectory spread over the whole GPU (persistent,
 // cooperative launch); `part` holds [G][2d] doubles, `sync` 4 zeroed words.
 // Every inter-workgroup wait gives up after `timeout_ticks` of the device's
 // constant-rate wall clock (status -1).
 hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const double *params,
-                              const double *y0, double *F, const double *W, double *Y,
-                              int64_t *status, double *part, uint32_t *sync,
+                              const double *y0, const double *y1, double *F, const double *W,
+                              double *Y, int64_t *status, double *part, uint32_t *sync,
                               uint64_t timeout_ticks, hipStream_t s);
 
 // BLOCKED path, one trajectory, as a sequence of step kernels on stream `s`

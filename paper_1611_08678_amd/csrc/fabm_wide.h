@@ -39,6 +39,7 @@ struct WideArgs {
     const InstMeta *meta;   // [batch]; alpha, h, N and the scalars are shared
     const double *params;   // [batch][d*d + 2d]
     const double *y0;       // [batch][d]
+    const double *y1;       // [batch][d] y'(0) (orders above one), or null
     double *Y;              // caller rows
     const double *W;        // b, a, c tables of length wlen (shared)
     const float *W32;       // binary32 b, a (FP32 far)

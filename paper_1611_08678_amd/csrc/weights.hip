@@ -9,7 +9,8 @@
 //   b_m = m^a * expm1(a * log1p(1/m)) / Gamma(a+1)                   (m >= 1)
 //   a_m = x^(a+1) * 2 * sum_{k>=1} C(a+1, 2k) x^(-2k) / Gamma(a+2),  x = m+1
 //         (the even part of the binomial series of (1 +- 1/x)^(a+1); every
-//          term is >= 0 for 0 < a <= 1), evaluated as
+//          term is >= 0 for 0 < a <= 1, the terms after the first are <= 0
+//          for 1 < a < 2 and vanish at a = 2), evaluated as
 //         a x^a / (x Gamma(a+1)) * (1 + sum_{k>=2} C(a+1,2k)/C(a+1,2) x^(2-2k))
 //   a_0 = 2 expm1(a ln 2) / Gamma(a+2)
 //   c_n = (a+1) n^a sum_{j>=1} C(a, j) j/(j+1) n^(-j) / Gamma(a+2)   (n >= 2)
@@ -41,7 +42,7 @@ __device__ __forceinline__ double weight_a(double al, double ig1, double ig2, in
         const double q = (double)(2 * k);
         r *= (al + (3.0 - q)) * (al + (2.0 - q)) / ((q - 1.0) * q) * u2;
         s += r;
-        if (r <= 1e-18 * s) break;
+        if (fabs(r) <= 1e-18 * s) break;
     }
     return al * ig1 * (pow(x, al) / x) * s;
 }

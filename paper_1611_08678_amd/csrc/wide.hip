@@ -408,6 +408,8 @@ __global__ __launch_bounds__(256) void k_wide_band(WideArgs A, int s)
     }
     const double b0 = act ? p[d * d + lane] : 0.0, b1 = act ? p[d * d + d + lane] : 0.0;
     const double y0 = act ? A.y0[i * d + lane] : 0.0;
+    // y'(0), used for orders above one
+    const double y1 = (act && A.y1 != nullptr && m.alpha > 1.0) ? A.y1[i * d + lane] : 0.0;
 
     const double *wb = A.W, *wa = wb + A.wlen, *wc = wa + A.wlen;
     if (w == 0) {
@@ -470,9 +472,10 @@ __global__ __launch_bounds__(256) void k_wide_band(WideArgs A, int s)
                 C = fma(a0w, fprev, C);
             }
             const double t = (double)T * h;
-            const double yp = fma(ha, P, y0);
+            const double base = fma(t, y1, y0);  // Taylor part of eq. (1)
+            const double yp = fma(ha, P, base);
             const double fp = fval(yp, t);
-            y = fma(ha, fma(fp, ig2, C), y0);
+            y = fma(ha, fma(fp, ig2, C), base);
             f = fval(y, t);
             if (__ballot(act && !(isfinite(y) && isfinite(f)))) {
                 if (act && w == 0) {

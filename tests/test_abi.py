@@ -153,3 +153,37 @@ def test_shared_grid_needs_shared_alpha_h_N(fabm):
                                     hh.ctypes.data_as(fabm._DP), Ns.ctypes.data_as(fabm._I64P),
                                     fake, fake, ro.ctypes.data_as(fabm._I64P), fake, fake, None)
         assert code == 2
+
+
+def test_initial_slope_flag_rules(fabm):
+    """Orders above one need y'(0): plans with FABM_PLAN_INITIAL_SLOPE take
+    [batch][2][d] initial values (workspace grows by the split copies); without
+    it 1 < alpha <= 2 is UNSUPPORTED; alpha > 2 is INVALID_ARG; unknown plan
+    flags are INVALID_ARG. All checked on the host before any device work."""
+    import ctypes as C
+    import numpy as np
+    p = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 4, 1000, 4000)
+    q = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 4, 1000, 4000, initial_slope=True)
+    assert q.initial_slope and not p.initial_slope
+    Ns = [1000, 10, 300, 999]
+    extra = fabm.fabm_workspace_size(q, Ns) - fabm.fabm_workspace_size(p, Ns)
+    assert 2 * 4 * 2 * 8 <= extra <= 2 * 4 * 2 * 8 + 256
+    for path in ("direct", "auto"):
+        fabm.fabm_plan("chen", 3, path, "fp64", 1, 100, initial_slope=True)
+    fabm.fabm_plan("linear", 8, "blocked", "fp16x2", 2, 100, 200, initial_slope=True)
+    lib = fabm.load()
+    desc = fabm._PlanDesc(fabm.FABM_SYS_VDP, 2, 0, 0, 1, 100, 0, 0, 2)
+    h = C.c_void_p()
+    assert lib.fabm_plan(C.byref(desc), C.byref(h), None) == 1
+    fake = C.c_void_p(1 << 40)
+    Nb = np.asarray([100, 100], np.int64)
+    ro = np.asarray([0, 101], np.int64)
+    hh = np.asarray([0.01, 0.01])
+    for plan, alphas, code in ((p, [0.9, 1.5], 2), (p, [0.9, 2.0], 2), (q, [0.9, 2.5], 1),
+                               (p, [0.9, 2.5], 1), (q, [0.0, 1.5], 1)):
+        al = np.asarray(alphas, float)
+        got = lib.fabm_solve_batch(plan.handle, fake, plan.workspace_bytes, 2,
+                                   al.ctypes.data_as(fabm._DP), hh.ctypes.data_as(fabm._DP),
+                                   Nb.ctypes.data_as(fabm._I64P), fake, fake,
+                                   ro.ctypes.data_as(fabm._I64P), fake, fake, None)
+        assert got == code, (alphas, got)

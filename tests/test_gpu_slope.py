@@ -1,0 +1,236 @@
+"""GPU parity at orders 1 < alpha <= 2 (eq. (1) with y(0) and y'(0); plans
+with FABM_PLAN_INITIAL_SLOPE) against the CPU oracle, through the C ABI:
+weights, DIRECT and BLOCKED (single, batched, FP32 far windows), the shared
+grid, a captured solve, blow-up status and the adjoint (gradients with respect
+to y(0), y'(0) and theta). 1e-11 normwise for the FP64 paths and 1e-10 for
+gradients, as at alpha <= 1. Reduced-precision far sums get their own bound:
+above order one the weights grow like m^(alpha-1) and the history sums, which
+cancel the growing Taylor term t y'(0), reach some 20 times the largest |y|
+(against a few hundredths at alpha <= 1), so a binary32 rounding of them is
+that much larger relative to the solution."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.test_gpu_direct import _batch_parity, _to_np, relerr
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+FP32_BOUND = 1e-4  # binary32 / split binary16 far sums above order one (measured <= 4.5e-5)
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1611_08678_amd as F
+    F.load()
+    return F
+
+
+def _lin(d, seed):
+    rng = np.random.default_rng(seed)
+    A = -(2 * np.eye(d) + rng.standard_normal((d, d)) / 8)
+    return np.concatenate([A.ravel(), rng.standard_normal(d), 0.05 * rng.standard_normal(d)])
+
+
+@pytest.mark.parametrize("alpha", [1.3, 1.5, 1.9, 2.0])
+def test_weights_parity_above_one(F, orc, alpha):
+    import torch
+    n = 1 << 16
+    b, a, c = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3))
+    F.fabm_weights(alpha, n, b, a, c)
+    torch.cuda.synchronize()
+    rb, ra, rc = orc.weights(alpha, n)
+    stats = {}
+    for got, ref, name in ((b, rb, "b"), (a, ra, "a"), (c, rc, "c")):
+        ulp = np.abs(_to_np(got) - ref) / np.spacing(np.abs(ref))
+        stats[name] = (float(ulp.max()), float(ulp.mean()))
+    print("weight ulps (max, mean):", alpha, stats)
+    # the device pow/expm1/log1p carry a few ulp more than the host's at these
+    # orders (a host replay of the same forms measures a mean of 0.9-2.6 ulp)
+    assert all(mx <= 32 and mean <= 8 for mx, mean in stats.values()), stats
+
+
+@pytest.mark.parametrize("path", ["direct", "blocked"])
+@pytest.mark.parametrize("sysname,sid,theta,alpha,N", [
+    ("vdp", 3, [1.3], 1.5, 3000),
+    ("vdp", 3, [0.7], 2.0, 1500),
+    ("linear", 0, None, 1.7, 5000),
+    ("financial", 4, [3.0, 0.1, 1.0], 1.2, 2600),
+    ("hindmarsh_rose", 5, [1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25], 1.5, 4100),
+])
+def test_single_trajectory(F, orc, path, sysname, sid, theta, alpha, N):
+    rng = np.random.default_rng(12)
+    theta = _lin(3, 4) if theta is None else np.asarray(theta, float)
+    d = {"vdp": 2}.get(sysname, 3)
+    init = 0.5 * rng.uniform(-1, 1, (2, d))
+    y, st = F.solve(sysname, theta, alpha, 0.01, N, init, path=path)
+    ref, _, _, rst = orc.solve(sid, theta, alpha, 0.01, N, init)
+    assert int(st.item()) == rst == 0
+    assert relerr(_to_np(y), ref) <= 1e-11
+
+
+def _mixed_batch(rng, B, sid, d, lo=200, hi=2500):
+    """Per-instance alpha in (0.6, 2] (a quarter at or below one, whose y'(0)
+    row must be ignored), ragged N, two initial rows."""
+    alphas = rng.uniform(1.05, 2.0, B)
+    alphas[::4] = rng.uniform(0.6, 1.0, len(alphas[::4]))
+    alphas[1] = 2.0
+    if sid == 3:
+        theta = rng.uniform(0.5, 2, (B, 1))
+    elif sid == 4:
+        theta = np.tile([3.0, 0.1, 1.0], (B, 1))
+        alphas = np.minimum(alphas, 1.5)
+    else:
+        theta = np.stack([_lin(d, 100 + i) for i in range(B)])
+    return dict(system=sid, d=d, theta=theta, alpha=alphas,
+                h=rng.uniform(0.005, 0.02, B), N=rng.integers(lo, hi, B, endpoint=True),
+                y0=0.5 * rng.uniform(-1, 1, (B, 2, d)))
+
+
+@pytest.mark.parametrize("path", ["direct", "blocked", "blocked_fp32"])
+@pytest.mark.parametrize("sid,d", [(3, 2), (0, 3), (4, 3)])
+def test_batch_mixed_orders(F, orc, path, sid, d):
+    rng = np.random.default_rng(40 + sid)
+    w = _mixed_batch(rng, 12, sid, d)
+    w["N"][:3] = [1, 256, 511]  # one row, a full block, block + 255 rows
+    _batch_parity(F, orc, w, tol=FP32_BOUND if path.endswith("fp32") else 1e-11, path=path)
+
+
+def test_batch_alpha_le_one_ignores_slope_row(F):
+    rng = np.random.default_rng(3)
+    B, d = 6, 2
+    th = rng.uniform(0.5, 2, (B, 1))
+    al, hs = rng.uniform(0.6, 1.0, B), np.full(B, 0.01)
+    Ns = rng.integers(300, 900, B)
+    init = rng.uniform(-1, 1, (B, 2, d))
+    for path in ("direct", "blocked"):
+        y2, _, s2 = F.solve_batch("vdp", th, al, hs, Ns, init, path=path)
+        y1, _, s1 = F.solve_batch("vdp", th, al, hs, Ns, init[:, 0], path=path)
+        assert np.array_equal(_to_np(y2), _to_np(y1))
+        assert np.array_equal(_to_np(s2), _to_np(s1))
+
+
+def test_blow_up_status_above_one(F, orc):
+    """Chen leaves every bounded set at these orders: the status (first
+    non-finite step) matches the oracle's, and the rows before agree to 1e-10
+    (they grow through some 300 orders of magnitude before the overflow, and
+    relative rounding differences grow with them: measured 1.7e-11)."""
+    rng = np.random.default_rng(8)
+    B = 6
+    w = dict(system=1, d=3, theta=np.tile([35.0, 3.0, 28.0], (B, 1)),
+             alpha=np.array([1.2, 1.5, 1.8, 2.0, 1.35, 1.65]), h=np.full(B, 0.001),
+             N=np.full(B, 2500), y0=np.concatenate([np.tile([[[-9.0, -5.0, 14.0]]], (B, 1, 1)),
+                                                    rng.uniform(-0.5, 0.5, (B, 1, 3))], axis=1))
+    for path in ("direct", "blocked"):
+        _batch_parity(F, orc, w, tol=1e-10, path=path)
+
+
+@pytest.mark.parametrize("far_prec,tol", [("fp64", 1e-11), ("fp32", FP32_BOUND),
+                                          ("fp16x2", FP32_BOUND)])
+def test_shared_grid_above_one(F, orc, far_prec, tol):
+    """Linear d = 8, one alpha, h and N for all instances (the shared-grid form)."""
+    rng = np.random.default_rng(21)
+    B, d, N, alpha = 6, 8, 700, 1.6
+    th = np.stack([_lin(d, 200 + i) for i in range(B)])
+    init = 0.5 * rng.uniform(-1, 1, (B, 2, d))
+    y, off, st = F.solve_batch("linear", th, np.full(B, alpha), np.full(B, 0.01),
+                               np.full(B, N), init, path="blocked", far_prec=far_prec)
+    ref, roff, rst = orc.solve_batch(0, th, np.full(B, alpha), np.full(B, 0.01), np.full(B, N),
+                                     init)
+    assert np.array_equal(off, roff) and np.all(_to_np(st) == 0) and np.all(rst == 0)
+    err = relerr(_to_np(y), ref)
+    assert err <= tol
+    if far_prec != "fp64":
+        assert err > 1e-12
+
+
+def test_captured_solve_above_one(F, orc):
+    """A captured batched solve with two initial rows: three replays with new
+    initial values written eagerly in between, each bitwise equal to an eager
+    solve and within 1e-11 of the oracle."""
+    import torch
+    rng = np.random.default_rng(9)
+    B, d = 5, 2
+    th = F._dev(rng.uniform(0.5, 2, (B, 1)))
+    al, hs = np.array([1.2, 1.5, 0.8, 2.0, 1.7]), np.full(B, 0.01)
+    Ns = np.array([700, 1200, 300, 999, 1024], dtype=np.int64)
+    ro = np.concatenate([[0], np.cumsum(Ns + 1)[:-1]]).astype(np.int64)
+    plan = F.fabm_plan("vdp", d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
+                       initial_slope=True)
+    ws = F._workspace(F.fabm_workspace_size(plan, Ns))
+    init = torch.empty((B, 2, d), dtype=torch.float64, device="cuda")
+    y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
+    st = torch.zeros(B, dtype=torch.int64, device="cuda")
+    g = F.fabm_graph_solve_batch(plan, ws, al, hs, Ns, init, th, ro, y, st)
+    for rep in range(3):
+        v = 0.5 * rng.uniform(-1, 1, (B, 2, d))
+        init.copy_(torch.as_tensor(v))
+        g.launch()
+        torch.cuda.synchronize()
+        yg = _to_np(y).copy()
+        ye, _, _ = F.solve_batch("vdp", th, al, hs, Ns, v, path="blocked")
+        assert np.array_equal(yg, _to_np(ye)), rep
+        ref, _, rst = orc.solve_batch(3, _to_np(th), al, hs, Ns, v)
+        assert np.all(rst == 0) and relerr(yg, ref) <= 1e-11
+
+
+def _offsets(Ns):
+    off = np.zeros(len(Ns), dtype=np.int64)
+    off[1:] = np.cumsum(np.asarray(Ns) + 1)[:-1]
+    return off
+
+
+@pytest.mark.parametrize("sysname,sid,d", [("vdp", 3, 2), ("linear", 0, 3),
+                                           ("hindmarsh_rose", 5, 3)])
+def test_adjoint_above_one(F, orc, sysname, sid, d):
+    """Gradients with respect to y(0), y'(0) and theta against the oracle's
+    reverse mode (mixed orders; instances at or below one get a zero y'(0)
+    gradient)."""
+    rng = np.random.default_rng(30 + sid)
+    B = 8
+    if sid == 3:
+        th = rng.uniform(0.5, 2, (B, 1))
+    elif sid == 5:
+        th = np.tile([1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25], (B, 1))
+    else:
+        th = np.stack([_lin(d, 300 + i) for i in range(B)])
+    al = rng.uniform(1.05, 2.0, B)
+    al[::3] = rng.uniform(0.6, 1.0, len(al[::3]))
+    hs = np.full(B, 0.01)
+    Ns = rng.integers(200, 2000, B, endpoint=True)
+    Ns[0] = 256
+    init = 0.5 * rng.uniform(-1, 1, (B, 2, d))
+    gy = rng.standard_normal((int((Ns + 1).sum()), d))
+    gy0, gth, st = F.adjoint_batch(sysname, th, al, hs, Ns, init, gy)
+    gy0, gth, st = _to_np(gy0), _to_np(gth), _to_np(st)
+    assert gy0.shape == (B, 2, d)
+    off = _offsets(Ns)
+    worst = 0.0
+    for i in range(B):
+        rg0, rgt, rst = orc.adjoint(sid, th[i], al[i], hs[i], int(Ns[i]), init[i],
+                                    gy[off[i]:off[i] + Ns[i] + 1])
+        assert st[i] == rst == 0
+        if al[i] <= 1.0:
+            assert np.all(gy0[i][1] == 0.0) and np.all(rg0[1] == 0.0)
+        ref = np.concatenate([rg0.ravel(), rgt])
+        got = np.concatenate([gy0[i].ravel(), gth[i]])
+        worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    assert worst <= 1e-10, worst
+
+
+def test_autograd_above_one(F):
+    """torch.autograd through the two-call adjoint with [B, 2, d] initial
+    values: gradients bitwise equal to the one-call adjoint."""
+    import torch
+    rng = np.random.default_rng(5)
+    B, d = 4, 2
+    th = torch.tensor(rng.uniform(0.5, 2, (B, 1)), device="cuda", requires_grad=True)
+    init = torch.tensor(0.5 * rng.uniform(-1, 1, (B, 2, d)), device="cuda", requires_grad=True)
+    al, hs = np.array([1.4, 0.9, 2.0, 1.1]), np.full(B, 0.01)
+    Ns = np.array([600, 257, 1000, 40], dtype=np.int64)
+    y = F.solve_batch_autograd(init, th, "vdp", al, hs, Ns)
+    gy = torch.tensor(rng.standard_normal(tuple(y.shape)), device="cuda")
+    (y * gy).sum().backward()
+    g0, gt, _ = F.adjoint_batch("vdp", th.detach(), al, hs, Ns, init.detach(), gy)
+    assert torch.equal(init.grad, g0) and torch.equal(th.grad, gt)
