@@ -369,6 +369,110 @@ int64_t oracle_solve(int system, int d, const double *theta, double alpha, doubl
     return solve_one(&r, alpha, h, N, y0, wb, wa, wc, y, yp, f);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Non-commensurate orders: eq. (1) with its own order alpha_i for each     */
+/* state component. Component i takes the Section 2 scheme with its own     */
+/* weights b^(i), a^(i), c^(i), h^alpha_i and Gamma(alpha_i + 2), and its    */
+/* own ceil(alpha_i) initial values; the components meet only through f.    */
+/* alpha is [d]; init is [n_init][d] (y(0), then y'(0), which components    */
+/* with alpha_i > 1 need). Outputs and status as in solve_one.              */
+/* ------------------------------------------------------------------------ */
+static int64_t solve_orders(const orc_rhs *r, const double *alpha, double h, int64_t N,
+                            const double *init, int n_init, double *y, double *yp, double *f)
+{
+    int d = r->d;
+    size_t L = (size_t)N + 1;
+    double *W = malloc(sizeof(double) * 3 * L * d); /* component i: b, a, c at 3 i L */
+    double *ha = malloc(sizeof(double) * d), *ig2 = malloc(sizeof(double) * d);
+    for (int i = 0; i < d; ++i) {
+        oracle_weights(alpha[i], N, W + 3 * i * L, W + (3 * i + 1) * L, W + (3 * i + 2) * L);
+        step_scalars(alpha[i], h, &ha[i], &ig2[i]);
+    }
+    double *F = f ? f : malloc(sizeof(double) * L * d);
+    double *ypr = malloc(sizeof(double) * d), *fp = malloc(sizeof(double) * d);
+    double *T = malloc(sizeof(double) * d);
+    long double *SP = malloc(sizeof(long double) * d), *SC = malloc(sizeof(long double) * d);
+
+    memcpy(y, init, sizeof(double) * d);
+    if (yp) memcpy(yp, init, sizeof(double) * d);
+    rhs_eval(r, 0.0, init, F);
+    int64_t status = 0;
+
+    for (int64_t n = 0; n < N; ++n) {
+        double *yn1 = y + (n + 1) * d;
+        if (status) {
+            for (int i = 0; i < d; ++i) {
+                yn1[i] = NAN;
+                F[(n + 1) * d + i] = NAN;
+                if (yp) yp[(n + 1) * d + i] = NAN;
+            }
+            continue;
+        }
+        double t1 = (double)(n + 1) * h;
+        for (int i = 0; i < d; ++i) {
+            const double *bb = W + 3 * i * L, *aa = bb + L, *cc = aa + L;
+            SP[i] = 0.0L;
+            SC[i] = (long double)cc[n] * F[i];
+            for (int64_t k = 0; k <= n; ++k) {
+                long double wbk = bb[n - k];
+                SP[i] += wbk * F[k * d + i];
+                if (k >= 1) {
+                    long double wak = aa[n - k];
+                    SC[i] += wak * F[k * d + i];
+                }
+            }
+            T[i] = init[i];
+            if (n_init_of(alpha[i]) == 2 && n_init == 2) T[i] += t1 * init[d + i];
+        }
+        for (int i = 0; i < d; ++i) ypr[i] = T[i] + ha[i] * (double)SP[i];
+        rhs_eval(r, t1, ypr, fp);
+        for (int i = 0; i < d; ++i) yn1[i] = T[i] + ha[i] * ((double)SC[i] + fp[i] * ig2[i]);
+        rhs_eval(r, t1, yn1, F + (n + 1) * d);
+        if (yp) memcpy(yp + (n + 1) * d, ypr, sizeof(double) * d);
+        if (!all_finite(yn1, d) || !all_finite(F + (n + 1) * d, d)) {
+            status = n + 1;
+            for (int i = 0; i < d; ++i) {
+                yn1[i] = NAN;
+                F[(n + 1) * d + i] = NAN;
+            }
+        }
+    }
+    if (!f) free(F);
+    free(W); free(ha); free(ig2); free(ypr); free(fp); free(T); free(SP); free(SC);
+    return status;
+}
+
+int64_t oracle_solve_orders(int system, int d, const double *theta, const double *alpha,
+                            double h, int64_t N, const double *init, int n_init, double *y,
+                            double *yp, double *f)
+{
+    orc_rhs r = {system, d, theta, 0, 0};
+    return solve_orders(&r, alpha, h, N, init, n_init, y, yp, f);
+}
+
+int64_t oracle_solve_orders_cb(orc_rhs_cb cb, void *user, int d, const double *alpha, double h,
+                               int64_t N, const double *init, int n_init, double *y, double *yp,
+                               double *f)
+{
+    orc_rhs r = {ORC_CALLBACK, d, 0, cb, user};
+    return solve_orders(&r, alpha, h, N, init, n_init, y, yp, f);
+}
+
+/* Batch of non-commensurate trajectories: alpha [batch][d], init
+ * [batch][n_init][d], theta [batch][n_theta]; rows at row_off[i]. */
+void oracle_solve_orders_batch(int system, int d, int n_theta, int n_init, int64_t batch,
+                               const double *alpha, const double *h, const int64_t *N,
+                               const double *init, const double *theta, const int64_t *row_off,
+                               double *y, int64_t *status)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < batch; ++i) {
+        orc_rhs r = {system, d, theta + i * n_theta, 0, 0};
+        status[i] = solve_orders(&r, alpha + i * d, h[i], N[i], init + i * n_init * d, n_init,
+                                 y + row_off[i] * d, 0, 0);
+    }
+}
+
 /* One step of the same scheme from a given history (teacher forcing), to
  * check single rows of trajectories too long to re-solve: with f_0..f_{t-1}
  * read from f_hist (row-major [t][d]), the step n = t-1 of solve_one, with

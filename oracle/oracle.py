@@ -60,6 +60,14 @@ def lib():
                                          _I64,
                                          _D, _D, _I64, _D, _D, _D, _I64]
         L.oracle_history_sums.argtypes = [C.c_double, C.c_int64, C.c_int, _D, _D, _D, _D, _D]
+        L.oracle_solve_orders.argtypes = [C.c_int, C.c_int, _D, _D, C.c_double, C.c_int64, _D,
+                                          C.c_int, _D, _D, _D]
+        L.oracle_solve_orders.restype = C.c_int64
+        L.oracle_solve_orders_cb.argtypes = [RHS_CB, C.c_void_p, C.c_int, _D, C.c_double,
+                                             C.c_int64, _D, C.c_int, _D, _D, _D]
+        L.oracle_solve_orders_cb.restype = C.c_int64
+        L.oracle_solve_orders_batch.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
+                                                _D, _D, _I64, _D, _D, _I64, _D, _I64]
         L.oracle_adjoint.argtypes = [C.c_int, C.c_int, _D, C.c_double, C.c_double, C.c_int64,
                                      _D, _D, _D, _D]
         L.oracle_adjoint.restype = C.c_int64
@@ -202,6 +210,65 @@ def solve_batch(system: int, thetas, alphas, hs, Ns, y0s, want_f: bool = False):
                              st.ctypes.data_as(_I64))
     if want_f:
         return y, off, st, f
+    return y, off, st
+
+
+def _orders_init(y0, alphas):
+    """Initial values [n_init][d] for per-component orders (y'(0) needed when
+    any component's order exceeds one)."""
+    y0 = _f64(y0)
+    rows = 1 if y0.ndim == 1 else y0.shape[0]
+    assert rows in (1, 2) and (np.all(_f64(alphas) <= 1.0) or rows == 2)
+    return np.ascontiguousarray(y0.reshape(-1)), y0.shape[-1], rows
+
+
+def solve_orders(system: int, theta, alphas, h: float, N: int, y0):
+    """One trajectory with a separate order per component (alphas [d]); y0 is
+    [d] or [2][d] as in solve(). Returns (y, yP, f, status)."""
+    al = np.ascontiguousarray(_f64(alphas).ravel())
+    init, d, rows = _orders_init(y0, al)
+    assert al.size == d
+    y, yp, f = (np.empty((N + 1, d)) for _ in range(3))
+    st = lib().oracle_solve_orders(system, d, _p(_f64(theta).ravel()), _p(al), float(h), int(N),
+                                   _p(init), rows, _p(y), _p(yp), _p(f))
+    return y, yp, f, int(st)
+
+
+def solve_orders_callback(fn, alphas, h: float, N: int, y0):
+    """Per-component orders with a Python right-hand side (small N only)."""
+    al = np.ascontiguousarray(_f64(alphas).ravel())
+    init, d, rows = _orders_init(y0, al)
+
+    def _cb(t, yptr, fptr, _user):
+        out = np.asarray(fn(t, np.ctypeslib.as_array(yptr, shape=(d,)).copy()), dtype=np.float64)
+        for i in range(d):
+            fptr[i] = float(out[i])
+
+    cb = RHS_CB(_cb)
+    y, yp, f = (np.empty((N + 1, d)) for _ in range(3))
+    st = lib().oracle_solve_orders_cb(cb, None, d, _p(al), float(h), int(N), _p(init), rows,
+                                      _p(y), _p(yp), _p(f))
+    return y, yp, f, int(st)
+
+
+def solve_orders_batch(system: int, thetas, alphas, hs, Ns, y0s):
+    """Ragged batch with per-component orders: alphas [B][d], y0s [B][d] or
+    [B][2][d]. Returns (y_rows, row_off, status) as solve_batch."""
+    y0s = _f64(y0s)
+    B, d = y0s.shape[0], y0s.shape[-1]
+    n_init = 1 if y0s.ndim == 2 else y0s.shape[1]
+    al = np.ascontiguousarray(_f64(alphas).reshape(B, d))
+    assert n_init == 2 or np.all(al <= 1.0)
+    th = _f64(thetas).reshape(B, -1)
+    Nn = np.ascontiguousarray(Ns, dtype=np.int64).ravel()
+    off = np.zeros(B, dtype=np.int64)
+    off[1:] = np.cumsum(Nn + 1)[:-1]
+    y = np.empty((int((Nn + 1).sum()), d))
+    st = np.zeros(B, dtype=np.int64)
+    lib().oracle_solve_orders_batch(system, d, th.shape[1], n_init, B, _p(al),
+                                    _p(_f64(hs).ravel()), Nn.ctypes.data_as(_I64),
+                                    _p(np.ascontiguousarray(y0s.reshape(-1))), _p(th),
+                                    off.ctypes.data_as(_I64), _p(y), st.ctypes.data_as(_I64))
     return y, off, st
 
 
