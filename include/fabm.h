@@ -120,7 +120,8 @@ typedef struct {
     int32_t tile_L;          /* BLOCKED block length: 0 (planner's choice), 256 (per
                               * trajectory) or 64 (shared grid); other multiples of 64
                               * are UNSUPPORTED */
-    int32_t flags;           /* 0 or FABM_PLAN_INITIAL_SLOPE; other bits INVALID_ARG */
+    int32_t flags;           /* FABM_PLAN_INITIAL_SLOPE | FABM_PLAN_PER_COMPONENT_ORDER
+                              * or 0; other bits INVALID_ARG */
 } fabm_plan_desc;
 
 /* Plan flag: the calls of the plan pass two initial values per instance, y0
@@ -130,6 +131,17 @@ typedef struct {
  * dL/dy'(0), zero for alpha <= 1). Without the flag, 1 < alpha <= 2 is
  * UNSUPPORTED. */
 #define FABM_PLAN_INITIAL_SLOPE 1
+
+/* Plan flag: non-commensurate orders (eq. (1) with a separate order alpha_i
+ * for each state component). The batched calls of the plan take alpha as
+ * [batch][d] (host); component i of an instance runs the scheme with its own
+ * weights b, a, c, h^alpha_i and Gamma(alpha_i + 2), and with
+ * FABM_PLAN_INITIAL_SLOPE its own Taylor term (y'(0) used where alpha_i > 1;
+ * without the flag every alpha_i must be <= 1). Such plans run the DIRECT
+ * kernels: path BLOCKED, the shared grid (LINEAR d > 4, FP16X2, tile_L != 0)
+ * and the adjoint calls are UNSUPPORTED, and so is fabm_solve (one alpha):
+ * a single trajectory is a batch of one. */
+#define FABM_PLAN_PER_COMPONENT_ORDER 2
 
 /* A plan is used by one host thread at a time: calls that share a plan share
  * its pinned staging buffer and schedule cache. Different plans are
@@ -184,7 +196,8 @@ fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes
 
 /* A batch of independent trajectories of one system, each with its own
  * alpha, h, N, y0 and theta (ragged lengths), in one enqueue.
- *   alpha, h (host) [batch];  N (host) [batch]
+ *   alpha (host) [batch] ([batch][d] with FABM_PLAN_PER_COMPONENT_ORDER)
+ *   h, N  (host) [batch]
  *   y0      (device) [batch][d] ([batch][2][d] with FABM_PLAN_INITIAL_SLOPE);
  *   params  (device) [batch][n_params]
  *   row_off (host) [batch]  first row of instance i in y_out; the rows

@@ -177,6 +177,7 @@ class Plan:
     n_params: int
     path: int
     initial_slope: bool = False  # calls pass y0 as [batch][2][d] (y(0), y'(0))
+    per_component_order: bool = False  # calls pass alpha as [batch][d]
 
     def __del__(self):
         if self.handle and _lib is not None:
@@ -185,21 +186,23 @@ class Plan:
 
 
 FABM_PLAN_INITIAL_SLOPE = 1
+FABM_PLAN_PER_COMPONENT_ORDER = 2
 
 
 def fabm_plan(system, dim: int, path="auto", far_prec="fp64", max_batch: int = 1,
               max_steps: int = 1, max_total_steps: int = 0, tile_L: int = 0,
-              initial_slope: bool = False) -> Plan:
+              initial_slope: bool = False, per_component_order: bool = False) -> Plan:
     L = load()
     desc = _PlanDesc(_enum(system, SYSTEMS), int(dim), _enum(path, PATHS),
                      _enum(far_prec, FAR_PRECS), int(max_batch), int(max_steps),
                      int(max_total_steps), int(tile_L),
-                     FABM_PLAN_INITIAL_SLOPE if initial_slope else 0)
+                     (FABM_PLAN_INITIAL_SLOPE if initial_slope else 0) |
+                     (FABM_PLAN_PER_COMPONENT_ORDER if per_component_order else 0))
     h = C.c_void_p()
     ws = C.c_size_t()
     _check(L.fabm_plan(C.byref(desc), C.byref(h), C.byref(ws)), "fabm_plan")
     return Plan(h, int(ws.value), desc.system, desc.dim, fabm_n_params(desc.system, desc.dim),
-                desc.path, bool(initial_slope))
+                desc.path, bool(initial_slope), bool(per_component_order))
 
 
 def fabm_workspace_size(plan: Plan, N) -> int:
@@ -226,7 +229,7 @@ def fabm_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_
     Ns = np.ascontiguousarray(N, dtype=np.int64)
     ro = np.ascontiguousarray(row_off, dtype=np.int64)
     _check(load().fabm_solve_batch(plan.handle, _ptr(workspace),
-                                   workspace.numel() * workspace.element_size(), al.size,
+                                   workspace.numel() * workspace.element_size(), Ns.size,
                                    al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
                                    Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                                    ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
@@ -252,7 +255,7 @@ def fabm_tune(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out, st
     ro = np.ascontiguousarray(row_off, dtype=np.int64)
     rep = _TuneReport()
     _check(load().fabm_tune(plan.handle, _ptr(workspace), workspace.numel() * workspace.element_size(),
-                            al.size, al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
+                            Ns.size, al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
                             Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                             ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status), _stream(stream),
                             C.byref(rep)), "fabm_tune")
@@ -286,7 +289,7 @@ def fabm_graph_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_o
     ro = np.ascontiguousarray(row_off, dtype=np.int64)
     g = C.c_void_p()
     _check(load().fabm_graph_solve_batch(plan.handle, _ptr(workspace),
-                                         workspace.numel() * workspace.element_size(), al.size,
+                                         workspace.numel() * workspace.element_size(), Ns.size,
                                          al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
                                          Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                                          ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
@@ -311,7 +314,7 @@ def fabm_adjoint(plan: Plan, workspace, alpha, h, N, y0, params, row_off, gy, gy
     Ns = np.ascontiguousarray(np.atleast_1d(N), dtype=np.int64)
     ro = np.ascontiguousarray(np.atleast_1d(row_off), dtype=np.int64)
     _check(load().fabm_adjoint(plan.handle, _ptr(workspace),
-                               workspace.numel() * workspace.element_size(), al.size,
+                               workspace.numel() * workspace.element_size(), Ns.size,
                                al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
                                Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                                ro.ctypes.data_as(_I64P), _ptr(gy), _ptr(gy0), _ptr(gparams),
@@ -330,7 +333,7 @@ def fabm_adjoint_forward(plan: Plan, workspace, alpha, h, N, y0, params, row_off
                          stream=None):
     al, hh, Ns, ro = _host_arrays(alpha, h, N, row_off)
     _check(load().fabm_adjoint_forward(plan.handle, _ptr(workspace),
-                                       workspace.numel() * workspace.element_size(), al.size,
+                                       workspace.numel() * workspace.element_size(), Ns.size,
                                        al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
                                        Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                                        ro.ctypes.data_as(_I64P), _ptr(y_out), _ptr(status),
@@ -341,7 +344,7 @@ def fabm_adjoint_reverse(plan: Plan, workspace, alpha, h, N, y0, params, row_off
                          gparams, stream=None):
     al, hh, Ns, ro = _host_arrays(alpha, h, N, row_off)
     _check(load().fabm_adjoint_reverse(plan.handle, _ptr(workspace),
-                                       workspace.numel() * workspace.element_size(), al.size,
+                                       workspace.numel() * workspace.element_size(), Ns.size,
                                        al.ctypes.data_as(_DP), hh.ctypes.data_as(_DP),
                                        Ns.ctypes.data_as(_I64P), _ptr(y0), _ptr(params),
                                        ro.ctypes.data_as(_I64P), _ptr(gy), _ptr(gy0),
@@ -411,8 +414,15 @@ def _init_rows(y0, lead: int):
 def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_prec="fp64",
           plan: Plan | None = None, tile_L: int = 0):
     """One trajectory; returns (y [N+1, d] float64 device tensor, status int).
-    y0 is y(0) [d], or [2, d] holding y(0) and y'(0) (orders 1 < alpha <= 2)."""
+    y0 is y(0) [d], or [2, d] holding y(0) and y'(0) (orders 1 < alpha <= 2).
+    alpha may be one order per component ([d]): a batch of one on the DIRECT
+    kernels (non-commensurate orders)."""
+    import numpy as np
     import torch
+    if np.ndim(alpha) == 1:
+        y, _, st = solve_batch(system, np.reshape(theta, (1, -1)), np.reshape(alpha, (1, -1)),
+                               [h], [N], _dev(y0)[None], path=path, far_prec=far_prec, plan=plan)
+        return y, st
     y0, d, two = _init_rows(y0, 0)
     th = _dev(theta).reshape(-1)
     if plan is None:
@@ -427,18 +437,20 @@ def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_pr
 def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64",
                 plan: Plan | None = None, tile_L: int = 0):
     """Ragged batch; returns (y_rows [sum(N+1), d], row_off numpy, status tensor).
-    y0s is [B, d], or [B, 2, d] with y'(0) as the second row (orders above one)."""
+    y0s is [B, d], or [B, 2, d] with y'(0) as the second row (orders above one);
+    alphas is [B], or [B, d] for a separate order per component (DIRECT)."""
     import numpy as np
     import torch
     y0s, d, two = _init_rows(y0s, 1)
     B = int(y0s.shape[0])
+    pc = np.ndim(alphas) == 2
     th = _dev(thetas).reshape(B, -1)
     Ns = np.ascontiguousarray(Ns, dtype=np.int64)
     row_off = np.zeros(B, dtype=np.int64)
     row_off[1:] = np.cumsum(Ns + 1)[:-1]
     if plan is None:
         plan = fabm_plan(system, d, path, far_prec, B, int(Ns.max()), int(Ns.sum()),
-                         tile_L=tile_L, initial_slope=two)
+                         tile_L=tile_L, initial_slope=two, per_component_order=pc)
     ws = _workspace(fabm_workspace_size(plan, Ns))
     y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
     st = torch.zeros(B, dtype=torch.int64, device="cuda")

@@ -102,6 +102,10 @@ fabm_status check_alpha_h(double alpha, double h, bool two_init)
 }
 
 bool has_slope(const fabm_plan_s *pl) { return (pl->desc.flags & FABM_PLAN_INITIAL_SLOPE) != 0; }
+bool per_component(const fabm_plan_s *pl)
+{
+    return (pl->desc.flags & FABM_PLAN_PER_COMPONENT_ORDER) != 0;
+}
 
 enum class Path { Direct, Blocked, Wide, Unsupported };
 
@@ -116,6 +120,7 @@ bool wide_plan(const fabm_plan_desc &d)
 
 Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 {
+    if (per_component(pl)) return Path::Direct;  // the only path with per-component weights
     if (wide_plan(pl->desc)) return Path::Wide;
     switch (pl->desc.path) {
     case FABM_PATH_DIRECT: return Path::Direct;
@@ -139,6 +144,7 @@ struct Layout {
     // shared grid: low binary16 parts, their scales, Toeplitz operand table
     size_t flo, fexp, t16, t16exp;
     size_t init;   // initial values split into y0 [batch][d] and y'(0) [batch][d]
+    size_t cmeta;  // per-component orders: [batch][d] entries (staged after meta)
     int64_t cp;    // shared grid: padded history columns
     size_t total;
     int64_t wlen;  // single-trajectory BLOCKED: weight table length
@@ -297,10 +303,16 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
     } else {
         L.wlen = 0;
+        const bool pc = per_component(pl);
+        if (pc) {  // one entry per (instance, component): its order's weights and scalars
+            off = (off + 15) / 16 * 16;
+            L.cmeta = off;
+            off += sizeof(InstMeta) * (size_t)batch * d;
+        }
         L.stage_bytes = off;
         off = align_up(off);
         L.w = off;
-        off = align_up(off + sizeof(double) * 3 * (size_t)sumN);
+        off = align_up(off + sizeof(double) * 3 * (size_t)sumN * (pc ? d : 1));
         L.f = off;
         off = align_up(off + sizeof(double) * (size_t)d * (size_t)sumRows);
         L.part = off;  // grid-kernel partials [G][2d]
@@ -456,10 +468,14 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     char *stage = graph_stage ? graph_stage : pl->h_stage;
 
     InstMeta *hm = (InstMeta *)(stage + L.meta);
+    const bool pc = per_component(pl);
+    InstMeta *hc = pc ? (InstMeta *)(stage + L.cmeta) : nullptr;
     int64_t w_off = 0, f_off = 0, maxw = 0;
     for (int64_t i = 0; i < batch; ++i) {
         InstMeta &m = hm[i];
-        host_scalars(alpha[i], h[i], m);
+        // per-component orders: alpha is [batch][d]; the instance entry takes
+        // component 0's scalars (its own weights are never read)
+        host_scalars(pc ? alpha[i * d] : alpha[i], h[i], m);
         m.N = N[i];
         m.row_off = row_off ? row_off[i] : 0;
         m.wlen = L.path == Path::Wide ? L.wlen
@@ -471,6 +487,15 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         m.p_off = (int64_t)pl->n_params * i;
         m.f_off = f_off;
         w_off += 3 * m.wlen;
+        if (pc) {
+            for (int c = 0; c < d; ++c) {
+                InstMeta &q = hc[i * d + c];
+                q = m;
+                host_scalars(alpha[i * d + c], h[i], q);
+                q.w_off = m.w_off + (int64_t)c * 3 * m.wlen;
+            }
+            w_off += (int64_t)(d - 1) * 3 * m.wlen;
+        }
         f_off += N[i] + 1;
         maxw = std::max(maxw, m.wlen);
     }
@@ -493,9 +518,12 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     const bool f32 = (L.path == Path::Blocked || L.path == Path::Wide) &&
                      pl->desc.far_prec == FABM_FAR_FP32;
     float *W32 = f32 ? (float *)(base + L.w32) : nullptr;
-    // the shared grid has one weight table, that of instance 0
-    if ((st = ok_or_device(fabm::launch_weights(dmeta, L.path == Path::Wide ? 1 : batch, maxw, W,
-                                                s, W32))) != FABM_OK)
+    // the shared grid has one weight table, that of instance 0; per-component
+    // orders have one per (instance, component)
+    const InstMeta *dcmeta = pc ? (const InstMeta *)(base + L.cmeta) : nullptr;
+    if ((st = ok_or_device(fabm::launch_weights(pc ? dcmeta : dmeta,
+                                                L.path == Path::Wide ? 1 : pc ? batch * d : batch,
+                                                maxw, W, s, W32))) != FABM_OK)
         return st;
     if (T) HIP_TRY(T->end(s));
     if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
@@ -587,15 +615,15 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     if (batch == 1 && N[0] >= kGridDirectMinSteps) {
         double *part = (double *)(base + L.part);
         if (T) HIP_TRY(T->begin(fabm::KC_DIRECT_GRID, s));
-        st = ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta, params,
-                                                   y0, y1, F, W, Yi, status, part, sync,
+        st = ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta, dcmeta,
+                                                   params, y0, y1, F, W, Yi, status, part, sync,
                                                    pl->timeout_ticks, s));
         if (T) HIP_TRY(T->end(s));
         return st;
     }
     if (T) HIP_TRY(T->begin(fabm::KC_DIRECT_WG, s));
-    st = ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, batch, params, y0, y1, F,
-                                             W, y_out, status, s));
+    st = ok_or_device(fabm::launch_direct_wg(pl->desc.system, d, dmeta, dcmeta, batch, params, y0,
+                                             y1, F, W, y_out, status, s));
     if (T) HIP_TRY(T->end(s));
     return st;
 }
@@ -724,9 +752,12 @@ fabm_status check_batch(const fabm_plan_s *plan, int64_t batch, const double *al
                                   : plan->desc.max_batch * plan->desc.max_steps;
     int64_t sumN = 0;
     std::vector<std::pair<int64_t, int64_t>> spans((size_t)batch);
+    const int na = per_component(plan) ? plan->desc.dim : 1;  // orders per instance
     for (int64_t i = 0; i < batch; ++i) {
-        fabm_status st = check_alpha_h(alpha[i], h[i], has_slope(plan));
-        if (st != FABM_OK) return st;
+        for (int c = 0; c < na; ++c) {
+            fabm_status st = check_alpha_h(alpha[i * na + c], h[i], has_slope(plan));
+            if (st != FABM_OK) return st;
+        }
         if (N[i] < 1 || N[i] > plan->desc.max_steps || row_off[i] < 0)
             return FABM_ERR_INVALID_ARG;
         sumN += N[i];
@@ -766,7 +797,8 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     const int32_t np = n_params_of(desc->system, desc->dim);
     if (np < 0) return FABM_ERR_INVALID_ARG;
     if (desc->max_batch < 1 || desc->max_steps < 1 || desc->max_total_steps < 0 ||
-        (desc->flags & ~FABM_PLAN_INITIAL_SLOPE) != 0 || desc->max_steps > ((int64_t)1 << 30))
+        (desc->flags & ~(FABM_PLAN_INITIAL_SLOPE | FABM_PLAN_PER_COMPONENT_ORDER)) != 0 ||
+        desc->max_steps > ((int64_t)1 << 30))
         return FABM_ERR_INVALID_ARG;
     if (desc->tile_L < 0 || desc->tile_L % 64 != 0) return FABM_ERR_INVALID_ARG;
     if (desc->path != FABM_PATH_AUTO && desc->path != FABM_PATH_DIRECT &&
@@ -784,6 +816,10 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     if (desc->tile_L != 0 && desc->tile_L != (wide ? fabm::kWideBlk : fabm::step_block_len()))
         return FABM_ERR_UNSUPPORTED;
     if (wide && desc->path == FABM_PATH_DIRECT) return FABM_ERR_UNSUPPORTED;
+    // per-component orders run on the DIRECT kernels only
+    if ((desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) &&
+        (wide || desc->path == FABM_PATH_BLOCKED || desc->tile_L != 0))
+        return FABM_ERR_UNSUPPORTED;
     if (wide && desc->max_batch > kWideMaxCols / desc->dim) return FABM_ERR_UNSUPPORTED;
 
     fabm_plan_s *pl = new (std::nothrow) fabm_plan_s();
@@ -837,6 +873,8 @@ fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes
                        double *y_out, int64_t *status, hipStream_t stream)
 {
     if (!plan) return FABM_ERR_INVALID_ARG;
+    // one alpha per component comes through the batched entry points
+    if (per_component(plan)) return FABM_ERR_UNSUPPORTED;
     fabm_status st = check_alpha_h(alpha, h, has_slope(plan));
     if (st != FABM_OK) return st;
     if (N < 1 || N > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
@@ -1022,6 +1060,7 @@ fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const i
     for (int64_t i = 0; i < batch; ++i)
         if (N[i] < 1 || N[i] > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
     if (plan->desc.system == FABM_SYS_LINEAR && plan->desc.dim > 4) return FABM_ERR_UNSUPPORTED;
+    if (per_component(plan)) return FABM_ERR_UNSUPPORTED;  // the reverse pass is BLOCKED
     *bytes = layout_for(plan, batch, N, true).total;
     return FABM_OK;
 }

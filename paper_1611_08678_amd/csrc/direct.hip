@@ -76,8 +76,82 @@ __device__ __forceinline__ void partial_sums(const double *__restrict__ Fh,
     }
 }
 
+// Non-commensurate orders: component i has its own order, so its own weight
+// rows and step scalars (cmeta[i], placed like an instance's).
+template <int D>
+struct CompOrders {
+    const double *wb[D], *wa[D], *wc[D];
+    double ha[D], ig2[D], alpha[D];
+};
+
+template <int D>
+__device__ __forceinline__ CompOrders<D> comp_orders(const InstMeta *__restrict__ cm,
+                                                     const double *__restrict__ W)
+{
+    CompOrders<D> O;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const InstMeta q = cm[i];
+        O.wb[i] = W + q.w_off;
+        O.wa[i] = O.wb[i] + q.wlen;
+        O.wc[i] = O.wa[i] + q.wlen;
+        O.ha[i] = q.ha;
+        O.ig2[i] = q.ig2;
+        O.alpha[i] = q.alpha;
+    }
+    return O;
+}
+
+// partial_sums with each component's own weight rows
+template <int D>
+__device__ __forceinline__ void partial_sums_orders(const double *__restrict__ Fh,
+                                                    const CompOrders<D> &O, int64_t t,
+                                                    int64_t lo, int64_t hi, int tid,
+                                                    double (&sp)[D], double (&sc)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) sp[i] = sc[i] = 0.0;
+    for (int64_t k = lo + tid; k < hi; k += kBlock) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double bw = O.wb[i][t - 1 - k];
+            const double aw = (k == 0) ? O.wc[i][t - 1] : O.wa[i][t - 1 - k];
+            const double fk = Fh[k * D + i];
+            sp[i] = fma(bw, fk, sp[i]);
+            sc[i] = fma(aw, fk, sc[i]);
+        }
+    }
+}
+
+// y'(0) of the components whose order exceeds one, zeros elsewhere
+template <int D>
+__device__ __forceinline__ void load_slope_orders(const CompOrders<D> &O, const double *y1,
+                                                  double (&v)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = (y1 != nullptr && O.alpha[i] > 1.0) ? y1[i] : 0.0;
+}
+
+// pece_update with each component's h^alpha and 1/Gamma(alpha+2)
 template <int SYS, int D>
+__device__ __forceinline__ void pece_update_orders(const CompOrders<D> &O, double tt,
+                                                   const double (&base)[D], const double (&P)[D],
+                                                   const double (&Cs)[D],
+                                                   const double *__restrict__ p, double (&y)[D],
+                                                   double (&f)[D])
+{
+    double yp[D], fp[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) yp[i] = fma(O.ha[i], P[i], base[i]);
+    rhs<SYS, D>(tt, yp, fp, p);
+#pragma unroll
+    for (int i = 0; i < D; ++i) y[i] = fma(O.ha[i], fma(fp[i], O.ig2[i], Cs[i]), base[i]);
+    rhs<SYS, D>(tt, y, f, p);
+}
+
+template <int SYS, int D, bool PC>
 __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict__ meta,
+                                                      const InstMeta *__restrict__ cmeta,
                                                       const double *__restrict__ params,
                                                       const double *__restrict__ y0g,
                                                       const double *__restrict__ y1g,
@@ -97,7 +171,13 @@ __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict
     double y0[D], y1[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = y0g[(int64_t)inst * D + i];
-    load_slope<D>(m, y1g ? y1g + (int64_t)inst * D : nullptr, y1);
+    CompOrders<D> O;
+    if constexpr (PC) {
+        O = comp_orders<D>(cmeta + (int64_t)inst * D, W);
+        load_slope_orders<D>(O, y1g ? y1g + (int64_t)inst * D : nullptr, y1);
+    } else {
+        load_slope<D>(m, y1g ? y1g + (int64_t)inst * D : nullptr, y1);
+    }
 
     if (tid == 0) {
         double f0[D];
@@ -114,13 +194,15 @@ __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict
     for (int64_t t = 1; t <= N; ++t) {
         if (s_dead) break;
         double sp[D], sc[D];
-        partial_sums<D>(Fh, wb, wa, wc, t, 0, t, tid, sp, sc);
+        if constexpr (PC) partial_sums_orders<D>(Fh, O, t, 0, t, tid, sp, sc);
+        else partial_sums<D>(Fh, wb, wa, wc, t, 0, t, tid, sp, sc);
         block_sum2<D>(sp, sc, red, tid);
         if (tid == 0) {
             double y[D], f[D], base[D];
             const double tt = (double)t * m.h;
             taylor_base<D>(tt, y0, y1, base);
-            pece_update<SYS, D>(m, tt, base, sp, sc, p, y, f);
+            if constexpr (PC) pece_update_orders<SYS, D>(O, tt, base, sp, sc, p, y, f);
+            else pece_update<SYS, D>(m, tt, base, sp, sc, p, y, f);
             if (!finite_all(y) || !finite_all(f)) {
                 s_dead = t;
             } else {
@@ -145,8 +227,9 @@ __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict
 // rows published (rows 0..sync[1]-1 of F and Y are complete); sync[2]: step at
 // which the trajectory stopped being finite (0 while finite); sync[3]: abort
 // (a bounded wait timed out). All four are flags in the sense of flag_read.
-template <int SYS, int D>
+template <int SYS, int D, bool PC>
 __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restrict__ meta,
+                                                        const InstMeta *__restrict__ cmeta,
                                                         const double *__restrict__ params,
                                                         const double *__restrict__ y0g,
                                                         const double *__restrict__ y1g,
@@ -168,7 +251,13 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
     double y0[D], y1[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = y0g[i];
-    load_slope<D>(m, y1g, y1);
+    CompOrders<D> O;
+    if constexpr (PC) {
+        O = comp_orders<D>(cmeta, W);
+        load_slope_orders<D>(O, y1g, y1);
+    } else {
+        load_slope<D>(m, y1g, y1);
+    }
 
     if (g == 0 && tid == 0) {
         double f0[D];
@@ -191,7 +280,8 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
         fence_acquire();
         const int64_t lo = (t * g) / G, hi = (t * (g + 1)) / G;
         double sp[D], sc[D];
-        partial_sums<D>(F, wb, wa, wc, t, lo, hi, tid, sp, sc);
+        if constexpr (PC) partial_sums_orders<D>(F, O, t, lo, hi, tid, sp, sc);
+        else partial_sums<D>(F, wb, wa, wc, t, lo, hi, tid, sp, sc);
         block_sum2<D>(sp, sc, red, tid);
         if (tid == 0) {
 #pragma unroll
@@ -219,7 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
                 double y[D], f[D], base[D];
                 const double tt = (double)t * m.h;
                 taylor_base<D>(tt, y0, y1, base);
-                pece_update<SYS, D>(m, tt, base, qp, qc, p, y, f);
+                if constexpr (PC) pece_update_orders<SYS, D>(O, tt, base, qp, qc, p, y, f);
+                else pece_update<SYS, D>(m, tt, base, qp, qc, p, y, f);
                 if (!finite_all(y) || !finite_all(f)) {
                     flag_max(&sync[2], (uint32_t)t);
                 } else {
@@ -355,33 +446,41 @@ struct Dispatch;
     MACRO(SYS_LINEAR, 4) MACRO(SYS_CHEN, 3) MACRO(SYS_ROSSLER, 3)  \
     MACRO(SYS_VDP, 2) MACRO(SYS_FINANCIAL, 3) MACRO(SYS_HINDMARSH_ROSE, 3)
 
-hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
-                            const double *params, const double *y0, const double *y1, double *F,
-                            const double *W, double *Y, int64_t *status, hipStream_t s)
+hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, const InstMeta *cmeta,
+                            int64_t batch, const double *params, const double *y0,
+                            const double *y1, double *F, const double *W, double *Y,
+                            int64_t *status, hipStream_t s)
 {
-#define FABM_WG_CASE(S, DD)                                                                   \
-    if (sys == S && d == DD) {                                                                \
-        hipLaunchKernelGGL((k_direct_wg<S, DD>), dim3((unsigned)batch), dim3(kBlock), 0, s, \
-                           meta, params, y0, y1, F, W, Y, status);                           \
-        return hipGetLastError();                                                             \
+#define FABM_WG_CASE(S, DD)                                                                  \
+    if (sys == S && d == DD) {                                                               \
+        if (cmeta)                                                                           \
+            hipLaunchKernelGGL((k_direct_wg<S, DD, true>), dim3((unsigned)batch), dim3(kBlock), \
+                               0, s, meta, cmeta, params, y0, y1, F, W, Y, status);          \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_direct_wg<S, DD, false>), dim3((unsigned)batch),          \
+                               dim3(kBlock), 0, s, meta, cmeta, params, y0, y1, F, W, Y,    \
+                               status);                                                      \
+        return hipGetLastError();                                                            \
     }
     FABM_DIRECT_CASES(FABM_WG_CASE)
 #undef FABM_WG_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const double *params,
-                              const double *y0, const double *y1, double *F, const double *W,
-                              double *Y, int64_t *status, double *part, uint32_t *sync,
-                              uint64_t timeout_ticks, hipStream_t s)
+hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const InstMeta *cmeta,
+                              const double *params, const double *y0, const double *y1,
+                              double *F, const double *W, double *Y, int64_t *status,
+                              double *part, uint32_t *sync, uint64_t timeout_ticks,
+                              hipStream_t s)
 {
-    void *args[] = {(void *)&meta, (void *)&params, (void *)&y0,     (void *)&y1,
-                    (void *)&F,    (void *)&W,      (void *)&Y,      (void *)&status,
-                    (void *)&part, (void *)&sync,   (void *)&timeout_ticks};
+    void *args[] = {(void *)&meta,   (void *)&cmeta, (void *)&params, (void *)&y0,
+                    (void *)&y1,     (void *)&F,     (void *)&W,      (void *)&Y,
+                    (void *)&status, (void *)&part,  (void *)&sync,   (void *)&timeout_ticks};
 #define FABM_GRID_CASE(S, DD)                                                                \
     if (sys == S && d == DD)                                                                 \
-        return hipLaunchCooperativeKernel((const void *)k_direct_grid<S, DD>, dim3(G),     \
-                                          dim3(kBlock), args, 0, s);
+        return hipLaunchCooperativeKernel(cmeta ? (const void *)k_direct_grid<S, DD, true>   \
+                                                : (const void *)k_direct_grid<S, DD, false>, \
+                                          dim3(G), dim3(kBlock), args, 0, s);
     FABM_DIRECT_CASES(FABM_GRID_CASE)
 #undef FABM_GRID_CASE
     return hipErrorInvalidValue;

@@ -24,19 +24,22 @@ hipError_t launch_split_init(const double *init, int64_t batch, int d, double *y
                              hipStream_t s);
 
 // DIRECT path, one workgroup per instance. y1 (y'(0) per instance, used for
-// orders above one) may be null.
-hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, int64_t batch,
-                            const double *params, const double *y0, const double *y1, double *F,
-                            const double *W, double *Y, int64_t *status, hipStream_t s);
+// orders above one) may be null. cmeta, when given, holds [batch][d] entries
+// with each component's own order (weights at its w_off, its step scalars).
+hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, const InstMeta *cmeta,
+                            int64_t batch, const double *params, const double *y0,
+                            const double *y1, double *F, const double *W, double *Y,
+                            int64_t *status, hipStream_t s);
 
 // DIRECT path, one trajectory spread over the whole GPU (persistent,
 // cooperative launch); `part` holds [G][2d] doubles, `sync` 4 zeroed words.
 // Every inter-workgroup wait gives up after `timeout_ticks` of the device's
 // constant-rate wall clock (status -1).
-hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const double *params,
-                              const double *y0, const double *y1, double *F, const double *W,
-                              double *Y, int64_t *status, double *part, uint32_t *sync,
-                              uint64_t timeout_ticks, hipStream_t s);
+hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const InstMeta *cmeta,
+                              const double *params, const double *y0, const double *y1,
+                              double *F, const double *W, double *Y, int64_t *status,
+                              double *part, uint32_t *sync, uint64_t timeout_ticks,
+                              hipStream_t s);
 
 // BLOCKED path, one trajectory, as a sequence of step kernels on stream `s`
 // (decomposition in fabm_blocked.h). On failure *where names the call.

@@ -172,7 +172,7 @@ def test_initial_slope_flag_rules(fabm):
         fabm.fabm_plan("chen", 3, path, "fp64", 1, 100, initial_slope=True)
     fabm.fabm_plan("linear", 8, "blocked", "fp16x2", 2, 100, 200, initial_slope=True)
     lib = fabm.load()
-    desc = fabm._PlanDesc(fabm.FABM_SYS_VDP, 2, 0, 0, 1, 100, 0, 0, 2)
+    desc = fabm._PlanDesc(fabm.FABM_SYS_VDP, 2, 0, 0, 1, 100, 0, 0, 4)
     h = C.c_void_p()
     assert lib.fabm_plan(C.byref(desc), C.byref(h), None) == 1
     fake = C.c_void_p(1 << 40)
@@ -187,3 +187,46 @@ def test_initial_slope_flag_rules(fabm):
                                    Nb.ctypes.data_as(fabm._I64P), fake, fake,
                                    ro.ctypes.data_as(fabm._I64P), fake, fake, None)
         assert got == code, (alphas, got)
+
+
+def test_per_component_order_rules(fabm):
+    """Non-commensurate plans: DIRECT only (BLOCKED, the shared grid and the
+    adjoint are UNSUPPORTED, so is fabm_solve with its single alpha); alpha is
+    [batch][d], every entry checked (an order above one needs the slope flag);
+    one weight table per component. Host-side checks only."""
+    import ctypes as C
+    import numpy as np
+    F = fabm
+    for kw in (dict(path="blocked"), dict(path="auto", tile_L=256)):
+        with pytest.raises(F.FabmError) as e:
+            F.fabm_plan("chen", 3, max_batch=2, max_steps=100, per_component_order=True, **kw)
+        assert e.value.code == 2
+    with pytest.raises(F.FabmError) as e:
+        F.fabm_plan("linear", 8, "auto", "fp64", 2, 100, per_component_order=True)
+    assert e.value.code == 2
+    p = F.fabm_plan("chen", 3, "auto", "fp64", 2, 100, per_component_order=True)
+    q = F.fabm_plan("chen", 3, "auto", "fp64", 2, 100)
+    Ns = [100, 60]
+    extra = F.fabm_workspace_size(p, Ns) - F.fabm_workspace_size(q, Ns)
+    assert extra >= 8 * 3 * 160 * 2  # two more weight tables per instance
+    lib = F.load()
+    n = C.c_size_t()
+    Nb = np.asarray(Ns, np.int64)
+    assert lib.fabm_adjoint_workspace_size(p.handle, 2, Nb.ctypes.data_as(F._I64P),
+                                           C.byref(n)) == 2
+    fake = C.c_void_p(1 << 40)
+    assert lib.fabm_solve(p.handle, fake, p.workspace_bytes, C.c_double(0.9), C.c_double(0.01),
+                          100, fake, fake, fake, fake, None) == 2
+    ro = np.asarray([0, 101], np.int64)
+    hh = np.asarray([0.01, 0.01])
+    ps = F.fabm_plan("chen", 3, "auto", "fp64", 2, 100, per_component_order=True,
+                     initial_slope=True)
+    for plan, al, code in ((p, [0.9, 0.8, 0.7, 0.9, 1.5, 0.6], 2),
+                           (p, [0.9, 0.8, 0.7, 0.9, 0.0, 0.6], 1),
+                           (ps, [0.9, 0.8, 0.7, 0.9, 2.5, 0.6], 1)):
+        a = np.asarray(al, float)
+        got = lib.fabm_solve_batch(plan.handle, fake, plan.workspace_bytes, 2,
+                                   a.ctypes.data_as(F._DP), hh.ctypes.data_as(F._DP),
+                                   Nb.ctypes.data_as(F._I64P), fake, fake,
+                                   ro.ctypes.data_as(F._I64P), fake, fake, None)
+        assert got == code, (al, got)
