@@ -62,6 +62,9 @@ def parse():
                          "instance, HBM-bound)")
     ap.add_argument("--tune", action="store_true",
                     help="batch workloads: run fabm_tune on the plan before timing (untimed)")
+    ap.add_argument("--per-component-orders", action="store_true",
+                    help="batch workloads on the DIRECT path: a separate order per state "
+                         "component, alpha ~ U[0.8, 1] (non-commensurate system)")
     ap.add_argument("--sweep-N", default=None,
                     help="hr_table2: comma list of step counts (default: all of the table's)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
@@ -179,10 +182,16 @@ def bench_batch(F, W, args):
     import torch
     w = {"rossler_batch": W.rossler_batch, "linear64_batch": W.linear64_batch}.get(
         args.workload, W.vdp_adjoint)()
+    pc = args.per_component_orders
+    if pc:
+        if args.batch_path != "direct":
+            sys.exit("--per-component-orders runs on the DIRECT path (--batch-path direct)")
+        w = W.per_component_orders(w)
     prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" else "fp64")
     Ns = np.asarray(w["N"], dtype=np.int64)
     B, d = len(Ns), w["d"]
-    plan = F.fabm_plan(w["system"], d, args.batch_path, prec, B, int(Ns.max()), int(Ns.sum()))
+    plan = F.fabm_plan(w["system"], d, args.batch_path, prec, B, int(Ns.max()), int(Ns.sum()),
+                       per_component_order=pc)
     ws = torch.empty(F.fabm_workspace_size(plan, Ns), dtype=torch.uint8, device="cuda")
     y0 = torch.as_tensor(w["y0"], dtype=torch.float64, device="cuda").contiguous()
     th = torch.as_tensor(w["theta"], dtype=torch.float64, device="cuda").contiguous()
@@ -226,7 +235,8 @@ def bench_batch(F, W, args):
            "data": "synthetic",
            "config": {"workload": w["name"], "batch": B, "N_min": int(Ns.min()),
                       "N_max": int(Ns.max()), "path": args.batch_path,
-                      "far_prec": prec if args.batch_path == "blocked" else None},
+                      "far_prec": prec if args.batch_path == "blocked" else None,
+                      "orders": "per component, U[0.8, 1]" if pc else "one per instance"},
            "history_gflops": flops / t / 1e9,
            "status_nonzero": int((st.cpu().numpy() != 0).sum()),
            "tune": tune,
@@ -242,7 +252,9 @@ def bench_batch(F, W, args):
                                algorithmic_flops_per_launch=flops / launches)
     if "direct_wg" in kt:
         secs, launches = kt["direct_wg"]
-        by = float((4.0 * Ns * (Ns + 1) * (d + 2)).sum())  # weights + history per step
+        # every step reads the history (d values per row) and the weight rows
+        # b, a: one pair per instance, or one per component with per-component orders
+        by = float((4.0 * Ns * (Ns + 1) * (3 * d if pc else d + 2)).sum())
         out["roofline"] = dict(bound="hbm", achieved=by / secs / 1e9, peak=HBM_PEAK_GBPS,
                                unit="GB/s", frac=by / secs / 1e9 / HBM_PEAK_GBPS, traffic=None,
                                kernel="k_direct_wg", launches=launches,
@@ -294,8 +306,12 @@ def bench_batch(F, W, args):
         yy = y.cpu().numpy()
         errs = []
         for i in np.argsort(Ns)[:3]:
-            ref, _, _, _ = O.solve(w["system"], w["theta"][i], float(w["alpha"][i]),
-                                   float(w["h"][i]), int(Ns[i]), w["y0"][i])
+            if pc:
+                ref, _, _, _ = O.solve_orders(w["system"], w["theta"][i], w["alpha"][i],
+                                              float(w["h"][i]), int(Ns[i]), w["y0"][i])
+            else:
+                ref, _, _, _ = O.solve(w["system"], w["theta"][i], float(w["alpha"][i]),
+                                       float(w["h"][i]), int(Ns[i]), w["y0"][i])
             g = yy[row_off[i]:row_off[i] + Ns[i] + 1]
             errs.append(float(np.abs(g - ref).max() / np.abs(ref).max()))
         out["rel_err_shortest_3"] = errs

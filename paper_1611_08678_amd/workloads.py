@@ -20,6 +20,7 @@ y0 [B, d] (B = 1 for single trajectories) plus descriptive fields.
                  (1, 3, 1, 5, 0.006, 4, -1.6, 3.25), alpha 0.95, h = 0.01,
                  y0 = (-1.6, -10, 2); N from the step counts of the paper's
                  Section 4 timing table (TABLE2_N)
+  per_component_orders  any of the above with alpha [B][d] ~ U[0.8, 1] (seed 6)
 """
 from __future__ import annotations
 
@@ -94,6 +95,17 @@ def hindmarsh_rose(N: int = 1_000_000, h: float = 0.01, alpha: float = 0.95):
     return dict(name="hindmarsh_rose", system=HINDMARSH_ROSE, d=3,
                 theta=np.array([HR_THETA]), alpha=np.array([alpha]), h=np.array([h]),
                 N=np.array([N], dtype=np.int64), y0=np.array([[-1.6, -10.0, 2.0]]))
+
+
+def per_component_orders(w: dict, lo: float = 0.8, hi: float = 1.0, seed: int = 6):
+    """The same workload with a separate order per state component
+    (non-commensurate system): alpha [B][d] uniform in [lo, hi]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B, d = len(w["N"]), w["d"]
+    out = dict(w)
+    out["alpha"] = rng.uniform(lo, hi, size=(B, d))
+    out["name"] = w["name"] + "_orders"
+    return out
 
 
 def random_history(N: int, d: int, seed: int = 0):
