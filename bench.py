@@ -63,8 +63,9 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="batch workloads: run fabm_tune on the plan before timing (untimed)")
     ap.add_argument("--per-component-orders", action="store_true",
-                    help="batch workloads on the DIRECT path: a separate order per state "
-                         "component, alpha ~ U[0.8, 1] (non-commensurate system)")
+                    help="batch workloads: a separate order per state component, alpha ~ "
+                         "U[0.8, 1] (non-commensurate system; DIRECT, or BLOCKED with FP64 "
+                         "far windows)")
     ap.add_argument("--sweep-N", default=None,
                     help="hr_table2: comma list of step counts (default: all of the table's)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
@@ -184,10 +185,11 @@ def bench_batch(F, W, args):
         args.workload, W.vdp_adjoint)()
     pc = args.per_component_orders
     if pc:
-        if args.batch_path != "direct":
-            sys.exit("--per-component-orders runs on the DIRECT path (--batch-path direct)")
-        w = W.per_component_orders(w)
-    prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" else "fp64")
+        if args.batch_path == "blocked" and (args.far_prec or "fp64") != "fp64":
+            sys.exit("--per-component-orders on the BLOCKED path takes FP64 far windows")
+        # the workload's own order range: Rossler's [0.9, 1], else [0.8, 1]
+        w = W.per_component_orders(w, lo=0.9 if args.workload == "rossler_batch" else 0.8)
+    prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" and not pc else "fp64")
     Ns = np.asarray(w["N"], dtype=np.int64)
     B, d = len(Ns), w["d"]
     plan = F.fabm_plan(w["system"], d, args.batch_path, prec, B, int(Ns.max()), int(Ns.sum()),
@@ -236,7 +238,8 @@ def bench_batch(F, W, args):
            "config": {"workload": w["name"], "batch": B, "N_min": int(Ns.min()),
                       "N_max": int(Ns.max()), "path": args.batch_path,
                       "far_prec": prec if args.batch_path == "blocked" else None,
-                      "orders": "per component, U[0.8, 1]" if pc else "one per instance"},
+                      "orders": (f"per component, U[{float(np.min(w['alpha'])):.2f}.., 1]"
+                                 if pc else "one per instance")},
            "history_gflops": flops / t / 1e9,
            "status_nonzero": int((st.cpu().numpy() != 0).sum()),
            "tune": tune,

@@ -138,9 +138,11 @@ typedef struct {
  * weights b, a, c, h^alpha_i and Gamma(alpha_i + 2), and with
  * FABM_PLAN_INITIAL_SLOPE its own Taylor term (y'(0) used where alpha_i > 1;
  * without the flag every alpha_i must be <= 1). Such plans run the DIRECT
- * kernels: path BLOCKED, the shared grid (LINEAR d > 4, FP16X2, tile_L != 0)
- * and the adjoint calls are UNSUPPORTED, and so is fabm_solve (one alpha):
- * a single trajectory is a batch of one. */
+ * kernels and the per-trajectory BLOCKED kernels with FP64 far windows (one
+ * weight table per component in the band and as the A operand of the
+ * windows); FP32 and FP16X2 far tiles, the shared grid (LINEAR d > 4,
+ * tile_L 64) and the adjoint calls are UNSUPPORTED, and so is fabm_solve
+ * (one alpha): a single trajectory is a batch of one. */
 #define FABM_PLAN_PER_COMPONENT_ORDER 2
 
 /* A plan is used by one host thread at a time: calls that share a plan share

@@ -91,15 +91,19 @@ __device__ __forceinline__ int band_wait_rows(int *s_cnt, int *s_dead, int need)
     }
 }
 
-template <int SYS, int D, bool YPOUT>
+// PC: non-commensurate orders, one weight table set and one h^a, Gamma(a+2)
+// per component (component k's tables at k * 3 wlen from the instance's,
+// its scalars in A.cmeta[k]).
+template <int SYS, int D, bool YPOUT, bool PC = false>
 __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
-    double *sb = (double *)smem;   // b lags 0..511 (next block's sums)
-    double *sa = sb + 2 * kBlk;    // a lags 0..511
-    double *sbh = sa + 2 * kBlk;   // h^a b lags 0..255 (this block's sums)
-    double *sah = sbh + kBlk;      // h^a a lags 0..255
-    double *sF = sah + kBlk;       // [256][D] f of this block's rows
+    constexpr int K = PC ? D : 1;     // weight tables held
+    double *sb = (double *)smem;      // [K] b lags 0..511 (next block's sums)
+    double *sa = sb + K * 2 * kBlk;   // [K] a lags 0..511
+    double *sbh = sa + K * 2 * kBlk;  // [K] h^a b lags 0..255 (this block's sums)
+    double *sah = sbh + K * kBlk;     // [K] h^a a lags 0..255
+    double *sF = sah + K * kBlk;      // [256][D] f of this block's rows
     double *sY = sF + kBlk * D;    // [256][D] y of this block's rows
     double *sYP = sY + kBlk * D;   // [256][D] predictor values (YPOUT)
     double *sTh = sYP + (YPOUT ? kBlk * D : 0);  // theta, for systems with many parameters
@@ -111,9 +115,16 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     const int64_t N = m.N;
     const int64_t pitch = (int64_t)A.NB * kBlk;
     const double *wb = A.W, *wa = wb + m.wlen, *wc = wa + m.wlen;
+    const int64_t cw = 3 * m.wlen;  // stride between the components' tables (PC)
     const int64_t t0 = (int64_t)J * kBlk;
     const int nrows = (int)((t0 + kBlk - 1 < N ? t0 + kBlk - 1 : N) - t0 + 1);
     constexpr int nthr = kBandWaves * kWave;
+    double hav[K], ig2v[K];  // h^a and 1 / Gamma(a + 2) of each table set
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        hav[k] = PC ? A.cmeta[k].ha : m.ha;
+        ig2v[k] = PC ? A.cmeta[k].ig2 : m.ig2;
+    }
 
     // a non-finite state in an earlier block ends the trajectory
     if (*A.dead != 0u) {
@@ -135,13 +146,16 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     const double *th = kThLds ? sTh : thr;
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = A.y0[i];
-    for (int j = tid; j < 2 * kBlk; j += nthr) {
-        sb[j] = wb[j];
-        sa[j] = wa[j];
-    }
-    for (int j = tid; j < kBlk; j += nthr) {
-        sbh[j] = m.ha * wb[j];
-        sah[j] = m.ha * wa[j];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        for (int j = tid; j < 2 * kBlk; j += nthr) {
+            sb[k * 2 * kBlk + j] = wb[k * cw + j];
+            sa[k * 2 * kBlk + j] = wa[k * cw + j];
+        }
+        for (int j = tid; j < kBlk; j += nthr) {
+            sbh[k * kBlk + j] = hav[k] * wb[k * cw + j];
+            sah[k * kBlk + j] = hav[k] * wa[k * cw + j];
+        }
     }
     // f_0 (block 0 forms row 0 here; later blocks need it for the c - a fix)
     double f0[D];
@@ -172,7 +186,13 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     double base[D];
     {
         double y1[D];
-        load_slope<D>(m, A.y1, y1);
+        if constexpr (PC) {  // y'(0) enters the components whose own order exceeds one
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                y1[i] = (A.y1 != nullptr && A.cmeta[i].alpha > 1.0) ? A.y1[i] : 0.0;
+        } else {
+            load_slope<D>(m, A.y1, y1);
+        }
         taylor_base<D>((double)T * m.h, y0, y1, base);
     }
     double pc[D], cc[D], pn[D], cn[D];
@@ -180,10 +200,11 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         // source row 0 takes b_{T-1} and c_{T-1}
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = fma(m.ha, T >= 1 ? wb[T - 1] * f0[i] : 0.0, base[i]);
-            cc[i] = fma(m.ha, T >= 1 ? wc[T - 1] * f0[i] : 0.0, base[i]);
-            pn[i] = wb[kBlk + row - 1] * f0[i];
-            cn[i] = wc[kBlk + row - 1] * f0[i];
+            const int64_t o = PC ? i * cw : 0;
+            pc[i] = fma(hav[PC ? i : 0], T >= 1 ? wb[o + T - 1] * f0[i] : 0.0, base[i]);
+            cc[i] = fma(hav[PC ? i : 0], T >= 1 ? wc[o + T - 1] * f0[i] : 0.0, base[i]);
+            pn[i] = wb[o + kBlk + row - 1] * f0[i];
+            cn[i] = wc[o + kBlk + row - 1] * f0[i];
         }
     } else {
         const double *cin = A.carry + (int64_t)(J & 1) * 2 * D * kBlk;
@@ -200,9 +221,10 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             const int rho = row >> 4, sig = row & 15;
             const int e = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
             const double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
-            const double dca = wc[T - 1] - wa[T - 1];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
+                const int64_t o = PC ? i * cw : 0;
+                const double dca = wc[o + T - 1] - wa[o + T - 1];
                 P[i] += aj[i * kBlk + e];
                 // source row 0 takes c_{T-1} where the tiles used a_{T-1}
                 Cs[i] = fma(dca, f0[i], Cs[i] + aj[(D + i) * kBlk + e]);
@@ -210,8 +232,8 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = fma(m.ha, P[i], base[i]);
-            cc[i] = fma(m.ha, Cs[i], base[i]);
+            pc[i] = fma(hav[PC ? i : 0], P[i], base[i]);
+            cc[i] = fma(hav[PC ? i : 0], Cs[i], base[i]);
         }
     }
     __syncthreads();
@@ -230,10 +252,13 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         }
         const int upto = c < lo ? c : lo;
         for (; done < upto; ++done) {
-            const double bw = sbh[row - done - 1], aw = sah[row - done - 1];
-            const double bn = sb[kBlk + row - done - 1], an = sa[kBlk + row - done - 1];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
+                const int k = PC ? i : 0;
+                const double bw = sbh[k * kBlk + row - done - 1];
+                const double aw = sah[k * kBlk + row - done - 1];
+                const double bn = sb[k * 2 * kBlk + kBlk + row - done - 1];
+                const double an = sa[k * 2 * kBlk + kBlk + row - done - 1];
                 const double f = sF[done * D + i];
                 pc[i] = fma(bw, f, pc[i]);
                 cc[i] = fma(aw, f, cc[i]);
@@ -250,7 +275,13 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     // row t-1 to the other sums and reading out those of row t+1 overlap it.
     // Rows are checked for non-finite values when they are published.
     const int first = done;
-    const double hb0 = sbh[0], ha0 = sah[0], hig2 = m.ha * m.ig2;
+    double hb0[K], ha0[K], hig2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        hb0[k] = sbh[k * kBlk];
+        ha0[k] = sah[k * kBlk];
+        hig2[k] = hav[k] * ig2v[k];
+    }
     double fprev[D], ypb[D], ycb[D];
     {
         const int l0 = first - lo < 63 ? first - lo : 63;
@@ -266,26 +297,37 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     // publish check runs once per group; the weights of the next step are
     // loaded one step ahead
     int lc0 = row - first;
-    double bw = sbh[lc0 > 0 ? lc0 : 0], aw = sah[lc0 > 0 ? lc0 : 0];
+    double bw[K], aw[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        bw[k] = sbh[k * kBlk + (lc0 > 0 ? lc0 : 0)];
+        aw[k] = sah[k * kBlk + (lc0 > 0 ? lc0 : 0)];
+    }
     for (int g0 = first & ~(kPublishEvery - 1); go && g0 < hi; g0 += kPublishEvery) {
 #pragma unroll
         for (int k = 0; k < kPublishEvery; ++k) {
             const int t = g0 + k;
             if (t < first || t >= hi) continue;
             const int lagn = row - t - 1;
-            const double bwn = sbh[lagn > 0 ? lagn : 0], awn = sah[lagn > 0 ? lagn : 0];
+            double bwn[K], awn[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                bwn[q] = sbh[q * kBlk + (lagn > 0 ? lagn : 0)];
+                awn[q] = sah[q * kBlk + (lagn > 0 ? lagn : 0)];
+            }
             const double tt = (double)(t0 + t) * m.h;
             double yp[D], fp[D], y[D], f[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) yp[i] = fma(hb0, fprev[i], ypb[i]);
+            for (int i = 0; i < D; ++i) yp[i] = fma(hb0[PC ? i : 0], fprev[i], ypb[i]);
             rhs<SYS, D>(tt, yp, fp, th);
 #pragma unroll
-            for (int i = 0; i < D; ++i) y[i] = fma(hig2, fp[i], fma(ha0, fprev[i], ycb[i]));
+            for (int i = 0; i < D; ++i)
+                y[i] = fma(hig2[PC ? i : 0], fp[i], fma(ha0[PC ? i : 0], fprev[i], ycb[i]));
             rhs<SYS, D>(tt, y, f, th);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                pc[i] = fma(bw, fprev[i], pc[i]);
-                cc[i] = fma(aw, fprev[i], cc[i]);
+                pc[i] = fma(bw[PC ? i : 0], fprev[i], pc[i]);
+                cc[i] = fma(aw[PC ? i : 0], fprev[i], cc[i]);
             }
             const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
 #pragma unroll
@@ -302,8 +344,11 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
                     if constexpr (YPOUT) sYP[t * D + i] = yp[i];
                 }
             }
-            bw = bwn;
-            aw = awn;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                bw[q] = bwn[q];
+                aw[q] = awn[q];
+            }
         }
         const int tl = g0 + kPublishEvery < hi ? g0 + kPublishEvery : hi;  // rows formed: < tl
         {
@@ -335,9 +380,11 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         // wavefront), then rows formed by later wavefronts
         __builtin_amdgcn_wave_barrier();
         for (int t = first; t < hi; ++t) {
-            const double bn = sb[kBlk + row - t - 1], an = sa[kBlk + row - t - 1];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
+                const int k = PC ? i : 0;
+                const double bn = sb[k * 2 * kBlk + kBlk + row - t - 1];
+                const double an = sa[k * 2 * kBlk + kBlk + row - t - 1];
                 const double f = sF[t * D + i];
                 pn[i] = fma(bn, f, pn[i]);
                 cn[i] = fma(an, f, cn[i]);
@@ -347,9 +394,11 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             const int c = __builtin_amdgcn_readfirstlane(band_wait_rows(s_cnt, s_dead, done + 1));
             if (c < 0) break;
             for (; done < c; ++done) {
-                const double bn = sb[kBlk + row - done - 1], an = sa[kBlk + row - done - 1];
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
+                    const int k = PC ? i : 0;
+                    const double bn = sb[k * 2 * kBlk + kBlk + row - done - 1];
+                    const double an = sa[k * 2 * kBlk + kBlk + row - done - 1];
                     const double f = sF[done * D + i];
                     pn[i] = fma(bn, f, pn[i]);
                     cn[i] = fma(an, f, cn[i]);
@@ -423,11 +472,14 @@ __device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB)
 // all components, added into `acc` (one wavefront). The history column of
 // lane rho is staged column rho - u + coff; columns past the staged range
 // (coff > 15 only) belong to blocks not yet formed and are masked to zero.
-template <int D, int NC = kSrcCols>
+// PC: each component has its own weight tables, cw doubles apart, so each
+// takes its own A operand.
+template <int D, int NC = kSrcCols, bool PC = false>
 __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__restrict__ wb,
                                            const double *__restrict__ wa, const double *sB,
-                                           int64_t m, int u, int coff)
+                                           int64_t m, int u, int coff, int64_t cw = 0)
 {
+    constexpr int K = PC ? D : 1;
     const int lane = threadIdx.x & (kWave - 1);
     const int r16 = lane & 15, kq = lane >> 4;  // A row sigma / B column rho; K slot
     const int c = r16 - u + coff;
@@ -436,7 +488,12 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
     const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const double ab = wb[wi - 4 * j], aa = wa[wi - 4 * j];
+        double ab[K], aa[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            ab[k] = wb[k * cw + wi - 4 * j];
+            aa[k] = wa[k * cw + wi - 4 * j];
+        }
         double bf[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -445,8 +502,10 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            acc[0][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab, bf[i], acc[0][i], 0, 0, 0);
-            acc[1][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa, bf[i], acc[1][i], 0, 0, 0);
+            acc[0][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab[PC ? i : 0], bf[i], acc[0][i], 0,
+                                                             0, 0);
+            acc[1][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[PC ? i : 0], bf[i], acc[1][i], 0,
+                                                             0, 0);
         }
     }
 }
@@ -530,13 +589,14 @@ __device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, 
 
 // Far window m = J - s of target block J (one wavefront; staged columns
 // rho - u + 15), added to the target's sums in place.
-template <int D, bool PAIR = false>
+template <int D, bool PAIR = false, bool PC = false>
 __device__ __forceinline__ void far_target(const InstView &A, int s, int J, const double *sB,
                                            bool first)
 {
     constexpr int NC = PAIR ? kPairCols : kSrcCols;
     const InstMeta m = A.meta[0];
     const double *wb = A.W, *wa = wb + m.wlen;
+    const int64_t cw = 3 * m.wlen;
     const int lane = threadIdx.x & (kWave - 1);
     double *aj = A.acc + (int64_t)J * 2 * D * kBlk + lane;
     dbl4 acc[2][D];
@@ -551,11 +611,12 @@ __device__ __forceinline__ void far_target(const InstView &A, int s, int J, cons
     if constexpr (PAIR) {
         // source block s - 1 first: the order of the one-window launches
 #pragma unroll 2
-        for (int u = 0; u < kTile; ++u) window_lag<D, NC>(acc, wb, wa, sB, mm + 1, u, kTile - 1);
+        for (int u = 0; u < kTile; ++u)
+            window_lag<D, NC, PC>(acc, wb, wa, sB, mm + 1, u, kTile - 1, cw);
     }
 #pragma unroll 2
     for (int u = 0; u < kTile; ++u)
-        window_lag<D, NC>(acc, wb, wa, sB, mm, u, PAIR ? 2 * kTile - 1 : kTile - 1);
+        window_lag<D, NC, PC>(acc, wb, wa, sB, mm, u, PAIR ? 2 * kTile - 1 : kTile - 1, cw);
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -570,12 +631,13 @@ __device__ __forceinline__ void far_target(const InstView &A, int s, int J, cons
 // NW wavefronts. Their partial sums are added in wavefront order, either all
 // at once from NW LDS slots (SEQ = false, red holds NW tiles) or one
 // wavefront after another into a single slot (SEQ = true).
-template <int D, int NW, bool SEQ>
+template <int D, int NW, bool SEQ, bool PC = false>
 __device__ __forceinline__ void near_part(const InstView &A, int s, const double *sB,
                                           double *red)
 {
     const InstMeta m = A.meta[0];
     const double *wb = A.W, *wa = wb + m.wlen;
+    const int64_t cw = 3 * m.wlen;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid >> 6;
     const int J = s + 2;
     constexpr int kLags = 31;
@@ -587,9 +649,9 @@ __device__ __forceinline__ void near_part(const InstView &A, int s, const double
     const int p0 = kLags * w / NW, p1 = kLags * (w + 1) / NW;
     for (int p = p0; p < p1; ++p) {
         if (p < kTile)
-            window_lag<D>(acc, wb, wa, sB, 2, p, kTile - 1);
+            window_lag<D, kSrcCols, PC>(acc, wb, wa, sB, 2, p, kTile - 1, cw);
         else
-            window_lag<D>(acc, wb, wa, sB, 1, p - (kTile - 1), 2 * kTile - 1);
+            window_lag<D, kSrcCols, PC>(acc, wb, wa, sB, 1, p - (kTile - 1), 2 * kTile - 1, cw);
     }
     double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
     if constexpr (!SEQ) {
@@ -629,20 +691,21 @@ __device__ __forceinline__ void near_part(const InstView &A, int s, const double
 
 __device__ __forceinline__ InstView single_view(const StepArgs &A)
 {
-    return InstView{A.meta, A.params, A.y0, A.y1, A.Y, nullptr, A.W, A.W32, A.Fc, A.carry, A.acc,
-                    A.dead, A.NB};
+    return InstView{A.meta, A.cmeta, A.params, A.y0, A.y1, A.Y, nullptr, A.W, A.W32, A.Fc,
+                    A.carry, A.acc, A.dead, A.NB};
 }
 
 // Launch s of the single-trajectory pipeline; `wpw` wavefronts of each far
 // workgroup take part (wavefront g of G handles targets s + 3 + g + k G).
-template <int SYS, int D, bool F32>
+template <int SYS, int D, bool F32, bool PC = false>
 __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wpw)
 {
+    static_assert(!(F32 && PC), "per-component orders run FP64 windows");
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x, wave = threadIdx.x >> 6;
     const InstView V = single_view(A);
     if (b == 0) {
-        if (wave < kBandWaves) band_block<SYS, D, false>(V, s + 1, smem);
+        if (wave < kBandWaves) band_block<SYS, D, false, PC>(V, s + 1, smem);
         return;
     }
     if (*A.dead != 0u) return;  // the trajectory has ended; later rows are NaN
@@ -652,13 +715,14 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         __syncthreads();
         if (b == 1) {
             if (wave < kNearWaves)
-                near_part<D, kNearWaves, false>(V, s, sB, (double *)(smem + staged_bytes<D>()));
+                near_part<D, kNearWaves, false, PC>(V, s, sB,
+                                                    (double *)(smem + staged_bytes<D>()));
             return;
         }
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
         for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G)
-            far_target<D>(V, s, J, sB, s == 0);
+            far_target<D, false, PC>(V, s, J, sB, s == 0);
     } else {
         float *sB = (float *)smem;
         stage_sources<D, float>(V, s, sB);
@@ -679,6 +743,7 @@ __device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
     const InstMeta *m = A.meta + i;
     const BlkInst &b = A.inst[i];
     return InstView{m,
+                    A.cmeta ? A.cmeta + (int64_t)i * D : nullptr,
                     A.params + m->p_off,
                     A.y0 + (int64_t)i * D,
                     A.y1 ? A.y1 + (int64_t)i * D : nullptr,
@@ -693,16 +758,17 @@ __device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
                     b.NB};
 }
 
-template <int SYS, int D, bool F32, bool YPOUT>
+template <int SYS, int D, bool F32, bool YPOUT, bool PC = false>
 __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s, int nband,
                                                               int nnear, const int *far_off,
                                                               int nfar)
 {
+    static_assert(!(F32 && PC), "per-component orders run FP64 windows");
     extern __shared__ __align__(16) char smem[];
     int q = blockIdx.x;
     if (q < nband) {
         const InstView V = batch_view<D>(A, A.order[q]);
-        band_block<SYS, D, YPOUT>(V, s + 1, smem);
+        band_block<SYS, D, YPOUT, PC>(V, s + 1, smem);
         return;
     }
     q -= nband;
@@ -739,15 +805,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
             stage_sources<D, double>(V, s, sB);
         __syncthreads();
         if (first < 0) {
-            near_part<D, kBatchThreads / kWave, true>(V, s, sB,
-                                                      (double *)(smem + staged_bytes<D>()));
+            near_part<D, kBatchThreads / kWave, true, PC>(V, s, sB,
+                                                          (double *)(smem + staged_bytes<D>()));
             return;
         }
         if (mine) {
             if (pair)
-                far_target<D, true>(V, s, J, sB, s <= 1);
+                far_target<D, true, PC>(V, s, J, sB, s <= 1);
             else
-                far_target<D>(V, s, J, sB, s <= 1);
+                far_target<D, false, PC>(V, s, J, sB, s <= 1);
         }
     } else {
         float *sB = (float *)smem;
@@ -788,9 +854,18 @@ __global__ void k_step_status(StepArgs A)
 // Every workgroup asks for more than half of a compute unit's 160 KiB of
 // LDS, so no two step workgroups share a compute unit: the band has one to
 // itself and each far workgroup owns four SIMDs.
-size_t step_smem_bytes(int d)
+// Band LDS: weight tables (one set, or one per component with per-component
+// orders), f / y / predictor rows, theta, two counters.
+static size_t band_smem_bytes(int d, bool pc)
 {
-    const size_t band = sizeof(double) * (6 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    return sizeof(double) * (6 * kBlk * (size_t)(pc ? d : 1) + 3 * kBlk * (size_t)d + d * d +
+                             2 * d) +
+           16;
+}
+
+size_t step_smem_bytes(int d, bool pc)
+{
+    const size_t band = band_smem_bytes(d, pc);
     const size_t near = sizeof(double) * (kNearWaves * 2 * (size_t)d * kBlk +
                                           (size_t)d * kSrcCols * kColPitch);
     const size_t exclusive = 81 * 1024;
@@ -817,7 +892,7 @@ void step_grid(int NB, int s, int *grid, int *wpw, int far_cap)
     *grid += std::min(cap, (nt + *wpw - 1) / *wpw);
 }
 
-template <int SYS, int D, bool F32>
+template <int SYS, int D, bool F32, bool PC>
 static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer *T,
                                   const char **where)
 {
@@ -831,10 +906,10 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
         }                                  \
     } while (0)
     static bool attr_done = false;
-    const size_t smem = step_smem_bytes(D);
+    const size_t smem = step_smem_bytes(D, PC);
     if (!attr_done) {
         FABM_STEP_TRY("hipFuncSetAttribute(step LDS)",
-                      hipFuncSetAttribute((const void *)k_step<SYS, D, F32>,
+                      hipFuncSetAttribute((const void *)k_step<SYS, D, F32, PC>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
         attr_done = true;
     }
@@ -842,8 +917,8 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
         int grid, wpw;
         step_grid(A.NB, s, &grid, &wpw, A.far_cap);
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
-        hipLaunchKernelGGL((k_step<SYS, D, F32>), dim3(grid), dim3(kStepThreads), smem, st, A, s,
-                           wpw);
+        hipLaunchKernelGGL((k_step<SYS, D, F32, PC>), dim3(grid), dim3(kStepThreads), smem, st, A,
+                           s, wpw);
         FABM_STEP_TRY("launch k_step", hipGetLastError());
         if (T) FABM_STEP_TRY("timer end", T->end(st));
     }
@@ -853,15 +928,15 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
 #undef FABM_STEP_TRY
 }
 
-size_t batch_smem_bytes(int d)
+size_t batch_smem_bytes(int d, bool pc)
 {
-    const size_t band = sizeof(double) * (6 * kBlk + 3 * kBlk * (size_t)d + d * d + 2 * d) + 16;
+    const size_t band = band_smem_bytes(d, pc);
     const size_t near = sizeof(double) * (2 * (size_t)d * kBlk + (size_t)d * kSrcCols * kColPitch);
     const size_t pair = sizeof(double) * (size_t)d * kPairCols * kColPitch;
     return std::max(std::max(band, near), pair);
 }
 
-template <int SYS, int D, bool F32, bool YPOUT>
+template <int SYS, int D, bool F32, bool YPOUT, bool PC>
 static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, const int *far_off,
                                   hipStream_t st, KernelTimer *T, const char **where)
 {
@@ -873,7 +948,14 @@ static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, co
             return e_;                     \
         }                                  \
     } while (0)
-    const size_t smem = batch_smem_bytes(D);
+    const size_t smem = batch_smem_bytes(D, PC);
+    static bool attr_done = false;
+    if (PC && !attr_done) {  // above the default limit only with per-component tables
+        FABM_STEP_TRY("hipFuncSetAttribute(batch LDS)",
+                      hipFuncSetAttribute((const void *)k_step_batch<SYS, D, F32, YPOUT, PC>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        attr_done = true;
+    }
     for (int s = -1; s <= S.max_NB - 2; ++s) {
         const size_t k = (size_t)(s + 1);
         const int nb = S.nband[k], nn = S.nnear[k], nf = S.nfar[k];
@@ -881,7 +963,7 @@ static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, co
         const int grid = nb + nn + nfw;
         if (grid == 0) continue;
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
-        hipLaunchKernelGGL((k_step_batch<SYS, D, F32, YPOUT>), dim3(grid), dim3(kBatchThreads), smem,
+        hipLaunchKernelGGL((k_step_batch<SYS, D, F32, YPOUT, PC>), dim3(grid), dim3(kBatchThreads), smem,
                            st, A, s,
                            nb, nn, far_off + S.far_base[k], nf);
         FABM_STEP_TRY("launch k_step_batch", hipGetLastError());
@@ -897,11 +979,17 @@ hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const Bat
                          const int *far_off, hipStream_t s, KernelTimer *T, const char **where)
 {
     // predictor rows are written when A.YP is set (FP64 far windows only)
-#define FABM_BATCH_CASE(SS, DD)                                                          \
-    if (sys == SS && d == DD)                                                            \
-        return A.YP  ? enqueue_batch_t<SS, DD, false, true>(A, S, far_off, s, T, where)  \
-               : f32 ? enqueue_batch_t<SS, DD, true, false>(A, S, far_off, s, T, where)  \
-                     : enqueue_batch_t<SS, DD, false, false>(A, S, far_off, s, T, where);
+    // per-component orders (A.cmeta): FP64 windows, no predictor rows
+    if (A.cmeta && (f32 || A.YP)) {
+        *where = "per-component orders with FP32 windows or predictor rows";
+        return hipErrorInvalidValue;
+    }
+#define FABM_BATCH_CASE(SS, DD)                                                                \
+    if (sys == SS && d == DD)                                                                  \
+        return A.cmeta ? enqueue_batch_t<SS, DD, false, false, true>(A, S, far_off, s, T, where) \
+               : A.YP  ? enqueue_batch_t<SS, DD, false, true, false>(A, S, far_off, s, T, where) \
+               : f32   ? enqueue_batch_t<SS, DD, true, false, false>(A, S, far_off, s, T, where) \
+                       : enqueue_batch_t<SS, DD, false, false, false>(A, S, far_off, s, T, where);
     FABM_BATCH_CASE(SYS_LINEAR, 1)
     FABM_BATCH_CASE(SYS_LINEAR, 2)
     FABM_BATCH_CASE(SYS_LINEAR, 3)
@@ -919,10 +1007,15 @@ hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const Bat
 hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_t s,
                          KernelTimer *T, const char **where)
 {
+    if (A.cmeta && f32) {
+        *where = "per-component orders with FP32 windows";
+        return hipErrorInvalidValue;
+    }
 #define FABM_STEP_CASE(SS, DD)                                                   \
     if (sys == SS && d == DD)                                                    \
-        return f32 ? enqueue_steps_t<SS, DD, true>(A, s, T, where)               \
-                   : enqueue_steps_t<SS, DD, false>(A, s, T, where);
+        return A.cmeta ? enqueue_steps_t<SS, DD, false, true>(A, s, T, where)    \
+               : f32   ? enqueue_steps_t<SS, DD, true, false>(A, s, T, where)    \
+                       : enqueue_steps_t<SS, DD, false, false>(A, s, T, where);
     FABM_STEP_CASE(SYS_LINEAR, 1)
     FABM_STEP_CASE(SYS_LINEAR, 2)
     FABM_STEP_CASE(SYS_LINEAR, 3)

@@ -120,8 +120,7 @@ bool wide_plan(const fabm_plan_desc &d)
 
 Path choose_path(const fabm_plan_s *pl, int64_t batch, const int64_t *N)
 {
-    if (per_component(pl)) return Path::Direct;  // the only path with per-component weights
-    if (wide_plan(pl->desc)) return Path::Wide;
+    if (wide_plan(pl->desc)) return Path::Wide;  // never with per-component orders
     switch (pl->desc.path) {
     case FABM_PATH_DIRECT: return Path::Direct;
     case FABM_PATH_BLOCKED: return Path::Blocked;
@@ -208,10 +207,16 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
             L.meta_adj = off;
             off += sizeof(InstMeta) * (size_t)batch;
         }
+        const bool pc = per_component(pl);
+        if (pc) {  // one entry per (instance, component): its order's weights and scalars
+            off = (off + 15) / 16 * 16;
+            L.cmeta = off;
+            off += sizeof(InstMeta) * (size_t)batch * d;
+        }
         L.stage_bytes = off;
         off = align_up(off);
         L.w = off;
-        off = align_up(off + sizeof(double) * nw);
+        off = align_up(off + sizeof(double) * nw * (pc ? d : 1));
         L.w32 = off;  // binary32 b, a for FP32 far windows
         if (pl->desc.far_prec == FABM_FAR_FP32 && !adjoint)
             off = align_up(off + sizeof(float) * nw / 3 * 2);
@@ -285,10 +290,16 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         L.NB = blocks_of(N[0]);
         L.wlen = (int64_t)L.NB * Lb + Lb;
         const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;  // one [2d][256] block of sums
+        const bool pc = per_component(pl);
+        if (pc) {
+            off = (off + 15) / 16 * 16;
+            L.cmeta = off;
+            off += sizeof(InstMeta) * (size_t)d;
+        }
         L.stage_bytes = off;
         off = align_up(off);
         L.w = off;
-        off = align_up(off + sizeof(double) * 3 * (size_t)L.wlen);
+        off = align_up(off + sizeof(double) * 3 * (size_t)L.wlen * (pc ? d : 1));
         L.w32 = off;  // binary32 b, a for FP32 far windows
         if (pl->desc.far_prec == FABM_FAR_FP32)
             off = align_up(off + sizeof(float) * 2 * (size_t)L.wlen);
@@ -570,6 +581,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     if (L.path == Path::Blocked && batch > 1) {
         fabm::BatchArgs A{};
         A.meta = dmeta;
+        A.cmeta = dcmeta;
         A.inst = (const fabm::BlkInst *)(base + L.inst);
         A.order = (const int *)(base + L.order);
         A.params = params;
@@ -593,6 +605,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     if (L.path == Path::Blocked) {
         fabm::StepArgs A{};
         A.meta = dmeta;
+        A.cmeta = dcmeta;
         A.params = params;
         A.y0 = y0;
         A.y1 = y1;
@@ -816,9 +829,9 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     if (desc->tile_L != 0 && desc->tile_L != (wide ? fabm::kWideBlk : fabm::step_block_len()))
         return FABM_ERR_UNSUPPORTED;
     if (wide && desc->path == FABM_PATH_DIRECT) return FABM_ERR_UNSUPPORTED;
-    // per-component orders run on the DIRECT kernels only
+    // per-component orders: DIRECT, or BLOCKED per trajectory with FP64 windows
     if ((desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) &&
-        (wide || desc->path == FABM_PATH_BLOCKED || desc->tile_L != 0))
+        (wide || desc->far_prec != FABM_FAR_FP64))
         return FABM_ERR_UNSUPPORTED;
     if (wide && desc->max_batch > kWideMaxCols / desc->dim) return FABM_ERR_UNSUPPORTED;
 

@@ -38,6 +38,7 @@ constexpr int kMaxFarWg = 254;      // far workgroups per launch (+ band + near 
 // One trajectory as seen by the step kernels' device code.
 struct InstView {
     const InstMeta *meta;
+    const InstMeta *cmeta;  // non-commensurate orders: [D] entries of this instance, or null
     const double *params;
     const double *y0;
     const double *y1;   // y'(0) [D] (orders above one), or null
@@ -54,6 +55,7 @@ struct InstView {
 
 struct StepArgs {
     const InstMeta *meta;
+    const InstMeta *cmeta;  // non-commensurate orders: [D] per-component entries, or null
     const double *params;
     const double *y0;
     const double *y1;   // y'(0) [D] (orders above one), or null
@@ -97,6 +99,7 @@ struct BlkInst {
 
 struct BatchArgs {
     const InstMeta *meta;  // [batch]
+    const InstMeta *cmeta; // non-commensurate orders: [batch][D], or null
     const BlkInst *inst;   // [batch]
     const int *order;      // instances by block count, descending
     const double *params;  // [batch][n_params]

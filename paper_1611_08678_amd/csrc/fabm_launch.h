@@ -48,7 +48,7 @@ struct KernelTimer;
 hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_t s,
                          KernelTimer *T, const char **where);
 int step_block_len();
-size_t step_smem_bytes(int d);
+size_t step_smem_bytes(int d, bool pc = false);
 void step_grid(int NB, int s, int *grid, int *wpw, int far_cap);
 
 // BLOCKED path for a batch (> 1) of trajectories: one launch per block step
@@ -57,7 +57,7 @@ struct BatchArgs;
 struct BatchSchedule;
 hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const BatchSchedule &S,
                          const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
-size_t batch_smem_bytes(int d);
+size_t batch_smem_bytes(int d, bool pc = false);
 
 // Single-launch persistent variant of the BLOCKED path (not dispatched).
 struct BlockedArgs;

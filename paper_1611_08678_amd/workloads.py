@@ -20,7 +20,8 @@ y0 [B, d] (B = 1 for single trajectories) plus descriptive fields.
                  (1, 3, 1, 5, 0.006, 4, -1.6, 3.25), alpha 0.95, h = 0.01,
                  y0 = (-1.6, -10, 2); N from the step counts of the paper's
                  Section 4 timing table (TABLE2_N)
-  per_component_orders  any of the above with alpha [B][d] ~ U[0.8, 1] (seed 6)
+  per_component_orders  any of the above with alpha [B][d] ~ U[lo, 1] (seed 6;
+                 lo = 0.8, 0.9 for the Rossler batch)
 """
 from __future__ import annotations
 

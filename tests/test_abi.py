@@ -190,17 +190,23 @@ def test_initial_slope_flag_rules(fabm):
 
 
 def test_per_component_order_rules(fabm):
-    """Non-commensurate plans: DIRECT only (BLOCKED, the shared grid and the
-    adjoint are UNSUPPORTED, so is fabm_solve with its single alpha); alpha is
-    [batch][d], every entry checked (an order above one needs the slope flag);
-    one weight table per component. Host-side checks only."""
+    """Non-commensurate plans: DIRECT and per-trajectory BLOCKED with FP64
+    windows (FP32 windows, the shared grid and the adjoint are UNSUPPORTED, so
+    is fabm_solve with its single alpha); alpha is [batch][d], every entry
+    checked (an order above one needs the slope flag); one weight table per
+    component. Host-side checks only."""
     import ctypes as C
     import numpy as np
     F = fabm
-    for kw in (dict(path="blocked"), dict(path="auto", tile_L=256)):
-        with pytest.raises(F.FabmError) as e:
-            F.fabm_plan("chen", 3, max_batch=2, max_steps=100, per_component_order=True, **kw)
-        assert e.value.code == 2
+    for kw in (dict(path="blocked"), dict(path="auto", tile_L=256), dict(path="direct")):
+        F.fabm_plan("chen", 3, max_batch=2, max_steps=100, per_component_order=True, **kw)
+    with pytest.raises(F.FabmError) as e:
+        F.fabm_plan("chen", 3, "blocked", "fp32", 2, 100, per_component_order=True)
+    assert e.value.code == 2
+    pb = F.fabm_plan("vdp", 2, "blocked", "fp64", 3, 2000, per_component_order=True)
+    qb = F.fabm_plan("vdp", 2, "blocked", "fp64", 3, 2000)
+    for Ns in ([2000], [2000, 5, 700]):  # single and batched layouts: one table set per component
+        assert F.fabm_workspace_size(pb, Ns) > F.fabm_workspace_size(qb, Ns)
     with pytest.raises(F.FabmError) as e:
         F.fabm_plan("linear", 8, "auto", "fp64", 2, 100, per_component_order=True)
     assert e.value.code == 2

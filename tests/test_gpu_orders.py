@@ -1,10 +1,10 @@
 """GPU parity of non-commensurate orders (a separate alpha per component;
-plans with FABM_PLAN_PER_COMPONENT_ORDER, DIRECT kernels) against the
-oracle's per-component solver, through the C ABI: ragged batches on the
-workgroup-per-instance kernel, single long trajectories on the whole-GPU
-kernel, orders above one with y'(0), blow-up status, and equal orders giving
-the commensurate DIRECT result bitwise. 1e-11 normwise, as for every FP64
-path."""
+plans with FABM_PLAN_PER_COMPONENT_ORDER) against the oracle's per-component
+solver, through the C ABI: ragged batches on the DIRECT workgroup-per-instance
+kernel and the batched BLOCKED pipeline, single long trajectories on the
+whole-GPU DIRECT kernel and the BLOCKED step kernels, orders above one with
+y'(0), blow-up status, and equal orders giving the commensurate result
+bitwise (DIRECT). 1e-11 normwise, as for every FP64 path."""
 import numpy as np
 import pytest
 
@@ -59,13 +59,13 @@ def _horizons(orc, sid, th, al, hs, Ns, init, ref, off, rows):
     return out
 
 
-def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11):
+def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11, path="direct"):
     """Status equal (or one step apart at the top of the binary64 range, as
     for commensurate orders), NaN rows from there on, and the rows of
     _horizons within tol normwise."""
     sid = SYSTEMS[sysname][0] if sysname in SYSTEMS else {"chen": 1}[sysname]
     name = "linear" if sysname.startswith("linear") else sysname
-    y, off, st = F.solve_batch(name, th, al, hs, Ns, init, path="direct")
+    y, off, st = F.solve_batch(name, th, al, hs, Ns, init, path=path)
     ref, roff, rst = orc.solve_orders_batch(sid, th, al, hs, Ns, init)
     assert np.array_equal(off, roff)
     yy, gst = _to_np(y), _to_np(st)
@@ -87,9 +87,10 @@ def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11):
     return rst
 
 
+@pytest.mark.parametrize("path", ["direct", "blocked"])
 @pytest.mark.parametrize("sysname", list(SYSTEMS))
 @pytest.mark.parametrize("slope", [False, True])
-def test_batch_per_component_orders(F, orc, sysname, slope):
+def test_batch_per_component_orders(F, orc, sysname, slope, path):
     sid, d, th_of = SYSTEMS[sysname]
     rng = np.random.default_rng(60 + sid + 10 * slope)
     B = 10
@@ -102,22 +103,24 @@ def test_batch_per_component_orders(F, orc, sysname, slope):
     Ns = rng.integers(100, 2500, B, endpoint=True)
     Ns[:3] = [1, 255, 1024]
     init = 0.5 * rng.uniform(-1, 1, (B, 2, d) if slope else (B, d))
-    _compare(F, orc, sysname, th, al, hs, Ns, init)
+    _compare(F, orc, sysname, th, al, hs, Ns, init, path=path)
 
 
+@pytest.mark.parametrize("path", ["direct", "blocked"])
 @pytest.mark.parametrize("sysname,al,N", [("vdp", [0.8, 0.95], 9000),
                                           ("hindmarsh_rose", [0.9, 1.0, 0.95], 10000),
                                           ("linear3", [0.6, 1.6, 1.95], 8500)])
-def test_single_long_trajectory_whole_gpu_kernel(F, orc, sysname, al, N):
-    """N >= 8192: one trajectory spread over the GPU (cooperative kernel)."""
+def test_single_long_trajectory(F, orc, sysname, al, N, path):
+    """N >= 8192: one trajectory on the whole-GPU DIRECT kernel or the BLOCKED
+    step kernels (35-40 blocks of 256 rows, far windows in every launch)."""
     sid, d, th_of = SYSTEMS[sysname]
     rng = np.random.default_rng(4)
     th = th_of(rng, 0)[None]
     init = 0.5 * rng.uniform(-1, 1, (1, 2, d))
-    _compare(F, orc, sysname, th, np.array([al]), [0.01], [N], init)
+    _compare(F, orc, sysname, th, np.array([al]), [0.01], [N], init, path=path)
     # the single-trajectory convenience call takes the per-component orders too
     name = "linear" if sysname.startswith("linear") else sysname
-    y, st = F.solve(name, th[0], al, 0.01, N, init[0], path="direct")
+    y, st = F.solve(name, th[0], al, 0.01, N, init[0], path=path)
     ref, _, _, rst = orc.solve_orders(sid, th[0], al, 0.01, N, init[0])
     assert int(st.item()) == rst == 0 and relerr(_to_np(y), ref) <= 1e-11
 
