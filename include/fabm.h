@@ -140,9 +140,10 @@ typedef struct {
  * without the flag every alpha_i must be <= 1). Such plans run the DIRECT
  * kernels and the per-trajectory BLOCKED kernels with FP64 far windows (one
  * weight table per component in the band and as the A operand of the
- * windows); FP32 and FP16X2 far tiles, the shared grid (LINEAR d > 4,
- * tile_L 64) and the adjoint calls are UNSUPPORTED, and so is fabm_solve
- * (one alpha): a single trajectory is a batch of one. */
+ * windows), and the adjoint calls (alpha [batch][d] there too); FP32 and
+ * FP16X2 far tiles and the shared grid (LINEAR d > 4, tile_L 64) are
+ * UNSUPPORTED, and so is fabm_solve (one alpha): a single trajectory is a
+ * batch of one. */
 #define FABM_PLAN_PER_COMPONENT_ORDER 2
 
 /* A plan is used by one host thread at a time: calls that share a plan share

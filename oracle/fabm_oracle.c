@@ -685,6 +685,75 @@ int64_t oracle_adjoint(int system, int d, const double *theta, double alpha, dou
     return st;
 }
 
+/* Discrete adjoint of solve_orders (non-commensurate orders), the recursion
+ * of oracle_adjoint with component i's own weights, h^alpha_i and
+ * Gamma(alpha_i + 2) wherever component i's sums and updates appear. init is
+ * [n_init][d]; gy0 receives [n_init][d] (dL/dy(0), then dL/dy'(0) for
+ * components with alpha_i > 1, zero for the others). */
+int64_t oracle_adjoint_orders(int system, int d, const double *theta, const double *alpha,
+                              double h, int64_t N, const double *init, int n_init,
+                              const double *gy, double *gy0, double *gtheta)
+{
+    orc_rhs r = {system, d, theta, 0, 0};
+    int nth = oracle_n_params(system, d);
+    size_t L = (size_t)N + 1;
+    double *W = malloc(sizeof(double) * 3 * L * d);
+    double *ha = malloc(sizeof(double) * d), *ig2 = malloc(sizeof(double) * d);
+    for (int i = 0; i < d; ++i) {
+        oracle_weights(alpha[i], N, W + 3 * i * L, W + (3 * i + 1) * L, W + (3 * i + 2) * L);
+        step_scalars(alpha[i], h, &ha[i], &ig2[i]);
+    }
+    double *Y = malloc(sizeof(double) * L * d);
+    double *YP = malloc(sizeof(double) * L * d);
+    int64_t st = solve_orders(&r, alpha, h, N, init, n_init, Y, YP, 0);
+
+    long double *fbar = calloc(L * d, sizeof(long double));
+    long double *gy0l = calloc(d, sizeof(long double));
+    long double *gy1l = calloc(d, sizeof(long double));
+    long double *gthl = calloc(nth > 0 ? nth : 1, sizeof(long double));
+    long double *ybar = calloc(d, sizeof(long double));
+    long double *u = calloc(d, sizeof(long double)), *v = calloc(d, sizeof(long double));
+    long double *tmp = calloc(d, sizeof(long double));
+    long double *ypbar = calloc(d, sizeof(long double));
+
+    for (int i = 0; i < d; ++i) gy0l[i] = gy[i];
+    for (int64_t n = N; n >= 1; --n) {
+        double tn = (double)n * h;
+        for (int i = 0; i < d; ++i) ybar[i] = gy[n * d + i];
+        rhs_vjp(&r, tn, Y + n * d, fbar + n * d, ybar, gthl);
+        for (int i = 0; i < d; ++i) {
+            gy0l[i] += ybar[i];
+            u[i] = (long double)ha[i] * ybar[i];
+            tmp[i] = u[i] * ig2[i];
+        }
+        for (int i = 0; i < d; ++i) ypbar[i] = 0;
+        rhs_vjp(&r, tn, YP + n * d, tmp, ypbar, gthl);
+        for (int i = 0; i < d; ++i) {
+            gy0l[i] += ypbar[i];
+            if (n_init_of(alpha[i]) == 2) gy1l[i] += (long double)tn * (ybar[i] + ypbar[i]);
+            v[i] = (long double)ha[i] * ypbar[i];
+        }
+        for (int i = 0; i < d; ++i) {
+            const double *bb = W + 3 * i * L, *aa = bb + L, *cc = aa + L;
+            fbar[i] += (long double)cc[n - 1] * u[i];
+            for (int64_t k = 1; k <= n - 1; ++k) fbar[k * d + i] += (long double)aa[n - 1 - k] * u[i];
+            for (int64_t k = 0; k <= n - 1; ++k) fbar[k * d + i] += (long double)bb[n - 1 - k] * v[i];
+        }
+    }
+    rhs_vjp(&r, 0.0, init, fbar, gy0l, gthl);
+    for (int i = 0; i < d; ++i) gy0[i] = (double)gy0l[i];
+    if (n_init == 2)
+        for (int i = 0; i < d; ++i) gy0[d + i] = (double)gy1l[i];
+    for (int q = 0; q < nth; ++q) gtheta[q] = (double)gthl[q];
+    if (st) {
+        for (int i = 0; i < n_init * d; ++i) gy0[i] = NAN;
+        for (int q = 0; q < nth; ++q) gtheta[q] = NAN;
+    }
+    free(W); free(ha); free(ig2); free(Y); free(YP); free(fbar); free(gy0l); free(gy1l);
+    free(gthl); free(ybar); free(u); free(v); free(tmp); free(ypbar);
+    return st;
+}
+
 /* Right-hand side alone, for tests of the system definitions. */
 void oracle_rhs(int system, int d, const double *theta, double t, const double *y, double *f)
 {

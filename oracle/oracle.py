@@ -68,6 +68,9 @@ def lib():
         L.oracle_solve_orders_cb.restype = C.c_int64
         L.oracle_solve_orders_batch.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int64,
                                                 _D, _D, _I64, _D, _D, _I64, _D, _I64]
+        L.oracle_adjoint_orders.argtypes = [C.c_int, C.c_int, _D, _D, C.c_double, C.c_int64,
+                                            _D, C.c_int, _D, _D, _D]
+        L.oracle_adjoint_orders.restype = C.c_int64
         L.oracle_adjoint.argtypes = [C.c_int, C.c_int, _D, C.c_double, C.c_double, C.c_int64,
                                      _D, _D, _D, _D]
         L.oracle_adjoint.restype = C.c_int64
@@ -270,6 +273,21 @@ def solve_orders_batch(system: int, thetas, alphas, hs, Ns, y0s):
                                     _p(np.ascontiguousarray(y0s.reshape(-1))), _p(th),
                                     off.ctypes.data_as(_I64), _p(y), st.ctypes.data_as(_I64))
     return y, off, st
+
+
+def adjoint_orders(system: int, theta, alphas, h: float, N: int, y0, gy):
+    """Discrete adjoint of solve_orders for L = sum_n <gy[n], y[n]>. Returns
+    (gy0 shaped like y0, gtheta, status)."""
+    al = np.ascontiguousarray(_f64(alphas).ravel())
+    shape = np.shape(y0)
+    init, d, rows = _orders_init(y0, al)
+    th = _f64(theta).ravel()
+    g = _f64(gy).reshape(N + 1, d)
+    gy0 = np.zeros(rows * d)
+    gth = np.empty(max(th.size, 1))
+    st = lib().oracle_adjoint_orders(system, d, _p(th), _p(al), float(h), int(N), _p(init), rows,
+                                     _p(g), _p(gy0), _p(gth))
+    return gy0.reshape(shape), gth[: th.size], int(st)
 
 
 def history_sums(alpha: float, f_hist):

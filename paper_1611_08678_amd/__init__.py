@@ -466,6 +466,7 @@ def adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, plan: Plan | None = N
     import torch
     y0s, d, two = _init_rows(y0s, 1)
     B = int(y0s.shape[0])
+    pc = np.ndim(alphas) == 2
     th = _dev(thetas).reshape(B, -1)
     gy = _dev(gy)
     Ns = np.ascontiguousarray(Ns, dtype=np.int64)
@@ -473,7 +474,7 @@ def adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, plan: Plan | None = N
     row_off[1:] = np.cumsum(Ns + 1)[:-1]
     if plan is None:
         plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
-                         initial_slope=two)
+                         initial_slope=two, per_component_order=pc)
     ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
     gy0 = torch.empty_like(y0s)
     gth = torch.empty_like(th)
@@ -507,7 +508,7 @@ def _solve_function():
             row_off = np.zeros(B, dtype=np.int64)
             row_off[1:] = np.cumsum(Ns + 1)[:-1]
             plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
-                             initial_slope=two)
+                             initial_slope=two, per_component_order=al.ndim == 2)
             ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
             y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
             st = torch.zeros(B, dtype=torch.int64, device="cuda")

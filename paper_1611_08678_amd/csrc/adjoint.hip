@@ -44,6 +44,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // One instance as seen by the reverse kernels.
 struct AdjView {
     const InstMeta *meta;
+    const InstMeta *cmeta; // non-commensurate orders: [D] entries of this instance, or null
     const double *params;
     const double *Y, *YP;  // forward rows [N+1][D]
     const double *G;       // dL/dy rows [N+1][D]
@@ -64,6 +65,7 @@ __device__ __forceinline__ AdjView adj_view(const AdjArgs &A, int i, int np)
     const InstMeta *m = A.meta + i;
     const BlkInst &b = A.inst[i];
     return AdjView{m,
+                   A.cmeta ? A.cmeta + (int64_t)i * D : nullptr,
                    A.params + m->p_off,
                    A.Y + m->f_off * D,
                    A.YP + m->f_off * D,
@@ -86,16 +88,19 @@ __device__ __forceinline__ AdjView adj_view(const AdjArgs &A, int i, int np)
 // targets T > r; one barrier per row. Each thread's gradient contributions
 // (its single row) are reduced over the block in a fixed order at the end.
 // ---------------------------------------------------------------------------
-template <int SYS, int D>
+// PC: non-commensurate orders (component k's tables at k * 3 wlen, its
+// scalars in A.cmeta[k]).
+template <int SYS, int D, bool PC = false>
 __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
+    constexpr int K = PC ? D : 1;  // weight tables held
     // gradient partials: theta, y(0), then y'(0) (orders above one: every
     // row's initial part is y(0) + t_n y'(0))
     constexpr int NG = NP + 2 * D;
-    double *sa = (double *)smem;  // a lags 0..511
-    double *sb = sa + 2 * kBlk;   // b lags 0..511
-    double *sU = sb + 2 * kBlk;   // [256][D]
+    double *sa = (double *)smem;      // [K] a lags 0..511
+    double *sb = sa + K * 2 * kBlk;   // [K] b lags 0..511
+    double *sU = sb + K * 2 * kBlk;   // [256][D]
     double *sV = sU + kBlk * D;   // [256][D]
     double *sRed = sV + kBlk * D; // [256] reduction scratch
     const int tid = threadIdx.x;
@@ -103,13 +108,22 @@ __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
     const int64_t N = m.N;
     const int64_t pitch = (int64_t)A.NB * kBlk;
     const double *wb = A.W, *wa = wb + m.wlen;
+    const int64_t cw = 3 * m.wlen;
     const int64_t r0 = (int64_t)J * kBlk;
     const int nrows = (int)((r0 + kBlk - 1 < N ? r0 + kBlk - 1 : N) - r0 + 1);
     const int nstep = (int)((r0 + kBlk - 1 < N - 1 ? r0 + kBlk - 1 : N - 1) - r0 + 1);
-    for (int j = tid; j < 2 * kBlk; j += kBlk) {
-        sa[j] = wa[j];
-        sb[j] = wb[j];
+    double hav[D], ig2v[D];  // h^a and 1 / Gamma(a + 2) of each component
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        hav[i] = PC ? A.cmeta[i].ha : m.ha;
+        ig2v[i] = PC ? A.cmeta[i].ig2 : m.ig2;
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int j = tid; j < 2 * kBlk; j += kBlk) {
+            sa[k * 2 * kBlk + j] = wa[k * cw + j];
+            sb[k * 2 * kBlk + j] = wb[k * cw + j];
+        }
     double S[D], Sn[D];
     if (J == 0) {
 #pragma unroll
@@ -159,14 +173,14 @@ __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
             }
             rhs_vjp<SYS, D>(tn, yv, S, th, ybar, gpart);
 #pragma unroll
-            for (int i = 0; i < D; ++i) w2[i] = m.ha * ybar[i] * m.ig2;
+            for (int i = 0; i < D; ++i) w2[i] = hav[i] * ybar[i] * ig2v[i];
             rhs_vjp<SYS, D>(tn, ypv, w2, th, ypbar, gpart);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 gpart[NP + i] += ybar[i] + ypbar[i];
                 gpart[NP + D + i] = fma(tn, ybar[i] + ypbar[i], gpart[NP + D + i]);
-                sU[r * D + i] = m.ha * ybar[i];
-                sV[r * D + i] = m.ha * ypbar[i];
+                sU[r * D + i] = hav[i] * ybar[i];
+                sV[r * D + i] = hav[i] * ypbar[i];
             }
         }
         __syncthreads();
@@ -178,14 +192,20 @@ __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
         }
         if (tid > r) {
             const int lag = tid - r - 1;
-            const double aw = sa[lag], bw = sb[lag];
 #pragma unroll
-            for (int i = 0; i < D; ++i) S[i] = fma(bw, v[i], fma(aw, u[i], S[i]));
+            for (int i = 0; i < D; ++i) {
+                const int k = PC ? i : 0;
+                const double aw = sa[k * 2 * kBlk + lag], bw = sb[k * 2 * kBlk + lag];
+                S[i] = fma(bw, v[i], fma(aw, u[i], S[i]));
+            }
         }
         const int lag = kBlk + tid - r - 1;
-        const double aw = sa[lag], bw = sb[lag];
 #pragma unroll
-        for (int i = 0; i < D; ++i) Sn[i] = fma(bw, v[i], fma(aw, u[i], Sn[i]));
+        for (int i = 0; i < D; ++i) {
+            const int k = PC ? i : 0;
+            const double aw = sa[k * 2 * kBlk + lag], bw = sb[k * 2 * kBlk + lag];
+            Sn[i] = fma(bw, v[i], fma(aw, u[i], Sn[i]));
+        }
     }
     // reversed row N (fbar_0 without its c - a correction) lies in this block
     if (N - r0 < kBlk && tid == (int)(N - r0)) {
@@ -237,11 +257,12 @@ __device__ __forceinline__ void stage_uv(const AdjView &A, int s, double *sB)
     }
 }
 
-template <int D>
+template <int D, bool PC = false>
 __device__ __forceinline__ void window_adj(dbl4 (&acc)[D], const double *__restrict__ wa,
                                            const double *__restrict__ wb, const double *sB,
-                                           int64_t m, int u, int coff)
+                                           int64_t m, int u, int coff, int64_t cw = 0)
 {
+    constexpr int K = PC ? D : 1;
     const int lane = threadIdx.x & (kWave - 1);
     const int r16 = lane & 15, kq = lane >> 4;
     const int c = r16 - u + coff;
@@ -250,22 +271,30 @@ __device__ __forceinline__ void window_adj(dbl4 (&acc)[D], const double *__restr
     const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const double aa = wa[wi - 4 * j], ab = wb[wi - 4 * j];
+        double aa[K], ab[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            aa[k] = wa[k * cw + wi - 4 * j];
+            ab[k] = wb[k * cw + wi - 4 * j];
+        }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const double vu = sB[i * kSrcCols * kColPitch + sbase + 4 * j];
             const double vv = sB[(D + i) * kSrcCols * kColPitch + sbase + 4 * j];
-            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa, ok ? vu : 0.0, acc[i], 0, 0, 0);
-            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab, ok ? vv : 0.0, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[PC ? i : 0], ok ? vu : 0.0, acc[i],
+                                                          0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab[PC ? i : 0], ok ? vv : 0.0, acc[i],
+                                                          0, 0, 0);
         }
     }
 }
 
-template <int D>
+template <int D, bool PC = false>
 __device__ __forceinline__ void far_adj(const AdjView &A, int s, int J, const double *sB)
 {
     const InstMeta m = A.meta[0];
     const double *wb = A.W, *wa = wb + m.wlen;
+    const int64_t cw = 3 * m.wlen;
     const int lane = threadIdx.x & (kWave - 1);
     double *aj = A.acc + (int64_t)J * D * kBlk + lane;
     dbl4 acc[D];
@@ -274,7 +303,7 @@ __device__ __forceinline__ void far_adj(const AdjView &A, int s, int J, const do
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[i][v] = s == 0 ? 0.0 : aj[(i * 4 + v) * kWave];
 #pragma unroll 2
-    for (int u = 0; u < kTile; ++u) window_adj<D>(acc, wa, wb, sB, J - s, u, kTile - 1);
+    for (int u = 0; u < kTile; ++u) window_adj<D, PC>(acc, wa, wb, sB, J - s, u, kTile - 1, cw);
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -283,11 +312,12 @@ __device__ __forceinline__ void far_adj(const AdjView &A, int s, int J, const do
 
 // Near part of reversed target block s + 2 (four wavefronts, partial sums
 // added one wavefront after another into one LDS slot).
-template <int D>
+template <int D, bool PC = false>
 __device__ __forceinline__ void near_adj(const AdjView &A, int s, const double *sB, double *red)
 {
     const InstMeta m = A.meta[0];
     const double *wb = A.W, *wa = wb + m.wlen;
+    const int64_t cw = 3 * m.wlen;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid >> 6;
     constexpr int NW = kBatchThreads / kWave;
     constexpr int kLags = 31;
@@ -297,9 +327,9 @@ __device__ __forceinline__ void near_adj(const AdjView &A, int s, const double *
     const int p0 = kLags * w / NW, p1 = kLags * (w + 1) / NW;
     for (int p = p0; p < p1; ++p) {
         if (p < kTile)
-            window_adj<D>(acc, wa, wb, sB, 2, p, kTile - 1);
+            window_adj<D, PC>(acc, wa, wb, sB, 2, p, kTile - 1, cw);
         else
-            window_adj<D>(acc, wa, wb, sB, 1, p - (kTile - 1), 2 * kTile - 1);
+            window_adj<D, PC>(acc, wa, wb, sB, 1, p - (kTile - 1), 2 * kTile - 1, cw);
     }
     for (int k = 0; k < NW; ++k) {
         if (w == k) {
@@ -318,7 +348,7 @@ __device__ __forceinline__ void near_adj(const AdjView &A, int s, const double *
 }
 
 // Launch s of the reverse pipeline (same schedule as the forward batch).
-template <int SYS, int D>
+template <int SYS, int D, bool PC = false>
 __global__ __launch_bounds__(kBatchThreads) void k_adj_batch(AdjArgs A, int s, int nband, int nnear,
                                                              const int *far_off, int nfar)
 {
@@ -328,7 +358,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_adj_batch(AdjArgs A, int s, i
     if (q < nband) {
         const AdjView V = adj_view<D>(A, A.order[q], NP);
         if (*V.dead != 0u) return;  // forward blew up: gradients are NaN
-        band_adj<SYS, D>(V, s + 1, smem);
+        band_adj<SYS, D, PC>(V, s + 1, smem);
         return;
     }
     q -= nband;
@@ -352,17 +382,17 @@ __global__ __launch_bounds__(kBatchThreads) void k_adj_batch(AdjArgs A, int s, i
     stage_uv<D>(V, s, sB);
     __syncthreads();
     if (first < 0) {
-        near_adj<D>(V, s, sB, sB + 2 * D * kSrcCols * kColPitch);
+        near_adj<D, PC>(V, s, sB, sB + 2 * D * kSrcCols * kColPitch);
         return;
     }
     const int J = first + (threadIdx.x >> 6);
-    if (J < V.NB) far_adj<D>(V, s, J, sB);
+    if (J < V.NB) far_adj<D, PC>(V, s, J, sB);
 }
 
 // Per instance (one workgroup): fbar_0 = band sums of reversed row N plus
 // sum_r (c - a)_{N-1-r} U_r; then the terms at y0 and the block partials,
 // added in block order.
-template <int SYS, int D>
+template <int SYS, int D, bool PC = false>
 __global__ __launch_bounds__(kBatchThreads) void k_adj_final(AdjArgs A)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
@@ -385,10 +415,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_adj_final(AdjArgs A)
     }
     const int64_t pitch = (int64_t)V.NB * kBlk;
     const double *wb = V.W, *wa = wb + m.wlen, *wc = wa + m.wlen;
+    const int64_t cw = 3 * m.wlen;
     for (int c = 0; c < D; ++c) {
+        const int64_t o = PC ? c * cw : 0;  // component c's tables
         double s = 0.0;
         for (int64_t r = tid; r < N; r += kBatchThreads)
-            s = fma(wc[N - 1 - r] - wa[N - 1 - r], V.UV[c * pitch + r], s);
+            s = fma(wc[o + N - 1 - r] - wa[o + N - 1 - r], V.UV[c * pitch + r], s);
         red[tid] = s;
         __syncthreads();
         for (int w = kBatchThreads / 2; w >= 1; w >>= 1) {
@@ -430,21 +462,23 @@ __global__ __launch_bounds__(kBatchThreads) void k_adj_final(AdjArgs A)
         // y'(0) enters only for orders above one
         if (slope)
 #pragma unroll
-            for (int c = 0; c < D; ++c) gy0[D + c] = m.alpha > 1.0 ? gy1[c] : 0.0;
+            for (int c = 0; c < D; ++c)
+                gy0[D + c] = (PC ? V.cmeta[c].alpha : m.alpha) > 1.0 ? gy1[c] : 0.0;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-size_t adj_smem_bytes(int d)
+size_t adj_smem_bytes(int d, bool pc)
 {
-    const size_t band = sizeof(double) * (4 * kBlk + 2 * kBlk * (size_t)d + kBlk);
+    const size_t band = sizeof(double) * (4 * kBlk * (size_t)(pc ? d : 1) + 2 * kBlk * (size_t)d +
+                                          kBlk);
     const size_t win = sizeof(double) * (2 * (size_t)d * kSrcCols * kColPitch + (size_t)d * kBlk);
     return std::max(band, win);
 }
 
-template <int SYS, int D>
+template <int SYS, int D, bool PC>
 static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, const int *far_off,
                                     hipStream_t st, KernelTimer *T, const char **where)
 {
@@ -456,7 +490,14 @@ static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, co
             return e_;                     \
         }                                  \
     } while (0)
-    const size_t smem = adj_smem_bytes(D);
+    const size_t smem = adj_smem_bytes(D, PC);
+    static bool attr_done = false;
+    if (PC && !attr_done) {  // above the default limit only with per-component tables
+        FABM_ADJ_TRY("hipFuncSetAttribute(adjoint LDS)",
+                     hipFuncSetAttribute((const void *)k_adj_batch<SYS, D, PC>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        attr_done = true;
+    }
     for (int s = -1; s <= S.max_NB - 2; ++s) {
         const size_t k = (size_t)(s + 1);
         const int nb = S.nband[k], nn = S.nnear[k], nf = S.nfar[k];
@@ -464,13 +505,13 @@ static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, co
         const int grid = nb + nn + nfw;
         if (grid == 0) continue;
         if (T) FABM_ADJ_TRY("timer begin", T->begin(KC_ADJOINT, st));
-        hipLaunchKernelGGL((k_adj_batch<SYS, D>), dim3(grid), dim3(kBatchThreads), smem, st, A, s,
-                           nb, nn, far_off + S.far_base[k], nf);
+        hipLaunchKernelGGL((k_adj_batch<SYS, D, PC>), dim3(grid), dim3(kBatchThreads), smem, st,
+                           A, s, nb, nn, far_off + S.far_base[k], nf);
         FABM_ADJ_TRY("launch k_adj_batch", hipGetLastError());
         if (T) FABM_ADJ_TRY("timer end", T->end(st));
     }
-    hipLaunchKernelGGL((k_adj_final<SYS, D>), dim3((unsigned)A.batch), dim3(kBatchThreads), 0, st,
-                       A);
+    hipLaunchKernelGGL((k_adj_final<SYS, D, PC>), dim3((unsigned)A.batch), dim3(kBatchThreads), 0,
+                       st, A);
     FABM_ADJ_TRY("launch k_adj_final", hipGetLastError());
     return hipSuccess;
 #undef FABM_ADJ_TRY
@@ -479,8 +520,10 @@ static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, co
 hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule &S,
                            const int *far_off, hipStream_t s, KernelTimer *T, const char **where)
 {
-#define FABM_ADJ_CASE(SS, DD) \
-    if (sys == SS && d == DD) return enqueue_adjoint_t<SS, DD>(A, S, far_off, s, T, where);
+#define FABM_ADJ_CASE(SS, DD)                                                          \
+    if (sys == SS && d == DD)                                                          \
+        return A.cmeta ? enqueue_adjoint_t<SS, DD, true>(A, S, far_off, s, T, where)   \
+                       : enqueue_adjoint_t<SS, DD, false>(A, S, far_off, s, T, where);
     FABM_ADJ_CASE(SYS_LINEAR, 1)
     FABM_ADJ_CASE(SYS_LINEAR, 2)
     FABM_ADJ_CASE(SYS_LINEAR, 3)

@@ -979,14 +979,15 @@ hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const Bat
                          const int *far_off, hipStream_t s, KernelTimer *T, const char **where)
 {
     // predictor rows are written when A.YP is set (FP64 far windows only)
-    // per-component orders (A.cmeta): FP64 windows, no predictor rows
-    if (A.cmeta && (f32 || A.YP)) {
-        *where = "per-component orders with FP32 windows or predictor rows";
+    // per-component orders (A.cmeta): FP64 windows
+    if (A.cmeta && f32) {
+        *where = "per-component orders with FP32 windows";
         return hipErrorInvalidValue;
     }
 #define FABM_BATCH_CASE(SS, DD)                                                                \
     if (sys == SS && d == DD)                                                                  \
-        return A.cmeta ? enqueue_batch_t<SS, DD, false, false, true>(A, S, far_off, s, T, where) \
+        return A.cmeta ? (A.YP ? enqueue_batch_t<SS, DD, false, true, true>(A, S, far_off, s, T, where) \
+                               : enqueue_batch_t<SS, DD, false, false, true>(A, S, far_off, s, T, where)) \
                : A.YP  ? enqueue_batch_t<SS, DD, false, true, false>(A, S, far_off, s, T, where) \
                : f32   ? enqueue_batch_t<SS, DD, true, false, false>(A, S, far_off, s, T, where) \
                        : enqueue_batch_t<SS, DD, false, false, false>(A, S, far_off, s, T, where);

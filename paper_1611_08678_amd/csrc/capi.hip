@@ -662,10 +662,12 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     if ((st = ensure_stage(pl, L.stage_bytes)) != FABM_OK) return st;
     InstMeta *hm = (InstMeta *)(pl->h_stage + L.meta);
     InstMeta *ham = (InstMeta *)(pl->h_stage + L.meta_adj);
+    const bool pc = per_component(pl);
+    InstMeta *hc = pc ? (InstMeta *)(pl->h_stage + L.cmeta) : nullptr;
     int64_t w_off = 0, f_off = 0, maxw = 0;
     for (int64_t i = 0; i < batch; ++i) {
         InstMeta &m = hm[i];
-        host_scalars(alpha[i], h[i], m);
+        host_scalars(pc ? alpha[i * d] : alpha[i], h[i], m);
         m.N = N[i];
         m.wlen = (int64_t)blocks_of(N[i]) * fabm::step_block_len() + fabm::step_block_len();
         m.w_off = w_off;
@@ -675,6 +677,15 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
         ham[i] = m;
         ham[i].row_off = row_off[i];  // dL/dy rows are the caller's
         w_off += 3 * m.wlen;
+        if (pc) {
+            for (int c = 0; c < d; ++c) {
+                InstMeta &q = hc[i * d + c];
+                q = m;
+                host_scalars(alpha[i * d + c], h[i], q);
+                q.w_off = m.w_off + (int64_t)c * 3 * m.wlen;
+            }
+            w_off += (int64_t)(d - 1) * 3 * m.wlen;
+        }
         f_off += N[i] + 1;
         maxw = std::max(maxw, m.wlen);
     }
@@ -688,9 +699,11 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     uint32_t *sync = (uint32_t *)(base + L.sync);
     fabm::KernelTimer *T = pl->timer.on ? &pl->timer : nullptr;
     if (T) T->reset();
+    const InstMeta *dcmeta = pc ? (const InstMeta *)(base + L.cmeta) : nullptr;
     if (phase != AdjPhase::Reverse) {
         if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
-        if ((st = ok_or_device(fabm::launch_weights(dmeta, batch, maxw, W, s))) != FABM_OK)
+        if ((st = ok_or_device(fabm::launch_weights(pc ? dcmeta : dmeta, pc ? batch * d : batch,
+                                                    maxw, W, s))) != FABM_OK)
             return st;
         if (T) HIP_TRY(T->end(s));
         if ((st = ok_or_device(fabm::launch_fill_u32(sync, (int64_t)L.n_sync_words, 0u, s))) !=
@@ -699,6 +712,7 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     }
     fabm::BatchArgs A{};
     A.meta = dmeta;
+    A.cmeta = dcmeta;
     A.inst = (const fabm::BlkInst *)(base + L.inst);
     A.order = (const int *)(base + L.order);
     A.params = params;
@@ -728,6 +742,7 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     }
     fabm::AdjArgs R{};
     R.meta = (const InstMeta *)(base + L.meta_adj);
+    R.cmeta = dcmeta;
     R.inst = A.inst;
     R.order = A.order;
     R.params = params;
@@ -1073,7 +1088,6 @@ fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const i
     for (int64_t i = 0; i < batch; ++i)
         if (N[i] < 1 || N[i] > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
     if (plan->desc.system == FABM_SYS_LINEAR && plan->desc.dim > 4) return FABM_ERR_UNSUPPORTED;
-    if (per_component(plan)) return FABM_ERR_UNSUPPORTED;  // the reverse pass is BLOCKED
     *bytes = layout_for(plan, batch, N, true).total;
     return FABM_OK;
 }

@@ -16,6 +16,7 @@ namespace fabm {
 // inst[i].acc_off / (2 D 256) * (n_params + 2 D).
 struct AdjArgs {
     const InstMeta *meta;   // [batch]
+    const InstMeta *cmeta;  // non-commensurate orders: [batch][D] (scalars, table offsets), or null
     const BlkInst *inst;    // [batch] (same as the forward batch)
     const int *order;       // instances by block count, descending
     const double *params;   // [batch][n_params]
@@ -38,7 +39,7 @@ struct AdjArgs {
 struct KernelTimer;
 hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule &S,
                            const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
-size_t adj_smem_bytes(int d);
+size_t adj_smem_bytes(int d, bool pc = false);
 
 // Rows 0..N_i of every instance from src (placed by src_meta[i].f_off) to dst
 // (placed by dst_meta[i].row_off), d doubles per row.

@@ -190,9 +190,9 @@ def test_initial_slope_flag_rules(fabm):
 
 
 def test_per_component_order_rules(fabm):
-    """Non-commensurate plans: DIRECT and per-trajectory BLOCKED with FP64
-    windows (FP32 windows, the shared grid and the adjoint are UNSUPPORTED, so
-    is fabm_solve with its single alpha); alpha is [batch][d], every entry
+    """Non-commensurate plans: DIRECT, per-trajectory BLOCKED with FP64
+    windows and the adjoint (FP32 windows and the shared grid are UNSUPPORTED,
+    so is fabm_solve with its single alpha); alpha is [batch][d], every entry
     checked (an order above one needs the slope flag); one weight table per
     component. Host-side checks only."""
     import ctypes as C
@@ -219,7 +219,7 @@ def test_per_component_order_rules(fabm):
     n = C.c_size_t()
     Nb = np.asarray(Ns, np.int64)
     assert lib.fabm_adjoint_workspace_size(p.handle, 2, Nb.ctypes.data_as(F._I64P),
-                                           C.byref(n)) == 2
+                                           C.byref(n)) == 0 and n.value > 0
     fake = C.c_void_p(1 << 40)
     assert lib.fabm_solve(p.handle, fake, p.workspace_bytes, C.c_double(0.9), C.c_double(0.01),
                           100, fake, fake, fake, fake, None) == 2

@@ -152,3 +152,55 @@ def test_blow_up_status_per_component(F, orc):
                            rng.uniform(-0.5, 0.5, (B, 1, 3))], axis=1)
     rst = _compare(F, orc, "chen", th, al, np.full(B, 0.001), np.full(B, 2500), init)
     assert np.any(rst > 0)
+
+
+@pytest.mark.parametrize("sysname", ["vdp", "hindmarsh_rose", "linear3"])
+@pytest.mark.parametrize("slope", [False, True])
+def test_adjoint_per_component_orders(F, orc, sysname, slope):
+    """Gradients with respect to y(0) (and y'(0)) and theta against the
+    oracle's per-component reverse mode; components at or below order one get
+    a zero y'(0) gradient."""
+    sid, d, th_of = SYSTEMS[sysname]
+    name = "linear" if sysname.startswith("linear") else sysname
+    rng = np.random.default_rng(90 + sid + 10 * slope)
+    B = 8
+    th = np.stack([th_of(rng, i) for i in range(B)])
+    al = rng.uniform(0.6, 2.0 if slope else 1.0, (B, d))
+    if slope:
+        al[0] = np.minimum(al[0], 1.0)
+    hs = np.full(B, 0.01)
+    Ns = rng.integers(200, 1500, B, endpoint=True)
+    Ns[:2] = [1, 256]
+    init = 0.5 * rng.uniform(-1, 1, (B, 2, d) if slope else (B, d))
+    gy = rng.standard_normal((int((Ns + 1).sum()), d))
+    gy0, gth, st = F.adjoint_batch(name, th, al, hs, Ns, init, gy)
+    gy0, gth, st = _to_np(gy0), _to_np(gth), _to_np(st)
+    off = np.concatenate([[0], np.cumsum(Ns + 1)[:-1]]).astype(np.int64)
+    worst = 0.0
+    for i in range(B):
+        rg0, rgt, rst = orc.adjoint_orders(sid, th[i], al[i], hs[i], int(Ns[i]), init[i],
+                                           gy[off[i]:off[i] + Ns[i] + 1])
+        assert st[i] == rst == 0
+        ref = np.concatenate([np.ravel(rg0), rgt])
+        got = np.concatenate([np.ravel(gy0[i]), gth[i]])
+        worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+        if slope:
+            assert np.all(gy0[i][1][al[i] <= 1.0] == 0.0)
+    assert worst <= 1e-10, worst
+
+
+def test_autograd_per_component_orders(F):
+    """torch.autograd through the two-call adjoint with per-component orders:
+    gradients bitwise equal to the one-call adjoint."""
+    import torch
+    rng = np.random.default_rng(6)
+    B, d = 4, 2
+    th = torch.tensor(rng.uniform(0.5, 2, (B, 1)), device="cuda", requires_grad=True)
+    init = torch.tensor(0.5 * rng.uniform(-1, 1, (B, 2, d)), device="cuda", requires_grad=True)
+    al, hs = rng.uniform(0.7, 1.8, (B, d)), np.full(B, 0.01)
+    Ns = np.array([600, 257, 1000, 40], dtype=np.int64)
+    y = F.solve_batch_autograd(init, th, "vdp", al, hs, Ns)
+    gy = torch.tensor(rng.standard_normal(tuple(y.shape)), device="cuda")
+    (y * gy).sum().backward()
+    g0, gt, _ = F.adjoint_batch("vdp", th.detach(), al, hs, Ns, init.detach(), gy)
+    assert torch.equal(init.grad, g0) and torch.equal(th.grad, gt)

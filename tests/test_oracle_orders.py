@@ -11,7 +11,10 @@ Independent facts used:
     its slowest component;
   * tiny N against a 50-digit mpmath implementation with per-component
     weights;
-  * batch = single.
+  * batch = single;
+  * the per-component adjoint: equal orders give the commensurate adjoint
+    bitwise, and every gradient entry matches central differences of the
+    per-component forward solve.
 """
 import math
 
@@ -141,3 +144,53 @@ def test_orders_batch_equals_single(orc):
     for i in range(B):
         yi, _, _, si = orc.solve_orders(orc.VDP, th[i], al[i], 0.01, int(Ns[i]), init[i])
         assert st[i] == si and np.array_equal(y[off[i]: off[i] + Ns[i] + 1], yi)
+
+
+def test_orders_adjoint_equal_orders_is_commensurate_adjoint(orc):
+    th = [1.3]
+    for alpha, init in ((0.9, [1.1, -0.7]), (1.5, [[1.1, -0.7], [0.4, 0.9]])):
+        g = np.random.default_rng(1).standard_normal((301, 2))
+        a0, at, sa = orc.adjoint(orc.VDP, th, alpha, 0.01, 300, init, g)
+        b0, bt, sb = orc.adjoint_orders(orc.VDP, th, [alpha, alpha], 0.01, 300, init, g)
+        assert sa == sb == 0 and np.array_equal(a0, b0) and np.array_equal(at, bt)
+
+
+@pytest.mark.parametrize("sid,theta,alphas,init", [
+    (3, [1.3], [0.7, 0.95], [1.1, -0.7]),
+    (3, [0.8], [1.6, 0.8], [[1.1, -0.7], [0.4, 0.9]]),
+    (4, [3.0, 0.1, 1.0], [0.85, 1.3, 0.7], [[0.5, 1.0, -0.3], [0.2, -0.4, 0.6]]),
+])
+def test_orders_adjoint_vs_central_differences(orc, sid, theta, alphas, init):
+    """Gradients with respect to every initial value and theta against central
+    differences of the oracle's own per-component forward solve."""
+    theta, init = np.asarray(theta, float), np.asarray(init, float)
+    N, h = 250, 0.01
+    g = np.random.default_rng(3).standard_normal((N + 1, init.shape[-1]))
+
+    def loss(th, y0):
+        y, _, _, st = orc.solve_orders(sid, th, alphas, h, N, y0)
+        assert st == 0
+        return float(np.sum(g * y))
+
+    gy0, gth, st = orc.adjoint_orders(sid, theta, alphas, h, N, init, g)
+    assert st == 0
+    for label, base, grad in (("y0", init, gy0), ("theta", theta, gth)):
+        flat, gflat = base.ravel(), np.ravel(grad)
+        for i in range(flat.size):
+            errs = []
+            for rel in (1e-4, 1e-5):
+                dl = rel * max(1.0, abs(flat[i]))
+                p, m = flat.copy(), flat.copy()
+                p[i] += dl
+                m[i] -= dl
+                if label == "y0":
+                    fd = (loss(theta, p.reshape(base.shape)) - loss(theta, m.reshape(base.shape))) / (2 * dl)
+                else:
+                    fd = (loss(p, init) - loss(m, init)) / (2 * dl)
+                errs.append(abs(fd - gflat[i]))
+            scale = max(abs(gflat[i]), 1e-3 * np.abs(gflat).max(), 1e-12)
+            assert min(errs) <= 2e-6 * scale, (label, i, gflat[i], errs)
+    if init.ndim == 2:  # components at or below order one: zero y'(0) gradient
+        for i, a in enumerate(alphas):
+            if a <= 1.0:
+                assert gy0[1][i] == 0.0
