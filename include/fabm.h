@@ -138,12 +138,11 @@ typedef struct {
  * weights b, a, c, h^alpha_i and Gamma(alpha_i + 2), and with
  * FABM_PLAN_INITIAL_SLOPE its own Taylor term (y'(0) used where alpha_i > 1;
  * without the flag every alpha_i must be <= 1). Such plans run the DIRECT
- * kernels and the per-trajectory BLOCKED kernels with FP64 far windows (one
- * weight table per component in the band and as the A operand of the
- * windows), and the adjoint calls (alpha [batch][d] there too); FP32 and
- * FP16X2 far tiles and the shared grid (LINEAR d > 4, tile_L 64) are
- * UNSUPPORTED, and so is fabm_solve (one alpha): a single trajectory is a
- * batch of one. */
+ * kernels and the per-trajectory BLOCKED kernels with FP64 or FP32 far
+ * windows (one weight table per component in the band and as the A operand
+ * of the windows), and the adjoint calls (alpha [batch][d] there too); the
+ * shared grid (LINEAR d > 4, FP16X2, tile_L 64) is UNSUPPORTED, and so is
+ * fabm_solve (one alpha): a single trajectory is a batch of one. */
 #define FABM_PLAN_PER_COMPONENT_ORDER 2
 
 /* A plan is used by one host thread at a time: calls that share a plan share

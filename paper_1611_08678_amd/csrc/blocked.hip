@@ -512,23 +512,30 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
 
 // The same column lag on the binary32 matrix cores (v_mfma_f32_16x16x4f32):
 // weights and history rounded to binary32, products summed in binary32.
-template <int D, int NC = kSrcCols>
+template <int D, int NC = kSrcCols, bool PC = false>
 __device__ __forceinline__ void window_lag_f32(flt4 (&acc)[2][D], const float *__restrict__ wb,
                                                const float *__restrict__ wa, const float *sB,
-                                               int64_t m, int u, int coff = kTile - 1)
+                                               int64_t m, int u, int coff = kTile - 1,
+                                               int64_t cw = 0)
 {
+    constexpr int K = PC ? D : 1;  // one A operand per component with per-component orders
     const int lane = threadIdx.x & (kWave - 1);
     const int r16 = lane & 15, kq = lane >> 4;
     const int sbase = (r16 - u + coff) * kColPitch + kq;
     const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float ab = wb[wi - 4 * j], aa = wa[wi - 4 * j];
+        float ab[K], aa[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            ab[k] = wb[k * cw + wi - 4 * j];
+            aa[k] = wa[k * cw + wi - 4 * j];
+        }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const float bf = sB[i * NC * kColPitch + sbase + 4 * j];
-            acc[0][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab, bf, acc[0][i], 0, 0, 0);
-            acc[1][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa, bf, acc[1][i], 0, 0, 0);
+            acc[0][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[PC ? i : 0], bf, acc[0][i], 0, 0, 0);
+            acc[1][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[PC ? i : 0], bf, acc[1][i], 0, 0, 0);
         }
     }
 }
@@ -543,13 +550,14 @@ __device__ __forceinline__ int f32_result_row(int l, int v) { return kF32RowMajo
 // out of kPairCols staged columns; each window is summed in binary32 and added
 // to the binary64 sums in source order. `first`: no earlier window has
 // written the target's sums.
-template <int D, bool PAIR = false>
+template <int D, bool PAIR = false, bool PC = false>
 __device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, const float *sB,
                                                bool first)
 {
     constexpr int NC = PAIR ? kPairCols : kSrcCols;
     const InstMeta m = A.meta[0];
     const float *wb = A.W32, *wa = wb + m.wlen;
+    const int64_t cw = 2 * m.wlen;  // binary32 b, a of the next component (PC)
     const int lane = threadIdx.x & (kWave - 1);
     double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
     flt4 acc[2][D], acc2[2][D];
@@ -561,13 +569,13 @@ __device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, 
     if constexpr (PAIR) {
 #pragma unroll 2
         for (int u = 0; u < kTile; ++u)
-            window_lag_f32<D, NC>(acc, wb, wa, sB, mm + 1, u, kTile - 1);
+            window_lag_f32<D, NC, PC>(acc, wb, wa, sB, mm + 1, u, kTile - 1, cw);
 #pragma unroll 2
         for (int u = 0; u < kTile; ++u)
-            window_lag_f32<D, NC>(acc2, wb, wa, sB, mm, u, 2 * kTile - 1);
+            window_lag_f32<D, NC, PC>(acc2, wb, wa, sB, mm, u, 2 * kTile - 1, cw);
     } else {
 #pragma unroll 2
-        for (int u = 0; u < kTile; ++u) window_lag_f32<D, NC>(acc, wb, wa, sB, mm, u);
+        for (int u = 0; u < kTile; ++u) window_lag_f32<D, NC, PC>(acc, wb, wa, sB, mm, u, kTile - 1, cw);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -700,7 +708,6 @@ __device__ __forceinline__ InstView single_view(const StepArgs &A)
 template <int SYS, int D, bool F32, bool PC = false>
 __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wpw)
 {
-    static_assert(!(F32 && PC), "per-component orders run FP64 windows");
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x, wave = threadIdx.x >> 6;
     const InstView V = single_view(A);
@@ -730,7 +737,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
         for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G)
-            far_target_f32<D>(V, s, J, sB, s == 0);
+            far_target_f32<D, false, PC>(V, s, J, sB, s == 0);
     }
 }
 
@@ -763,7 +770,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
                                                               int nnear, const int *far_off,
                                                               int nfar)
 {
-    static_assert(!(F32 && PC), "per-component orders run FP64 windows");
     extern __shared__ __align__(16) char smem[];
     int q = blockIdx.x;
     if (q < nband) {
@@ -824,9 +830,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
         __syncthreads();
         if (mine) {
             if (pair)
-                far_target_f32<D, true>(V, s, J, sB, s <= 1);
+                far_target_f32<D, true, PC>(V, s, J, sB, s <= 1);
             else
-                far_target_f32<D>(V, s, J, sB, s <= 1);
+                far_target_f32<D, false, PC>(V, s, J, sB, s <= 1);
         }
     }
 }
@@ -979,14 +985,11 @@ hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const Bat
                          const int *far_off, hipStream_t s, KernelTimer *T, const char **where)
 {
     // predictor rows are written when A.YP is set (FP64 far windows only)
-    // per-component orders (A.cmeta): FP64 windows
-    if (A.cmeta && f32) {
-        *where = "per-component orders with FP32 windows";
-        return hipErrorInvalidValue;
-    }
+    // per-component orders (A.cmeta): FP64 or FP32 windows; predictor rows with FP64
 #define FABM_BATCH_CASE(SS, DD)                                                                \
     if (sys == SS && d == DD)                                                                  \
         return A.cmeta ? (A.YP ? enqueue_batch_t<SS, DD, false, true, true>(A, S, far_off, s, T, where) \
+                          : f32 ? enqueue_batch_t<SS, DD, true, false, true>(A, S, far_off, s, T, where) \
                                : enqueue_batch_t<SS, DD, false, false, true>(A, S, far_off, s, T, where)) \
                : A.YP  ? enqueue_batch_t<SS, DD, false, true, false>(A, S, far_off, s, T, where) \
                : f32   ? enqueue_batch_t<SS, DD, true, false, false>(A, S, far_off, s, T, where) \
@@ -1008,13 +1011,10 @@ hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const Bat
 hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_t s,
                          KernelTimer *T, const char **where)
 {
-    if (A.cmeta && f32) {
-        *where = "per-component orders with FP32 windows";
-        return hipErrorInvalidValue;
-    }
 #define FABM_STEP_CASE(SS, DD)                                                   \
     if (sys == SS && d == DD)                                                    \
-        return A.cmeta ? enqueue_steps_t<SS, DD, false, true>(A, s, T, where)    \
+        return A.cmeta ? (f32 ? enqueue_steps_t<SS, DD, true, true>(A, s, T, where)     \
+                              : enqueue_steps_t<SS, DD, false, true>(A, s, T, where))   \
                : f32   ? enqueue_steps_t<SS, DD, true, false>(A, s, T, where)    \
                        : enqueue_steps_t<SS, DD, false, false>(A, s, T, where);
     FABM_STEP_CASE(SYS_LINEAR, 1)

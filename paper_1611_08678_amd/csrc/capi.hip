@@ -219,7 +219,7 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         off = align_up(off + sizeof(double) * nw * (pc ? d : 1));
         L.w32 = off;  // binary32 b, a for FP32 far windows
         if (pl->desc.far_prec == FABM_FAR_FP32 && !adjoint)
-            off = align_up(off + sizeof(float) * nw / 3 * 2);
+            off = align_up(off + sizeof(float) * nw / 3 * 2 * (pc ? d : 1));
         L.f = off;  // per instance: component-major history [d][NB_i*256]
         off = align_up(off + sizeof(double) * nf);
         L.carry = off;
@@ -302,7 +302,7 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         off = align_up(off + sizeof(double) * 3 * (size_t)L.wlen * (pc ? d : 1));
         L.w32 = off;  // binary32 b, a for FP32 far windows
         if (pl->desc.far_prec == FABM_FAR_FP32)
-            off = align_up(off + sizeof(float) * 2 * (size_t)L.wlen);
+            off = align_up(off + sizeof(float) * 2 * (size_t)L.wlen * (pc ? d : 1));
         L.f = off;  // component-major history [d][NB*256]
         off = align_up(off + sizeof(double) * (size_t)d * (size_t)L.NB * Lb);
         L.carry = off;
@@ -844,10 +844,8 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     if (desc->tile_L != 0 && desc->tile_L != (wide ? fabm::kWideBlk : fabm::step_block_len()))
         return FABM_ERR_UNSUPPORTED;
     if (wide && desc->path == FABM_PATH_DIRECT) return FABM_ERR_UNSUPPORTED;
-    // per-component orders: DIRECT, or BLOCKED per trajectory with FP64 windows
-    if ((desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) &&
-        (wide || desc->far_prec != FABM_FAR_FP64))
-        return FABM_ERR_UNSUPPORTED;
+    // per-component orders: DIRECT, or BLOCKED per trajectory (FP64 or FP32 windows)
+    if ((desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) && wide) return FABM_ERR_UNSUPPORTED;
     if (wide && desc->max_batch > kWideMaxCols / desc->dim) return FABM_ERR_UNSUPPORTED;
 
     fabm_plan_s *pl = new (std::nothrow) fabm_plan_s();

@@ -190,9 +190,9 @@ def test_initial_slope_flag_rules(fabm):
 
 
 def test_per_component_order_rules(fabm):
-    """Non-commensurate plans: DIRECT, per-trajectory BLOCKED with FP64
-    windows and the adjoint (FP32 windows and the shared grid are UNSUPPORTED,
-    so is fabm_solve with its single alpha); alpha is [batch][d], every entry
+    """Non-commensurate plans: DIRECT, per-trajectory BLOCKED (FP64 or FP32
+    windows) and the adjoint (the shared grid is UNSUPPORTED, so is fabm_solve
+    with its single alpha); alpha is [batch][d], every entry
     checked (an order above one needs the slope flag); one weight table per
     component. Host-side checks only."""
     import ctypes as C
@@ -200,8 +200,9 @@ def test_per_component_order_rules(fabm):
     F = fabm
     for kw in (dict(path="blocked"), dict(path="auto", tile_L=256), dict(path="direct")):
         F.fabm_plan("chen", 3, max_batch=2, max_steps=100, per_component_order=True, **kw)
+    F.fabm_plan("chen", 3, "blocked", "fp32", 2, 100, per_component_order=True)
     with pytest.raises(F.FabmError) as e:
-        F.fabm_plan("chen", 3, "blocked", "fp32", 2, 100, per_component_order=True)
+        F.fabm_plan("linear", 4, "blocked", "fp16x2", 2, 100, per_component_order=True)
     assert e.value.code == 2
     pb = F.fabm_plan("vdp", 2, "blocked", "fp64", 3, 2000, per_component_order=True)
     qb = F.fabm_plan("vdp", 2, "blocked", "fp64", 3, 2000)

@@ -59,13 +59,13 @@ def _horizons(orc, sid, th, al, hs, Ns, init, ref, off, rows):
     return out
 
 
-def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11, path="direct"):
+def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11, path="direct", far_prec="fp64"):
     """Status equal (or one step apart at the top of the binary64 range, as
     for commensurate orders), NaN rows from there on, and the rows of
     _horizons within tol normwise."""
     sid = SYSTEMS[sysname][0] if sysname in SYSTEMS else {"chen": 1}[sysname]
     name = "linear" if sysname.startswith("linear") else sysname
-    y, off, st = F.solve_batch(name, th, al, hs, Ns, init, path=path)
+    y, off, st = F.solve_batch(name, th, al, hs, Ns, init, path=path, far_prec=far_prec)
     ref, roff, rst = orc.solve_orders_batch(sid, th, al, hs, Ns, init)
     assert np.array_equal(off, roff)
     yy, gst = _to_np(y), _to_np(st)
@@ -104,6 +104,27 @@ def test_batch_per_component_orders(F, orc, sysname, slope, path):
     Ns[:3] = [1, 255, 1024]
     init = 0.5 * rng.uniform(-1, 1, (B, 2, d) if slope else (B, d))
     _compare(F, orc, sysname, th, al, hs, Ns, init, path=path)
+
+
+@pytest.mark.parametrize("sysname", ["vdp", "hindmarsh_rose", "linear3"])
+def test_batch_per_component_orders_fp32_windows(F, orc, sysname):
+    """Binary32 far windows with per-component orders (one binary32 A operand
+    per component): within the FP32 bound of the commensurate paths, and
+    visibly different from FP64."""
+    sid, d, th_of = SYSTEMS[sysname]
+    rng = np.random.default_rng(120 + sid)
+    B = 10
+    th = np.stack([th_of(rng, i) for i in range(B)])
+    al = rng.uniform(0.6, 1.0, (B, d))
+    hs = rng.uniform(0.005, 0.015, B)
+    Ns = rng.integers(300, 2500, B, endpoint=True)
+    Ns[:2] = [1, 1024]
+    init = 0.5 * rng.uniform(-1, 1, (B, d))
+    _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-5, path="blocked", far_prec="fp32")
+    name = "linear" if sysname.startswith("linear") else sysname
+    y32, _, _ = F.solve_batch(name, th, al, hs, Ns, init, path="blocked", far_prec="fp32")
+    y64, _, _ = F.solve_batch(name, th, al, hs, Ns, init, path="blocked")
+    assert relerr(_to_np(y32), _to_np(y64)) > 1e-12
 
 
 @pytest.mark.parametrize("path", ["direct", "blocked"])
