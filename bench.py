@@ -32,6 +32,8 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense binary16 matrix rate
 HBM_PEAK_GBPS = 8000.0
+BAND_CYCLES_PER_ROW = 640  # measured band walk (profiles/k_step_chen_N2p20_kernel_stats.md)
+CLOCK_HZ = 2.4e9
 
 
 def parse():
@@ -158,11 +160,18 @@ def roofline(kt: dict, N: int, d: int):
         # every history flop of the BLOCKED path is done inside the step
         # kernels (MFMA near/far windows plus the sequential band)
         ach = flops / secs / 1e12
+        # the band forms one row after another: N rows at the walk's measured
+        # 640 cycles per row (clock-counter probe, 2.4 GHz) bound the solve
+        # from below whatever the matrix cores do
+        band_floor = N * BAND_CYCLES_PER_ROW / CLOCK_HZ
         return dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=measured_traffic("k_step"),
                     kernel="k_step",
                     launches=launches, avg_launch_s=secs / launches,
-                    algorithmic_flops_per_launch=flops / launches)
+                    algorithmic_flops_per_launch=flops / launches,
+                    sequential_floor=dict(s=band_floor, frac=band_floor / secs,
+                                          basis=f"N rows x {BAND_CYCLES_PER_ROW} cycles per row "
+                                                f"of the band walk at {CLOCK_HZ / 1e9:.1f} GHz"))
     if dom == "direct_grid":
         alg_bytes = 4.0 * N * (N + 1) * (d + 2)  # sum_t 8 t (d + 2): history row + two weights
         ach = alg_bytes / secs / 1e9
