@@ -236,9 +236,14 @@ def bench_batch(F, W, args):
         torch.cuda.synchronize()
         kt = {k: v for k, v in F.fabm_plan_kernel_times(plan).items() if v[1]}
     t = float(np.mean(per))
-    flops = float((2.0 * d * Ns * (Ns + 1)).sum())
+    # an instance whose state leaves every bounded set stops at its status
+    # step (later rows NaN, its remaining windows skipped): count the rows
+    # actually formed
+    stv = st.cpu().numpy()
+    Neff = np.where(stv > 0, stv - 1, Ns).astype(np.float64)
+    flops = float((2.0 * d * Neff * (Neff + 1)).sum())
     out = {"metric": "steps*states/s (history GFLOP/s alongside), batched blocked",
-           "value": float(Ns.sum()) * d / t, "unit": "steps*states/s", "n_gpus": 1,
+           "value": float(Neff.sum()) * d / t, "unit": "steps*states/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": {"fp64": "f64", "fp32": "f64 band, f32 far windows",
@@ -250,7 +255,9 @@ def bench_batch(F, W, args):
                       "orders": (f"per component, U[{float(np.min(w['alpha'])):.2f}.., 1]"
                                  if pc else "one per instance")},
            "history_gflops": flops / t / 1e9,
-           "status_nonzero": int((st.cpu().numpy() != 0).sum()),
+           "status_nonzero": int((stv != 0).sum()),
+           "rows_counted": "rows formed: N_i, or status_i - 1 for instances that left every "
+                           "bounded set",
            "tune": tune,
            "kernel_times_s": {k: v[0] for k, v in kt.items()},
            "kernel_launches": {k: v[1] for k, v in kt.items()}}
@@ -266,7 +273,7 @@ def bench_batch(F, W, args):
         secs, launches = kt["direct_wg"]
         # every step reads the history (d values per row) and the weight rows
         # b, a: one pair per instance, or one per component with per-component orders
-        by = float((4.0 * Ns * (Ns + 1) * (3 * d if pc else d + 2)).sum())
+        by = float((4.0 * Neff * (Neff + 1) * (3 * d if pc else d + 2)).sum())
         out["roofline"] = dict(bound="hbm", achieved=by / secs / 1e9, peak=HBM_PEAK_GBPS,
                                unit="GB/s", frac=by / secs / 1e9 / HBM_PEAK_GBPS, traffic=None,
                                kernel="k_direct_wg", launches=launches,
@@ -275,7 +282,7 @@ def bench_batch(F, W, args):
         # far sums of the shared grid: every target row t takes the 64 * (t // 64)
         # source rows of earlier blocks, both tables, every column
         secs, launches = kt["wide_far"]
-        t_rows = np.arange(int(Ns[0]) + 1, dtype=np.float64)
+        t_rows = np.arange(int(Neff.max()) + 1, dtype=np.float64)
         far_flops = float((4.0 * B * d * 64.0 * np.floor(t_rows / 64.0)).sum())
         hw = 3.0 if prec == "fp16x2" else 1.0  # hi*hi + hi*lo + lo*hi products
         peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,

@@ -10,7 +10,9 @@ y0 [B, d] (B = 1 for single trajectories) plus descriptive fields.
   chen           Chen (a, b, c) = (35, 3, 28), alpha 0.95, y0 = (-9, -5, 14),
                  h = 0.001, N = 2^20
   rossler_batch  4096 Rossler (0.2, 0.2, 5.7), y0 ~ U[-5, 5]^3,
-                 alpha ~ U[0.9, 1.0], N ~ U{2^14 .. 2^17}, h = 0.005 (seed 2)
+                 alpha ~ U[0.9, 1.0], N ~ U{2^14 .. 2^17}, h = 0.005 (seed 2);
+                 about 2% of these starting points leave every bounded set
+                 within a few hundred steps
   linear64_batch 512 linear systems, d = 64, A = -(2 I + G/8), G_ij ~ N(0, 1),
                  y0 ~ N(0, 1), alpha 0.8, h = 0.01, N = 2^16 (seed 3)
   vdp_adjoint    1024 Van der Pol, mu ~ U[0.5, 2], y0 ~ U[-2, 2]^2,

@@ -171,3 +171,33 @@ def test_adjoint_in_two_calls_matches_one_call(F):
         assert torch.equal(torch.isnan(a), torch.isnan(b))
         assert torch.equal(a[~torch.isnan(a)], b[~torch.isnan(b)])
     assert torch.all(torch.isnan(gy0[3])) and not torch.any(torch.isnan(gy0[[0, 1, 2, 4]]))
+
+
+def test_adjoint_vdp_full_size(F, orc):
+    """The adjoint workload at full size (1024 Van der Pol instances, N = 2^15)
+    in the benchmark's two-call form: gradients of the MSE loss against the
+    trajectories of the perturbed parameters, two instances against the
+    oracle's reverse mode (1e-10), every status 0 and every gradient finite."""
+    import torch
+    from paper_1611_08678_amd import workloads as W
+    w = W.vdp_adjoint()
+    Ns = w["N"]
+    B, N = len(Ns), int(Ns[0])
+    tgt, _, _ = F.solve_batch(w["system"], w["theta_target"], w["alpha"], w["h"], Ns, w["y0"],
+                              path="blocked")
+    y0 = torch.tensor(w["y0"], device="cuda", requires_grad=True)
+    th = torch.tensor(w["theta"], device="cuda", requires_grad=True)
+    y = F.solve_batch_autograd(y0, th, w["system"], w["alpha"], w["h"], Ns)
+    loss = ((y - tgt) ** 2).sum() / y.numel()
+    loss.backward()
+    g0, gt = _to_np(y0.grad), _to_np(th.grad)
+    assert np.all(np.isfinite(g0)) and np.all(np.isfinite(gt))
+    gy = _to_np(2.0 * (y.detach() - tgt) / y.numel())
+    off = _offsets(Ns)
+    for i in (3, 1000):
+        rg0, rgt, rst = orc.adjoint(w["system"], w["theta"][i], w["alpha"][i], w["h"][i], N,
+                                    w["y0"][i], gy[off[i]: off[i] + N + 1])
+        assert rst == 0
+        ref = np.concatenate([rg0, rgt])
+        got = np.concatenate([g0[i], gt[i]])
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max(), i

@@ -285,3 +285,62 @@ def test_blocked_batch_alpha_range(F, orc):
     w = dict(system=0, theta=th, alpha=al, h=np.full(B, 0.01),
              N=np.array([1200, 700, 2049, 256, 1, 900]), y0=rng.uniform(-1, 1, (B, d)))
     _batch_parity(F, orc, w, path="blocked")
+
+
+@pytest.mark.parametrize("far_prec", ["fp32", "fp64"])
+def test_blocked_batch_rossler_full_size(F, orc, far_prec):
+    """The Rossler batch at full size (4096 instances, N 2^14..2^17, per-instance
+    alpha) in the benchmark's launch configuration (FP32 far windows; FP64
+    beside it): every status 0, every row finite and bounded; the first 2000
+    rows of four instances against the oracle; and rows at t = 4097, N/2 and N
+    of the longest, shortest and two other instances re-formed by the oracle
+    from the GPU's own history. Bounds: FP64 as for Chen at full size; FP32
+    windows round weights and history to binary32 and sum up to 64 products in
+    binary32, at most 2^-18 of the history terms' magnitude (2^-17 used).
+    About 2% of the starting points leave every bounded set within the first
+    few hundred steps (the oracle finds 7 of the 300 shortest instances doing
+    so, at steps 241-405): their status is checked against the oracle's for
+    the three found there, and every such instance has finite rows before its
+    status and NaN rows from it."""
+    from paper_1611_08678_amd import workloads as W
+    w = W.rossler_batch()
+    Ns = w["N"]
+    y, off, st = F.solve_batch(w["system"], w["theta"], w["alpha"], w["h"], Ns, w["y0"],
+                               path="blocked", far_prec=far_prec)
+    yy, gst = _to_np(y), _to_np(st)
+    assert 0 < int((gst > 0).sum()) < 0.05 * len(Ns)
+    for i in range(len(Ns)):
+        rows = yy[off[i]: off[i] + Ns[i] + 1]
+        k = int(gst[i]) if gst[i] else int(Ns[i]) + 1
+        assert np.all(np.isfinite(rows[:k])) and np.abs(rows[:k]).max() < 1e300, i
+        if gst[i] == 0:
+            assert np.abs(rows).max() < 100.0, i
+        else:
+            assert np.all(np.isnan(rows[k:])), i
+    u = np.finfo(np.float64).eps / 2
+    for i, rst in ((2902, 241), (988, 258), (1823, 307)):  # oracle statuses
+        # FP64: the oracle's step, or one apart at the top of the binary64 range;
+        # FP32 far operands overflow first, never later
+        assert (abs(int(gst[i]) - rst) <= 1 if far_prec == "fp64" else 0 < gst[i] <= rst), \
+            (i, gst[i], rst)
+        ref, _, _, _ = orc.solve(w["system"], w["theta"][i], w["alpha"][i], w["h"][i], rst - 1,
+                                 w["y0"][i])
+        rows = yy[off[i]: off[i] + 200]
+        assert relerr(rows, ref[:200]) <= (1e-5 if far_prec == "fp32" else 1e-11), i
+    order = np.argsort(Ns)
+    finite = [int(j) for j in order if gst[j] == 0]
+    picks = [finite[-1], finite[0], finite[len(finite) // 3], 1234]
+    assert gst[1234] == 0
+    for i in picks:
+        th, a, h, y0 = w["theta"][i], w["alpha"][i], w["h"][i], w["y0"][i]
+        N = int(Ns[i])
+        rows = yy[off[i]: off[i] + N + 1]
+        ref, _, _, _ = orc.solve(w["system"], th, a, h, 2000, y0)
+        assert relerr(rows[:2001], ref) <= (1e-5 if far_prec == "fp32" else 1e-11), i
+        wts = orc.weights(a, N)
+        f = orc.rhs_rows(w["system"], th, h, rows)
+        for t in (4097, N // 2, N):
+            yt, mag = orc.step_from_history(w["system"], th, a, h, t, y0, f, wts)
+            tol = (2.0 ** -17 * mag if far_prec == "fp32" else 10.0 * np.sqrt(t) * u * mag)
+            tol = tol + 4 * u * np.abs(yt)
+            assert np.all(np.abs(rows[t] - yt) <= tol), (i, t, rows[t], yt, mag)

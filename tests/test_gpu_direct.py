@@ -201,3 +201,20 @@ def test_grid_direct_deterministic(F):
                         path="direct")
         ys.append(_to_np(y))
     assert np.array_equal(ys[0], ys[1])
+
+
+def test_direct_vdp_batch_full_size(F, orc):
+    """The Van der Pol batch at full size (1024 instances, N = 2^15) on the
+    DIRECT workgroup-per-instance kernel, as the benchmark runs it: every status
+    0, every row finite, and two whole instances against the oracle."""
+    from paper_1611_08678_amd import workloads as W
+    w = W.vdp_adjoint()
+    y, off, st = F.solve_batch(w["system"], w["theta"], w["alpha"], w["h"], w["N"], w["y0"],
+                               path="direct")
+    yy, gst = _to_np(y), _to_np(st)
+    assert np.all(gst == 0) and np.all(np.isfinite(yy))
+    N = int(w["N"][0])
+    for i in (0, 777):
+        ref, _, _, rst = orc.solve(w["system"], w["theta"][i], w["alpha"][i], w["h"][i], N,
+                                   w["y0"][i])
+        assert rst == 0 and relerr(yy[off[i]: off[i] + N + 1], ref) <= 1e-11, i
