@@ -215,13 +215,13 @@ __device__ __forceinline__ double wave_sum(double v)
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
-// Flags shared between workgroups on different XCDs. Each XCD has its own L2;
-// an ordinary (even atomic) load or store of a flag may be served from, or
-// left dirty in, the local L2 with nothing forcing it across. Flags are
-// therefore only touched with read-modify-write atomics, which every XCD
-// performs at the same coherence point; data published under a flag is made
-// visible by the release fence before the flag write and the acquire fence
-// after the flag read.
+// Flags shared between workgroups on different XCDs (each XCD has its own
+// L2). Flag writes are read-modify-write atomics, performed at the device's
+// coherence point. A flag read is an agent-scope atomic (an add of zero,
+// which the compiler emits on gfx950 as the memory model's agent-coherent
+// load, global_load with sc1, not as a plain cached load); data published
+// under a flag is made visible by the release fence before the flag write and
+// the acquire fence after the flag read.
 __device__ __forceinline__ uint32_t flag_read(uint32_t *p)
 {
     return __hip_atomic_fetch_add(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
