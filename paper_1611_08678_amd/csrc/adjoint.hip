@@ -491,13 +491,10 @@ static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, co
         }                                  \
     } while (0)
     const size_t smem = adj_smem_bytes(D, PC);
-    static bool attr_done = false;
-    if (PC && !attr_done) {  // above the default limit only with per-component tables
+    static std::atomic<uint64_t> attr_dev{0};
+    if (PC)  // above the default limit only with per-component tables
         FABM_ADJ_TRY("hipFuncSetAttribute(adjoint LDS)",
-                     hipFuncSetAttribute((const void *)k_adj_batch<SYS, D, PC>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-        attr_done = true;
-    }
+                     ensure_lds_attr((const void *)k_adj_batch<SYS, D, PC>, smem, attr_dev));
     for (int s = -1; s <= S.max_NB - 2; ++s) {
         const size_t k = (size_t)(s + 1);
         const int nb = S.nband[k], nn = S.nnear[k], nf = S.nfar[k];

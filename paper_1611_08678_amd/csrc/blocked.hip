@@ -911,14 +911,10 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
             return e_;                     \
         }                                  \
     } while (0)
-    static bool attr_done = false;
+    static std::atomic<uint64_t> attr_dev{0};
     const size_t smem = step_smem_bytes(D, PC);
-    if (!attr_done) {
-        FABM_STEP_TRY("hipFuncSetAttribute(step LDS)",
-                      hipFuncSetAttribute((const void *)k_step<SYS, D, F32, PC>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-        attr_done = true;
-    }
+    FABM_STEP_TRY("hipFuncSetAttribute(step LDS)",
+                  ensure_lds_attr((const void *)k_step<SYS, D, F32, PC>, smem, attr_dev));
     for (int s = -1; s <= A.NB - 2; ++s) {
         int grid, wpw;
         step_grid(A.NB, s, &grid, &wpw, A.far_cap);
@@ -955,13 +951,11 @@ static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, co
         }                                  \
     } while (0)
     const size_t smem = batch_smem_bytes(D, PC);
-    static bool attr_done = false;
-    if (PC && !attr_done) {  // above the default limit only with per-component tables
+    static std::atomic<uint64_t> attr_dev{0};
+    if (PC)  // above the default limit only with per-component tables
         FABM_STEP_TRY("hipFuncSetAttribute(batch LDS)",
-                      hipFuncSetAttribute((const void *)k_step_batch<SYS, D, F32, YPOUT, PC>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-        attr_done = true;
-    }
+                      ensure_lds_attr((const void *)k_step_batch<SYS, D, F32, YPOUT, PC>, smem,
+                                      attr_dev));
     for (int s = -1; s <= S.max_NB - 2; ++s) {
         const size_t k = (size_t)(s + 1);
         const int nb = S.nband[k], nn = S.nnear[k], nf = S.nfar[k];

@@ -4,9 +4,27 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace fabm {
 
 struct InstMeta;
+
+// Raise a kernel's dynamic LDS limit to `bytes` on the current device, once
+// per device: `done` is the kernel's own set of devices already configured
+// (the attribute is per device, so a process driving several GPUs sets it on
+// each).
+inline hipError_t ensure_lds_attr(const void *fn, size_t bytes, std::atomic<uint64_t> &done)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
+    return e;
+}
 
 // Weight tables for every instance of a call (one table per instance).
 // With W32, b and a are also written in binary32 (far windows in FP32).

@@ -33,6 +33,12 @@ def _case(name):
         B = 4
         return ("vdp", rng.uniform(0.5, 2, (B, 1)), np.full(B, 0.9), np.full(B, 0.01),
                 np.array([500, 20, 333, 800]), rng.uniform(-2, 2, (B, 2)), "direct", "fp64")
+    if name in ("per_component_blocked", "per_component_direct"):  # alpha [B][d]
+        B = 5
+        return ("hindmarsh_rose", np.tile([1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25], (B, 1)),
+                rng.uniform(0.7, 1.0, (B, 3)), np.full(B, 0.01),
+                np.array([300, 1200, 1, 513, 900]), rng.uniform(-1, 1, (B, 3)),
+                name.split("_")[-1], "fp64")
     B, d = 4, 16  # shared grid, split binary16 far tiles
     A = -(2 * np.eye(d)[None] + rng.standard_normal((B, d, d)) / 8)
     th = np.concatenate([A.reshape(B, -1), 0.1 * rng.standard_normal((B, 2 * d))], axis=1)
@@ -41,12 +47,14 @@ def _case(name):
 
 
 @pytest.mark.parametrize("name", ["batch_blocked_fp32", "single_blocked", "batch_direct",
-                                  "shared_grid_fp16x2"])
+                                  "shared_grid_fp16x2", "per_component_blocked",
+                                  "per_component_direct"])
 def test_graph_replays_match_eager(F, name):
     import torch
     system, th, al, hs, Ns, y0s, path, prec = _case(name)
     B, d = y0s.shape
-    plan = F.fabm_plan(system, d, path, prec, B, int(Ns.max()), int(Ns.sum()))
+    plan = F.fabm_plan(system, d, path, prec, B, int(Ns.max()), int(Ns.sum()),
+                       per_component_order=np.ndim(al) == 2)
     ws = F._workspace(F.fabm_workspace_size(plan, Ns))
     row_off = np.concatenate([[0], np.cumsum(Ns + 1)[:-1]]).astype(np.int64)
     y0 = torch.tensor(y0s, device="cuda")

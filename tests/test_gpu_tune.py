@@ -74,3 +74,22 @@ def test_tune_nothing_to_choose(F):
     rep = F.fabm_tune(plan, ws, np.full(B, 0.9), np.full(B, 0.01), [700, 300, 500], y0d, thd,
                       ro, y, st)
     assert rep == {"knob": "none", "candidates": [], "seconds": [], "chosen": None}
+
+
+def test_tune_single_trajectory_per_component_orders(F, orc):
+    """A single trajectory with one order per component (a batch of one on the
+    BLOCKED step kernels): the tuned plan's result is bitwise the untuned
+    one's and matches the oracle's per-component solver."""
+    N = 6000
+    th = np.array([[1.0, 3.0, 1.0, 5.0, 0.006, 4.0, -1.6, 3.25]])
+    y0 = np.array([[-1.6, -10.0, 2.0]])
+    al = np.array([[0.95, 0.9, 1.0]])
+    plan = F.fabm_plan("hindmarsh_rose", 3, "blocked", "fp64", 1, N, per_component_order=True)
+    ws, ro, y0d, thd, y, st = _buffers(F, plan, [N], y0, th)
+    rep = F.fabm_tune(plan, ws, al, [0.01], [N], y0d, thd, ro, y, st)
+    assert rep["knob"] == "far_workgroups" and 0 <= rep["chosen"] < 4
+    y1, _, s1 = F.solve_batch("hindmarsh_rose", th, al, [0.01], [N], y0, plan=plan)
+    y2, _, _ = F.solve_batch("hindmarsh_rose", th, al, [0.01], [N], y0, path="blocked")
+    assert int(_to_np(s1)[0]) == 0 and np.array_equal(_to_np(y1), _to_np(y2))
+    ref, _, _, rst = orc.solve_orders(5, th[0], al[0], 0.01, N, y0[0])
+    assert rst == 0 and relerr(_to_np(y1), ref) <= 1e-11
