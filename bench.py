@@ -68,6 +68,12 @@ def parse():
                     help="batch workloads: a separate order per state component, alpha ~ "
                          "U[0.8, 1] (non-commensurate system; DIRECT, or BLOCKED with FP64 "
                          "far windows)")
+    ap.add_argument("--alpha", type=float, default=None,
+                    help="batch workloads: one order for every instance (1 < alpha <= 2 "
+                         "needs --slope)")
+    ap.add_argument("--slope", action="store_true",
+                    help="batch workloads: pass y'(0) ~ 0.5 N(0, 1) as a second initial "
+                         "row (orders above one, eq. (1))")
     ap.add_argument("--sweep-N", default=None,
                     help="hr_table2: comma list of step counts (default: all of the table's)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
@@ -201,8 +207,13 @@ def bench_batch(F, W, args):
     prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" and not pc else "fp64")
     Ns = np.asarray(w["N"], dtype=np.int64)
     B, d = len(Ns), w["d"]
+    if args.alpha is not None:
+        w = dict(w, alpha=np.full(w["alpha"].shape, args.alpha))
+    if args.slope:
+        slope = 0.5 * np.random.Generator(np.random.PCG64(7)).standard_normal((B, d))
+        w = dict(w, y0=np.stack([w["y0"], slope], axis=1))
     plan = F.fabm_plan(w["system"], d, args.batch_path, prec, B, int(Ns.max()), int(Ns.sum()),
-                       per_component_order=pc)
+                       per_component_order=pc, initial_slope=args.slope)
     ws = torch.empty(F.fabm_workspace_size(plan, Ns), dtype=torch.uint8, device="cuda")
     y0 = torch.as_tensor(w["y0"], dtype=torch.float64, device="cuda").contiguous()
     th = torch.as_tensor(w["theta"], dtype=torch.float64, device="cuda").contiguous()
@@ -253,7 +264,8 @@ def bench_batch(F, W, args):
                       "N_max": int(Ns.max()), "path": args.batch_path,
                       "far_prec": prec if args.batch_path == "blocked" else None,
                       "orders": (f"per component, U[{float(np.min(w['alpha'])):.2f}.., 1]"
-                                 if pc else "one per instance")},
+                                 if pc else "one per instance"),
+                      "alpha": args.alpha, "initial_slope": args.slope},
            "history_gflops": flops / t / 1e9,
            "status_nonzero": int((stv != 0).sum()),
            "rows_counted": "rows formed: N_i, or status_i - 1 for instances that left every "
