@@ -82,11 +82,12 @@ def parse():
     return ap.parse_args()
 
 
-def setup(F, w, path):
+def setup(F, w, path, fft_level=0):
     import torch
     N = int(w["N"][0])
     d = w["d"]
-    plan = F.fabm_plan(w["system"], d, path, "fp64", 1, N)
+    plan = F.fabm_plan(w["system"], d, path, "fp64", 1, N,
+                       fft_level=fft_level if path == "blocked" else 0)
     ws = torch.empty(F.fabm_workspace_size(plan, [N]), dtype=torch.uint8, device="cuda")
     y0 = torch.as_tensor(w["y0"][0], device="cuda").contiguous()
     th = torch.as_tensor(w["theta"][0], device="cuda").contiguous()

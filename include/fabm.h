@@ -122,7 +122,26 @@ typedef struct {
                               * are UNSUPPORTED */
     int32_t flags;           /* FABM_PLAN_INITIAL_SLOPE | FABM_PLAN_PER_COMPONENT_ORDER
                               * or 0; other bits INVALID_ARG */
+    int32_t fft_level;       /* 0: every far window on the matrix cores. l in 1..15:
+                              * sub-quadratic far history, see below */
 } fabm_plan_desc;
+
+/* Sub-quadratic far history (fft_level = l > 0). The far sums of a BLOCKED
+ * trajectory (the Section 2 history sums over source blocks at least three
+ * blocks of 256 rows before the target block) are the block pairs
+ * (J - 2, K) with K < J - 2; the pairs whose highest differing bit is l' form
+ * dyadic squares of 2^l' source by 2^l' target blocks. Levels l' >= l are
+ * evaluated by FFT convolution (four-step binary64 transforms of length
+ * 512 * 2^l') right after the step that forms the square's last source block,
+ * levels below l by the matrix-core windows, so the far work falls from
+ * O(N^2 d) to O(N log^2 N d) with O(N d) windows. The results differ from
+ * fft_level = 0 by rounding, bounded normwise rather than per term (about
+ * log2(512 * 2^l') u times the norms of the weights and of the history
+ * involved). Plans: path BLOCKED, far_prec FP64, max_batch 1, no
+ * per-component orders, not the shared grid (else UNSUPPORTED); N <= 2^24.
+ * Calls: fabm_solve and batches of one; the adjoint calls of such a plan are
+ * UNSUPPORTED. The workspace grows by 16 (d + 3) M bytes, M the longest
+ * transform (at most 4 (N + 1) rounded up to a power of two). */
 
 /* Plan flag: the calls of the plan pass two initial values per instance, y0
  * as [batch][2][d] (y(0), then y'(0)), which orders 1 < alpha <= 2 need
@@ -334,7 +353,9 @@ typedef enum {
     FABM_KERNEL_ADJOINT = 5,      /* reverse pass: band plus MFMA windows of one block */
     FABM_KERNEL_WIDE_FAR = 6,     /* shared-grid batch: far sums of one block (matrix cores) */
     FABM_KERNEL_WIDE_BAND = 7,    /* shared-grid batch: rows of one block, all instances */
-    FABM_KERNEL_COUNT = 8
+    FABM_KERNEL_FFT_FAR = 8,      /* sub-quadratic far history: weight spectra, and the
+                                     FFT convolution of one dyadic square */
+    FABM_KERNEL_COUNT = 9
 } fabm_kernel_class;
 
 /* Instrumentation. While enabled, every solve call of the plan records a pair

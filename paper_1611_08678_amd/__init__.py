@@ -37,7 +37,7 @@ EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan"
            "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy", "fabm_tune",
            "fabm_adjoint_forward", "fabm_adjoint_reverse")
 KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint",
-                  "wide_far", "wide_band")
+                  "wide_far", "wide_band", "fft_far")
 
 
 class FabmError(RuntimeError):
@@ -55,7 +55,8 @@ class FabmError(RuntimeError):
 class _PlanDesc(C.Structure):
     _fields_ = [("system", C.c_int), ("dim", C.c_int32), ("path", C.c_int),
                 ("far_prec", C.c_int), ("max_batch", C.c_int64), ("max_steps", C.c_int64),
-                ("max_total_steps", C.c_int64), ("tile_L", C.c_int32), ("flags", C.c_int32)]
+                ("max_total_steps", C.c_int64), ("tile_L", C.c_int32), ("flags", C.c_int32),
+                ("fft_level", C.c_int32)]
 
 
 _lib = None
@@ -191,13 +192,17 @@ FABM_PLAN_PER_COMPONENT_ORDER = 2
 
 def fabm_plan(system, dim: int, path="auto", far_prec="fp64", max_batch: int = 1,
               max_steps: int = 1, max_total_steps: int = 0, tile_L: int = 0,
-              initial_slope: bool = False, per_component_order: bool = False) -> Plan:
+              initial_slope: bool = False, per_component_order: bool = False,
+              fft_level: int = 0) -> Plan:
+    """fft_level > 0: the far history of one BLOCKED trajectory by FFT convolution
+    of dyadic block squares of level >= fft_level (sub-quadratic variant)."""
     L = load()
     desc = _PlanDesc(_enum(system, SYSTEMS), int(dim), _enum(path, PATHS),
                      _enum(far_prec, FAR_PRECS), int(max_batch), int(max_steps),
                      int(max_total_steps), int(tile_L),
                      (FABM_PLAN_INITIAL_SLOPE if initial_slope else 0) |
-                     (FABM_PLAN_PER_COMPONENT_ORDER if per_component_order else 0))
+                     (FABM_PLAN_PER_COMPONENT_ORDER if per_component_order else 0),
+                     int(fft_level))
     h = C.c_void_p()
     ws = C.c_size_t()
     _check(L.fabm_plan(C.byref(desc), C.byref(h), C.byref(ws)), "fabm_plan")
@@ -412,8 +417,9 @@ def _init_rows(y0, lead: int):
 
 
 def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_prec="fp64",
-          plan: Plan | None = None, tile_L: int = 0):
+          plan: Plan | None = None, tile_L: int = 0, fft_level: int = 0):
     """One trajectory; returns (y [N+1, d] float64 device tensor, status int).
+    fft_level > 0 (path "blocked"): far history by FFT squares of that level on.
     y0 is y(0) [d], or [2, d] holding y(0) and y'(0) (orders 1 < alpha <= 2).
     alpha may be one order per component ([d]): a batch of one on the DIRECT
     kernels (non-commensurate orders)."""
@@ -426,7 +432,8 @@ def solve(system, theta, alpha: float, h: float, N: int, y0, path="auto", far_pr
     y0, d, two = _init_rows(y0, 0)
     th = _dev(theta).reshape(-1)
     if plan is None:
-        plan = fabm_plan(system, d, path, far_prec, 1, N, tile_L=tile_L, initial_slope=two)
+        plan = fabm_plan(system, d, path, far_prec, 1, N, tile_L=tile_L, initial_slope=two,
+                         fft_level=fft_level)
     ws = _workspace(fabm_workspace_size(plan, [N]))
     y = torch.empty((N + 1, d), dtype=torch.float64, device="cuda")
     st = torch.zeros(1, dtype=torch.int64, device="cuda")

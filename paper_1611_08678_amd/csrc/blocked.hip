@@ -454,9 +454,10 @@ constexpr size_t staged_bytes()
 }
 
 // NC = kSrcCols: columns 16 s - 15 .. 16 s + 15; NC = kPairCols: the 16 columns
-// before those as well (the window of source block s - 1 too).
+// before those as well (the window of source block s - 1 too). Rows below
+// `lo` are staged as zero.
 template <int D, typename T, int NC = kSrcCols>
-__device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB)
+__device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB, int64_t lo = 0)
 {
     const int64_t pitch = (int64_t)A.NB * kBlk;
     const int64_t r0 = (int64_t)kBlk * s - kTile * (NC - kTile);  // row of staged column 0
@@ -464,7 +465,7 @@ __device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB)
         const int i = e / (NC * kTile), rem = e - i * (NC * kTile);
         const int c = rem / kTile, tau = rem - c * kTile;
         const int64_t row = r0 + kTile * c + tau;
-        sB[(i * NC + c) * kColPitch + tau] = row >= 0 ? (T)A.Fc[i * pitch + row] : (T)0;
+        sB[(i * NC + c) * kColPitch + tau] = row >= lo ? (T)A.Fc[i * pitch + row] : (T)0;
     }
 }
 
@@ -704,9 +705,12 @@ __device__ __forceinline__ InstView single_view(const StepArgs &A)
 }
 
 // Launch s of the single-trajectory pipeline; `wpw` wavefronts of each far
-// workgroup take part (wavefront g of G handles targets s + 3 + g + k G).
+// workgroup take part (wavefront g of G handles targets s + 3 + g + k G). With
+// the far history of larger distances in FFT squares, far targets end at block
+// `jend` and the far windows take no source rows below `flo` (0 otherwise).
 template <int SYS, int D, bool F32, bool PC = false>
-__global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wpw)
+__global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wpw, int jend,
+                                                       int64_t flo)
 {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x, wave = threadIdx.x >> 6;
@@ -718,7 +722,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
     if (*A.dead != 0u) return;  // the trajectory has ended; later rows are NaN
     if (b == 1 || !F32) {
         double *sB = (double *)smem;
-        stage_sources<D, double>(V, s, sB);
+        stage_sources<D, double>(V, s, sB, b == 1 ? 0 : flo);
         __syncthreads();
         if (b == 1) {
             if (wave < kNearWaves)
@@ -728,15 +732,15 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         }
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
-        for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G)
+        for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
             far_target<D, false, PC>(V, s, J, sB, s == 0);
     } else {
         float *sB = (float *)smem;
-        stage_sources<D, float>(V, s, sB);
+        stage_sources<D, float>(V, s, sB, flo);
         __syncthreads();
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
-        for (int J = s + 3 + (b - 2) * wpw + wave; J < A.NB; J += G)
+        for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
             far_target_f32<D, false, PC>(V, s, J, sB, s == 0);
     }
 }
@@ -883,13 +887,13 @@ size_t step_smem_bytes(int d, bool pc)
 // Launch shape of step s: band and near workgroups plus up to far_cap far
 // workgroups of wpw wavefronts (the far loop strides over the targets, so any
 // cap covers all of them).
-void step_grid(int NB, int s, int *grid, int *wpw, int far_cap)
+void step_grid(int NB, int jend, int s, int *grid, int *wpw, int far_cap)
 {
     *grid = 1;
     *wpw = 0;
     if (s < 0 || s + 2 > NB - 1) return;
     *grid = 2;
-    const int nt = NB - (s + 3);  // far targets
+    const int nt = std::min(jend, NB) - (s + 3);  // far targets
     if (nt <= 0) return;
     const int cap = std::max(1, std::min(far_cap > 0 ? far_cap : kMaxFarWg, kMaxFarWg));
     const int per_round = 4 * cap;
@@ -915,14 +919,28 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
     const size_t smem = step_smem_bytes(D, PC);
     FABM_STEP_TRY("hipFuncSetAttribute(step LDS)",
                   ensure_lds_attr((const void *)k_step<SYS, D, F32, PC>, smem, attr_dev));
+    const bool fft = A.fft_level > 0 && fft_far_top_level(A.NB, A.fft_level) >= 0;
+    if (fft) {
+        if (T) FABM_STEP_TRY("timer begin", T->begin(KC_FFT_FAR, st));
+        FABM_STEP_TRY("FFT weight spectra", fft_far_prepare(A, st));
+        if (T) FABM_STEP_TRY("timer end", T->end(st));
+    }
     for (int s = -1; s <= A.NB - 2; ++s) {
         int grid, wpw;
-        step_grid(A.NB, s, &grid, &wpw, A.far_cap);
+        const int jend = fft ? fft_far_target_end(A.NB, A.fft_level, s) : A.NB;
+        const int64_t flo = fft && fft_far_mask_prev(A.fft_level, s) ? (int64_t)kBlk * s : 0;
+        step_grid(A.NB, jend, s, &grid, &wpw, A.far_cap);
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
         hipLaunchKernelGGL((k_step<SYS, D, F32, PC>), dim3(grid), dim3(kStepThreads), smem, st, A,
-                           s, wpw);
+                           s, wpw, jend, flo);
         FABM_STEP_TRY("launch k_step", hipGetLastError());
         if (T) FABM_STEP_TRY("timer end", T->end(st));
+        if (fft && fft_far_square_at(A.NB, A.fft_level, s) >= 0) {
+            // the square whose last source block this launch formed
+            if (T) FABM_STEP_TRY("timer begin", T->begin(KC_FFT_FAR, st));
+            FABM_STEP_TRY("FFT far square", fft_far_square(D, A, s, st));
+            if (T) FABM_STEP_TRY("timer end", T->end(st));
+        }
     }
     hipLaunchKernelGGL(k_step_status, dim3(1), dim3(kWave), 0, st, A);
     FABM_STEP_TRY("launch k_step_status", hipGetLastError());

@@ -144,6 +144,7 @@ struct Layout {
     size_t flo, fexp, t16, t16exp;
     size_t init;   // initial values split into y0 [batch][d] and y'(0) [batch][d]
     size_t cmeta;  // per-component orders: [batch][d] entries (staged after meta)
+    size_t ftw, fbuf, fspec;  // sub-quadratic far history: twiddles, transforms, spectra
     int64_t cp;    // shared grid: padded history columns
     size_t total;
     int64_t wlen;  // single-trajectory BLOCKED: weight table length
@@ -312,6 +313,16 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         L.sync = off;
         L.n_sync_words = 64;
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
+        const int64_t mfft = fabm::fft_far_max_len(L.NB, pl->desc.fft_level);
+        L.ftw = L.fbuf = L.fspec = off;
+        if (mfft > 0) {  // twiddles, one square's transforms, the weight spectra
+            L.ftw = off;
+            off = align_up(off + 16 * (size_t)mfft);
+            L.fbuf = off;
+            off = align_up(off + 16 * (size_t)mfft * d);
+            L.fspec = off;
+            off = align_up(off + 16 * (size_t)fabm::fft_far_spectra_len(L.NB, pl->desc.fft_level));
+        }
     } else {
         L.wlen = 0;
         const bool pc = per_component(pl);
@@ -619,6 +630,11 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
         A.status = status;
         A.NB = L.NB;
         A.far_cap = pl->far_cap;
+        A.fft_level = pl->desc.fft_level;
+        A.wlen = L.wlen;
+        A.fft_tw = (double2 *)(base + L.ftw);
+        A.fft_buf = (double2 *)(base + L.fbuf);
+        A.fft_spec = (double2 *)(base + L.fspec);
         const char *where = "";
         const hipError_t pe = fabm::enqueue_steps(pl->desc.system, d, f32, A, s, T, &where);
         if (pe != hipSuccess) return record_hip(where, pe);
@@ -655,6 +671,7 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
                         AdjPhase phase = AdjPhase::Both, double *y_out = nullptr)
 {
     const int d = pl->desc.dim;
+    if (pl->desc.fft_level > 0) return FABM_ERR_UNSUPPORTED;  // the reverse pass has no FFT form
     const Layout L = layout_for(pl, batch, N, true);
     fabm_status st = ensure_device(pl);
     if (st != FABM_OK) return st;
@@ -847,6 +864,13 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     // per-component orders: DIRECT, or BLOCKED per trajectory (FP64 or FP32 windows)
     if ((desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) && wide) return FABM_ERR_UNSUPPORTED;
     if (wide && desc->max_batch > kWideMaxCols / desc->dim) return FABM_ERR_UNSUPPORTED;
+    // sub-quadratic far history: one trajectory, FP64 windows, one order
+    if (desc->fft_level < 0 || desc->fft_level > 15) return FABM_ERR_INVALID_ARG;
+    if (desc->fft_level > 0 &&
+        (wide || desc->path != FABM_PATH_BLOCKED || desc->far_prec != FABM_FAR_FP64 ||
+         desc->max_batch != 1 || (desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) ||
+         desc->max_steps > ((int64_t)1 << 24)))
+        return FABM_ERR_UNSUPPORTED;
 
     fabm_plan_s *pl = new (std::nothrow) fabm_plan_s();
     if (!pl) return FABM_ERR_INVALID_ARG;
@@ -1086,6 +1110,7 @@ fabm_status fabm_adjoint_workspace_size(fabm_plan_t plan, int64_t batch, const i
     for (int64_t i = 0; i < batch; ++i)
         if (N[i] < 1 || N[i] > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
     if (plan->desc.system == FABM_SYS_LINEAR && plan->desc.dim > 4) return FABM_ERR_UNSUPPORTED;
+    if (plan->desc.fft_level > 0) return FABM_ERR_UNSUPPORTED;
     *bytes = layout_for(plan, batch, N, true).total;
     return FABM_OK;
 }

@@ -70,6 +70,13 @@ struct StepArgs {
     int64_t *status;
     int NB;
     int far_cap;        // far workgroups per launch (host side: launch shape only)
+    // sub-quadratic far history (fft_far.hip; host side): squares of level
+    // >= fft_level by FFT convolution, 0 = every far window on the matrix cores
+    int fft_level;
+    int64_t wlen;       // length of each weight table
+    double2 *fft_tw;    // twiddles exp(-2 pi i j / M) of the longest transform M
+    double2 *fft_buf;   // [D][M] transform of the current square
+    double2 *fft_spec;  // weight spectra of levels fft_level.., concatenated
 };
 
 // Value of StepArgs::dead when a bounded wait inside the band gave up

@@ -67,7 +67,19 @@ hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_
                          KernelTimer *T, const char **where);
 int step_block_len();
 size_t step_smem_bytes(int d, bool pc = false);
-void step_grid(int NB, int s, int *grid, int *wpw, int far_cap);
+void step_grid(int NB, int jend, int s, int *grid, int *wpw, int far_cap);
+
+// Sub-quadratic far history of the step pipeline (fft_far.hip). Level l of
+// the dyadic squares covers 2^l source blocks; the host enqueues at most one
+// square after each step launch.
+int fft_far_top_level(int NB, int level);         // highest level with a square, or -1
+int64_t fft_far_max_len(int NB, int level);       // longest transform (complex elements)
+int64_t fft_far_spectra_len(int NB, int level);   // complex elements of all weight spectra
+int fft_far_target_end(int NB, int level, int s); // end of launch s's window targets
+bool fft_far_mask_prev(int level, int s);         // launch s's windows skip block s - 1
+hipError_t fft_far_prepare(const StepArgs &A, hipStream_t st);  // twiddles and spectra
+int fft_far_square_at(int NB, int level, int s);  // level of the square after launch s, or -1
+hipError_t fft_far_square(int d, const StepArgs &A, int s, hipStream_t st);
 
 // BLOCKED path for a batch (> 1) of trajectories: one launch per block step
 // for all instances. `far_off` is S.far_off in device memory.

@@ -19,7 +19,8 @@ enum : int {
     KC_ADJOINT = 5,
     KC_WIDE_FAR = 6,
     KC_WIDE_BAND = 7,
-    KC_COUNT = 8
+    KC_FFT_FAR = 8,
+    KC_COUNT = 9
 };
 
 struct KernelTimer {
