@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--slope", action="store_true",
                     help="batch workloads: pass y'(0) ~ 0.5 N(0, 1) as a second initial "
                          "row (orders above one, eq. (1))")
+    ap.add_argument("--fft-level", type=int, default=0,
+                    help="chen / hr_table2: far history of block squares of this level and "
+                         "above by FFT convolution (sub-quadratic variant; 0 = off)")
     ap.add_argument("--sweep-N", default=None,
                     help="hr_table2: comma list of step counts (default: all of the table's)")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
@@ -96,9 +99,9 @@ def setup(F, w, path, fft_level=0):
     return plan, (plan, ws, float(w["alpha"][0]), float(w["h"][0]), N, y0, th, y, st), y, st
 
 
-def time_path(F, w, path: str, steps: int, warmup: int, kernel_times: bool):
+def time_path(F, w, path: str, steps: int, warmup: int, kernel_times: bool, fft_level: int = 0):
     import torch
-    plan, args, y, st = setup(F, w, path)
+    plan, args, y, st = setup(F, w, path, fft_level)
     for _ in range(warmup):
         F.fabm_solve(*args)
     torch.cuda.synchronize()
@@ -155,14 +158,28 @@ def measured_traffic(kernel: str):
     return val if cur == sha else None
 
 
-def roofline(kt: dict, N: int, d: int):
+def roofline(kt: dict, N: int, d: int, fft_level: int = 0):
     """Roofline object of the dominant kernel of the headline path, from the
-    library's per-launch HIP events (recorded on the kernel's own stream)."""
+    library's per-launch HIP events (recorded on the kernel's own stream).
+    With the FFT variant the flops are direct-equivalent: the 2 d N (N + 1) of
+    the plain sums, of which the variant performs O(N log^2 N)."""
     if not kt:
         return None
     dom = max(kt, key=lambda k: kt[k][0])
     secs, launches = kt[dom]
     flops = 2.0 * d * N * (N + 1)  # algorithmic history flops of one solve
+    if dom == "blocked_step" and fft_level > 0:
+        band_floor = N * BAND_CYCLES_PER_ROW / CLOCK_HZ
+        fsecs, fl = kt.get("fft_far", (0.0, 0))
+        ach = flops / secs / 1e12
+        return dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=None, kernel="k_step",
+                    flops_basis="direct-equivalent 2 d N (N + 1) (sub-quadratic variant)",
+                    launches=launches, avg_launch_s=secs / launches,
+                    fft_far=dict(seconds=fsecs, launches=fl),
+                    sequential_floor=dict(s=band_floor, frac=band_floor / (secs + fsecs),
+                                          basis=f"N rows x {BAND_CYCLES_PER_ROW} cycles per row "
+                                                f"of the band walk at {CLOCK_HZ / 1e9:.1f} GHz"))
     if dom == "blocked_step":
         # every history flop of the BLOCKED path is done inside the step
         # kernels (MFMA near/far windows plus the sequential band)
@@ -466,7 +483,7 @@ def bench_table2(F, W, args):
         print(f"# hr_table2: N={N} blocked, {args.warmup} warmup + {args.steps} timed",
               file=sys.stderr, flush=True)
         r = time_path(F, w, "blocked", args.steps, args.warmup,
-                      kernel_times=not args.no_kernel_times)
+                      kernel_times=not args.no_kernel_times, fft_level=args.fft_level)
         t = float(np.mean(r["solve_s"]))
         y = r["y"]
         hpc, cuda = PAPER_TABLE2_S.get(N, (None, None))
@@ -490,7 +507,7 @@ def bench_table2(F, W, args):
         "config": {"workload": ("fractional Hindmarsh-Rose (a,b,c,d,r,s,xr,I)=(1,3,1,5,0.006,4,"
                                 "-1.6,3.25), alpha=0.95, h=0.01, y0=(-1.6,-10,2), d=3, one "
                                 "trajectory per N, N in " + ",".join(str(n) for n in Ns)),
-                   "path": "blocked", "far_prec": "fp64"},
+                   "path": "blocked", "far_prec": "fp64", "fft_level": args.fft_level},
         "sweep": rows,
         "paper_context": ("paper Table 2: average seconds on a BlueGene/P partition and an "
                           "unnamed CUDA GPU for Hindmarsh-Rose runs of unstated parameters, "
@@ -499,7 +516,8 @@ def bench_table2(F, W, args):
     kt = r.get("kernel_times")
     if kt:
         out["kernel_times_s_at_largest_N"] = {k: v[0] for k, v in kt.items() if v[1]}
-    out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, 3)
+    out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, 3,
+                               args.fft_level)
     if out["roofline"]:
         out["roofline"]["at_N"] = N
     if args.cpu_sample > 0:
@@ -555,7 +573,8 @@ def main():
         head_path = path == "blocked" or "blocked" not in paths
         r = time_path(F, w, path, args.steps if head_path else args.direct_steps,
                       args.warmup if head_path else 0,
-                      kernel_times=head_path and not args.no_kernel_times)
+                      kernel_times=head_path and not args.no_kernel_times,
+                      fft_level=args.fft_level)
         results[path] = r
         print(f"# {path}: solve times {['%.4f' % s for s in r['solve_s']]} s", file=sys.stderr,
               flush=True)
@@ -571,7 +590,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"fractional Chen (35,3,28), alpha=0.95, y0=(-9,-5,14), "
                                f"h=0.001, N={N}, d=3, single trajectory",
-                   "path": head, "far_prec": "fp64"},
+                   "path": head, "far_prec": "fp64", "fft_level": args.fft_level},
         "history_gflops": flops / t / 1e9,
         "paths": {k: {"solve_s": float(np.mean(v["solve_s"])),
                       "steps_states_per_s": N * d / float(np.mean(v["solve_s"])),
@@ -582,7 +601,8 @@ def main():
     if kt:
         out["kernel_times_s"] = {k: v[0] for k, v in kt.items() if v[1]}
         out["kernel_launches"] = {k: v[1] for k, v in kt.items() if v[1]}
-    out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, d)
+    out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, d,
+                               args.fft_level)
     if "direct" in results:
         # DIRECT reads both weight rows and the history at every step:
         # sum_t 8 t (d + 2) B = 4 N (N + 1) (d + 2) B (algorithmic)

@@ -237,3 +237,31 @@ def test_per_component_order_rules(fabm):
                                    Nb.ctypes.data_as(F._I64P), fake, fake,
                                    ro.ctypes.data_as(F._I64P), fake, fake, None)
         assert got == code, (al, got)
+
+
+def test_plan_fft_far_rules(fabm):
+    """fft_level (sub-quadratic far history): 0 off, 1..15 valid; only for one
+    BLOCKED trajectory with FP64 windows and one order; the workspace grows by
+    the twiddles, one square's transforms and the weight spectra."""
+    for lv in (-1, 16):
+        with pytest.raises(fabm.FabmError) as e:
+            fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, 50000, fft_level=lv)
+        assert e.value.code == 1
+    for kw in (dict(path="auto"), dict(path="direct"), dict(far_prec="fp32"),
+               dict(max_batch=2), dict(per_component_order=True),
+               dict(system="linear", dim=8), dict(max_steps=(1 << 24) + 1)):
+        a = dict(system="vdp", dim=2, path="blocked", far_prec="fp64", max_batch=1,
+                 max_steps=50000)
+        a.update(kw)
+        with pytest.raises(fabm.FabmError) as e:
+            fabm.fabm_plan(a.pop("system"), a.pop("dim"), fft_level=3, **a)
+        assert e.value.code == 2, kw
+    N = 50000  # 196 blocks: squares up to level 7, longest transform 2^16 points
+    p0 = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, N)
+    p3 = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, N, fft_level=3)
+    p9 = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, N, fft_level=9)  # above the top
+    M = 1 << 16
+    grow = fabm.fabm_workspace_size(p3, [N]) - fabm.fabm_workspace_size(p0, [N])
+    spectra = sum(512 << lv for lv in range(3, 8))
+    assert 16 * (M + 2 * M + spectra) <= grow <= 16 * (M + 2 * M + spectra) + 3 * 4096
+    assert fabm.fabm_workspace_size(p9, [N]) == fabm.fabm_workspace_size(p0, [N])
