@@ -127,14 +127,15 @@ typedef struct {
 } fabm_plan_desc;
 
 /* Sub-quadratic far history (fft_level = l > 0). The far sums of a BLOCKED
- * trajectory (the Section 2 history sums over source blocks at least three
- * blocks of 256 rows before the target block) are the block pairs
- * (J - 2, K) with K < J - 2; the pairs whose highest differing bit is l' form
- * dyadic squares of 2^l' source by 2^l' target blocks. Levels l' >= l are
- * evaluated by FFT convolution (four-step binary64 transforms of length
- * 512 * 2^l') right after the step that forms the square's last source block,
- * levels below l by the matrix-core windows, so the far work falls from
- * O(N^2 d) to O(N log^2 N d) with O(N d) windows. The results differ from
+ * trajectory (the Section 2 history sums, blocks of 256 rows) take, for
+ * target block J, every whole source block K <= J - 4 plus a triangle of
+ * block J - 3. The whole-block pairs (J - 3, K), K < J - 3, whose highest
+ * differing bit is l' form dyadic squares of 2^l' source by 2^l' target
+ * blocks. Levels l' >= l are evaluated by FFT convolution (four-step binary64
+ * transforms of length 512 * 2^l') right after the step that forms the
+ * square's last source block; levels below l and the triangles stay on the
+ * matrix-core windows, so the far work falls from O(N^2 d) to
+ * O(N log^2 N d) plus O(N d 2^l) window work. The results differ from
  * fft_level = 0 by rounding, bounded normwise rather than per term (about
  * log2(512 * 2^l') u times the norms of the weights and of the history
  * involved). Plans: path BLOCKED, far_prec FP64, max_batch 1, no
