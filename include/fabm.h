@@ -138,11 +138,14 @@ typedef struct {
  * O(N log^2 N d) plus O(N d 2^l) window work. The results differ from
  * fft_level = 0 by rounding, bounded normwise rather than per term (about
  * log2(512 * 2^l') u times the norms of the weights and of the history
- * involved). Plans: path BLOCKED, far_prec FP64, max_batch 1, no
- * per-component orders, not the shared grid (else UNSUPPORTED); N <= 2^24.
- * Calls: fabm_solve and batches of one; the adjoint calls of such a plan are
- * UNSUPPORTED. The workspace grows by 16 (d + 3) M bytes, M the longest
- * transform (at most 4 (N + 1) rounded up to a power of two). */
+ * involved). Plans: path BLOCKED with 256-row blocks, max_batch 1, far_prec
+ * FP64 or FP32 (the windows' arithmetic; the transforms are binary64), one
+ * order or per-component orders (one weight spectrum per component), N <=
+ * 2^24; otherwise UNSUPPORTED. Calls: fabm_solve and batches of one; the
+ * adjoint calls of such a plan are UNSUPPORTED. The workspace grows by
+ * 16 (1 + d + 2 K) M bytes at most, M the longest transform (at most
+ * 4 (N + 1) rounded up to a power of two) and K the weight table sets (d with
+ * per-component orders, else 1). */
 
 /* Plan flag: the calls of the plan pass two initial values per instance, y0
  * as [batch][2][d] (y(0), then y'(0)), which orders 1 < alpha <= 2 need

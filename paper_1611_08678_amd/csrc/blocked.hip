@@ -922,7 +922,7 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
     const bool fft = A.fft_level > 0 && fft_far_top_level(A.NB, A.fft_level) >= 0;
     if (fft) {
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_FFT_FAR, st));
-        FABM_STEP_TRY("FFT weight spectra", fft_far_prepare(A, st));
+        FABM_STEP_TRY("FFT weight spectra", fft_far_prepare(D, A, st));
         if (T) FABM_STEP_TRY("timer end", T->end(st));
     }
     for (int s = -1; s <= A.NB - 2; ++s) {

@@ -321,7 +321,8 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
             L.fbuf = off;
             off = align_up(off + 16 * (size_t)mfft * d);
             L.fspec = off;
-            off = align_up(off + 16 * (size_t)fabm::fft_far_spectra_len(L.NB, pl->desc.fft_level));
+            off = align_up(off + 16 * (size_t)fabm::fft_far_spectra_len(L.NB, pl->desc.fft_level) *
+                                     (pc ? d : 1));
         }
     } else {
         L.wlen = 0;
@@ -864,11 +865,10 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     // per-component orders: DIRECT, or BLOCKED per trajectory (FP64 or FP32 windows)
     if ((desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) && wide) return FABM_ERR_UNSUPPORTED;
     if (wide && desc->max_batch > kWideMaxCols / desc->dim) return FABM_ERR_UNSUPPORTED;
-    // sub-quadratic far history: one trajectory, FP64 windows, one order
+    // sub-quadratic far history: one BLOCKED trajectory (FP64 or FP32 windows)
     if (desc->fft_level < 0 || desc->fft_level > 15) return FABM_ERR_INVALID_ARG;
     if (desc->fft_level > 0 &&
-        (wide || desc->path != FABM_PATH_BLOCKED || desc->far_prec != FABM_FAR_FP64 ||
-         desc->max_batch != 1 || (desc->flags & FABM_PLAN_PER_COMPONENT_ORDER) ||
+        (wide || desc->path != FABM_PATH_BLOCKED || desc->max_batch != 1 ||
          desc->max_steps > ((int64_t)1 << 24)))
         return FABM_ERR_UNSUPPORTED;
 

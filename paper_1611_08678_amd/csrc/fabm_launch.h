@@ -74,10 +74,10 @@ void step_grid(int NB, int jend, int s, int *grid, int *wpw, int far_cap);
 // square after each step launch.
 int fft_far_top_level(int NB, int level);         // highest level with a square, or -1
 int64_t fft_far_max_len(int NB, int level);       // longest transform (complex elements)
-int64_t fft_far_spectra_len(int NB, int level);   // complex elements of all weight spectra
+int64_t fft_far_spectra_len(int NB, int level);   // complex elements of one table set's spectra
 int fft_far_target_end(int NB, int level, int s); // end of launch s's window targets
 bool fft_far_mask_prev(int level, int s);         // launch s's windows skip block s - 1
-hipError_t fft_far_prepare(const StepArgs &A, hipStream_t st);  // twiddles and spectra
+hipError_t fft_far_prepare(int d, const StepArgs &A, hipStream_t st);  // twiddles, spectra
 int fft_far_square_at(int NB, int level, int s);  // level of the square after launch s, or -1
 hipError_t fft_far_square(int d, const StepArgs &A, int s, hipStream_t st);
 

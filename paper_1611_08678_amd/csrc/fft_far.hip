@@ -128,10 +128,14 @@ __global__ void k_fft_gather_hist(const double *__restrict__ Fc, int64_t pitch, 
         x[p] = make_double2(p < L ? Fc[c * pitch + S0 + p] : 0.0, 0.0);
 }
 
-// v[p] = (b[off + p], a[off + p]) for p < 2L - 1 inside the tables, else zero.
+// v[p] = (b[off + p], a[off + p]) for p < 2L - 1 inside the tables, else zero;
+// one table set per blockIdx.y (per-component orders: tables 3 wlen apart,
+// spectra M apart).
 __global__ void k_fft_gather_w(const double *__restrict__ W, int64_t wlen, int64_t off,
                                int64_t L, int64_t M, double2 *v)
 {
+    W += blockIdx.y * 3 * wlen;
+    v += blockIdx.y * M;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < M;
          p += (int64_t)gridDim.x * blockDim.x) {
         const bool in = p < 2 * L - 1 && off + p < wlen;
@@ -167,11 +171,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(double2 *buf, int64_t 
 
 // Row step of row k1 = blockIdx.x of component blockIdx.y. spec == nullptr:
 // forward transform only (weight spectra). Otherwise forward transform,
-// product with the spectrum, inverse transform and the conjugate twiddle
-// w_M^(-n2 k1).
+// product with the spectrum (that of component blockIdx.y at spec_cs
+// elements apart, or one shared spectrum with spec_cs = 0), inverse transform
+// and the conjugate twiddle w_M^(-n2 k1).
 __global__ __launch_bounds__(kFftThreads) void k_fft_rows(double2 *buf, int64_t M, int M2,
                                                           int logM2,
                                                           const double2 *__restrict__ spec,
+                                                          int64_t spec_cs,
                                                           const double2 *__restrict__ tw,
                                                           int64_t Mmax)
 {
@@ -185,7 +191,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(double2 *buf, int64_t 
         for (int e = threadIdx.x; e < M2; e += blockDim.x) x[e] = sr[e];
         return;
     }
-    const double2 *w = spec + (int64_t)k1 * M2;
+    const double2 *w = spec + blockIdx.y * spec_cs + (int64_t)k1 * M2;
     for (int e = threadIdx.x; e < M2; e += blockDim.x) sr[e] = cmul(sr[e], w[e]);
     __syncthreads();
     lds_dif(sr, M2, tw, Mmax, true);
@@ -256,7 +262,7 @@ int grid_of(int64_t n) { return (int)std::min<int64_t>((n + kFftThreads - 1) / k
 // forward transform of the ncomp arrays in buf (column step, then row step
 // with spec: the product and the inverse back through the columns)
 hipError_t transform(const Shape &S, double2 *buf, int ncomp, const double2 *spec,
-                     const double2 *tw, int64_t Mmax, hipStream_t st)
+                     int64_t spec_cs, const double2 *tw, int64_t Mmax, hipStream_t st)
 {
     if (S.M1 > 1) {
         hipLaunchKernelGGL(k_fft_cols, dim3(S.M2 / S.C, ncomp), dim3(kFftThreads),
@@ -264,7 +270,8 @@ hipError_t transform(const Shape &S, double2 *buf, int ncomp, const double2 *spe
                            tw, Mmax, 0);
     }
     hipLaunchKernelGGL(k_fft_rows, dim3(S.M1, ncomp), dim3(kFftThreads),
-                       sizeof(double2) * S.M2, st, buf, S.M, S.M2, S.logM2, spec, tw, Mmax);
+                       sizeof(double2) * S.M2, st, buf, S.M, S.M2, S.logM2, spec, spec_cs, tw,
+                       Mmax);
     if (spec && S.M1 > 1) {
         hipLaunchKernelGGL(k_fft_cols, dim3(S.M2 / S.C, ncomp), dim3(kFftThreads),
                            sizeof(double2) * S.C * S.M1, st, buf, S.M, S.M1, S.logM1, S.M2, S.C,
@@ -295,6 +302,11 @@ int64_t fft_far_spectra_len(int NB, int level)
     return n;
 }
 
+namespace {
+// weight table sets: one per component with per-component orders
+int table_sets(const StepArgs &A, int d) { return A.cmeta ? d : 1; }
+}  // namespace
+
 int fft_far_target_end(int NB, int level, int s)
 {
     if (level <= 0) return NB;
@@ -307,8 +319,9 @@ bool fft_far_mask_prev(int level, int s)
     return level > 0 && s > 0 && (s & ((1 << level) - 1)) == 0;
 }
 
-hipError_t fft_far_prepare(const StepArgs &A, hipStream_t st)
+hipError_t fft_far_prepare(int d, const StepArgs &A, hipStream_t st)
 {
+    const int K = table_sets(A, d);
     const int top = fft_far_top_level(A.NB, A.fft_level);
     if (top < 0) return hipSuccess;
     const int64_t Mmax = shape_of(top).M;
@@ -318,11 +331,11 @@ hipError_t fft_far_prepare(const StepArgs &A, hipStream_t st)
     for (int l = A.fft_level; l <= top; ++l) {
         const Shape S = shape_of(l);
         const int64_t L = (int64_t)kRows << l;
-        hipLaunchKernelGGL(k_fft_gather_w, dim3(grid_of(S.M)), dim3(kFftThreads), 0, st, A.W,
+        hipLaunchKernelGGL(k_fft_gather_w, dim3(grid_of(S.M), K), dim3(kFftThreads), 0, st, A.W,
                            A.wlen, (int64_t)3 * kRows, L, S.M, spec);
-        const hipError_t e = transform(S, spec, 1, nullptr, A.fft_tw, Mmax, st);
+        const hipError_t e = transform(S, spec, K, nullptr, 0, A.fft_tw, Mmax, st);
         if (e != hipSuccess) return e;
-        spec += S.M;
+        spec += S.M * K;
     }
     return hipGetLastError();
 }
@@ -348,11 +361,12 @@ hipError_t fft_far_square_t(const StepArgs &A, int s, hipStream_t st)
     const int64_t Mmax = shape_of(top).M;
     const int64_t L = (int64_t)kRows << l;
     const int64_t S0 = 2 * j * L;
+    const int K = table_sets(A, D);
     const double2 *spec = A.fft_spec;
-    for (int q = A.fft_level; q < l; ++q) spec += shape_of(q).M;
+    for (int q = A.fft_level; q < l; ++q) spec += shape_of(q).M * K;
     hipLaunchKernelGGL(k_fft_gather_hist, dim3(grid_of(S.M), D), dim3(kFftThreads), 0, st, A.Fc,
                        (int64_t)A.NB * kRows, S0, L, S.M, A.fft_buf);
-    const hipError_t e = transform(S, A.fft_buf, D, spec, A.fft_tw, Mmax, st);
+    const hipError_t e = transform(S, A.fft_buf, D, spec, K > 1 ? S.M : 0, A.fft_tw, Mmax, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fft_scatter<D>), dim3(grid_of(L)), dim3(kFftThreads), 0, st, A.fft_buf,
                        S.M, S.logM, L, S0 + L + 3 * kRows, A.NB, A.acc, S0 == 0 ? 1 : 0);

@@ -241,15 +241,16 @@ def test_per_component_order_rules(fabm):
 
 def test_plan_fft_far_rules(fabm):
     """fft_level (sub-quadratic far history): 0 off, 1..15 valid; only for one
-    BLOCKED trajectory with FP64 windows and one order; the workspace grows by
-    the twiddles, one square's transforms and the weight spectra."""
+    BLOCKED trajectory (FP64 or FP32 windows, one order or one per component);
+    the workspace grows by the twiddles, one square's transforms and the
+    weight spectra (one set per component with per-component orders)."""
     for lv in (-1, 16):
         with pytest.raises(fabm.FabmError) as e:
             fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, 50000, fft_level=lv)
         assert e.value.code == 1
-    for kw in (dict(path="auto"), dict(path="direct"), dict(far_prec="fp32"),
-               dict(max_batch=2), dict(per_component_order=True),
-               dict(system="linear", dim=8), dict(max_steps=(1 << 24) + 1)):
+    for kw in (dict(path="auto"), dict(path="direct"), dict(far_prec="fp16x2"),
+               dict(max_batch=2), dict(system="linear", dim=8),
+               dict(max_steps=(1 << 24) + 1)):
         a = dict(system="vdp", dim=2, path="blocked", far_prec="fp64", max_batch=1,
                  max_steps=50000)
         a.update(kw)
@@ -265,3 +266,9 @@ def test_plan_fft_far_rules(fabm):
     spectra = sum(512 << lv for lv in range(3, 8))
     assert 16 * (M + 2 * M + spectra) <= grow <= 16 * (M + 2 * M + spectra) + 3 * 4096
     assert fabm.fabm_workspace_size(p9, [N]) == fabm.fabm_workspace_size(p0, [N])
+    q0 = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, N, per_component_order=True)
+    q3 = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, N, per_component_order=True,
+                        fft_level=3)
+    grow_pc = fabm.fabm_workspace_size(q3, [N]) - fabm.fabm_workspace_size(q0, [N])
+    assert 16 * (M + 2 * M + 2 * spectra) <= grow_pc <= 16 * (M + 2 * M + 2 * spectra) + 3 * 4096
+    fabm.fabm_plan("vdp", 2, "blocked", "fp32", 1, N, fft_level=3)  # FP32 windows: accepted

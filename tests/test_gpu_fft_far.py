@@ -182,3 +182,30 @@ def test_fft_far_hindmarsh_rose_longest_table_size(F, orc):
         fft = 8.0 * log2M * u * h ** a * wn * fn
         tol = 10.0 * np.sqrt(t) * u * mag + 4 * u * np.abs(yt) + fft
         assert np.all(np.abs(yy[t] - yt) <= tol), (t, yy[t], yt, mag, fft)
+
+
+def test_fft_far_with_fp32_windows(F, orc):
+    """FP32 windows inside each group, binary64 transforms for the squares:
+    the FP32 path's bound (the far sums of the windows rounded to binary32)."""
+    from tests.test_gpu_blocked import FP32_BOUND
+    N, th, y0 = 1 << 15, [1.3], [0.8, -0.4]
+    ref, _, _, rst = orc.solve(3, th, 0.9, 0.01, N, y0)
+    y, st = F.solve("vdp", th, 0.9, 0.01, N, y0, path="blocked", far_prec="fp32", fft_level=2)
+    err = relerr(_to_np(y), ref)
+    assert int(st.item()) == rst == 0
+    assert 1e-12 < err <= FP32_BOUND, err
+
+
+@pytest.mark.parametrize("alphas,slope", [([0.75, 0.95], False), ([0.85, 1.5], True)])
+def test_fft_far_per_component_orders(F, orc, alphas, slope):
+    """One weight spectrum per component (non-commensurate orders), with y'(0)
+    for the component above order one."""
+    N, th, h = 20000, [1.1], 0.005
+    init = np.array([[0.5, -0.3], [0.2, 0.4]]) if slope else np.array([0.5, -0.3])
+    ref, _, _, rst = orc.solve_orders(orc.VDP, th, alphas, h, N, init)
+    plan = F.fabm_plan("vdp", 2, "blocked", "fp64", 1, N, initial_slope=slope,
+                       per_component_order=True, fft_level=2)
+    y, off, st = F.solve_batch("vdp", np.reshape(th, (1, -1)), np.reshape(alphas, (1, -1)),
+                               [h], [N], init[None], plan=plan)
+    assert int(st.cpu().numpy()[0]) == rst == 0
+    assert relerr(_to_np(y), ref) <= 1e-11
