@@ -209,3 +209,35 @@ def test_fft_far_per_component_orders(F, orc, alphas, slope):
                                [h], [N], init[None], plan=plan)
     assert int(st.cpu().numpy()[0]) == rst == 0
     assert relerr(_to_np(y), ref) <= 1e-11
+
+
+def test_fft_far_graph_replays_match_eager(F):
+    """The FFT squares are ordinary launches on the call's stream: a captured
+    solve of a plan with fft_level replays (with new initial values each time,
+    and eager solves in between) bit for bit like the eager call."""
+    import torch
+    N, d = 1 << 15, 2
+    th = np.array([[1.3]])
+    Ns = np.array([N], dtype=np.int64)
+    gplan = F.fabm_plan("vdp", d, "blocked", "fp64", 1, N, fft_level=2)
+    eplan = F.fabm_plan("vdp", d, "blocked", "fp64", 1, N, fft_level=2)
+    ws = F._workspace(F.fabm_workspace_size(gplan, Ns))
+    y0s = np.array([[0.4, -0.7]])
+    y0 = torch.tensor(y0s, device="cuda")
+    thd = torch.tensor(th, device="cuda")
+    y = torch.full((N + 1, d), -7.0, dtype=torch.float64, device="cuda")
+    st = torch.full((1,), -3, dtype=torch.int64, device="cuda")
+    g = F.fabm_graph_solve_batch(gplan, ws, [0.9], [0.01], Ns, y0, thd, [0], y, st)
+    torch.cuda.synchronize()
+    assert torch.all(y == -7.0)
+    for rep in range(3):
+        y0.copy_(torch.tensor(y0s * (1.0 + 0.05 * rep), device="cuda"))
+        g.launch()
+        torch.cuda.synchronize()
+        got, gst = y.clone(), st.clone()
+        ref, _, rst = F.solve_batch("vdp", thd, [0.9], [0.01], Ns, y0, plan=eplan)
+        torch.cuda.synchronize()
+        assert torch.equal(gst, rst) and int(rst.item()) == 0, rep
+        assert torch.equal(got, ref), rep
+    del g
+    torch.cuda.synchronize()
