@@ -336,13 +336,13 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
                 ycb[i] = readlane_f64(cc[i], ln);
                 fprev[i] = f[i];
             }
-            if (lane == 0) {
+            // every lane holds the same row values, so all lanes store them
+            // (no exec-mask change on the row's path)
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    sF[t * D + i] = f[i];
-                    sY[t * D + i] = y[i];
-                    if constexpr (YPOUT) sYP[t * D + i] = yp[i];
-                }
+            for (int i = 0; i < D; ++i) {
+                sF[t * D + i] = f[i];
+                sY[t * D + i] = y[i];
+                if constexpr (YPOUT) sYP[t * D + i] = yp[i];
             }
 #pragma unroll
             for (int q = 0; q < K; ++q) {
