@@ -147,6 +147,19 @@ typedef struct {
  * 4 (N + 1) rounded up to a power of two) and K the weight table sets (d with
  * per-component orders, else 1). */
 
+/* Schedule of the sub-quadratic far history (host only, for inspection and
+ * tests): for a trajectory of NB blocks of 256 rows, fft_level `level` and
+ * step launch s (-1 .. NB - 2), *jend is the end (exclusive) of the target
+ * blocks launch s adds matrix-core far windows to, *skip_prev is 1 when those
+ * windows leave out the columns of source block s - 1, and *square is the
+ * level of the FFT square enqueued right after launch s (its sources are the
+ * 2^square blocks ending at s + 1, its targets the 2^square blocks from s + 5
+ * on, clipped to NB), or -1. With level 0, or no square at all for this NB,
+ * every launch reads jend = NB, skip_prev = 0, square = -1. INVALID_ARG for
+ * null pointers, NB < 1, s outside -1 .. NB - 2 or level outside 0..15. */
+fabm_status fabm_fft_far_schedule(int32_t NB, int32_t level, int32_t s, int32_t *jend,
+                                  int32_t *skip_prev, int32_t *square);
+
 /* Plan flag: the calls of the plan pass two initial values per instance, y0
  * as [batch][2][d] (y(0), then y'(0)), which orders 1 < alpha <= 2 need
  * (eq. (1)); instances with alpha <= 1 ignore their y'(0) row. The adjoint

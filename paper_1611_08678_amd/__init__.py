@@ -35,7 +35,7 @@ EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan"
            "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
            "fabm_plan_kernel_times", "fabm_adjoint", "fabm_adjoint_workspace_size",
            "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy", "fabm_tune",
-           "fabm_adjoint_forward", "fabm_adjoint_reverse")
+           "fabm_adjoint_forward", "fabm_adjoint_reverse", "fabm_fft_far_schedule")
 KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint",
                   "wide_far", "wide_band", "fft_far")
 
@@ -98,6 +98,9 @@ def load():
     L.fabm_solve_batch.restype = C.c_int
     L.fabm_weights.argtypes = [C.c_double, C.c_int64, _VP, _VP, _VP, _VP]
     L.fabm_weights.restype = C.c_int
+    _IP = C.POINTER(C.c_int32)
+    L.fabm_fft_far_schedule.argtypes = [C.c_int32, C.c_int32, C.c_int32, _IP, _IP, _IP]
+    L.fabm_fft_far_schedule.restype = C.c_int
     L.fabm_history_sums.argtypes = [C.c_double, C.c_int64, C.c_int32, _VP, _VP, _VP, C.c_int,
                                     C.c_int, _VP, C.c_size_t, _VP]
     L.fabm_history_sums.restype = C.c_int
@@ -368,6 +371,14 @@ def fabm_plan_kernel_times(plan: Plan):
     cnt = (C.c_int64 * n)()
     _check(load().fabm_plan_kernel_times(plan.handle, sec, cnt), "fabm_plan_kernel_times")
     return {k: (float(sec[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def fabm_fft_far_schedule(NB: int, level: int, s: int):
+    """(jend, skip_prev, square) of step launch s (host only)."""
+    j, k, q = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().fabm_fft_far_schedule(int(NB), int(level), int(s), C.byref(j), C.byref(k),
+                                        C.byref(q)), "fabm_fft_far_schedule")
+    return int(j.value), bool(k.value), int(q.value)
 
 
 def fabm_weights(alpha: float, n: int, b, a, c, stream=None):

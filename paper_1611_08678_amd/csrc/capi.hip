@@ -1205,6 +1205,20 @@ size_t fabm_history_workspace_size(int64_t N, int32_t dim)
     return align_up(sizeof(double) * 3 * (size_t)N);
 }
 
+fabm_status fabm_fft_far_schedule(int32_t NB, int32_t level, int32_t s, int32_t *jend,
+                                  int32_t *skip_prev, int32_t *square)
+{
+    if (!jend || !skip_prev || !square || NB < 1 || s < -1 || s > NB - 2 || level < 0 ||
+        level > 15)
+        return FABM_ERR_INVALID_ARG;
+    // the same decisions as the step pipeline's enqueue
+    const bool fft = level > 0 && fabm::fft_far_top_level(NB, level) >= 0;
+    *jend = fft ? fabm::fft_far_target_end(NB, level, s) : NB;
+    *skip_prev = fft && fabm::fft_far_mask_prev(level, s) ? 1 : 0;
+    *square = fft ? fabm::fft_far_square_at(NB, level, s) : -1;
+    return FABM_OK;
+}
+
 fabm_status fabm_history_sums(double alpha, int64_t N, int32_t dim, const double *f, double *P,
                               double *C, fabm_path path, fabm_far_prec far_prec,
                               void *workspace, size_t workspace_bytes, hipStream_t stream)

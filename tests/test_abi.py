@@ -272,3 +272,59 @@ def test_plan_fft_far_rules(fabm):
     grow_pc = fabm.fabm_workspace_size(q3, [N]) - fabm.fabm_workspace_size(q0, [N])
     assert 16 * (M + 2 * M + 2 * spectra) <= grow_pc <= 16 * (M + 2 * M + 2 * spectra) + 3 * 4096
     fabm.fabm_plan("vdp", 2, "blocked", "fp32", 1, N, fft_level=3)  # FP32 windows: accepted
+
+
+def _far_cover_from_schedule(fabm, NB, level):
+    """Column-level cover of the far region by the library's schedule: matrix-core
+    window of launch s for target J (target column rho, lags 16 s + rho - u,
+    u < 16; columns of block s - 1 dropped when skip_prev) and, after launch s,
+    the square of level l = square: sources blocks (s + 2 - 2^l) .. s + 1, targets
+    s + 5 .. s + 4 + 2^l (< NB). Returns the first-writer order check too."""
+    seen, written, ok_first = {}, set(), True
+    for s in range(-1, NB - 1):
+        jend, skip_prev, square = fabm.fabm_fft_far_schedule(NB, level, s)
+        if 0 <= s and s + 2 <= NB - 1:  # near part of target s + 2
+            ok_first &= (s == 0) == (s + 2 not in written)
+            written.add(s + 2)
+        if s >= 0:
+            for J in range(s + 3, jend):
+                ok_first &= (s == 0) == (J not in written)
+                written.add(J)
+                for rho in range(16):
+                    for u in range(16):
+                        kap = 16 * s + rho - u
+                        if kap >= 0 and not (skip_prev and kap < 16 * s):
+                            key = (J, rho, kap)
+                            seen[key] = seen.get(key, 0) + 1
+        if square >= 0:
+            n = 1 << square
+            assert (s + 2) % n == 0 and ((s + 2) // n) % 2 == 1
+            first = s + 2 - n == 0
+            for J in range(s + 5, min(NB, s + 5 + n)):
+                ok_first &= first == (J not in written)
+                written.add(J)
+                for rho in range(16):
+                    for K in range(s + 2 - n, s + 2):
+                        for x in range(16):
+                            key = (J, rho, 16 * K + x)
+                            seen[key] = seen.get(key, 0) + 1
+    return seen, ok_first
+
+
+@pytest.mark.parametrize("NB", [5, 6, 7, 9, 12, 17, 21, 36, 69])
+def test_fft_far_schedule_covers_far_region_once(fabm, NB):
+    """The far part of target column rho of block J is every source column up
+    to 16 (J - 3) + rho; windows and squares must add each one exactly once,
+    after it is formed, and the first addition to a target must be the one
+    that overwrites (a window of launch 0, or a square whose sources start at
+    block 0)."""
+    need = {(J, rho, kap) for J in range(3, NB) for rho in range(16)
+            for kap in range(0, 16 * (J - 3) + rho + 1)}
+    for level in range(0, 6):
+        seen, ok_first = _far_cover_from_schedule(fabm, NB, level)
+        assert set(seen) == need and all(v == 1 for v in seen.values()), (NB, level)
+        assert ok_first, (NB, level)
+    with pytest.raises(fabm.FabmError):
+        fabm.fabm_fft_far_schedule(NB, 16, 0)
+    with pytest.raises(fabm.FabmError):
+        fabm.fabm_fft_far_schedule(NB, 1, NB - 1)
