@@ -27,12 +27,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
 # reference copy kernel (profiles/k_step_chen_N2p20_pmc.md), valid only for
 # the kernel source it was measured on (sha256 prefix of blocked.hip).
-MEASURED_TRAFFIC = {"k_step": (59.14e6, "85c5b6a07003f9f8")}
+MEASURED_TRAFFIC = {"k_step": (59.12e6, "66c96f50e43922b2")}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense binary16 matrix rate
 HBM_PEAK_GBPS = 8000.0
-BAND_CYCLES_PER_ROW = 618  # band-dominated last launches of the trace (profiles/k_step_chen_N2p20_kernel_stats.md)
+BAND_CYCLES_PER_ROW = 587  # band-dominated last launches of the trace (profiles/k_step_chen_N2p20_kernel_stats.md)
 CLOCK_HZ = 2.4e9
 
 

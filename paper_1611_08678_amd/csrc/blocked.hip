@@ -303,51 +303,60 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         bw[k] = sbh[k * kBlk + (lc0 > 0 ? lc0 : 0)];
         aw[k] = sah[k * kBlk + (lc0 > 0 ? lc0 : 0)];
     }
+    // one row of the walk; full groups of kPublishEvery rows run without the
+    // per-row range check
+    auto step_row = [&](const int t) __attribute__((always_inline)) {
+        const int lagn = row - t - 1;
+        double bwn[K], awn[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            bwn[q] = sbh[q * kBlk + (lagn > 0 ? lagn : 0)];
+            awn[q] = sah[q * kBlk + (lagn > 0 ? lagn : 0)];
+        }
+        const double tt = (double)(t0 + t) * m.h;
+        double yp[D], fp[D], y[D], f[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) yp[i] = fma(hb0[PC ? i : 0], fprev[i], ypb[i]);
+        rhs<SYS, D>(tt, yp, fp, th);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            y[i] = fma(hig2[PC ? i : 0], fp[i], fma(ha0[PC ? i : 0], fprev[i], ycb[i]));
+        rhs<SYS, D>(tt, y, f, th);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            pc[i] = fma(bw[PC ? i : 0], fprev[i], pc[i]);
+            cc[i] = fma(aw[PC ? i : 0], fprev[i], cc[i]);
+        }
+        const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            ypb[i] = readlane_f64(pc[i], ln);
+            ycb[i] = readlane_f64(cc[i], ln);
+            fprev[i] = f[i];
+        }
+        // every lane holds the same row values, so all lanes store them
+        // (no exec-mask change on the row's path)
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            sF[t * D + i] = f[i];
+            sY[t * D + i] = y[i];
+            if constexpr (YPOUT) sYP[t * D + i] = yp[i];
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            bw[q] = bwn[q];
+            aw[q] = awn[q];
+        }
+            };
     for (int g0 = first & ~(kPublishEvery - 1); go && g0 < hi; g0 += kPublishEvery) {
+        if (g0 >= first && g0 + kPublishEvery <= hi) {
 #pragma unroll
-        for (int k = 0; k < kPublishEvery; ++k) {
-            const int t = g0 + k;
-            if (t < first || t >= hi) continue;
-            const int lagn = row - t - 1;
-            double bwn[K], awn[K];
+            for (int k = 0; k < kPublishEvery; ++k) step_row(g0 + k);
+        } else {
 #pragma unroll
-            for (int q = 0; q < K; ++q) {
-                bwn[q] = sbh[q * kBlk + (lagn > 0 ? lagn : 0)];
-                awn[q] = sah[q * kBlk + (lagn > 0 ? lagn : 0)];
-            }
-            const double tt = (double)(t0 + t) * m.h;
-            double yp[D], fp[D], y[D], f[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) yp[i] = fma(hb0[PC ? i : 0], fprev[i], ypb[i]);
-            rhs<SYS, D>(tt, yp, fp, th);
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-                y[i] = fma(hig2[PC ? i : 0], fp[i], fma(ha0[PC ? i : 0], fprev[i], ycb[i]));
-            rhs<SYS, D>(tt, y, f, th);
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                pc[i] = fma(bw[PC ? i : 0], fprev[i], pc[i]);
-                cc[i] = fma(aw[PC ? i : 0], fprev[i], cc[i]);
-            }
-            const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                ypb[i] = readlane_f64(pc[i], ln);
-                ycb[i] = readlane_f64(cc[i], ln);
-                fprev[i] = f[i];
-            }
-            // every lane holds the same row values, so all lanes store them
-            // (no exec-mask change on the row's path)
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                sF[t * D + i] = f[i];
-                sY[t * D + i] = y[i];
-                if constexpr (YPOUT) sYP[t * D + i] = yp[i];
-            }
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                bw[q] = bwn[q];
-                aw[q] = awn[q];
+            for (int k = 0; k < kPublishEvery; ++k) {
+                const int t = g0 + k;
+                if (t >= first && t < hi) step_row(t);
             }
         }
         const int tl = g0 + kPublishEvery < hi ? g0 + kPublishEvery : hi;  // rows formed: < tl
