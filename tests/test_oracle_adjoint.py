@@ -94,6 +94,10 @@ def _torch_forward(torch, sid, th, y0, alpha, h, N):
         if sid == 4:
             a, b, c = th[0], th[1], th[2]
             return torch.stack([y[2] + (y[1] - a) * y[0], 1 - b * y[1] - y[0] ** 2, -y[0] - c * y[2]])
+        if sid == 5:
+            a, b, c, dd, r, s, xr, I = (th[j] for j in range(8))
+            return torch.stack([y[1] - a * y[0] ** 3 + b * y[0] ** 2 - y[2] + I,
+                                c - dd * y[0] ** 2 - y[1], r * (s * (y[0] - xr) - y[2])])
         d = y.shape[0]
         A = th[: d * d].reshape(d, d)
         return A @ y + th[d * d: d * d + d] + th[d * d + d:] * t
@@ -114,7 +118,7 @@ def _torch_forward(torch, sid, th, y0, alpha, h, N):
     return torch.stack(ys)
 
 
-@pytest.mark.parametrize("name", ["vdp", "chen", "linear"])
+@pytest.mark.parametrize("name", ["vdp", "chen", "rossler", "financial", "hindmarsh_rose", "linear"])
 def test_adjoint_vs_torch_autograd(orc, name):
     torch = pytest.importorskip("torch")
     sid, th, y0, alpha, h, N = _theta(name)
