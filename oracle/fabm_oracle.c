@@ -605,6 +605,45 @@ void oracle_history_sums(double alpha, int64_t N, int d, const double *f, double
     free(cc);
 }
 
+/* The same sums for selected targets only: rows[j] (1 <= rows[j] <= N) is a  */
+/* target t, and row j of P, C, Pabs, Cabs receives its P_t, C_t and          */
+/* magnitude sums. Weights come from oracle_weights, the sums run over the    */
+/* whole history in ascending source order exactly as above. OpenMP over the  */
+/* selected targets.                                                          */
+void oracle_history_sums_rows(double alpha, int64_t N, int d, const double *f, int64_t n_rows,
+                              const int64_t *rows, double *P, double *C, double *Pabs,
+                              double *Cabs)
+{
+    double *bb = malloc(sizeof(double) * (N + 1));
+    double *aa = malloc(sizeof(double) * (N + 1));
+    double *cc = malloc(sizeof(double) * (N + 1));
+    oracle_weights(alpha, N, bb, aa, cc);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n_rows; ++j) {
+        const int64_t t = rows[j];
+        for (int i = 0; i < d; ++i) {
+            long double sp = 0, sc = (long double)cc[t - 1] * f[i];
+            long double ap = 0, ac = fabsl((long double)cc[t - 1] * f[i]);
+            for (int64_t k = 0; k < t; ++k) {
+                long double fk = f[k * d + i];
+                sp += bb[t - 1 - k] * fk;
+                ap += fabsl(bb[t - 1 - k] * fk);
+                if (k >= 1) {
+                    sc += aa[t - 1 - k] * fk;
+                    ac += fabsl(aa[t - 1 - k] * fk);
+                }
+            }
+            P[j * d + i] = (double)sp;
+            C[j * d + i] = (double)sc;
+            if (Pabs) Pabs[j * d + i] = (double)ap;
+            if (Cabs) Cabs[j * d + i] = (double)ac;
+        }
+    }
+    free(bb);
+    free(aa);
+    free(cc);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Discrete adjoint of the PECE scheme above (reverse mode, derived by hand  */
 /* from the forward recursion). For L = sum_{n=0}^{N} <g_n, y_n>:            */

@@ -60,6 +60,8 @@ def lib():
                                          _I64,
                                          _D, _D, _I64, _D, _D, _D, _I64]
         L.oracle_history_sums.argtypes = [C.c_double, C.c_int64, C.c_int, _D, _D, _D, _D, _D]
+        L.oracle_history_sums_rows.argtypes = [C.c_double, C.c_int64, C.c_int, _D, C.c_int64,
+                                               _I64, _D, _D, _D, _D]
         L.oracle_solve_orders.argtypes = [C.c_int, C.c_int, _D, _D, C.c_double, C.c_int64, _D,
                                           C.c_int, _D, _D, _D]
         L.oracle_solve_orders.restype = C.c_int64
@@ -299,6 +301,21 @@ def history_sums(alpha: float, f_hist):
     N, d = f.shape
     P, Cc, Pa, Ca = (np.empty((N, d)) for _ in range(4))
     lib().oracle_history_sums(float(alpha), int(N), int(d), _p(f), _p(P), _p(Cc), _p(Pa), _p(Ca))
+    return P, Cc, Pa, Ca
+
+
+def history_sums_rows(alpha: float, f_hist, rows):
+    """history_sums for the targets in `rows` only (1 <= t <= N, N = len(f_hist)).
+    Returns (P, C, Pabs, Cabs), each [len(rows), d]."""
+    f = _f64(f_hist)
+    if f.ndim == 1:
+        f = f[:, None]
+    N, d = f.shape
+    r = np.ascontiguousarray(rows, dtype=np.int64).ravel()
+    assert r.size == 0 or (r.min() >= 1 and r.max() <= N)
+    P, Cc, Pa, Ca = (np.empty((r.size, d)) for _ in range(4))
+    lib().oracle_history_sums_rows(float(alpha), int(N), int(d), _p(f), int(r.size),
+                                   r.ctypes.data_as(_I64), _p(P), _p(Cc), _p(Pa), _p(Ca))
     return P, Cc, Pa, Ca
 
 

@@ -201,3 +201,14 @@ def test_history_sums_random_history_definition(orc, alpha):
         assert np.all(np.abs(P[t - 1] - p) <= 1e-14 * pa + 1e-300), t
         assert np.all(np.abs(C[t - 1] - q) <= 1e-14 * Ca[t - 1] + 1e-300), t
         assert np.allclose(Pa[t - 1], pa, rtol=1e-13)
+
+
+def test_history_sums_rows_are_the_full_sums(orc):
+    """The row-subset form returns exactly the rows of the full form."""
+    rng = np.random.default_rng(29)
+    f = rng.standard_normal((2500, 2)) * [3.0, 0.5]
+    full = orc.history_sums(0.7, f)
+    rows = np.array([1, 2, 255, 256, 257, 1024, 2499, 2500])
+    part = orc.history_sums_rows(0.7, f, rows)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[rows - 1], b)
