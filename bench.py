@@ -1,15 +1,22 @@
 """Benchmark of the fractional ABM hot path on one MI355X.
 
-Workload: the single fractional Chen trajectory (a, b, c) = (35, 3, 28),
-alpha = 0.95, y0 = (-9, -5, 14), h = 0.001, N = 2^20 steps (d = 3). One
-bench "step" is one complete solve (weight generation, history contraction,
-predictor/corrector updates, output) with inputs already in device memory.
+Headline workload: the single fractional Chen trajectory (a, b, c) =
+(35, 3, 28), alpha = 0.95, y0 = (-9, -5, 14), h = 0.001, N = 2^20 steps
+(d = 3). One bench "step" is one complete solve (weight generation, history
+contraction, predictor/corrector updates, output) with inputs already in
+device memory.
 
 Prints one JSON line: steps*states/s of the headline (BLOCKED) path as
 `value`, history GFLOP/s (2 d N (N+1) flops per trajectory), the per-path
-breakdown (DIRECT vs BLOCKED), the roofline of the dominant kernel from HIP
-events recorded by the library on the kernel's own stream, and the CPU oracle
-timed on a bounded sample of the same trajectory.
+breakdown (DIRECT vs BLOCKED), the roofline of the dominant kernel (average
+launch time from the un-instrumented timed solves, HIP events on the stream
+the kernels run on), the CPU oracle timed on bounded samples (one thread on
+the Chen trajectory; all host cores on a sample of the Rossler batch), and,
+under "configs", every other workload of the benchmark set measured the same
+way: the scalar linear test equation, the Rossler batch (FP32 and FP64 far
+windows), the linear d = 64 batch (FP64, FP32 and split-FP16 far tiles) and
+the Van der Pol forward + adjoint pass, each with its error against the FP64
+oracle.
 """
 from __future__ import annotations
 
@@ -32,8 +39,6 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense binary16 matrix rate
 HBM_PEAK_GBPS = 8000.0
-BAND_CYCLES_PER_ROW = 587  # band-dominated last launches of the trace (profiles/k_step_chen_N2p20_kernel_stats.md)
-CLOCK_HZ = 2.4e9
 
 
 def parse():
@@ -79,6 +84,12 @@ def parse():
                          "above by FFT convolution (sub-quadratic variant; 0 = off)")
     ap.add_argument("--sweep-N", default=None,
                     help="hr_table2: comma list of step counts (default: all of the table's)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="chen: skip the other workloads of the benchmark set")
+    ap.add_argument("--config-steps", type=int, default=2,
+                    help="chen: timed solves of each additional workload")
+    ap.add_argument("--config-warmup", type=int, default=1,
+                    help="chen: untimed solves before each additional workload")
     ap.add_argument("--far-prec", default=None, choices=["fp64", "fp32", "fp16x2"],
                     help="far-window arithmetic (default: fp64; rossler_batch: fp32; "
                          "fp16x2 only for linear64_batch)")
@@ -158,71 +169,92 @@ def measured_traffic(kernel: str):
     return val if cur == sha else None
 
 
-def roofline(kt: dict, N: int, d: int, fft_level: int = 0):
-    """Roofline object of the dominant kernel of the headline path, from the
-    library's per-launch HIP events (recorded on the kernel's own stream).
-    With the FFT variant the flops are direct-equivalent: the 2 d N (N + 1) of
-    the plain sums, of which the variant performs O(N log^2 N)."""
+def roofline(kt: dict, N: int, d: int, fft_level: int = 0, solve_s: float = None):
+    """Roofline object of the dominant kernel of the headline path. The
+    average launch time is the un-instrumented timed solve (HIP events on the
+    stream the kernels run on) less the other kernels' instrumented time,
+    over the launch count; the instrumented per-launch average (an event pair
+    around every launch) is reported beside it. With the FFT variant the flops
+    are direct-equivalent: the 2 d N (N + 1) of the plain sums, of which the
+    variant performs O(N log^2 N)."""
     if not kt:
         return None
     dom = max(kt, key=lambda k: kt[k][0])
     secs, launches = kt[dom]
+    other = sum(v[0] for k, v in kt.items() if k != dom)
+    run = solve_s - other if solve_s is not None and solve_s > other else secs
     flops = 2.0 * d * N * (N + 1)  # algorithmic history flops of one solve
-    if dom == "blocked_step" and fft_level > 0:
-        band_floor = N * BAND_CYCLES_PER_ROW / CLOCK_HZ
-        fsecs, fl = kt.get("fft_far", (0.0, 0))
-        ach = flops / secs / 1e12
-        return dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=None, kernel="k_step",
-                    flops_basis="direct-equivalent 2 d N (N + 1) (sub-quadratic variant)",
-                    launches=launches, avg_launch_s=secs / launches,
-                    fft_far=dict(seconds=fsecs, launches=fl),
-                    sequential_floor=dict(s=band_floor, frac=band_floor / (secs + fsecs),
-                                          basis=f"N rows x {BAND_CYCLES_PER_ROW} cycles per row "
-                                                f"of the band walk at {CLOCK_HZ / 1e9:.1f} GHz"))
+    base = dict(launches=launches, avg_launch_s=run / launches,
+                avg_launch_s_instrumented=secs / launches,
+                launch_time_basis="timed solves (no per-launch events) minus the other "
+                                  "kernels' instrumented time, over the launches")
     if dom == "blocked_step":
         # every history flop of the BLOCKED path is done inside the step
         # kernels (MFMA near/far windows plus the sequential band)
-        ach = flops / secs / 1e12
-        # the band forms one row after another: N rows at the walk's measured
-        # cycles per row (2.4 GHz) bound the solve from below whatever the
-        # matrix cores do
-        band_floor = N * BAND_CYCLES_PER_ROW / CLOCK_HZ
-        return dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_MFMA_PEAK_TFLOPS, traffic=measured_traffic("k_step"),
-                    kernel="k_step",
-                    launches=launches, avg_launch_s=secs / launches,
-                    algorithmic_flops_per_launch=flops / launches,
-                    sequential_floor=dict(s=band_floor, frac=band_floor / secs,
-                                          basis=f"N rows x {BAND_CYCLES_PER_ROW} cycles per row "
-                                                f"of the band walk at {CLOCK_HZ / 1e9:.1f} GHz"))
+        ach = flops / run / 1e12
+        out = dict(bound="mfma", achieved=ach, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                   frac=ach / FP64_MFMA_PEAK_TFLOPS, kernel="k_step",
+                   algorithmic_flops_per_launch=flops / launches, **base)
+        if fft_level > 0:
+            out["traffic"] = None
+            out["flops_basis"] = "direct-equivalent 2 d N (N + 1) (sub-quadratic variant)"
+            out["fft_far"] = dict(zip(("seconds", "launches"), kt.get("fft_far", (0.0, 0))))
+        else:
+            out["traffic"] = measured_traffic("k_step")
+        return out
     if dom == "direct_grid":
         alg_bytes = 4.0 * N * (N + 1) * (d + 2)  # sum_t 8 t (d + 2): history row + two weights
-        ach = alg_bytes / secs / 1e9
+        ach = alg_bytes / run / 1e9
         return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=ach / HBM_PEAK_GBS, traffic=None, kernel="k_direct_grid",
-                    launches=launches, avg_launch_s=secs / launches,
-                    algorithmic_bytes_per_launch=alg_bytes / launches)
+                    algorithmic_bytes_per_launch=alg_bytes / launches, **base)
     return dict(bound="unknown", kernel=dom, seconds=secs)
 
 
-def bench_batch(F, W, args):
-    """Batched BLOCKED solve of a batch workload: Rossler (4096 instances,
-    N uniform in [2^14, 2^17], per-instance alpha, FP32 far windows), the
-    Van der Pol forward pass (1024 instances, N = 2^15), or the linear d = 64
-    batch (512 instances sharing alpha = 0.8, h = 0.01, N = 2^16: the
-    shared-grid form, far tiles FP64, FP32 or FP16X2)."""
+def _timed(call, steps: int, warmup: int, label: str):
+    """Run `call` warmup times untimed, then `steps` times between HIP events on
+    torch's current stream (the stream the library launches on)."""
+    import torch
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record(stream)
+        call()
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) / 1e3 for a, b in evs]
+    print(f"# {label}: solve times {['%.4f' % t for t in per]} s", file=sys.stderr, flush=True)
+    return per
+
+
+def bench_batch(F, W, args, workload=None, prec=None, steps=None, warmup=None, ref_y=None,
+                keep_y=False):
+    """Batched solve of a batch workload: Rossler (4096 instances, N uniform in
+    [2^14, 2^17], per-instance alpha, FP32 far windows by default), the Van der
+    Pol forward pass (1024 instances, N = 2^15), or the linear d = 64 batch
+    (512 instances sharing alpha = 0.8, h = 0.01, N = 2^16: the shared-grid
+    form, far tiles FP64, FP32 or FP16X2). Returns the result dict; with
+    `ref_y` (device rows of the same batch in FP64) the normwise error of
+    every instance against it is added; with `keep_y` the rows are returned
+    under "_y"."""
     import numpy as np
     import torch
+    workload = workload or args.workload
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     w = {"rossler_batch": W.rossler_batch, "linear64_batch": W.linear64_batch}.get(
-        args.workload, W.vdp_adjoint)()
+        workload, W.vdp_adjoint)()
     pc = args.per_component_orders
     if pc:
         if args.batch_path == "blocked" and (args.far_prec or "fp64") != "fp64":
             sys.exit("--per-component-orders on the BLOCKED path takes FP64 far windows")
         # the workload's own order range: Rossler's [0.9, 1], else [0.8, 1]
-        w = W.per_component_orders(w, lo=0.9 if args.workload == "rossler_batch" else 0.8)
-    prec = args.far_prec or ("fp32" if args.workload == "rossler_batch" and not pc else "fp64")
+        w = W.per_component_orders(w, lo=0.9 if workload == "rossler_batch" else 0.8)
+    prec = prec or args.far_prec or ("fp32" if workload == "rossler_batch" and not pc else "fp64")
     Ns = np.asarray(w["N"], dtype=np.int64)
     B, d = len(Ns), w["d"]
     if args.alpha is not None:
@@ -244,26 +276,14 @@ def bench_batch(F, W, args):
     if args.tune:
         tune = F.fabm_tune(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
         print(f"# tune: {tune}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        call()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(stream)
-        call()
-        b.record(stream)
-    torch.cuda.synchronize()
-    per = [a.elapsed_time(b) / 1e3 for a, b in evs]
-    print(f"# {args.workload}: solve times {['%.4f' % t for t in per]} s", file=sys.stderr,
-          flush=True)
+    per = _timed(call, steps, warmup, f"{workload} {prec}")
     kt = {}
     if not args.no_kernel_times:
         F.fabm_plan_set_profiling(plan, True)
         call()
         torch.cuda.synchronize()
         kt = {k: v for k, v in F.fabm_plan_kernel_times(plan).items() if v[1]}
+        F.fabm_plan_set_profiling(plan, False)
     t = float(np.mean(per))
     # an instance whose state leaves every bounded set stops at its status
     # step (later rows NaN, its remaining windows skipped): count the rows
@@ -271,9 +291,9 @@ def bench_batch(F, W, args):
     stv = st.cpu().numpy()
     Neff = np.where(stv > 0, stv - 1, Ns).astype(np.float64)
     flops = float((2.0 * d * Neff * (Neff + 1)).sum())
-    out = {"metric": "steps*states/s (history GFLOP/s alongside), batched blocked",
+    out = {"metric": "steps*states/s (history GFLOP/s alongside), batched",
            "value": float(Neff.sum()) * d / t, "unit": "steps*states/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
+           "steps": steps, "warmup": warmup, "ms_per_step": t * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": {"fp64": "f64", "fp32": "f64 band, f32 far windows",
                      "fp16x2": "f64 band, fp16 hi+lo far tiles (f32 sums)"}[prec],
@@ -291,55 +311,79 @@ def bench_batch(F, W, args):
            "tune": tune,
            "kernel_times_s": {k: v[0] for k, v in kt.items()},
            "kernel_launches": {k: v[1] for k, v in kt.items()}}
+    instr = sum(v[0] for v in kt.values())
+    # un-instrumented share of each kernel class: the timed solve scaled by its
+    # fraction of the instrumented kernel time
+    share = (t / instr) if instr > 0 else 1.0
+    basis = ("timed solve x the kernel's share of the instrumented kernel time, over the "
+             "launches")
     if "blocked_step" in kt:
         secs, launches = kt["blocked_step"]
+        run = secs * share
         peak = FP32_MFMA_PEAK_TFLOPS if prec == "fp32" else FP64_MFMA_PEAK_TFLOPS
-        ach = flops / secs / 1e12
+        ach = flops / run / 1e12
         out["roofline"] = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
                                frac=ach / peak, traffic=None, kernel="k_step_batch",
-                               launches=launches, avg_launch_s=secs / launches,
+                               launches=launches, avg_launch_s=run / launches,
+                               avg_launch_s_instrumented=secs / launches,
+                               launch_time_basis=basis,
                                algorithmic_flops_per_launch=flops / launches)
     if "direct_wg" in kt:
         secs, launches = kt["direct_wg"]
+        run = secs * share
         # every step reads the history (d values per row) and the weight rows
         # b, a: one pair per instance, or one per component with per-component orders
         by = float((4.0 * Neff * (Neff + 1) * (3 * d if pc else d + 2)).sum())
-        out["roofline"] = dict(bound="hbm", achieved=by / secs / 1e9, peak=HBM_PEAK_GBPS,
-                               unit="GB/s", frac=by / secs / 1e9 / HBM_PEAK_GBPS, traffic=None,
+        out["roofline"] = dict(bound="hbm", achieved=by / run / 1e9, peak=HBM_PEAK_GBPS,
+                               unit="GB/s", frac=by / run / 1e9 / HBM_PEAK_GBPS, traffic=None,
                                kernel="k_direct_wg", launches=launches,
-                               avg_launch_s=secs / launches, algorithmic_bytes_per_launch=by)
+                               avg_launch_s=run / launches,
+                               avg_launch_s_instrumented=secs / launches,
+                               launch_time_basis=basis, algorithmic_bytes_per_launch=by)
     if "wide_far" in kt:
         # far sums of the shared grid: every target row t takes the 64 * (t // 64)
         # source rows of earlier blocks, both tables, every column
         secs, launches = kt["wide_far"]
+        run = secs * share
         t_rows = np.arange(int(Neff.max()) + 1, dtype=np.float64)
         far_flops = float((4.0 * B * d * 64.0 * np.floor(t_rows / 64.0)).sum())
         hw = 3.0 if prec == "fp16x2" else 1.0  # hi*hi + hi*lo + lo*hi products
         peak = {"fp64": FP64_MFMA_PEAK_TFLOPS, "fp32": FP32_MFMA_PEAK_TFLOPS,
                 "fp16x2": FP16_MFMA_PEAK_TFLOPS}[prec]
-        ach = hw * far_flops / secs / 1e12
+        ach = far_flops / run / 1e12
         # history read by the far launches: every earlier row, every column,
         # once per workgroup column tile (8, 4 or 2 + 2 bytes per value)
         eb = {"fp64": 8.0, "fp32": 4.0, "fp16x2": 4.0}[prec]
         hist = float((64.0 * np.floor(t_rows[::64] / 64.0)).sum()) * B * d * eb
+        common = dict(traffic=None, kernel="k_wide_far", launches=launches,
+                      avg_launch_s=run / launches, avg_launch_s_instrumented=secs / launches,
+                      launch_time_basis=basis, far_seconds=run,
+                      algorithmic_flops_per_launch=far_flops / launches,
+                      algorithmic_bytes_per_launch=hist / launches)
         if prec == "fp16x2":
             # 64 flop per history byte: 512 TFLOP/s at 8 TB/s, below the
             # 833 TFLOP/s of algorithmic work the binary16 matrix cores give at
             # three products per term, so HBM bounds this kernel
-            out["roofline"] = dict(bound="hbm", achieved=hist / secs / 1e9, peak=HBM_PEAK_GBPS,
-                                   unit="GB/s", frac=hist / secs / 1e9 / HBM_PEAK_GBPS,
-                                   traffic=None, kernel="k_wide_far", launches=launches,
-                                   avg_launch_s=secs / launches,
-                                   algorithmic_bytes_per_launch=hist / launches,
-                                   mfma_tflops=ach, mfma_frac=ach / peak,
-                                   mfma_flops_per_algorithmic_flop=hw)
+            out["roofline"] = dict(bound="hbm", achieved=hist / run / 1e9, peak=HBM_PEAK_GBPS,
+                                   unit="GB/s", frac=hist / run / 1e9 / HBM_PEAK_GBPS,
+                                   mfma_tflops=ach, hw_mfma_tflops=ach * hw,
+                                   hw_mfma_frac=ach * hw / peak,
+                                   mfma_flops_per_algorithmic_flop=hw, **common)
         else:
             out["roofline"] = dict(bound="mfma", achieved=ach, peak=peak, unit="TFLOP/s",
-                                   frac=ach / peak, traffic=None, kernel="k_wide_far",
-                                   launches=launches, avg_launch_s=secs / launches,
-                                   algorithmic_flops_per_launch=far_flops / launches,
-                                   history_gbps=hist / secs / 1e9)
-    if args.cpu_sample > 0 and args.workload == "linear64_batch":
+                                   frac=ach / peak, history_gbps=hist / run / 1e9, **common)
+    if ref_y is not None:
+        # normwise error of every instance against the FP64 rows (whole
+        # trajectories): max_n |y_n - y64_n|_inf / max_n |y64_n|_inf
+        N0 = int(Ns[0])
+        a = y.view(B, N0 + 1, d)
+        r = ref_y.view(B, N0 + 1, d)
+        num = (a - r).abs().amax(dim=(1, 2))
+        den = r.abs().amax(dim=(1, 2))
+        e = (num / den).cpu().numpy()
+        out["rel_err_vs_fp64_gpu_full"] = dict(max=float(e.max()), median=float(np.median(e)),
+                                               instances=B)
+    if args.cpu_sample > 0 and workload == "linear64_batch":
         # oracle check of the first 1000 steps of the first and last instance
         from oracle import oracle as O
         errs = []
@@ -348,26 +392,48 @@ def bench_batch(F, W, args):
                                    float(w["h"][i]), 1000, w["y0"][i])
             g = y[int(row_off[i]):int(row_off[i]) + 1001].cpu().numpy()
             errs.append(float(np.abs(g - ref).max() / np.abs(ref).max()))
-        out["rel_err_first_1000_steps"] = errs
+        out["rel_err_vs_oracle_first_1000_steps"] = errs
     elif args.cpu_sample > 0:
-        # oracle check of the three shortest instances
+        # oracle check of the three shortest instances (whole trajectories)
         from oracle import oracle as O
-        yy = y.cpu().numpy()
-        errs = []
-        for i in np.argsort(Ns)[:3]:
-            if pc:
+        idx = np.argsort(Ns)[:3]
+        if pc:
+            errs = []
+            yy = y.cpu().numpy()
+            for i in idx:
                 ref, _, _, _ = O.solve_orders(w["system"], w["theta"][i], w["alpha"][i],
                                               float(w["h"][i]), int(Ns[i]), w["y0"][i])
-            else:
-                ref, _, _, _ = O.solve(w["system"], w["theta"][i], float(w["alpha"][i]),
-                                       float(w["h"][i]), int(Ns[i]), w["y0"][i])
-            g = yy[row_off[i]:row_off[i] + Ns[i] + 1]
-            errs.append(float(np.abs(g - ref).max() / np.abs(ref).max()))
-        out["rel_err_shortest_3"] = errs
-    print(json.dumps(out), flush=True)
+                g = yy[row_off[i]:row_off[i] + Ns[i] + 1]
+                errs.append(float(np.abs(g - ref).max() / np.abs(ref).max()))
+        else:
+            yr, ro, _ = O.solve_batch(w["system"], w["theta"][idx], w["alpha"][idx],
+                                      w["h"][idx], Ns[idx], np.asarray(w["y0"])[idx])
+            errs = []
+            for k, i in enumerate(idx):
+                g = y[int(row_off[i]):int(row_off[i] + Ns[i] + 1)].cpu().numpy()
+                ref = yr[ro[k]:ro[k] + Ns[i] + 1]
+                errs.append(float(np.abs(g - ref).max() / np.abs(ref).max()))
+        out["rel_err_vs_oracle_shortest_3"] = errs
+    if keep_y:
+        out["_y"] = y
+    return out
 
 
-def bench_adjoint(F, W, args):
+def bench_linear64_precisions(F, W, args, steps, warmup):
+    """The linear d = 64 batch with FP64, FP32 and split-FP16 far tiles; the
+    reduced-precision rows are compared over every instance and step with the
+    FP64 rows (whose own error against the oracle is stated on a prefix)."""
+    res = {}
+    r64 = bench_batch(F, W, args, "linear64_batch", "fp64", steps, warmup, keep_y=True)
+    y64 = r64.pop("_y")
+    res["fp64"] = r64
+    for prec in ("fp32", "fp16x2"):
+        res[prec] = bench_batch(F, W, args, "linear64_batch", prec, steps, warmup, ref_y=y64)
+    del y64
+    return res
+
+
+def bench_adjoint(F, W, args, steps=None, warmup=None):
     """Van der Pol x1024, N = 2^15: forward solve, MSE loss against targets from
     mu + N(0, 0.05) (computed once by the same forward pass, untimed) and the
     adjoint for d/dmu and d/dy0. Timed: forward + backward, as a training step
@@ -376,6 +442,8 @@ def bench_adjoint(F, W, args):
     recomputes the forward) after a plain solve is timed beside it."""
     import numpy as np
     import torch
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     w = W.vdp_adjoint()
     Ns = np.asarray(w["N"], dtype=np.int64)
     B, d = len(Ns), w["d"]
@@ -395,53 +463,43 @@ def bench_adjoint(F, W, args):
     gth = torch.empty_like(th)
     F.fabm_solve_batch(plan, ws, w["alpha"], w["h"], Ns, y0, tht, row_off, yt, st)
     scale = 2.0 / (rows * d)  # d/dy of the mean of squared differences
+    hold = {}
 
     def step():
         F.fabm_adjoint_forward(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
         gy = (y - yt) * scale
         F.fabm_adjoint_reverse(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, gy, gy0, gth)
-        return gy
+        hold["gy"] = gy
 
     def step_one_call():
         F.fabm_solve_batch(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
         gy = (y - yt) * scale
         F.fabm_adjoint(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, gy, gy0, gth, st)
-        return gy
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(stream)
-        gy = step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    per = [a.elapsed_time(b) / 1e3 for a, b in evs]
-    print(f"# vdp_adjoint: forward+backward times {['%.4f' % t for t in per]} s", file=sys.stderr,
-          flush=True)
-    step_one_call()
-    a, b = evs[0]
-    a.record(stream)
-    step_one_call()
-    b.record(stream)
-    torch.cuda.synchronize()
-    one_call = a.elapsed_time(b) / 1e3
+    per = _timed(step, steps, warmup, "vdp_adjoint forward+backward")
+    one_call = float(np.mean(_timed(step_one_call, 1, 1, "vdp_adjoint solve + one-call adjoint")))
     step()  # leave the split path's gradients in gy0, gth
+    gy = hold["gy"]
     F.fabm_plan_set_profiling(plan, True)
     F.fabm_adjoint(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, gy, gy0, gth, st)
     torch.cuda.synchronize()
     kt = {k: v for k, v in F.fabm_plan_kernel_times(plan).items() if v[1]}
+    F.fabm_plan_set_profiling(plan, False)
     t = float(np.mean(per))
     flops = float((2.0 * d * Ns * (Ns + 1)).sum())
     out = {"metric": "forward + backward (adjoint) time of a batched solve, d/dmu and d/dy0",
-           "value": t, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "value": t, "unit": "s", "n_gpus": 1, "steps": steps, "warmup": warmup,
            "ms_per_step": t * 1e3, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": w["name"], "batch": B, "N": int(Ns.max())},
+           "steps_states_per_s_fwd_plus_bwd": float(Ns.sum()) * d / t,
            "history_gflops_fwd_plus_bwd": 2.0 * flops / t / 1e9,
+           "roofline": dict(bound="mfma", achieved=2.0 * flops / t / 1e12,
+                            peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                            frac=2.0 * flops / t / 1e12 / FP64_MFMA_PEAK_TFLOPS, traffic=None,
+                            kernel="k_step_batch + k_adj_batch",
+                            basis="2 x 2 d N (N + 1) per instance (forward and reverse "
+                                  "history sums) over the timed forward + backward"),
            "solve_then_one_call_adjoint_s": one_call,
            "adjoint_kernel_times_s": {k: v[0] for k, v in kt.items()},
            "adjoint_kernel_launches": {k: v[1] for k, v in kt.items()}}
@@ -457,7 +515,74 @@ def bench_adjoint(F, W, args):
         got = np.concatenate([gy0.cpu().numpy()[i], gth.cpu().numpy()[i]])
         out["grad_rel_err_vs_oracle_instance0"] = float(np.abs(got - ref).max() / np.abs(ref).max())
         out["oracle_adjoint_seconds_one_instance"] = dt
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_scalar(F, W):
+    """The scalar linear test equation D^0.5 y = -y, y(0) = 1, h = 0.005,
+    N = 2000 on both paths: error against the oracle and against the exact
+    solution E_{1/2}(-t^{1/2}) = erfcx(t^{1/2}) (discretisation error)."""
+    import numpy as np
+    import torch
+    from scipy.special import erfcx
+    from oracle import oracle as O
+    w = W.scalar_linear()
+    N = int(w["N"][0])
+    ref, _, _, _ = O.solve(w["system"], w["theta"][0], float(w["alpha"][0]), float(w["h"][0]), N,
+                           w["y0"][0])
+    exact = erfcx(np.sqrt(np.arange(N + 1) * float(w["h"][0])))
+    out = {}
+    for path in ("direct", "blocked"):
+        r = time_path(F, w, path, 5, 2, kernel_times=False)
+        y = r["y"][:, 0]
+        t = float(np.mean(r["solve_s"]))
+        out[path] = dict(solve_s=t, steps_states_per_s=N / t,
+                         rel_err_vs_oracle=float(np.abs(y - ref[:, 0]).max() / np.abs(ref).max()),
+                         max_abs_err_vs_exact=float(np.abs(y - exact).max()),
+                         y_T=float(y[-1]), exact_y_T=float(exact[-1]))
+    return dict(workload="scalar linear D^0.5 y = -y, y(0)=1, h=0.005, N=2000 (T=10)",
+                bound="latency (correctness configuration)", **out)
+
+
+def cpu_all_cores(W, n_inst: int = 128, n_steps: int = 1 << 14):
+    """The oracle's batch solver (OpenMP over instances, every host core) on a
+    bounded sample of the Rossler batch: the first n_steps steps of n_inst
+    instances, rate in steps*states/s, extrapolated to the whole batch by
+    sum N_i (N_i + 1) of the history sums."""
+    import numpy as np
+    from oracle import oracle as O
+    w = W.rossler_batch()
+    idx = np.linspace(0, len(w["N"]) - 1, n_inst).astype(int)
+    Ns = np.full(n_inst, n_steps, dtype=np.int64)
+    t0 = time.perf_counter()
+    O.solve_batch(w["system"], w["theta"][idx], w["alpha"][idx], w["h"][idx], Ns,
+                  w["y0"][idx])
+    dt = time.perf_counter() - t0
+    Nall = np.asarray(w["N"], dtype=np.float64)
+    t_full = dt * float((Nall * (Nall + 1)).sum()) / float((Ns * (Ns + 1.0)).sum())
+    return dict(value=float(Nall.sum()) * 3 / t_full, unit="steps*states/s",
+                cores=O.threads(), kind="oracle",
+                sample=(f"first {n_steps} steps of {n_inst} instances of the Rossler batch "
+                        f"(4096 x N in [2^14, 2^17]), {dt:.2f} s on {O.threads()} host threads, "
+                        f"extrapolated by sum N_i (N_i + 1) to the whole batch"),
+                sample_seconds=dt, workload="rossler_batch (config of the FP32 batch row)")
+
+
+def host_info():
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(cpu_model=cpu, nproc=usable, os_cpu_count=os.cpu_count())
 
 
 # Average seconds the paper reports for its Hindmarsh-Rose runs (Section 4,
@@ -517,7 +642,7 @@ def bench_table2(F, W, args):
     if kt:
         out["kernel_times_s_at_largest_N"] = {k: v[0] for k, v in kt.items() if v[1]}
     out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, 3,
-                               args.fft_level)
+                               args.fft_level, solve_s=float(np.mean(r["solve_s"])))
     if out["roofline"]:
         out["roofline"]["at_N"] = N
     if args.cpu_sample > 0:
@@ -543,27 +668,24 @@ def copy_reference(mib: int):
     print(f"# copy reference: {mib} MiB read + {mib} MiB written", file=sys.stderr, flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    if args.copy_mib > 0:
-        copy_reference(args.copy_mib)
-    if args.workload != "chen":
-        import paper_1611_08678_amd as F
-        from paper_1611_08678_amd import workloads as W
-        F.load()
-        if args.workload == "vdp_adjoint":
-            return bench_adjoint(F, W, args)
-        if args.workload == "hr_table2":
-            return bench_table2(F, W, args)
-        return bench_batch(F, W, args)
+def chen_horizon(w, yref, n: int, thresh: float = 1e-12):
+    """First step where the oracle itself, started from y0 with its first
+    component moved by one ulp, differs from `yref` by more than thresh x
+    max|y| (normwise): beyond it no two correct binary64 evaluations of the
+    chaotic trajectory need agree."""
     import numpy as np
-    import paper_1611_08678_amd as F
-    from paper_1611_08678_amd import workloads as W
+    from oracle import oracle as O
+    y0p = np.array(w["y0"][0], dtype=np.float64)
+    y0p[0] = np.nextafter(y0p[0], np.inf)
+    alt, _, _, _ = O.solve(w["system"], w["theta"][0], float(w["alpha"][0]), float(w["h"][0]),
+                           n, y0p)
+    scale = np.abs(yref).max()
+    bad = np.nonzero(np.abs(alt - yref).max(axis=1) > thresh * scale)[0]
+    return int(bad[0]) if bad.size else n + 1
 
-    F.load()
+
+def bench_chen(F, W, args):
+    import numpy as np
     w = W.chen(N=args.N)
     N, d = int(w["N"][0]), w["d"]
     flops = 2.0 * d * N * (N + 1)
@@ -602,7 +724,7 @@ def main():
         out["kernel_times_s"] = {k: v[0] for k, v in kt.items() if v[1]}
         out["kernel_launches"] = {k: v[1] for k, v in kt.items() if v[1]}
     out["roofline"] = roofline({k: v for k, v in (kt or {}).items() if v[1]}, N, d,
-                               args.fft_level)
+                               args.fft_level, solve_s=t)
     if "direct" in results:
         # DIRECT reads both weight rows and the history at every step:
         # sum_t 8 t (d + 2) B = 4 N (N + 1) (d + 2) B (algorithmic)
@@ -615,16 +737,65 @@ def main():
                                               np.mean(results["blocked"]["solve_s"]))
     if args.cpu_sample > 0:
         yref, cpu = cpu_baseline(w, min(args.cpu_sample, N), N)
+        cpu.update(host_info())
         out["cpu_baseline"] = cpu
         n = yref.shape[0]
+        hz = chen_horizon(w, yref, n - 1)
         scale = np.abs(yref).max()
         for k, v in results.items():
             e = np.abs(v["y"][:n] - yref).max(axis=1) / scale
-            out["paths"][k]["rel_err_first_4096"] = float(e[:4097].max())
+            out["paths"][k]["rel_err_to_horizon"] = float(e[:min(hz, n)].max())
             out["paths"][k]["rel_err_sample_prefix"] = float(e.max())
-        out["rel_err_note"] = ("chaotic system: normwise error vs the FP64 oracle is stated on "
-                               "the first 4096 steps (before rounding differences amplify) and on "
-                               "the whole sampled prefix")
+        out["rel_err_horizon_steps"] = hz
+        out["rel_err_note"] = ("chaotic system: normwise error vs the FP64 oracle up to the "
+                               "calibrated horizon (the first step where the oracle, started "
+                               "one ulp away in y0, differs from itself by 1e-12 normwise), "
+                               "and over the whole sampled prefix")
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the library and its "
+                                   "benchmark drive a single device); --gpus must be 1"}))
+        sys.exit(2)
+    if args.copy_mib > 0:
+        copy_reference(args.copy_mib)
+    import paper_1611_08678_amd as F
+    from paper_1611_08678_amd import workloads as W
+    F.load()
+    if args.workload == "vdp_adjoint":
+        print(json.dumps(bench_adjoint(F, W, args)), flush=True)
+        return
+    if args.workload == "hr_table2":
+        return bench_table2(F, W, args)
+    if args.workload != "chen":
+        out = bench_batch(F, W, args)
+        print(json.dumps(out), flush=True)
+        return
+    out = bench_chen(F, W, args)
+    if not args.no_configs and args.N == 1 << 20 and args.fft_level == 0:
+        # the other workloads of the benchmark set, each timed the same way
+        import torch
+        cs, cw = args.config_steps, args.config_warmup
+        cfg = {}
+        cfg["scalar_linear"] = bench_scalar(F, W)
+        sub = argparse.Namespace(**{**vars(args), "far_prec": None, "batch_path": "blocked",
+                                    "per_component_orders": False, "alpha": None,
+                                    "slope": False, "tune": False})
+        cfg["rossler_batch_fp32"] = bench_batch(F, W, sub, "rossler_batch", "fp32", cs, cw)
+        torch.cuda.empty_cache()
+        cfg["rossler_batch_fp64"] = bench_batch(F, W, sub, "rossler_batch", "fp64", cs, cw)
+        torch.cuda.empty_cache()
+        for k, v in bench_linear64_precisions(F, W, sub, cs, cw).items():
+            cfg["linear64_batch_" + k] = v
+        torch.cuda.empty_cache()
+        cfg["vdp_adjoint"] = bench_adjoint(F, W, sub, cs, cw)
+        torch.cuda.empty_cache()
+        if args.cpu_sample > 0:
+            out["cpu_baseline_all_cores"] = {**cpu_all_cores(W), **host_info()}
+        out["configs"] = cfg
     print(json.dumps(out), flush=True)
 
 

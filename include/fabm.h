@@ -384,12 +384,20 @@ typedef enum {
 fabm_status fabm_plan_set_profiling(fabm_plan_t plan, int32_t enable);
 fabm_status fabm_plan_kernel_times(fabm_plan_t plan, double *seconds, int64_t *launches);
 
-/* History sums alone for a given history (teacher forcing): for t = 1..N,
+/* History sums alone for a given history (teacher forcing; the Section 2
+ * predictor sum of eq. (2) and the corrector sum): for t = 1..N,
  *   P[t-1] = sum_{k<t} b_{t-1-k} f[k],   C[t-1] = c_{t-1} f[0] + sum_{1<=k<t} a_{t-1-k} f[k]
- *   f (device) [N][dim];  P, C (device) [N][dim].
- * `path` selects the contraction kernel (DIRECT or BLOCKED, AUTO = BLOCKED);
- * `far_prec` the far-tile arithmetic of BLOCKED. Workspace: at least
- * fabm_history_workspace_size(N, dim) bytes. */
+ *   f (device) [N][dim], dim 1..4 (else UNSUPPORTED);  P, C (device) [N][dim].
+ * `path` selects the contraction:
+ *   DIRECT:  one thread per target row and component group reduces the whole
+ *            history (far_prec is ignored);
+ *   BLOCKED, AUTO: the step pipeline of the BLOCKED solver (band, near and
+ *            far matrix-core windows of 256-row blocks, far_prec FP64 or FP32;
+ *            FP16X2 is UNSUPPORTED), run with f read from the given rows in
+ *            place of the right-hand side; N <= 2^26.
+ * A non-finite entry of f makes that target and all later rows NaN on
+ * BLOCKED. Workspace (device, 256-byte aligned): at least
+ * fabm_history_workspace_size(N, dim) bytes (0 for invalid N or dim). */
 fabm_status fabm_history_sums(double alpha, int64_t N, int32_t dim, const double *f, double *P,
                               double *C, fabm_path path, fabm_far_prec far_prec,
                               void *workspace, size_t workspace_bytes, hipStream_t stream);

@@ -34,6 +34,9 @@
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <quadmath.h>
 #include <stdint.h>
@@ -798,4 +801,14 @@ void oracle_rhs(int system, int d, const double *theta, double t, const double *
 {
     orc_rhs r = {system, d, theta, 0, 0};
     rhs_eval(&r, t, y, f);
+}
+
+/* Threads the OpenMP loops above use (for reporting the cores of a timing). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -77,6 +77,7 @@ def lib():
                                      _D, _D, _D, _D]
         L.oracle_adjoint.restype = C.c_int64
         L.oracle_rhs.argtypes = [C.c_int, C.c_int, _D, C.c_double, _D, _D]
+        L.oracle_threads.restype = C.c_int
         L.oracle_rhs_rows.argtypes = [C.c_int, C.c_int, _D, C.c_double, C.c_int64, _D, _D]
         L.oracle_step_from_history.argtypes = [C.c_int, C.c_int, _D, C.c_double, C.c_double,
                                                C.c_int64, _D, _D, _D, _D, _D, _D, _D]
@@ -332,3 +333,8 @@ def adjoint(system: int, theta, alpha: float, h: float, N: int, y0, gy):
     st = lib().oracle_adjoint(system, d, _p(th), float(alpha), float(h), int(N), _p(y0), _p(g),
                               _p(gy0), _p(gth))
     return gy0.reshape(shape), gth[: th.size], int(st)
+
+
+def threads() -> int:
+    """OpenMP threads of the oracle's parallel loops (batches, history sums)."""
+    return int(lib().oracle_threads())

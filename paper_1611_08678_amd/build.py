@@ -1,11 +1,14 @@
 """Build step of the HIP library: compiles every ``csrc/*.hip`` / ``*.cpp`` source for
 gfx950 into ``libfabm.so`` inside the package directory (in-tree, so the
-built object travels with the source tree)."""
+built object travels with the source tree). Sources compile in parallel, one
+object each, then link into the shared library."""
 from __future__ import annotations
 
 import glob
 import os
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -14,7 +17,7 @@ SO = os.path.join(HERE, "libfabm.so")
 ARCH = os.environ.get("FABM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
@@ -30,12 +33,24 @@ def sources():
 def build(verbose: bool = False) -> str:
     """Compile the library (always recompiles); returns the path of the .so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = SO + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *sources(), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    jobs = max(1, min(len(sources()), os.cpu_count() or 1, 16))
+    with tempfile.TemporaryDirectory(prefix="fabm_build_") as tmpd:
+        def compile_one(src):
+            obj = os.path.join(tmpd, os.path.basename(src) + ".o")
+            cmd = [hipcc, *HIPCC_FLAGS, *inc, "-c", src, "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            return obj
+
+        with ThreadPoolExecutor(jobs) as ex:
+            objs = list(ex.map(compile_one, sources()))
+        tmp = SO + ".tmp"
+        cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(tmp, SO)
     return SO
 

@@ -136,14 +136,15 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     }
     // theta in registers when short; a linear system's matrix is read from LDS
     constexpr bool kThLds = NP > 12;
-    double thr[kThLds ? 1 : NP], y0[D];
+    double thr[kThLds || NP == 0 ? 1 : NP], y0[D];
     if constexpr (!kThLds) {
 #pragma unroll
         for (int k = 0; k < NP; ++k) thr[k] = A.params[k];
     } else {
         for (int k = tid; k < NP; k += nthr) sTh[k] = A.params[k];
     }
-    const double *th = kThLds ? sTh : thr;
+    // teacher forcing: "theta" is the given history itself
+    const double *th = SYS == SYS_TEACHER ? A.params : kThLds ? sTh : thr;
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = A.y0[i];
 #pragma unroll
@@ -280,7 +281,8 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     for (int k = 0; k < K; ++k) {
         hb0[k] = sbh[k * kBlk];
         ha0[k] = sah[k * kBlk];
-        hig2[k] = hav[k] * ig2v[k];
+        // teacher forcing returns the plain sums: y_t = C_t, yP_t = P_t
+        hig2[k] = SYS == SYS_TEACHER ? 0.0 : hav[k] * ig2v[k];
     }
     double fprev[D], ypb[D], ycb[D];
     {
@@ -709,7 +711,7 @@ __device__ __forceinline__ void near_part(const InstView &A, int s, const double
 
 __device__ __forceinline__ InstView single_view(const StepArgs &A)
 {
-    return InstView{A.meta, A.cmeta, A.params, A.y0, A.y1, A.Y, nullptr, A.W, A.W32, A.Fc,
+    return InstView{A.meta, A.cmeta, A.params, A.y0, A.y1, A.Y, A.YP, A.W, A.W32, A.Fc,
                     A.carry, A.acc, A.dead, A.NB};
 }
 
@@ -725,7 +727,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
     const int b = blockIdx.x, wave = threadIdx.x >> 6;
     const InstView V = single_view(A);
     if (b == 0) {
-        if (wave < kBandWaves) band_block<SYS, D, false, PC>(V, s + 1, smem);
+        // teacher forcing writes the predictor sums as well
+        if (wave < kBandWaves) band_block<SYS, D, SYS == SYS_TEACHER, PC>(V, s + 1, smem);
         return;
     }
     if (*A.dead != 0u) return;  // the trajectory has ended; later rows are NaN
@@ -1048,6 +1051,15 @@ hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_
     FABM_STEP_CASE(SYS_FINANCIAL, 3)
     FABM_STEP_CASE(SYS_HINDMARSH_ROSE, 3)
 #undef FABM_STEP_CASE
+#define FABM_TEACHER_CASE(DD)                                                    \
+    if (sys == SYS_TEACHER && d == DD && !A.cmeta)                               \
+        return f32 ? enqueue_steps_t<SYS_TEACHER, DD, true, false>(A, s, T, where) \
+                   : enqueue_steps_t<SYS_TEACHER, DD, false, false>(A, s, T, where);
+    FABM_TEACHER_CASE(1)
+    FABM_TEACHER_CASE(2)
+    FABM_TEACHER_CASE(3)
+    FABM_TEACHER_CASE(4)
+#undef FABM_TEACHER_CASE
     *where = "no BLOCKED kernel for this system/dimension";
     return hipErrorInvalidValue;
 }

@@ -72,6 +72,7 @@ constexpr int kGridMax = 256;                  // MI355X compute units
 constexpr int64_t kAutoBlockedMinSteps = 1024;
 constexpr uint64_t kWaitTimeoutSeconds = 10;  // no legitimate wait comes near this
 constexpr int64_t kWideMaxCols = (int64_t)1 << 30;  // shared grid: instances x d
+constexpr int64_t kMaxHistorySteps = (int64_t)1 << 26;  // teacher-forced sums: row index in int32 blocks
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -1198,11 +1199,66 @@ fabm_status fabm_plan_kernel_times(fabm_plan_t plan, double *seconds, int64_t *l
     return ok_or_device(plan->timer.totals(seconds, launches, fabm::KC_COUNT));
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of the teacher-forced BLOCKED contraction (offsets in bytes): the
+// step pipeline of one trajectory run on the internal system that reads f
+// from the given history, with the grid step 1 (so h^alpha = 1 and the
+// returned rows are the plain sums).
+struct HistLayout {
+    size_t meta, w, w32, f, carry, acc, sync, st, ftf, yc, yp, y0, total;
+    int64_t wlen;
+    int NB;
+};
+
+HistLayout hist_layout(int64_t N, int d)
+{
+    HistLayout H{};
+    const int Lb = fabm::step_block_len();
+    H.NB = blocks_of(N);
+    H.wlen = (int64_t)H.NB * Lb + Lb;
+    const size_t blk = sizeof(double) * 2 * d * (size_t)Lb;
+    const size_t rows = sizeof(double) * (size_t)d * (size_t)(N + 1);
+    size_t off = 0;
+    H.meta = off;
+    off = align_up(off + sizeof(InstMeta));
+    H.w = off;
+    off = align_up(off + sizeof(double) * 3 * (size_t)H.wlen);
+    H.w32 = off;
+    off = align_up(off + sizeof(float) * 2 * (size_t)H.wlen);
+    H.f = off;
+    off = align_up(off + sizeof(double) * (size_t)d * (size_t)H.NB * Lb);
+    H.carry = off;
+    off = align_up(off + 2 * blk);
+    H.acc = off;
+    off = align_up(off + blk * (size_t)H.NB);
+    H.sync = off;
+    off = align_up(off + sizeof(uint32_t) * 64);
+    H.st = off;
+    off = align_up(off + sizeof(int64_t));
+    H.ftf = off;  // the given history and a zero row N
+    off = align_up(off + rows);
+    H.yc = off;   // corrector sums, rows 0..N (row t holds target t)
+    off = align_up(off + rows);
+    H.yp = off;   // predictor sums
+    off = align_up(off + rows);
+    H.y0 = off;   // zero initial state
+    off = align_up(off + sizeof(double) * (size_t)d);
+    H.total = off;
+    return H;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t fabm_history_workspace_size(int64_t N, int32_t dim)
 {
-    (void)dim;
-    if (N < 1) return 0;
-    return align_up(sizeof(double) * 3 * (size_t)N);
+    if (N < 1 || dim < 1 || dim > 4) return 0;
+    const size_t direct = align_up(sizeof(double) * 3 * (size_t)N);
+    return std::max(direct, hist_layout(N, dim).total);
 }
 
 fabm_status fabm_fft_far_schedule(int32_t NB, int32_t level, int32_t s, int32_t *jend,
@@ -1232,17 +1288,71 @@ fabm_status fabm_history_sums(double alpha, int64_t N, int32_t dim, const double
         return FABM_ERR_INVALID_ARG;
     if (path != FABM_PATH_AUTO && path != FABM_PATH_DIRECT && path != FABM_PATH_BLOCKED)
         return FABM_ERR_INVALID_ARG;
-    if (path != FABM_PATH_DIRECT) return FABM_ERR_UNSUPPORTED;
+    if (path != FABM_PATH_DIRECT && far_prec == FABM_FAR_FP16X2) return FABM_ERR_UNSUPPORTED;
+    if (N > kMaxHistorySteps) return FABM_ERR_UNSUPPORTED;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0 ||
         workspace_bytes < fabm_history_workspace_size(N, dim))
         return FABM_ERR_WORKSPACE;
     InstMeta m{};
     host_scalars(alpha, 1.0, m);
-    double *W = (double *)workspace;
-    if ((st = ok_or_device(fabm::launch_weights_one(alpha, m.ig1, m.ig2, N, W, W + N, W + 2 * N,
-                                                    stream))) != FABM_OK)
+    if (path == FABM_PATH_DIRECT) {
+        double *W = (double *)workspace;
+        if ((st = ok_or_device(fabm::launch_weights_one(alpha, m.ig1, m.ig2, N, W, W + N,
+                                                        W + 2 * N, stream))) != FABM_OK)
+            return st;
+        return ok_or_device(fabm::launch_history_direct(W, N, dim, f, P, C, stream));
+    }
+    // BLOCKED: the step pipeline (band, near and far MFMA windows) with f read
+    // from the given rows; h = 1 makes h^alpha exactly 1, so the band's
+    // predictor and corrector rows are P_t and C_t themselves.
+    const HistLayout H = hist_layout(N, dim);
+    char *base = (char *)workspace;
+    m.N = N;
+    m.wlen = H.wlen;
+    InstMeta *dmeta = (InstMeta *)(base + H.meta);
+    double *W = (double *)(base + H.w);
+    const bool f32 = far_prec == FABM_FAR_FP32;
+    float *W32 = f32 ? (float *)(base + H.w32) : nullptr;
+    double *ftf = (double *)(base + H.ftf);
+    double *yc = (double *)(base + H.yc), *yp = (double *)(base + H.yp);
+    double *y0 = (double *)(base + H.y0);
+    uint32_t *sync = (uint32_t *)(base + H.sync);
+    const int64_t nrow = (int64_t)dim * (N + 1);
+    if ((st = ok_or_device(fabm::launch_put_meta(m, dmeta, stream))) != FABM_OK) return st;
+    if ((st = ok_or_device(fabm::launch_weights(dmeta, 1, H.wlen, W, stream, W32))) != FABM_OK)
         return st;
-    return ok_or_device(fabm::launch_history_direct(W, N, dim, f, P, C, stream));
+    if ((st = ok_or_device(fabm::launch_fill_u32(sync, 64, 0u, stream))) != FABM_OK) return st;
+    if ((st = ok_or_device(fabm::launch_copy_pad(f, (int64_t)dim * N, ftf, nrow, stream))) !=
+        FABM_OK)
+        return st;
+    if ((st = ok_or_device(fabm::launch_copy_pad(nullptr, 0, y0, dim, stream))) != FABM_OK)
+        return st;
+    fabm::StepArgs A{};
+    A.meta = dmeta;
+    A.params = ftf;
+    A.y0 = y0;
+    A.Y = yc;
+    A.YP = yp;
+    A.W = W;
+    A.W32 = W32;
+    A.Fc = (double *)(base + H.f);
+    A.carry = (double *)(base + H.carry);
+    A.acc = (double *)(base + H.acc);
+    A.dead = sync;
+    A.status = (int64_t *)(base + H.st);
+    A.NB = H.NB;
+    A.far_cap = fabm::kMaxFarWg;
+    A.wlen = H.wlen;
+    const char *where = "";
+    const hipError_t pe = fabm::enqueue_steps(fabm::SYS_TEACHER, dim, f32, A, stream, nullptr,
+                                              &where);
+    if (pe != hipSuccess) return record_hip(where, pe);
+    // row t of the band's output is target t; the caller's row t - 1
+    if ((st = ok_or_device(fabm::launch_copy_pad(yp + dim, (int64_t)dim * N, P, (int64_t)dim * N,
+                                                 stream))) != FABM_OK)
+        return st;
+    return ok_or_device(
+        fabm::launch_copy_pad(yc + dim, (int64_t)dim * N, C, (int64_t)dim * N, stream));
 }
 
 }  // extern "C"

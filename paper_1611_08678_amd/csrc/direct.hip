@@ -410,6 +410,37 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+// One instance entry written from a kernel argument (no host staging buffer).
+__global__ void k_put_meta(InstMeta m, InstMeta *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = m;
+}
+
+hipError_t launch_put_meta(const InstMeta &m, InstMeta *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_put_meta, dim3(1), dim3(64), 0, s, m, dst);
+    return hipGetLastError();
+}
+
+// dst[e] = e < n_src ? src[e] : 0 for e < n_dst (a kernel, safe inside graphs).
+__global__ void k_copy_pad(const double *__restrict__ src, int64_t n_src, double *__restrict__ dst,
+                           int64_t n_dst)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_dst;
+         e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = e < n_src ? src[e] : 0.0;
+}
+
+hipError_t launch_copy_pad(const double *src, int64_t n_src, double *dst, int64_t n_dst,
+                           hipStream_t s)
+{
+    if (n_dst <= 0) return hipSuccess;
+    const int64_t b = (n_dst + 255) / 256;
+    hipLaunchKernelGGL(k_copy_pad, dim3((unsigned)(b < 2048 ? b : 2048)), dim3(256), 0, s, src,
+                       n_src, dst, n_dst);
+    return hipGetLastError();
+}
+
 // init [batch][2][d] -> y0 [batch][d], y1 [batch][d]
 __global__ void k_split_init(const double *__restrict__ init, int64_t batch, int d,
                              double *__restrict__ y0, double *__restrict__ y1)

@@ -60,6 +60,7 @@ struct StepArgs {
     const double *y0;
     const double *y1;   // y'(0) [D] (orders above one), or null
     double *Y;          // caller rows [N+1][D]
+    double *YP;         // predictor rows [N+1][D] (teacher-forced sums only), or null
     const double *W;    // b, a, c tables of length meta->wlen each
     const float *W32;   // b, a in binary32 (FP32 far windows only)
     double *Fc;         // component-major history [D][NB*256]
@@ -133,31 +134,5 @@ struct BatchSchedule {
     int max_NB = 0;
 };
 void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S);
-
-// ---------------------------------------------------------------------------
-// Single-launch persistent variant (not dispatched; see blocked_persistent.hip).
-// ---------------------------------------------------------------------------
-struct BlockedArgs {
-    const InstMeta *meta;
-    const double *params;
-    const double *y0;
-    double *Y;          // caller rows [N+1][D]
-    int64_t *status;
-    const double *W;    // b, a, c tables of length meta->wlen each
-    double *Fc;         // component-major history [D][NB*L]
-    double *part;       // [n_tasks][2D][L] per-task partial sums
-    double *far;        // [NB][2D][L] far sums of each target block
-    const int4 *tasks;  // {J, I0, I1, 0}, grouped by J in source order
-    const int *queue;   // task ids in processing order
-    const int *task_off;// [NB + 1]
-    uint32_t *sync;     // [0] blocks complete, [1] queue head, [2] dead step, [3] abort
-    uint32_t *done;     // [NB] finished tasks per target block
-    uint32_t *ready;    // [NB] far sums published
-    int NB;
-    int n_tasks;
-    uint64_t timeout_ticks;  // bound of every wait, in wall-clock ticks
-};
-int blocked_count_tasks(int NB);
-void blocked_schedule(int NB, int4 *tasks, int *queue, int *task_off);
 
 }  // namespace fabm

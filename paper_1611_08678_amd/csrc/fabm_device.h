@@ -34,7 +34,10 @@ enum : int {
     SYS_ROSSLER = 2,
     SYS_VDP = 3,
     SYS_FINANCIAL = 4,
-    SYS_HINDMARSH_ROSE = 5
+    SYS_HINDMARSH_ROSE = 5,
+    // internal: f is read from a given history (teacher-forced history sums);
+    // theta points at the rows [N + 1][D] and t is the row index
+    SYS_TEACHER = 6
 };
 
 // Entries of theta of each system (LINEAR: A, b0, b1).
@@ -43,6 +46,7 @@ constexpr int n_params_of_sys(int sys, int d)
     return sys == SYS_LINEAR ? d * d + 2 * d
            : sys == SYS_VDP ? 1
            : sys == SYS_HINDMARSH_ROSE ? 8
+           : sys == SYS_TEACHER ? 0
                                        : 3;
 }
 
@@ -85,6 +89,11 @@ __device__ __forceinline__ void rhs(double t, const double (&y)[D], double (&f)[
         f[0] = fma(x2, fma(-p[0], x, p[1]), y[1] - y[2] + p[7]);
         f[1] = fma(-p[3], x2, p[2] - y[1]);
         f[2] = p[4] * fma(p[5], x - p[6], -y[2]);
+    } else if constexpr (SYS == SYS_TEACHER) {
+        // the given history row at index t (t is an integer: the grid step is 1)
+        const int64_t r = (int64_t)t;
+#pragma unroll
+        for (int i = 0; i < D; ++i) f[i] = p[r * D + i];
     }
 }
 
@@ -217,14 +226,15 @@ __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMI
 
 // Flags shared between workgroups on different XCDs (each XCD has its own
 // L2). Flag writes are read-modify-write atomics, performed at the device's
-// coherence point. A flag read is an agent-scope atomic (an add of zero,
-// which the compiler emits on gfx950 as the memory model's agent-coherent
-// load, global_load with sc1, not as a plain cached load); data published
-// under a flag is made visible by the release fence before the flag write and
-// the acquire fence after the flag read.
+// coherence point. A flag read is an agent-scope atomic load
+// (__hip_atomic_load, agent scope; emitted for gfx950 as global_load_dword
+// with the sc1 bit, which reads past the XCD's own L2); data published under
+// a flag is made visible by the
+// release fence before the flag write and the acquire fence after the flag
+// read.
 __device__ __forceinline__ uint32_t flag_read(uint32_t *p)
 {
-    return __hip_atomic_fetch_add(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void flag_publish(uint32_t *p, uint32_t v)
 {
@@ -236,7 +246,7 @@ __device__ __forceinline__ void flag_max(uint32_t *p, uint32_t v)
     __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Spin until *p >= v (then acquire), or until *abort becomes nonzero or
+// Spin until *p >= v modulo 2^32 (then acquire), or until *abort becomes nonzero or
 // `timeout_ticks` of the constant-rate wall clock have passed (then *abort is
 // raised and false is returned). Every wait of a persistent kernel is bounded
 // this way, so a scheduling mistake ends the launch with an error instead of a
@@ -246,7 +256,8 @@ __device__ __forceinline__ bool wait_geq(uint32_t *p, uint32_t v, uint32_t *abor
 {
     const uint64_t deadline = wall_clock64() + timeout_ticks;
     for (;;) {
-        if (flag_read(p) >= v) {
+        // wrap-safe: the counters are monotone and never more than 2^31 apart
+        if ((int32_t)(flag_read(p) - v) >= 0) {
             fence_acquire();
             return true;
         }

@@ -36,6 +36,13 @@ hipError_t launch_weights_one(double al, double ig1, double ig2, int64_t n, doub
 // Zero-fill of 32-bit words (a kernel, so it is safe inside captured graphs).
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
+// One instance entry written by a kernel from its argument (no staging copy).
+hipError_t launch_put_meta(const InstMeta &m, InstMeta *dst, hipStream_t s);
+
+// dst[e] = src[e] for e < n_src, 0 for n_src <= e < n_dst (a kernel).
+hipError_t launch_copy_pad(const double *src, int64_t n_src, double *dst, int64_t n_dst,
+                           hipStream_t s);
+
 // Split of the initial values [batch][2][d] (y(0), then y'(0)) into y0 and
 // y1, each [batch][d] (a kernel, so it is safe inside captured graphs).
 hipError_t launch_split_init(const double *init, int64_t batch, int d, double *y0, double *y1,
@@ -88,12 +95,6 @@ struct BatchSchedule;
 hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const BatchSchedule &S,
                          const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
 size_t batch_smem_bytes(int d, bool pc = false);
-
-// Single-launch persistent variant of the BLOCKED path (not dispatched).
-struct BlockedArgs;
-hipError_t launch_blocked_single(int sys, int d, int G, const BlockedArgs &A, hipStream_t s);
-size_t blocked_smem_bytes(int d);
-int blocked_block_len();
 
 // Teacher-forced history sums, direct contraction (one thread per target row
 // and component group).
