@@ -232,6 +232,26 @@ fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes
                        double h, int64_t N, const double *y0, const double *params,
                        double *y_out, int64_t *status, hipStream_t stream);
 
+/* fabm_solve without allocation, for callers that cannot allocate device
+ * memory or call hipMalloc (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation). Same arguments, checks and result
+ * as fabm_solve (bitwise the same rows), except that the workspace is a
+ * device array inside the library of FABM_NOALLOC_SCRATCH_BYTES bytes (one
+ * per device, held until the process ends), and the call allocates nothing:
+ * no device memory, no pinned staging buffer, no events (the plan's kernel
+ * timing does not apply). Plans: the per-trajectory paths (BLOCKED with
+ * 256-row blocks, DIRECT) without fft_level and per-component orders;
+ * otherwise UNSUPPORTED. A solve whose workspace (fabm_workspace_size with
+ * batch 1) exceeds the scratch size returns WORKSPACE and fabm_last_error
+ * states both sizes (about N <= 700000 for d = 3 on BLOCKED). Every call on a
+ * device uses that device's one array, which keeps the last call's contents
+ * (each call re-initialises what it reads): calls that overlap in time on one
+ * device race, whatever their streams or plans. */
+#define FABM_NOALLOC_SCRATCH_BYTES (64u << 20)
+fabm_status fabm_solve_noalloc(fabm_plan_t plan, double alpha, double h, int64_t N,
+                               const double *y0, const double *params, double *y_out,
+                               int64_t *status, hipStream_t stream);
+
 /* A batch of independent trajectories of one system, each with its own
  * alpha, h, N, y0 and theta (ragged lengths), in one enqueue.
  *   alpha (host) [batch] ([batch][d] with FABM_PLAN_PER_COMPONENT_ORDER)

@@ -35,7 +35,8 @@ EXPORTS = ("fabm_last_error", "fabm_status_string", "fabm_n_params", "fabm_plan"
            "fabm_history_sums", "fabm_history_workspace_size", "fabm_plan_set_profiling",
            "fabm_plan_kernel_times", "fabm_adjoint", "fabm_adjoint_workspace_size",
            "fabm_graph_solve_batch", "fabm_graph_launch", "fabm_graph_destroy", "fabm_tune",
-           "fabm_adjoint_forward", "fabm_adjoint_reverse", "fabm_fft_far_schedule")
+           "fabm_adjoint_forward", "fabm_adjoint_reverse", "fabm_fft_far_schedule",
+           "fabm_solve_noalloc")
 KERNEL_CLASSES = ("weights", "direct_wg", "direct_grid", "blocked_step", "history", "adjoint",
                   "wide_far", "wide_band", "fft_far")
 
@@ -44,7 +45,10 @@ class FabmError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
         detail = ""
-        if code == FABM_ERR_DEVICE:
+        # the library's text for device failures, and for a no-allocation
+        # solve refused for size (set by that call)
+        if code == FABM_ERR_DEVICE or (code == FABM_ERR_WORKSPACE and
+                                       where == "fabm_solve_noalloc"):
             try:
                 detail = " [" + load().fabm_last_error().decode() + "]"
             except Exception:
@@ -93,6 +97,9 @@ def load():
     L.fabm_solve.argtypes = [_VP, _VP, C.c_size_t, C.c_double, C.c_double, C.c_int64, _VP, _VP,
                              _VP, _VP, _VP]
     L.fabm_solve.restype = C.c_int
+    L.fabm_solve_noalloc.argtypes = [_VP, C.c_double, C.c_double, C.c_int64, _VP, _VP, _VP, _VP,
+                                     _VP]
+    L.fabm_solve_noalloc.restype = C.c_int
     L.fabm_solve_batch.argtypes = [_VP, _VP, C.c_size_t, C.c_int64, _DP, _DP, _I64P, _VP, _VP,
                                    _I64P, _VP, _VP, _VP]
     L.fabm_solve_batch.restype = C.c_int
@@ -189,6 +196,8 @@ class Plan:
             self.handle = None
 
 
+# device scratch array of fabm_solve_noalloc (bytes, per device; fabm.h)
+FABM_NOALLOC_SCRATCH_BYTES = 64 << 20
 FABM_PLAN_INITIAL_SLOPE = 1
 FABM_PLAN_PER_COMPONENT_ORDER = 2
 
@@ -227,6 +236,15 @@ def fabm_solve(plan: Plan, workspace, alpha: float, h: float, N: int, y0, params
     _check(load().fabm_solve(plan.handle, _ptr(workspace), workspace.numel() * workspace.element_size(),
                              float(alpha), float(h), int(N), _ptr(y0), _ptr(params), _ptr(y_out),
                              _ptr(status), _stream(stream)), "fabm_solve")
+
+
+def fabm_solve_noalloc(plan: Plan, alpha: float, h: float, N: int, y0, params, y_out, status,
+                       stream=None):
+    """fabm_solve with the library's own device scratch array as the workspace
+    (nothing is allocated by the call)."""
+    _check(load().fabm_solve_noalloc(plan.handle, float(alpha), float(h), int(N), _ptr(y0),
+                                     _ptr(params), _ptr(y_out), _ptr(status), _stream(stream)),
+           "fabm_solve_noalloc")
 
 
 def fabm_solve_batch(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out, status,

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -29,6 +30,7 @@ struct fabm_plan_s {
     hipEvent_t stage_ev; // recorded after the staging copy; waited on before reuse
     bool stage_pending;
     uint64_t timeout_ticks;  // bound of every inter-workgroup wait (device wall clock)
+    bool info_ready = false;  // device, grid_G and timeout_ticks are set
     fabm::KernelTimer timer;   // optional per-kernel timing
     // schedule of the last batched BLOCKED call, keyed by its block counts
     std::vector<int32_t> sched_nb;
@@ -384,11 +386,12 @@ fabm_status split_init(const fabm_plan_s *pl, const Layout &L, char *base, int64
     return FABM_OK;
 }
 
-// Device-side resources of a plan, created at its first solve so that
-// fabm_plan itself touches no device.
-fabm_status ensure_device(fabm_plan_s *pl)
+// Launch parameters read from the device (attribute queries only, nothing
+// allocated): compute units for the whole-GPU kernel, the wait bound in
+// ticks of the constant clock.
+fabm_status device_info(fabm_plan_s *pl)
 {
-    if (pl->h_stage) return FABM_OK;
+    if (pl->info_ready) return FABM_OK;
     int cus = 0;
     HIP_TRY(hipGetDevice(&pl->device));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device));
@@ -399,6 +402,17 @@ fabm_status ensure_device(fabm_plan_s *pl)
         rate_khz <= 0)
         rate_khz = 100000;  // gfx9 constant clock: 100 MHz
     pl->timeout_ticks = (uint64_t)rate_khz * 1000u * kWaitTimeoutSeconds;
+    pl->info_ready = true;
+    return FABM_OK;
+}
+
+// Device-side resources of a plan, created at its first solve so that
+// fabm_plan itself touches no device.
+fabm_status ensure_device(fabm_plan_s *pl)
+{
+    if (pl->h_stage) return FABM_OK;
+    fabm_status ist = device_info(pl);
+    if (ist != FABM_OK) return ist;
     pl->stage_cap = sizeof(InstMeta) * (size_t)pl->desc.max_batch;
     hipError_t e = hipHostMalloc((void **)&pl->h_stage, pl->stage_cap, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -467,15 +481,20 @@ const fabm::BatchSchedule &stage_batch(fabm_plan_s *pl, char *stage, const Layou
     return BS;
 }
 
-// Shared body of fabm_solve, fabm_solve_batch and fabm_graph_solve_batch after
-// validation. `graph_stage` (graph builds only) is a pinned buffer owned by the
-// graph: the instance table is written there and its copy becomes a node of
-// the graph; otherwise the plan's staging buffer is used and guarded by an
-// event.
+// Instance entries a call without allocation may stage (on the host stack).
+constexpr int kNoAllocStageEntries = 4;
+
+// Shared body of fabm_solve, fabm_solve_batch, fabm_graph_solve_batch and
+// fabm_solve_noalloc after validation. `graph_stage` (graph builds only) is a
+// pinned buffer owned by the graph: the instance table is written there and
+// its copy becomes a node of the graph. With `no_alloc` the table is built on
+// the stack and written to the device by one small kernel per entry (no
+// pinned buffer, no event, no timer). Otherwise the plan's staging buffer is
+// used and guarded by an event.
 fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *alpha,
                       const double *h, const int64_t *N, const double *y0, const double *params,
                       const int64_t *row_off, double *y_out, int64_t *status, hipStream_t s,
-                      char *graph_stage = nullptr)
+                      char *graph_stage = nullptr, bool no_alloc = false)
 {
     const int d = pl->desc.dim;
     const Layout L = layout_for(pl, batch, N);
@@ -483,13 +502,16 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     if (L.path == Path::Wide)
         for (int64_t i = 1; i < batch; ++i)
             if (alpha[i] != alpha[0] || h[i] != h[0] || N[i] != N[0]) return FABM_ERR_UNSUPPORTED;
-    fabm_status st = ensure_device(pl);
+    alignas(64) char local_stage[sizeof(InstMeta) * kNoAllocStageEntries];
+    if (no_alloc && (L.stage_bytes > sizeof(local_stage) || L.stage_bytes % sizeof(InstMeta)))
+        return FABM_ERR_UNSUPPORTED;
+    fabm_status st = no_alloc ? device_info(pl) : ensure_device(pl);
     if (st != FABM_OK) return st;
-    if (!graph_stage) {
+    if (!graph_stage && !no_alloc) {
         if ((st = wait_staging(pl)) != FABM_OK) return st;
         if ((st = ensure_stage(pl, L.stage_bytes)) != FABM_OK) return st;
     }
-    char *stage = graph_stage ? graph_stage : pl->h_stage;
+    char *stage = graph_stage ? graph_stage : no_alloc ? local_stage : pl->h_stage;
 
     InstMeta *hm = (InstMeta *)(stage + L.meta);
     const bool pc = per_component(pl);
@@ -526,17 +548,25 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     char *base = (char *)ws;
     const fabm::BatchSchedule *BS = nullptr;
     if (L.path == Path::Blocked && batch > 1) BS = &stage_batch(pl, stage, L, batch, N);
-    if (graph_stage)
+    if (graph_stage) {
         HIP_TRY(hipMemcpyAsync(base, graph_stage, L.stage_bytes, hipMemcpyHostToDevice, s));
-    else if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK)
+    } else if (no_alloc) {
+        // the staged bytes are whole instance entries (checked above)
+        const InstMeta *e = (const InstMeta *)stage;
+        for (size_t k = 0; k < L.stage_bytes / sizeof(InstMeta); ++k)
+            if ((st = ok_or_device(fabm::launch_put_meta(e[k], (InstMeta *)base + k, s))) !=
+                FABM_OK)
+                return st;
+    } else if ((st = stage_copy(pl, L.stage_bytes, base, s)) != FABM_OK) {
         return st;
+    }
     const double *y1 = nullptr;
     if ((st = split_init(pl, L, base, batch, y0, y1, s)) != FABM_OK) return st;
 
     InstMeta *dmeta = (InstMeta *)(base + L.meta);
     double *W = (double *)(base + L.w);
     uint32_t *sync = (uint32_t *)(base + L.sync);
-    fabm::KernelTimer *T = pl->timer.on && !graph_stage ? &pl->timer : nullptr;
+    fabm::KernelTimer *T = pl->timer.on && !graph_stage && !no_alloc ? &pl->timer : nullptr;
     if (T) T->reset();
     if (T) HIP_TRY(T->begin(fabm::KC_WEIGHTS, s));
     const bool f32 = (L.path == Path::Blocked || L.path == Path::Wide) &&
@@ -935,6 +965,80 @@ fabm_status fabm_solve(fabm_plan_t plan, void *workspace, size_t workspace_bytes
     if (workspace_bytes < layout_for(plan, 1, &N).total) return FABM_ERR_WORKSPACE;
     return run_solve(plan, workspace, 1, &alpha, &h, &N, y0, params, nullptr, y_out, status,
                      stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Solves without allocation (fabm_solve_noalloc): the workspace is this
+// file-scope device array. Each device the library runs on holds its own copy
+// (FABM_NOALLOC_SCRATCH_BYTES) until the process ends. In host code `scratch`
+// names a host-side stand-in, never the device memory: the device address is
+// taken once per device with hipGetSymbolAddress and only that address is
+// passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[FABM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];  // device address of `scratch`, per device
+
+// Device address of the current device's scratch array, looked up on the
+// first call on that device (with it current).
+fabm_status scratch_address(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return FABM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p % kAlign) != 0) {
+            std::snprintf(g_last_error, sizeof g_last_error,
+                          "hipGetSymbolAddress(scratch): unusable address %p", p);
+            return FABM_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FABM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fabm_status fabm_solve_noalloc(fabm_plan_t plan, double alpha, double h, int64_t N,
+                               const double *y0, const double *params, double *y_out,
+                               int64_t *status, hipStream_t stream)
+{
+    g_last_error[0] = '\0';
+    if (!plan) return FABM_ERR_INVALID_ARG;
+    if (per_component(plan)) return FABM_ERR_UNSUPPORTED;
+    fabm_status st = check_alpha_h(alpha, h, has_slope(plan));
+    if (st != FABM_OK) return st;
+    if (N < 1 || N > plan->desc.max_steps) return FABM_ERR_INVALID_ARG;
+    if (!aligned8(y0) || !aligned8(y_out) || !aligned8(status)) return FABM_ERR_INVALID_ARG;
+    if (plan->n_params > 0 && !aligned8(params)) return FABM_ERR_INVALID_ARG;
+    // the per-trajectory paths only: the shared grid and the FFT far history
+    // stage more than one instance entry or build tables with library calls
+    if (plan->desc.fft_level > 0) return FABM_ERR_UNSUPPORTED;
+    const Layout L = layout_for(plan, 1, &N);
+    if (L.path != Path::Blocked && L.path != Path::Direct) return FABM_ERR_UNSUPPORTED;
+    if (L.total > (size_t)FABM_NOALLOC_SCRATCH_BYTES) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "fabm_solve_noalloc: N = %lld needs %zu bytes of scratch, the library "
+                      "holds %zu",
+                      (long long)N, L.total, (size_t)FABM_NOALLOC_SCRATCH_BYTES);
+        return FABM_ERR_WORKSPACE;
+    }
+    void *ws = nullptr;
+    if ((st = scratch_address(&ws)) != FABM_OK) return st;
+    return run_solve(plan, ws, 1, &alpha, &h, &N, y0, params, nullptr, y_out, status, stream,
+                     nullptr, true);
 }
 
 fabm_status fabm_solve_batch(fabm_plan_t plan, void *workspace, size_t workspace_bytes,

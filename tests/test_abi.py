@@ -328,3 +328,27 @@ def test_fft_far_schedule_covers_far_region_once(fabm, NB):
         fabm.fabm_fft_far_schedule(NB, 16, 0)
     with pytest.raises(fabm.FabmError):
         fabm.fabm_fft_far_schedule(NB, 1, NB - 1)
+
+
+def test_noalloc_host_checks(fabm):
+    """fabm_solve_noalloc refuses on the host, before any device call
+    (placeholder device addresses are never touched): a workspace above the
+    scratch array, the shared grid, the FFT far history, bad arguments."""
+    import ctypes as C
+    lib = fabm.load()
+    fake = C.c_void_p(1 << 40)
+    big = fabm.fabm_plan("chen", 3, "blocked", "fp64", 1, 1 << 20)
+    assert fabm.fabm_workspace_size(big, [1 << 20]) > fabm.FABM_NOALLOC_SCRATCH_BYTES
+    assert lib.fabm_solve_noalloc(big.handle, 0.95, 0.001, 1 << 20, fake, fake, fake, fake,
+                                  None) == fabm.FABM_ERR_WORKSPACE
+    assert b"scratch" in lib.fabm_last_error()
+    assert lib.fabm_solve_noalloc(big.handle, 0.0, 0.001, 100, fake, fake, fake, fake,
+                                  None) == fabm.FABM_ERR_INVALID_ARG
+    assert lib.fabm_solve_noalloc(big.handle, 0.9, 0.001, (1 << 20) + 1, fake, fake, fake,
+                                  fake, None) == fabm.FABM_ERR_INVALID_ARG
+    wide = fabm.fabm_plan("linear", 8, "blocked", "fp64", 1, 1000)
+    assert lib.fabm_solve_noalloc(wide.handle, 0.8, 0.01, 1000, fake, fake, fake, fake,
+                                  None) == fabm.FABM_ERR_UNSUPPORTED
+    fft = fabm.fabm_plan("vdp", 2, "blocked", "fp64", 1, 100000, fft_level=2)
+    assert lib.fabm_solve_noalloc(fft.handle, 0.9, 0.01, 5000, fake, fake, fake, fake,
+                                  None) == fabm.FABM_ERR_UNSUPPORTED
