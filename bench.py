@@ -277,6 +277,16 @@ def bench_batch(F, W, args, workload=None, prec=None, steps=None, warmup=None, r
         tune = F.fabm_tune(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
         print(f"# tune: {tune}", file=sys.stderr, flush=True)
     per = _timed(call, steps, warmup, f"{workload} {prec}")
+    graph = None
+    if workload == "rossler_batch" and args.batch_path == "blocked":
+        # the same solve captured once as a HIP graph and replayed: every step
+        # launch of the pipeline in one graph launch
+        g = F.fabm_graph_solve_batch(plan, ws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
+        gper = _timed(lambda: g.launch(torch.cuda.current_stream()), steps, 1,
+                      f"{workload} {prec} graph")
+        del g
+        graph = dict(solve_s=float(np.mean(gper)), launches_per_graph="every step launch",
+                     eager_solve_s=float(np.mean(per)))
     kt = {}
     if not args.no_kernel_times:
         F.fabm_plan_set_profiling(plan, True)
@@ -309,6 +319,7 @@ def bench_batch(F, W, args, workload=None, prec=None, steps=None, warmup=None, r
            "rows_counted": "rows formed: N_i, or status_i - 1 for instances that left every "
                            "bounded set",
            "tune": tune,
+           "graph_replay": graph,
            "kernel_times_s": {k: v[0] for k, v in kt.items()},
            "kernel_launches": {k: v[1] for k, v in kt.items()}}
     instr = sum(v[0] for v in kt.values())

@@ -120,8 +120,8 @@ typedef struct {
     int32_t tile_L;          /* BLOCKED block length: 0 (planner's choice), 256 (per
                               * trajectory) or 64 (shared grid); other multiples of 64
                               * are UNSUPPORTED */
-    int32_t flags;           /* FABM_PLAN_INITIAL_SLOPE | FABM_PLAN_PER_COMPONENT_ORDER
-                              * or 0; other bits INVALID_ARG */
+    int32_t flags;           /* FABM_PLAN_INITIAL_SLOPE | FABM_PLAN_PER_COMPONENT_ORDER |
+                              * FABM_PLAN_ADJOINT_CHECKPOINT or 0; other bits INVALID_ARG */
     int32_t fft_level;       /* 0: every far window on the matrix cores. l in 1..15:
                               * sub-quadratic far history, see below */
 } fabm_plan_desc;
@@ -180,6 +180,20 @@ fabm_status fabm_fft_far_schedule(int32_t NB, int32_t level, int32_t s, int32_t 
  * shared grid (LINEAR d > 4, FP16X2, tile_L 64) is UNSUPPORTED, and so is
  * fabm_solve (one alpha): a single trajectory is a batch of one. */
 #define FABM_PLAN_PER_COMPONENT_ORDER 2
+
+/* Plan flag: block checkpoints for the adjoint calls. The forward pass keeps
+ * only what the far sums need anyway (the history f and the near + far sums
+ * of every 256-row block), not every trajectory and predictor row; the reverse
+ * pass re-forms the rows of each forward block shortly before it reaches them
+ * (the band of that block walked again from its stored sums, its incoming band
+ * sums re-formed from the previous block's history), four blocks per group of
+ * reverse launches, into a ring of five blocks per instance. The re-formed
+ * rows are bitwise the forward's, so the gradients are bitwise those of a plan
+ * without the flag; the adjoint workspace shrinks by 16 d (N_i + 1) bytes per
+ * instance (less rings of 60 KiB x d), at the cost of a second band walk per
+ * block. fabm_adjoint_forward writes the rows straight to y_out. No effect on
+ * the solve calls. */
+#define FABM_PLAN_ADJOINT_CHECKPOINT 4
 
 /* A plan is used by one host thread at a time: calls that share a plan share
  * its pinned staging buffer and schedule cache. Different plans are
@@ -298,17 +312,29 @@ void fabm_graph_destroy(fabm_graph_t graph);
  * checks as fabm_solve_batch; y_out and status receive a valid result) once
  * untimed and then once per candidate launch shape of the plan's path, times
  * each with events on `stream`, and keeps the fastest in the plan for its
- * later calls. Blocks the host until the runs end. Results of a plan differ
- * between launch shapes by rounding only (the summation order of the far
- * sums changes); a tuned plan is bitwise deterministic.
+ * later calls (also for its adjoint calls' forward pass). Blocks the host
+ * until the runs end. A tuned plan is bitwise deterministic.
  *   single-trajectory BLOCKED: far workgroups per step launch {32, 64, 128, 254}
+ *                (results bitwise independent of the choice)
+ *   batched BLOCKED (batch > 1): source blocks per group of far windows
+ *                {1, 2, 4}: one launch in every P adds the windows of its P
+ *                latest source blocks to every later target (one read and
+ *                write of the target's sums per P blocks), the others only
+ *                to the targets whose band comes first (results bitwise
+ *                independent of the choice; default 2)
  *   shared grid: far workgroups a launch aims for {256, 512, 1024, 2048, 4096}
  *                (the source range of a block is split until the column tiles
- *                times the splits reach it, at most 64 splits)
+ *                times the splits reach it, at most 64 splits; results differ
+ *                by rounding: the split changes the summation order)
  *   other paths: nothing to choose (knob NONE).
  * report (host, may be NULL) receives the candidates, their times and the
  * index chosen. */
-typedef enum { FABM_TUNE_NONE = 0, FABM_TUNE_FAR_WORKGROUPS = 1, FABM_TUNE_SPLIT_TARGET = 2 } fabm_tune_knob;
+typedef enum {
+    FABM_TUNE_NONE = 0,
+    FABM_TUNE_FAR_WORKGROUPS = 1,
+    FABM_TUNE_SPLIT_TARGET = 2,
+    FABM_TUNE_SOURCE_GROUP = 3
+} fabm_tune_knob;
 typedef struct {
     int32_t knob;       /* fabm_tune_knob */
     int32_t n;          /* candidates timed */

@@ -9,9 +9,18 @@ built, every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 from dataclasses import dataclass
+
+_exiting = False  # set when the interpreter starts to exit
+
+
+@atexit.register
+def _mark_exit():
+    global _exiting
+    _exiting = True
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "libfabm.so")
@@ -191,7 +200,10 @@ class Plan:
     per_component_order: bool = False  # calls pass alpha as [batch][d]
 
     def __del__(self):
-        if self.handle and _lib is not None:
+        # at interpreter exit the process is ending: leave the pinned staging
+        # buffer and event to the OS rather than call into a HIP runtime that
+        # may already be tearing down
+        if self.handle and _lib is not None and not _exiting:
             _lib.fabm_plan_destroy(self.handle)
             self.handle = None
 
@@ -200,20 +212,24 @@ class Plan:
 FABM_NOALLOC_SCRATCH_BYTES = 64 << 20
 FABM_PLAN_INITIAL_SLOPE = 1
 FABM_PLAN_PER_COMPONENT_ORDER = 2
+FABM_PLAN_ADJOINT_CHECKPOINT = 4
 
 
 def fabm_plan(system, dim: int, path="auto", far_prec="fp64", max_batch: int = 1,
               max_steps: int = 1, max_total_steps: int = 0, tile_L: int = 0,
               initial_slope: bool = False, per_component_order: bool = False,
-              fft_level: int = 0) -> Plan:
+              fft_level: int = 0, adjoint_checkpoint: bool = False) -> Plan:
     """fft_level > 0: the far history of one BLOCKED trajectory by FFT convolution
-    of dyadic block squares of level >= fft_level (sub-quadratic variant)."""
+    of dyadic block squares of level >= fft_level (sub-quadratic variant).
+    adjoint_checkpoint: the adjoint calls keep block checkpoints and re-form the
+    rows in the reverse pass instead of storing every row."""
     L = load()
     desc = _PlanDesc(_enum(system, SYSTEMS), int(dim), _enum(path, PATHS),
                      _enum(far_prec, FAR_PRECS), int(max_batch), int(max_steps),
                      int(max_total_steps), int(tile_L),
                      (FABM_PLAN_INITIAL_SLOPE if initial_slope else 0) |
-                     (FABM_PLAN_PER_COMPONENT_ORDER if per_component_order else 0),
+                     (FABM_PLAN_PER_COMPONENT_ORDER if per_component_order else 0) |
+                     (FABM_PLAN_ADJOINT_CHECKPOINT if adjoint_checkpoint else 0),
                      int(fft_level))
     h = C.c_void_p()
     ws = C.c_size_t()
@@ -267,7 +283,7 @@ class _TuneReport(C.Structure):
                 ("seconds", C.c_double * 8), ("chosen", C.c_int32)]
 
 
-TUNE_KNOBS = ("none", "far_workgroups", "split_target")
+TUNE_KNOBS = ("none", "far_workgroups", "split_target", "source_group")
 
 
 def fabm_tune(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out, status,
@@ -301,7 +317,7 @@ class Graph:
         _check(load().fabm_graph_launch(self.handle, _stream(stream)), "fabm_graph_launch")
 
     def __del__(self):
-        if self.handle and _lib is not None:
+        if self.handle and _lib is not None and not _exiting:
             _lib.fabm_graph_destroy(self.handle)
             self.handle = None
 
@@ -494,7 +510,8 @@ def solve_batch(system, thetas, alphas, hs, Ns, y0s, path="auto", far_prec="fp64
     return y, row_off, st
 
 
-def adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, plan: Plan | None = None):
+def adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, plan: Plan | None = None,
+                  checkpoint: bool = False):
     """Gradients of sum <gy, y> for a ragged batch (gy rows placed as solve_batch
     returns y); returns (gy0 shaped like y0s, gtheta [B, n_params], status)
     device tensors (with [B, 2, d] initial values gy0 holds dL/dy(0), dL/dy'(0))."""
@@ -510,7 +527,8 @@ def adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, plan: Plan | None = N
     row_off[1:] = np.cumsum(Ns + 1)[:-1]
     if plan is None:
         plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
-                         initial_slope=two, per_component_order=pc)
+                         initial_slope=two, per_component_order=pc,
+                         adjoint_checkpoint=checkpoint)
     ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
     gy0 = torch.empty_like(y0s)
     gth = torch.empty_like(th)
@@ -530,7 +548,7 @@ def _solve_function():
         solve_batch)."""
 
         @staticmethod
-        def forward(ctx, y0s, thetas, system, alphas, hs, Ns):
+        def forward(ctx, y0s, thetas, system, alphas, hs, Ns, checkpoint=False):
             # the forward pass of the adjoint: the workspace it leaves (rows,
             # predictor rows, history) is kept for the backward pass
             import numpy as np
@@ -544,7 +562,8 @@ def _solve_function():
             row_off = np.zeros(B, dtype=np.int64)
             row_off[1:] = np.cumsum(Ns + 1)[:-1]
             plan = fabm_plan(system, d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
-                             initial_slope=two, per_component_order=al.ndim == 2)
+                             initial_slope=two, per_component_order=al.ndim == 2,
+                             adjoint_checkpoint=bool(checkpoint))
             ws = _workspace(fabm_adjoint_workspace_size(plan, Ns))
             y = torch.empty((int((Ns + 1).sum()), d), dtype=torch.float64, device="cuda")
             st = torch.zeros(B, dtype=torch.int64, device="cuda")
@@ -563,11 +582,12 @@ def _solve_function():
             fabm_adjoint_reverse(plan, ws, al, hh, Ns, y0d, th, row_off,
                                  _dev(gy).contiguous(), gy0, gth)
             ctx.meta = None  # release the workspace
-            return gy0, gth, None, None, None, None
+            return gy0, gth, None, None, None, None, None
 
     return FabmSolveBatch
 
 
-def solve_batch_autograd(y0s, thetas, system, alphas, hs, Ns):
-    """Differentiable batched solve (torch autograd; see FabmSolveBatch)."""
-    return _solve_function().apply(y0s, thetas, system, alphas, hs, Ns)
+def solve_batch_autograd(y0s, thetas, system, alphas, hs, Ns, checkpoint: bool = False):
+    """Differentiable batched solve (torch autograd; see FabmSolveBatch).
+    checkpoint: block checkpoints in the adjoint (FABM_PLAN_ADJOINT_CHECKPOINT)."""
+    return _solve_function().apply(y0s, thetas, system, alphas, hs, Ns, checkpoint)

@@ -57,6 +57,7 @@ struct AdjView {
     const uint32_t *dead;  // forward non-finite flag
     int NB;
     int slope;             // y'(0) partials wanted
+    int ring;              // Y, YP are rings of this many 256-row blocks (0: every row)
 };
 
 template <int D>
@@ -67,8 +68,8 @@ __device__ __forceinline__ AdjView adj_view(const AdjArgs &A, int i, int np)
     return AdjView{m,
                    A.cmeta ? A.cmeta + (int64_t)i * D : nullptr,
                    A.params + m->p_off,
-                   A.Y + m->f_off * D,
-                   A.YP + m->f_off * D,
+                   A.ring ? A.Y + (int64_t)i * A.ring * kBlk * D : A.Y + m->f_off * D,
+                   A.ring ? A.YP + (int64_t)i * A.ring * kBlk * D : A.YP + m->f_off * D,
                    A.G + m->row_off * D,
                    A.W + m->w_off,
                    A.UV + 2 * b.fc_off,
@@ -78,7 +79,8 @@ __device__ __forceinline__ AdjView adj_view(const AdjArgs &A, int i, int np)
                    A.fbar0 + (int64_t)i * D,
                    A.dead + i,
                    b.NB,
-                   A.slope};
+                   A.slope,
+                   A.ring};
 }
 
 // ---------------------------------------------------------------------------
@@ -150,10 +152,12 @@ __device__ __forceinline__ void band_adj(const AdjView &A, int J, char *smem)
     double yv[D], ypv[D], gv[D];
     const bool steps = tid < nstep;
     const int64_t n = N - (r0 + tid);
+    // row n of the forward: its own row, or its place in the ring of blocks
+    const int64_t nr = A.ring ? ((n >> 8) % A.ring) * kBlk + (n & (kBlk - 1)) : n;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        yv[i] = steps ? A.Y[n * D + i] : 0.0;
-        ypv[i] = steps ? A.YP[n * D + i] : 0.0;
+        yv[i] = steps ? A.Y[nr * D + i] : 0.0;
+        ypv[i] = steps ? A.YP[nr * D + i] : 0.0;
         gv[i] = steps ? A.G[n * D + i] : 0.0;
     }
     constexpr int NPR = NP;
@@ -480,7 +484,8 @@ size_t adj_smem_bytes(int d, bool pc)
 
 template <int SYS, int D, bool PC>
 static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, const int *far_off,
-                                    hipStream_t st, KernelTimer *T, const char **where)
+                                    hipStream_t st, KernelTimer *T, const char **where,
+                                    const BatchArgs *fwd, const RecompArgs *rec)
 {
 #define FABM_ADJ_TRY(what, expr)           \
     do {                                   \
@@ -500,6 +505,14 @@ static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, co
         const int nb = S.nband[k], nn = S.nnear[k], nf = S.nfar[k];
         const int nfw = S.far_off[(size_t)S.far_base[k] + (size_t)nf];
         const int grid = nb + nn + nfw;
+        if (rec && (s + 1) % rec->G == 0 && nb > 0) {
+            // forward rows of reverse launches s .. s + G - 1 (reversed blocks
+            // s + 1 .. s + G); launch s reads none of the blocks it replaces
+            if (T) FABM_ADJ_TRY("timer begin", T->begin(KC_ADJOINT, st));
+            FABM_ADJ_TRY("launch k_recompute_batch",
+                         launch_recompute(SYS, D, *fwd, *rec, s + 1, nb, st));
+            if (T) FABM_ADJ_TRY("timer end", T->end(st));
+        }
         if (grid == 0) continue;
         if (T) FABM_ADJ_TRY("timer begin", T->begin(KC_ADJOINT, st));
         hipLaunchKernelGGL((k_adj_batch<SYS, D, PC>), dim3(grid), dim3(kBatchThreads), smem, st,
@@ -515,12 +528,17 @@ static hipError_t enqueue_adjoint_t(const AdjArgs &A, const BatchSchedule &S, co
 }
 
 hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule &S,
-                           const int *far_off, hipStream_t s, KernelTimer *T, const char **where)
+                           const int *far_off, hipStream_t s, KernelTimer *T, const char **where,
+                           const BatchArgs *fwd, const RecompArgs *rec)
 {
-#define FABM_ADJ_CASE(SS, DD)                                                          \
-    if (sys == SS && d == DD)                                                          \
-        return A.cmeta ? enqueue_adjoint_t<SS, DD, true>(A, S, far_off, s, T, where)   \
-                       : enqueue_adjoint_t<SS, DD, false>(A, S, far_off, s, T, where);
+    if ((rec != nullptr) != (A.ring != 0) || (rec && (!fwd || A.ring != rec->G + 1))) {
+        *where = "adjoint: block-checkpoint arguments inconsistent";
+        return hipErrorInvalidValue;
+    }
+#define FABM_ADJ_CASE(SS, DD)                                                                \
+    if (sys == SS && d == DD)                                                                \
+        return A.cmeta ? enqueue_adjoint_t<SS, DD, true>(A, S, far_off, s, T, where, fwd, rec) \
+                       : enqueue_adjoint_t<SS, DD, false>(A, S, far_off, s, T, where, fwd, rec);
     FABM_ADJ_CASE(SYS_LINEAR, 1)
     FABM_ADJ_CASE(SYS_LINEAR, 2)
     FABM_ADJ_CASE(SYS_LINEAR, 3)

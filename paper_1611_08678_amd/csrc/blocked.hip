@@ -126,11 +126,13 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         ig2v[k] = PC ? A.cmeta[k].ig2 : m.ig2;
     }
 
+    // rows go to Y and YP at row t - yrow0 (0 except in a recompute ring)
+    const int64_t ro = (t0 - A.yrow0) * D;
     // a non-finite state in an earlier block ends the trajectory
     if (*A.dead != 0u) {
         for (int e = tid; e < nrows * D; e += nthr) {
-            A.Y[t0 * D + e] = __builtin_nan("");
-            if constexpr (YPOUT) A.YP[t0 * D + e] = __builtin_nan("");
+            if (A.Y) A.Y[ro + e] = __builtin_nan("");
+            if constexpr (YPOUT) A.YP[ro + e] = __builtin_nan("");
         }
         return;
     }
@@ -421,12 +423,17 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     // rows of this block: final ones from LDS, NaN from the first non-finite on
     const int dead = *s_dead;
     const int valid = dead == -1 ? nrows : (dead < 0 ? 0 : dead);
-    for (int e = tid; e < nrows * D; e += nthr)
-        A.Y[t0 * D + e] = e / D < valid ? sY[e] : __builtin_nan("");
+    if (A.Y) {
+        for (int e = tid; e < nrows * D; e += nthr)
+            A.Y[ro + e] = e / D < valid ? sY[e] : __builtin_nan("");
+    }
     if constexpr (YPOUT) {
         for (int e = tid; e < nrows * D; e += nthr)
-            A.YP[t0 * D + e] = e / D < valid ? sYP[e] : __builtin_nan("");
+            A.YP[ro + e] = e / D < valid ? sYP[e] : __builtin_nan("");
     }
+    // a recomputation leaves the history and the next block's sums alone
+    // (they already hold these values)
+    if (A.recompute) return;
     for (int e = tid; e < valid; e += nthr) {
 #pragma unroll
         for (int i = 0; i < D; ++i) A.Fc[i * pitch + t0 + e] = sF[e * D + i];
@@ -451,7 +458,10 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 // distinct even bank pairs.
 // ---------------------------------------------------------------------------
 constexpr int kSrcCols = 31;
-constexpr int kPairCols = 47;  // blocks s - 2 .. s: the windows of sources s - 1 and s
+// Columns staged for the windows of NP consecutive source blocks s - NP + 1 ..
+// s (blocks s - NP .. s): 31 for one block, 47 for two, 79 for four.
+template <int NP>
+constexpr int group_cols() { return kTile * (NP + 1) - 1; }
 constexpr int kColPitch = 17;
 // Result layout of v_mfma_f32_16x16x4f32 (measured on gfx950 with one-hot
 // operands): element v of lane l is row 4 (l / 16) + v, column l % 16 -- not
@@ -464,8 +474,9 @@ constexpr size_t staged_bytes()
     return sizeof(T) * D * kSrcCols * kColPitch;
 }
 
-// NC = kSrcCols: columns 16 s - 15 .. 16 s + 15; NC = kPairCols: the 16 columns
-// before those as well (the window of source block s - 1 too). Rows below
+// NC = kSrcCols: columns 16 s - 15 .. 16 s + 15; NC = group_cols<NP>(): the
+// 16 (NP - 1) columns before those as well (the windows of source blocks
+// s - NP + 1 .. s - 1 too). Rows below
 // `lo` are staged as zero.
 template <int D, typename T, int NC = kSrcCols>
 __device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB, int64_t lo = 0)
@@ -556,64 +567,69 @@ __device__ __forceinline__ void window_lag_f32(flt4 (&acc)[2][D], const float *_
 // instruction (measured on gfx950 with one-hot operands).
 __device__ __forceinline__ int f32_result_row(int l, int v) { return kF32RowMajorLanes ? 4 * (l >> 4) + v : 4 * v + (l >> 4); }
 
-// Far window m = J - s of target block J in binary32: the window's sums are
-// formed in binary32 and added to the binary64 sums of the target.
-// PAIR: the windows of sources s - 1 (staged columns from 0) and s (from 16),
-// out of kPairCols staged columns; each window is summed in binary32 and added
-// to the binary64 sums in source order. `first`: no earlier window has
-// written the target's sums.
-template <int D, bool PAIR = false, bool PC = false>
+// Far windows of target block J in binary32, from the NP source blocks
+// s - NP + 1 .. s (source s - NP + 1 + p in staged columns from 16 p): each
+// window's sums are formed in binary32 and added, in source order, to the
+// binary64 sums of the target. `first`: no earlier window has written them.
+template <int D, int NP = 1, bool PC = false>
 __device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, const float *sB,
                                                bool first)
 {
-    constexpr int NC = PAIR ? kPairCols : kSrcCols;
+    constexpr int NC = NP == 1 ? kSrcCols : group_cols<NP>();
     const InstMeta m = A.meta[0];
     const float *wb = A.W32, *wa = wb + m.wlen;
     const int64_t cw = 2 * m.wlen;  // binary32 b, a of the next component (PC)
     const int lane = threadIdx.x & (kWave - 1);
     double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
-    flt4 acc[2][D], acc2[2][D];
+    // binary64 sums keep the binary64 result order (element sigma/4 of lane
+    // 16 (sigma % 4) + rho)
+    int e[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int sig = f32_result_row(lane, v), rho = lane & 15;
+        e[v] = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
+    }
+    double x[2][D][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int i = 0; i < D; ++i) acc[t][i] = acc2[t][i] = (flt4){0.0f, 0.0f, 0.0f, 0.0f};
-    const int64_t mm = J - s;
-    if constexpr (PAIR) {
-#pragma unroll 2
-        for (int u = 0; u < kTile; ++u)
-            window_lag_f32<D, NC, PC>(acc, wb, wa, sB, mm + 1, u, kTile - 1, cw);
-#pragma unroll 2
-        for (int u = 0; u < kTile; ++u)
-            window_lag_f32<D, NC, PC>(acc2, wb, wa, sB, mm, u, 2 * kTile - 1, cw);
-    } else {
-#pragma unroll 2
-        for (int u = 0; u < kTile; ++u) window_lag_f32<D, NC, PC>(acc, wb, wa, sB, mm, u, kTile - 1, cw);
-    }
+        for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        // binary64 sums keep the binary64 result order (element sigma/4 of lane
-        // 16 (sigma % 4) + rho)
-        const int sig = f32_result_row(lane, v), rho = lane & 15;
-        const int e = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
+            for (int v = 0; v < 4; ++v) x[t][i][v] = first ? 0.0 : aj[(t * D + i) * kBlk + e[v]];
+#pragma unroll 1
+    for (int p = 0; p < NP; ++p) {
+        flt4 acc[2][D];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                double *p = aj + (t * D + i) * kBlk + e;
-                double x = (first ? 0.0 : *p) + (double)acc[t][i][v];
-                if constexpr (PAIR) x += (double)acc2[t][i][v];
-                *p = x;
-            }
+            for (int i = 0; i < D; ++i) acc[t][i] = (flt4){0.0f, 0.0f, 0.0f, 0.0f};
+        const int64_t mm = J - (s - NP + 1 + p);
+#pragma unroll 2
+        for (int u = 0; u < kTile; ++u)
+            window_lag_f32<D, NC, PC>(acc, wb, wa, sB, mm, u, kTile * (p + 1) - 1, cw);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) x[t][i][v] += (double)acc[t][i][v];
     }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) aj[(t * D + i) * kBlk + e[v]] = x[t][i][v];
 }
 
-// Far window m = J - s of target block J (one wavefront; staged columns
-// rho - u + 15), added to the target's sums in place.
-template <int D, bool PAIR = false, bool PC = false>
+// Far windows of target block J from the NP source blocks s - NP + 1 .. s
+// (one wavefront; source s - NP + 1 + p in staged columns rho - u + 16 p + 15),
+// added to the target's sums in place, in source order.
+template <int D, int NP = 1, bool PC = false>
 __device__ __forceinline__ void far_target(const InstView &A, int s, int J, const double *sB,
                                            bool first)
 {
-    constexpr int NC = PAIR ? kPairCols : kSrcCols;
+    constexpr int NC = NP == 1 ? kSrcCols : group_cols<NP>();
     const InstMeta m = A.meta[0];
     const double *wb = A.W, *wa = wb + m.wlen;
     const int64_t cw = 3 * m.wlen;
@@ -627,16 +643,14 @@ __device__ __forceinline__ void far_target(const InstView &A, int s, int J, cons
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 acc[t][i][v] = first ? 0.0 : aj[((t * D + i) * 4 + v) * kWave];
-    const int64_t mm = J - s;
-    if constexpr (PAIR) {
-        // source block s - 1 first: the order of the one-window launches
+#pragma unroll 1
+    for (int p = 0; p < NP; ++p) {
+        // oldest source block first: the order of the one-window launches
+        const int64_t mm = J - (s - NP + 1 + p);
 #pragma unroll 2
         for (int u = 0; u < kTile; ++u)
-            window_lag<D, NC, PC>(acc, wb, wa, sB, mm + 1, u, kTile - 1, cw);
+            window_lag<D, NC, PC>(acc, wb, wa, sB, mm, u, kTile * (p + 1) - 1, cw);
     }
-#pragma unroll 2
-    for (int u = 0; u < kTile; ++u)
-        window_lag<D, NC, PC>(acc, wb, wa, sB, mm, u, PAIR ? 2 * kTile - 1 : kTile - 1, cw);
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -745,7 +759,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
         for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
-            far_target<D, false, PC>(V, s, J, sB, s == 0);
+            far_target<D, 1, PC>(V, s, J, sB, s == 0);
     } else {
         float *sB = (float *)smem;
         stage_sources<D, float>(V, s, sB, flo);
@@ -753,7 +767,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
         for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
-            far_target_f32<D, false, PC>(V, s, J, sB, s == 0);
+            far_target_f32<D, 1, PC>(V, s, J, sB, s == 0);
     }
 }
 
@@ -770,7 +784,7 @@ __device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
                     A.params + m->p_off,
                     A.y0 + (int64_t)i * D,
                     A.y1 ? A.y1 + (int64_t)i * D : nullptr,
-                    A.Y + m->row_off * D,
+                    A.Y ? A.Y + m->row_off * D : nullptr,
                     A.YP ? A.YP + m->row_off * D : nullptr,
                     A.W + m->w_off,
                     A.W32 ? A.W32 + m->w_off / 3 * 2 : nullptr,
@@ -784,7 +798,7 @@ __device__ __forceinline__ InstView batch_view(const BatchArgs &A, int i)
 template <int SYS, int D, bool F32, bool YPOUT, bool PC = false>
 __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s, int nband,
                                                               int nnear, const int *far_off,
-                                                              int nfar)
+                                                              int nfar, int P)
 {
     extern __shared__ __align__(16) char smem[];
     int q = blockIdx.x;
@@ -811,18 +825,25 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
     }
     const InstView V = batch_view<D>(A, inst);
     if (*V.dead != 0u) return;  // this trajectory has ended; its later rows are NaN
-    // Far windows in pairs of source blocks: an odd launch s adds the windows of
-    // sources s - 1 and s to every target J >= s + 3 with one read and write of
-    // its sums; an even launch adds source s to target s + 3 only (the one
-    // target whose band comes before the next odd launch). Every target gets
-    // every source block in the same order as one window per launch.
-    const bool pair = s > 0 && (s & 1) != 0;
+    // Far windows in groups of P source blocks (P = 1, 2 or 4): a launch s with
+    // (s + 1) % P == 0 adds the windows of sources s - P + 1 .. s to every
+    // target J >= s + 3 with one read and write of its sums; the other
+    // launches add source s only to the targets whose band comes before the
+    // next such launch sb (J <= sb + 2). Every target gets every source block
+    // in the same order as with one window per launch, so the results do not
+    // depend on P.
+    const bool big = P == 1 || ((s + 1) % P == 0 && s >= P - 1);
+    const int sb = s + (P - 1 - s % P);
     const int J = first + (threadIdx.x >> 6);
-    const bool mine = first >= 0 && J < V.NB && (pair || J == s + 3);
+    const bool mine = first >= 0 && J < V.NB && (big || J <= sb + 2);
+    // the first write of a target's sums: launch 0, or the first group
+    const bool fw = s == 0 || (big && s == P - 1);
     if (first < 0 || !F32) {
         double *sB = (double *)smem;
-        if (first >= 0 && pair)
-            stage_sources<D, double, kPairCols>(V, s, sB);
+        if (first >= 0 && big && P == 4)
+            stage_sources<D, double, group_cols<4>()>(V, s, sB);
+        else if (first >= 0 && big && P == 2)
+            stage_sources<D, double, group_cols<2>()>(V, s, sB);
         else
             stage_sources<D, double>(V, s, sB);
         __syncthreads();
@@ -832,25 +853,97 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
             return;
         }
         if (mine) {
-            if (pair)
-                far_target<D, true, PC>(V, s, J, sB, s <= 1);
+            if (big && P == 4)
+                far_target<D, 4, PC>(V, s, J, sB, fw);
+            else if (big && P == 2)
+                far_target<D, 2, PC>(V, s, J, sB, fw);
             else
-                far_target<D, false, PC>(V, s, J, sB, s <= 1);
+                far_target<D, 1, PC>(V, s, J, sB, fw);
         }
     } else {
         float *sB = (float *)smem;
-        if (pair)
-            stage_sources<D, float, kPairCols>(V, s, sB);
+        if (big && P == 4)
+            stage_sources<D, float, group_cols<4>()>(V, s, sB);
+        else if (big && P == 2)
+            stage_sources<D, float, group_cols<2>()>(V, s, sB);
         else
             stage_sources<D, float>(V, s, sB);
         __syncthreads();
         if (mine) {
-            if (pair)
-                far_target_f32<D, true, PC>(V, s, J, sB, s <= 1);
+            if (big && P == 4)
+                far_target_f32<D, 4, PC>(V, s, J, sB, fw);
+            else if (big && P == 2)
+                far_target_f32<D, 2, PC>(V, s, J, sB, fw);
             else
-                far_target_f32<D, false, PC>(V, s, J, sB, s <= 1);
+                far_target_f32<D, 1, PC>(V, s, J, sB, fw);
         }
     }
+}
+
+// Forward block of the reverse pass's next group (layout in fabm_blocked.h).
+// Reversed block J' covers forward rows (N - 256 J' - 256, N - 256 J'], i.e.
+// forward blocks klo(J') = floor((N - 256 J' - 255) / 256) .. floor((N -
+// 256 J') / 256) <= klo(J') + 1. The group of reverse launches J .. J + G - 1
+// needs klo(J) - G + 1 .. klo(J) + 1; klo(J) + 1 (when needed) was formed for
+// the group before, except for J = 0. Workgroup q forms block
+// start - q % (G + 1) of instance order[q / (G + 1)], start = klo(J), or the
+// highest block for J = 0.
+__device__ __forceinline__ int64_t floor_div256(int64_t x) { return x >= 0 ? x / 256 : -((255 - x) / 256); }
+
+template <int SYS, int D, bool PC = false>
+__global__ __launch_bounds__(kBatchThreads) void k_recompute_batch(BatchArgs A, RecompArgs R,
+                                                                   int J)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int G = R.G, slots = G + 1;
+    const int q = blockIdx.x, inst = A.order[q / slots], j = q % slots;
+    InstView V = batch_view<D>(A, inst);
+    const InstMeta m = V.meta[0];
+    const int64_t N = m.N;
+    const int64_t klo = floor_div256(N - (int64_t)kBlk * J - (kBlk - 1));
+    const int64_t khi = floor_div256(N - (int64_t)kBlk * J);
+    const int64_t K = (J == 0 ? khi : klo) - j;
+    if (K < 0 || K < klo - (G - 1) || K >= V.NB) return;
+    if (*V.dead != 0u) return;  // the forward blew up: the gradients are NaN
+    const int slot = (int)(K % slots);
+    const int64_t rs = (int64_t)inst * slots + slot;
+    double *cb = R.rcarry + rs * 2 * 2 * D * kBlk;
+    const int row = threadIdx.x;
+    if (K >= 1) {
+        // band sums of block K from the rows of block K - 1, formed as the
+        // forward band forms them: ascending rows, one fma per row (block 0
+        // starts from its row 0 with c_{T-1} in the corrector)
+        const int64_t pitch = (int64_t)V.NB * kBlk, tp = (K - 1) * kBlk;
+        const double *wb = V.W, *wa = wb + m.wlen, *wc = wa + m.wlen;
+        const int64_t cw = 3 * m.wlen;
+        double *cin = cb + (K & 1) * 2 * D * kBlk;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int64_t o = PC ? i * cw : 0;
+            const double *fi = V.Fc + i * pitch;
+            double pn = 0.0, cn = 0.0;
+            int t = 0;
+            if (K == 1) {
+                pn = wb[o + kBlk + row - 1] * fi[0];
+                cn = wc[o + kBlk + row - 1] * fi[0];
+                t = 1;
+            }
+            for (; t < kBlk; ++t) {
+                const double f = fi[tp + t];
+                pn = fma(wb[o + kBlk + row - t - 1], f, pn);
+                cn = fma(wa[o + kBlk + row - t - 1], f, cn);
+            }
+            cin[i * kBlk + row] = pn;
+            cin[(D + i) * kBlk + row] = cn;
+        }
+    }
+    __syncthreads();
+    V.Y = R.ringY + rs * kBlk * D;
+    V.YP = R.ringYP + rs * kBlk * D;
+    V.yrow0 = K * kBlk;
+    V.carry = cb;
+    V.recompute = 1;
+    band_block<SYS, D, true, PC>(V, (int)K, smem);
 }
 
 __global__ void k_batch_status(BatchArgs A)
@@ -960,12 +1053,13 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
 #undef FABM_STEP_TRY
 }
 
-size_t batch_smem_bytes(int d, bool pc)
+size_t batch_smem_bytes(int d, bool pc, int P)
 {
     const size_t band = band_smem_bytes(d, pc);
     const size_t near = sizeof(double) * (2 * (size_t)d * kBlk + (size_t)d * kSrcCols * kColPitch);
-    const size_t pair = sizeof(double) * (size_t)d * kPairCols * kColPitch;
-    return std::max(std::max(band, near), pair);
+    const int nc = P == 4 ? group_cols<4>() : P == 2 ? group_cols<2>() : kSrcCols;
+    const size_t group = sizeof(double) * (size_t)d * nc * kColPitch;
+    return std::max(std::max(band, near), group);
 }
 
 template <int SYS, int D, bool F32, bool YPOUT, bool PC>
@@ -980,12 +1074,12 @@ static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, co
             return e_;                     \
         }                                  \
     } while (0)
-    const size_t smem = batch_smem_bytes(D, PC);
+    const size_t smem = batch_smem_bytes(D, PC, S.P);
     static std::atomic<uint64_t> attr_dev{0};
-    if (PC)  // above the default limit only with per-component tables
+    if (smem > 64 * 1024)  // per-component tables, or wide groups of sources
         FABM_STEP_TRY("hipFuncSetAttribute(batch LDS)",
-                      ensure_lds_attr((const void *)k_step_batch<SYS, D, F32, YPOUT, PC>, smem,
-                                      attr_dev));
+                      ensure_lds_attr((const void *)k_step_batch<SYS, D, F32, YPOUT, PC>,
+                                      batch_smem_bytes(D, PC, 4), attr_dev));
     for (int s = -1; s <= S.max_NB - 2; ++s) {
         const size_t k = (size_t)(s + 1);
         const int nb = S.nband[k], nn = S.nnear[k], nf = S.nfar[k];
@@ -995,7 +1089,7 @@ static hipError_t enqueue_batch_t(const BatchArgs &A, const BatchSchedule &S, co
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
         hipLaunchKernelGGL((k_step_batch<SYS, D, F32, YPOUT, PC>), dim3(grid), dim3(kBatchThreads), smem,
                            st, A, s,
-                           nb, nn, far_off + S.far_base[k], nf);
+                           nb, nn, far_off + S.far_base[k], nf, S.P);
         FABM_STEP_TRY("launch k_step_batch", hipGetLastError());
         if (T) FABM_STEP_TRY("timer end", T->end(st));
     }
@@ -1029,6 +1123,43 @@ hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const Bat
     FABM_BATCH_CASE(SYS_HINDMARSH_ROSE, 3)
 #undef FABM_BATCH_CASE
     *where = "no BLOCKED kernel for this system/dimension";
+    return hipErrorInvalidValue;
+}
+
+template <int SYS, int D, bool PC>
+static hipError_t launch_recompute_t(const BatchArgs &A, const RecompArgs &R, int J, int ninst,
+                                     hipStream_t st)
+{
+    const size_t smem = band_smem_bytes(D, PC);
+    static std::atomic<uint64_t> attr_dev{0};
+    if (smem > 64 * 1024) {
+        const hipError_t e = ensure_lds_attr((const void *)k_recompute_batch<SYS, D, PC>, smem,
+                                             attr_dev);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_recompute_batch<SYS, D, PC>), dim3((unsigned)(ninst * (R.G + 1))),
+                       dim3(kBatchThreads), smem, st, A, R, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_recompute(int sys, int d, const BatchArgs &A, const RecompArgs &R, int J,
+                            int ninst, hipStream_t s)
+{
+    if (ninst <= 0) return hipSuccess;
+#define FABM_REC_CASE(SS, DD)                                                     \
+    if (sys == SS && d == DD)                                                     \
+        return A.cmeta ? launch_recompute_t<SS, DD, true>(A, R, J, ninst, s)      \
+                       : launch_recompute_t<SS, DD, false>(A, R, J, ninst, s);
+    FABM_REC_CASE(SYS_LINEAR, 1)
+    FABM_REC_CASE(SYS_LINEAR, 2)
+    FABM_REC_CASE(SYS_LINEAR, 3)
+    FABM_REC_CASE(SYS_LINEAR, 4)
+    FABM_REC_CASE(SYS_CHEN, 3)
+    FABM_REC_CASE(SYS_ROSSLER, 3)
+    FABM_REC_CASE(SYS_VDP, 2)
+    FABM_REC_CASE(SYS_FINANCIAL, 3)
+    FABM_REC_CASE(SYS_HINDMARSH_ROSE, 3)
+#undef FABM_REC_CASE
     return hipErrorInvalidValue;
 }
 

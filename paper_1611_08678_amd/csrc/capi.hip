@@ -38,6 +38,7 @@ struct fabm_plan_s {
     // launch shapes (defaults, or the fastest found by fabm_tune)
     int far_cap = fabm::kMaxFarWg;               // single-trajectory BLOCKED
     int split_target = fabm::kWideSplitTarget;  // shared grid
+    int batch_group = fabm::kDefaultBatchGroup; // batched BLOCKED: source blocks per group
 };
 
 // A captured solve: its instance table lives in its own pinned buffer, copied
@@ -109,6 +110,10 @@ bool per_component(const fabm_plan_s *pl)
 {
     return (pl->desc.flags & FABM_PLAN_PER_COMPONENT_ORDER) != 0;
 }
+bool adjoint_checkpoint(const fabm_plan_s *pl)
+{
+    return (pl->desc.flags & FABM_PLAN_ADJOINT_CHECKPOINT) != 0;
+}
 
 enum class Path { Direct, Blocked, Wide, Unsupported };
 
@@ -143,6 +148,7 @@ struct Layout {
     size_t w, w32, f, part, carry, acc, sync, n_sync_words;
     // reverse pass only: forward rows, reversed sources and sums, partials
     size_t yw, ypw, uv, acc_a, carry_a, part_a, fbar0;
+    size_t rcarry;  // block checkpoints: band sums entering each re-formed block
     // shared grid: low binary16 parts, their scales, Toeplitz operand table
     size_t flo, fexp, t16, t16exp;
     size_t init;   // initial values split into y0 [batch][d] and y'(0) [batch][d]
@@ -163,8 +169,8 @@ const fabm::BatchSchedule &batch_schedule_for(const fabm_plan_s *pl, int64_t bat
     fabm_plan_s *mp = const_cast<fabm_plan_s *>(pl);  // host-side cache only
     std::vector<int32_t> nb((size_t)batch);
     for (int64_t i = 0; i < batch; ++i) nb[(size_t)i] = blocks_of(N[i]);
-    if (nb != mp->sched_nb) {
-        fabm::batch_schedule(batch, nb.data(), mp->sched);
+    if (nb != mp->sched_nb || mp->sched.P != mp->batch_group) {
+        fabm::batch_schedule(batch, nb.data(), mp->sched, mp->batch_group);
         mp->sched_nb.swap(nb);
     }
     return mp->sched;
@@ -234,12 +240,23 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         L.n_sync_words = (size_t)std::max<int64_t>(64, batch);
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
         if (adjoint) {
-            size_t rows = 0;
-            for (int64_t i = 0; i < batch; ++i) rows += (size_t)N[i] + 1;
-            L.yw = off;
-            off = align_up(off + sizeof(double) * d * rows);
-            L.ypw = off;
-            off = align_up(off + sizeof(double) * d * rows);
+            if (adjoint_checkpoint(pl)) {
+                // rings of forward blocks re-formed during the reverse pass
+                const size_t ring = (size_t)batch * (fabm::kCkptGroup + 1) * Lb;
+                L.yw = off;
+                off = align_up(off + sizeof(double) * d * ring);
+                L.ypw = off;
+                off = align_up(off + sizeof(double) * d * ring);
+                L.rcarry = off;
+                off = align_up(off + sizeof(double) * 4 * d * ring);
+            } else {
+                size_t rows = 0;
+                for (int64_t i = 0; i < batch; ++i) rows += (size_t)N[i] + 1;
+                L.yw = off;
+                off = align_up(off + sizeof(double) * d * rows);
+                L.ypw = off;
+                off = align_up(off + sizeof(double) * d * rows);
+            }
             L.uv = off;
             off = align_up(off + sizeof(double) * 2 * nf);
             L.acc_a = off;
@@ -759,16 +776,20 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
             FABM_OK)
             return st;
     }
+    // block checkpoints: the forward keeps no predictor rows and its rows go
+    // straight to the caller (or nowhere); the reverse pass re-forms them
+    const bool ckpt = adjoint_checkpoint(pl);
+    const InstMeta *dmeta_adj = (const InstMeta *)(base + L.meta_adj);
     fabm::BatchArgs A{};
-    A.meta = dmeta;
+    A.meta = ckpt && phase == AdjPhase::Forward ? dmeta_adj : dmeta;
     A.cmeta = dcmeta;
     A.inst = (const fabm::BlkInst *)(base + L.inst);
     A.order = (const int *)(base + L.order);
     A.params = params;
     A.y0 = y0;
     A.y1 = y1;
-    A.Y = (double *)(base + L.yw);
-    A.YP = (double *)(base + L.ypw);
+    A.Y = !ckpt ? (double *)(base + L.yw) : phase == AdjPhase::Forward ? y_out : nullptr;
+    A.YP = ckpt ? nullptr : (double *)(base + L.ypw);
     A.W = W;
     A.Fc = (double *)(base + L.f);
     A.carry = (double *)(base + L.carry);
@@ -783,6 +804,7 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
         pe = fabm::enqueue_batch(pl->desc.system, d, false, A, BS, far_off, s, T, &where);
         if (pe != hipSuccess) return record_hip(where, pe);
     }
+    if (phase == AdjPhase::Forward && ckpt) return FABM_OK;  // rows already in y_out
     if (phase == AdjPhase::Forward) {
         int64_t maxr = 0;
         for (int64_t i = 0; i < batch; ++i) maxr = std::max(maxr, N[i] + 1);
@@ -796,8 +818,9 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     R.order = A.order;
     R.params = params;
     R.y0 = y0;
-    R.Y = A.Y;
-    R.YP = A.YP;
+    R.Y = (double *)(base + L.yw);
+    R.YP = (double *)(base + L.ypw);
+    R.ring = ckpt ? fabm::kCkptGroup + 1 : 0;
     R.G = gy;
     R.W = W;
     R.UV = (double *)(base + L.uv);
@@ -812,8 +835,14 @@ fabm_status run_adjoint(fabm_plan_s *pl, void *ws, int64_t batch, const double *
     R.batch = batch;
     fabm::BatchSchedule Sr = BS;  // one source block per launch
     Sr.far_off = BS.far_off_single;
+    fabm::RecompArgs RC{};
+    RC.ringY = (double *)(base + L.yw);
+    RC.ringYP = (double *)(base + L.ypw);
+    RC.rcarry = (double *)(base + L.rcarry);
+    RC.G = fabm::kCkptGroup;
+    A.meta = dmeta;  // the re-formed rows go to the ring, not to the caller
     pe = fabm::enqueue_adjoint(pl->desc.system, d, R, Sr, (const int *)(base + L.far_off_rev), s,
-                               T, &where);
+                               T, &where, ckpt ? &A : nullptr, ckpt ? &RC : nullptr);
     if (pe != hipSuccess) return record_hip(where, pe);
     return FABM_OK;
 }
@@ -874,7 +903,8 @@ fabm_status fabm_plan(const fabm_plan_desc *desc, fabm_plan_t *out, size_t *work
     const int32_t np = n_params_of(desc->system, desc->dim);
     if (np < 0) return FABM_ERR_INVALID_ARG;
     if (desc->max_batch < 1 || desc->max_steps < 1 || desc->max_total_steps < 0 ||
-        (desc->flags & ~(FABM_PLAN_INITIAL_SLOPE | FABM_PLAN_PER_COMPONENT_ORDER)) != 0 ||
+        (desc->flags & ~(FABM_PLAN_INITIAL_SLOPE | FABM_PLAN_PER_COMPONENT_ORDER |
+                         FABM_PLAN_ADJOINT_CHECKPOINT)) != 0 ||
         desc->max_steps > ((int64_t)1 << 30))
         return FABM_ERR_INVALID_ARG;
     if (desc->tile_L < 0 || desc->tile_L % 64 != 0) return FABM_ERR_INVALID_ARG;
@@ -1149,8 +1179,14 @@ fabm_status fabm_tune(fabm_plan_t plan, void *workspace, size_t workspace_bytes,
     int *knob = nullptr;
     static const int kCaps[] = {32, 64, 128, fabm::kMaxFarWg};
     static const int kTargets[] = {256, 512, 1024, 2048, fabm::kWideMaxSplitTarget};
+    static const int kGroups[] = {1, 2, 4};
     const int *cand = nullptr;
-    if (L.path == Path::Blocked && batch == 1) {
+    if (L.path == Path::Blocked && batch > 1) {
+        rep.knob = FABM_TUNE_SOURCE_GROUP;
+        knob = &plan->batch_group;
+        cand = kGroups;
+        rep.n = (int32_t)(sizeof kGroups / sizeof kGroups[0]);
+    } else if (L.path == Path::Blocked && batch == 1) {
         rep.knob = FABM_TUNE_FAR_WORKGROUPS;
         knob = &plan->far_cap;
         cand = kCaps;

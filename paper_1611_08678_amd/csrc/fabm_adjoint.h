@@ -34,11 +34,19 @@ struct AdjArgs {
     int slope;              // initial values include y'(0): gradients [batch][2][D]
     double *gparams;        // [batch][n_params] (at meta[i].p_off)
     int64_t batch;
+    // block checkpoints: Y and YP are rings of R = G + 1 forward blocks per
+    // instance ([batch][R][256][D]) re-formed before each group of G reverse
+    // launches; 0 when Y and YP hold every row
+    int ring;
 };
 
 struct KernelTimer;
+struct RecompArgs;
+// With `fwd` and `rec` (block checkpoints), the forward blocks each group of
+// reverse launches reads are re-formed first (A.ring = rec->G + 1).
 hipError_t enqueue_adjoint(int sys, int d, const AdjArgs &A, const BatchSchedule &S,
-                           const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
+                           const int *far_off, hipStream_t s, KernelTimer *T, const char **where,
+                           const BatchArgs *fwd = nullptr, const RecompArgs *rec = nullptr);
 size_t adj_smem_bytes(int d, bool pc = false);
 
 // Rows 0..N_i of every instance from src (placed by src_meta[i].f_off) to dst

@@ -51,6 +51,8 @@ struct InstView {
     double *acc;        // [NB][2D][4][64]
     uint32_t *dead;
     int NB;
+    int64_t yrow0 = 0;  // row of the trajectory stored at Y[0] (recompute rings)
+    int recompute = 0;  // band only re-forms rows: history and carry not written
 };
 
 struct StepArgs {
@@ -125,14 +127,35 @@ struct BatchArgs {
     int64_t batch;
 };
 
-// Host schedule of one batched call.
+// Recomputation of forward blocks for the reverse pass of an adjoint with
+// block checkpoints: the forward keeps only the history and the near + far
+// sums of every block; before the reverse pass reaches the rows of forward
+// block K, the band of block K is walked again (its incoming band sums
+// re-formed from block K - 1's history in the forward's order, so the rows
+// are bitwise the forward's) into a ring of R = G + 1 blocks per instance,
+// G forward blocks per group of G reverse launches.
+struct RecompArgs {
+    double *ringY;   // [batch][R][256][D] trajectory rows
+    double *ringYP;  // [batch][R][256][D] predictor rows
+    double *rcarry;  // [batch][R][2][2D][256] band sums entering the block
+    int G;           // reverse launches per group
+};
+constexpr int kCkptGroup = 4;
+
+// Host schedule of one batched call. Far windows go in groups of P source
+// blocks (P = 1, 2 or 4; k_step_batch): launches with (s + 1) % P == 0 take
+// sources s - P + 1 .. s for every later target, the others take source s for
+// the targets whose band runs before the next such launch.
 struct BatchSchedule {
     std::vector<int> order;
     std::vector<int> nband, nnear, nfar, far_base;  // per launch s + 1 (s = -1 .. S-2)
-    std::vector<int> far_off;         // concatenated prefix sums (source blocks in pairs)
+    std::vector<int> far_off;         // concatenated prefix sums (groups of P source blocks)
     std::vector<int> far_off_single;  // the same with one source block per launch (reverse pass)
     int max_NB = 0;
+    int P = 2;
 };
-void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S);
+constexpr int kDefaultBatchGroup = 2;
+void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S,
+                    int P = kDefaultBatchGroup);
 
 }  // namespace fabm

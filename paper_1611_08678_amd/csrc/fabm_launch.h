@@ -94,7 +94,14 @@ struct BatchArgs;
 struct BatchSchedule;
 hipError_t enqueue_batch(int sys, int d, bool f32, const BatchArgs &A, const BatchSchedule &S,
                          const int *far_off, hipStream_t s, KernelTimer *T, const char **where);
-size_t batch_smem_bytes(int d, bool pc = false);
+size_t batch_smem_bytes(int d, bool pc = false, int P = 2);
+
+// Block checkpoints of the adjoint: re-form the forward rows of the group of
+// reverse launches starting at reversed block J (one workgroup per instance
+// and ring slot; `ninst` instances of the order have a reversed block J).
+struct RecompArgs;
+hipError_t launch_recompute(int sys, int d, const BatchArgs &A, const RecompArgs &R, int J,
+                            int ninst, hipStream_t s);
 
 // Teacher-forced history sums, direct contraction (one thread per target row
 // and component group).

@@ -9,8 +9,9 @@
 
 namespace fabm {
 
-void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S)
+void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S, int P)
 {
+    S.P = P;
     S.order.resize((size_t)batch);
     for (int64_t i = 0; i < batch; ++i) S.order[(size_t)i] = (int)i;
     std::stable_sort(S.order.begin(), S.order.end(), [&](int a, int b) { return NB[a] > NB[b]; });
@@ -39,13 +40,15 @@ void batch_schedule(int64_t batch, const int32_t *NB, BatchSchedule &S)
         S.far_base[k] = (int)S.far_off.size();
         S.far_off.push_back(0);
         S.far_off_single.push_back(0);
-        // far windows go in pairs of source blocks: odd launches take every
-        // target J >= s + 3, even launches target s + 3 only (k_step_batch)
+        // far windows in groups of P source blocks: launch s with
+        // (s + 1) % P == 0 takes every target J >= s + 3, the others the
+        // targets J <= sb + 2 before the next such launch sb (k_step_batch)
         const int nf = s >= 0 ? count_at_least(s + 4) : 0;
-        const bool pair = s > 0 && (s & 1) != 0;
+        const bool big = P == 1 || (s >= P - 1 && (s + 1) % P == 0);
+        const int sb = s + (P - 1 - (s >= 0 ? s % P : 0));
         for (int j = 0; j < nf; ++j) {
             const int all = NB[S.order[(size_t)j]] - (s + 3);
-            const int targets = pair ? all : 1;
+            const int targets = big ? all : std::min(all, sb - s);
             S.far_off.push_back(S.far_off.back() + (targets + 3) / 4);
             S.far_off_single.push_back(S.far_off_single.back() + (all + 3) / 4);
         }

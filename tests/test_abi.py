@@ -172,7 +172,7 @@ def test_initial_slope_flag_rules(fabm):
         fabm.fabm_plan("chen", 3, path, "fp64", 1, 100, initial_slope=True)
     fabm.fabm_plan("linear", 8, "blocked", "fp16x2", 2, 100, 200, initial_slope=True)
     lib = fabm.load()
-    desc = fabm._PlanDesc(fabm.FABM_SYS_VDP, 2, 0, 0, 1, 100, 0, 0, 4)
+    desc = fabm._PlanDesc(fabm.FABM_SYS_VDP, 2, 0, 0, 1, 100, 0, 0, 8)  # unknown flag bit
     h = C.c_void_p()
     assert lib.fabm_plan(C.byref(desc), C.byref(h), None) == 1
     fake = C.c_void_p(1 << 40)

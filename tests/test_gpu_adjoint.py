@@ -201,3 +201,125 @@ def test_adjoint_vdp_full_size(F, orc):
         ref = np.concatenate([rg0, rgt])
         got = np.concatenate([g0[i], gt[i]])
         assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max(), i
+
+
+# ---------------------------------------------------------------------------
+# Block checkpoints (FABM_PLAN_ADJOINT_CHECKPOINT): the reverse pass re-forms
+# the forward rows of each block from the stored history and block sums.
+# ---------------------------------------------------------------------------
+def _ckpt_pair(F, system, thetas, alphas, hs, Ns, y0s, gy):
+    """Gradients with and without block checkpoints (one-call fabm_adjoint)."""
+    out = []
+    for ck in (False, True):
+        g0, gt, st = F.adjoint_batch(system, thetas, alphas, hs, Ns, y0s, gy, checkpoint=ck)
+        out.append((_to_np(g0), _to_np(gt), _to_np(st)))
+    return out
+
+
+def _bitwise(a, b):
+    return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)],
+                                                                       b[~np.isnan(b)])
+
+
+@pytest.mark.parametrize("system,d,theta_fn,alpha,h,Ns", [
+    ("vdp", 2, lambda r, B: r.uniform(0.5, 2.0, (B, 1)), 0.9, 0.01,
+     [1, 2, 255, 256, 257, 511, 512, 1023, 1300, 2600, 5000]),
+    ("chen", 3, lambda r, B: np.tile([35.0, 3.0, 28.0], (B, 1)), 0.95, 0.001, [1500, 700, 257]),
+    ("financial", 3, lambda r, B: np.tile([3.0, 0.1, 1.0], (B, 1)), 0.85, 0.01,
+     [2200, 1024, 90]),
+])
+def test_adjoint_checkpoint_bitwise_and_oracle(F, orc, system, d, theta_fn, alpha, h, Ns):
+    """Ragged lengths around the block and group edges (1, 255 … 1023, 5000:
+    20 blocks, five groups of re-formed blocks): the checkpointed gradients are
+    bitwise those of the plan that stores every row, and within 1e-10 of the
+    oracle's reverse mode."""
+    rng = np.random.default_rng(21)
+    Ns = np.asarray(Ns)
+    B = len(Ns)
+    th = theta_fn(rng, B)
+    y0 = rng.uniform(-1, 1, (B, d)) if system != "chen" else np.tile([-9.0, -5.0, 14.0], (B, 1))
+    al, hs = np.full(B, alpha), np.full(B, h)
+    gy = rng.standard_normal((int((Ns + 1).sum()), d))
+    (a0, at, ast), (b0, bt, bst) = _ckpt_pair(F, system, th, al, hs, Ns, y0, gy)
+    assert np.array_equal(ast, bst)
+    assert _bitwise(a0, b0) and _bitwise(at, bt)
+    off = _offsets(Ns)
+    for i in range(B):
+        rg0, rgt, rst = orc.adjoint(SID[system], th[i], al[i], hs[i], int(Ns[i]), y0[i],
+                                    gy[off[i]:off[i] + Ns[i] + 1])
+        assert rst == bst[i] == 0
+        ref, got = np.concatenate([rg0, rgt]), np.concatenate([b0[i], bt[i]])
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max(), (i, Ns[i])
+
+
+def test_adjoint_checkpoint_orders_slope_blowup(F):
+    """Per-component orders with y'(0) (orders up to 1.5) and an instance that
+    blows up: bitwise the store-every-row gradients, NaN and status for the
+    blow-up."""
+    rng = np.random.default_rng(22)
+    Ns = np.array([1700, 600, 2048, 300])
+    B = len(Ns)
+    al = rng.uniform(0.7, 1.5, (B, 2))
+    init = np.stack([rng.uniform(-1, 1, (B, 2)), 0.3 * rng.standard_normal((B, 2))], axis=1)
+    th = rng.uniform(0.5, 2.0, (B, 1))
+    hs = np.full(B, 0.01)
+    hs[2] = 1.0  # blows up
+    gy = rng.standard_normal((int((Ns + 1).sum()), 2))
+    (a0, at, ast), (b0, bt, bst) = _ckpt_pair(F, "vdp", th, al, hs, Ns, init, gy)
+    assert np.array_equal(ast, bst) and bst[2] > 0
+    assert _bitwise(a0, b0) and _bitwise(at, bt)
+    assert np.all(np.isnan(b0[2])) and np.all(np.isfinite(b0[[0, 1, 3]]))
+
+
+def test_adjoint_checkpoint_two_calls_and_autograd(F):
+    """The two-call form writes the forward rows straight to y_out (bitwise the
+    solve's), and the gradients through autograd with checkpoint=True equal
+    those without, bitwise; the checkpointed workspace is smaller by the stored
+    rows."""
+    import torch
+    rng = np.random.default_rng(23)
+    B, Ns = 3, np.array([2000, 900, 1300])
+    th = torch.tensor(rng.uniform(0.5, 2.0, (B, 1)), device="cuda")
+    y0 = torch.tensor(rng.uniform(-2, 2, (B, 2)), device="cuda")
+    al, hs = np.full(B, 0.9), np.full(B, 0.01)
+    grads, ys = [], []
+    for ck in (False, True):
+        a = y0.clone().requires_grad_(True)
+        b = th.clone().requires_grad_(True)
+        y = F.solve_batch_autograd(a, b, "vdp", al, hs, Ns, checkpoint=ck)
+        gy = torch.tensor(np.random.default_rng(5).standard_normal(tuple(y.shape)), device="cuda")
+        (y * gy).sum().backward()
+        grads.append((a.grad, b.grad))
+        ys.append(y.detach())
+    ysolve, _, _ = F.solve_batch("vdp", th, al, hs, Ns, y0, path="blocked")
+    assert torch.equal(ys[0], ys[1]) and torch.equal(ys[1], ysolve)
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    p0 = F.fabm_plan("vdp", 2, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()))
+    p1 = F.fabm_plan("vdp", 2, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
+                     adjoint_checkpoint=True)
+    w0 = F.fabm_adjoint_workspace_size(p0, Ns)
+    w1 = F.fabm_adjoint_workspace_size(p1, Ns)
+    assert w0 - w1 >= 16 * 2 * int((Ns + 1).sum()) - B * 5 * 256 * 2 * 8 * 6 - 4096
+
+
+def test_adjoint_checkpoint_vdp_full_size(F):
+    """The adjoint workload at full size (1024 Van der Pol instances, N = 2^15)
+    with block checkpoints: the gradients of the MSE loss are bitwise those of
+    the store-every-row plan (whose oracle parity is tested above)."""
+    import torch
+    from paper_1611_08678_amd import workloads as W
+    w = W.vdp_adjoint()
+    Ns = w["N"]
+    tgt, _, _ = F.solve_batch(w["system"], w["theta_target"], w["alpha"], w["h"], Ns, w["y0"],
+                              path="blocked")
+    grads = []
+    for ck in (False, True):
+        y0 = torch.tensor(w["y0"], device="cuda", requires_grad=True)
+        th = torch.tensor(w["theta"], device="cuda", requires_grad=True)
+        y = F.solve_batch_autograd(y0, th, w["system"], w["alpha"], w["h"], Ns, checkpoint=ck)
+        (((y - tgt) ** 2).sum() / y.numel()).backward()
+        grads.append((y0.grad, th.grad))
+        del y
+        torch.cuda.empty_cache()
+    assert torch.all(torch.isfinite(grads[1][0])) and torch.all(torch.isfinite(grads[1][1]))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])

@@ -194,6 +194,8 @@ def test_fft_far_with_fp32_windows(F, orc):
     err = relerr(_to_np(y), ref)
     assert int(st.item()) == rst == 0
     assert 1e-12 < err <= FP32_BOUND, err
+    from tests import reduced_bounds as RB
+    RB.check("fft_far_fp32_windows", err, FP32_BOUND)
 
 
 @pytest.mark.parametrize("alphas,slope", [([0.75, 0.95], False), ([0.85, 1.5], True)])

@@ -59,7 +59,8 @@ def _horizons(orc, sid, th, al, hs, Ns, init, ref, off, rows):
     return out
 
 
-def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11, path="direct", far_prec="fp64"):
+def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11, path="direct", far_prec="fp64",
+             errs=None):
     """Status equal (or one step apart at the top of the binary64 range, as
     for commensurate orders), NaN rows from there on, and the rows of
     _horizons within tol normwise."""
@@ -84,6 +85,8 @@ def _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-11, path="direct", fa
         sl = slice(off[i], off[i] + hz[i])
         err = relerr(yy[sl], ref[sl])
         assert err <= tol, (i, err, hz[i], rows[i])
+        if errs is not None:
+            errs.append(err)
     return rst
 
 
@@ -120,7 +123,11 @@ def test_batch_per_component_orders_fp32_windows(F, orc, sysname):
     Ns = rng.integers(300, 2500, B, endpoint=True)
     Ns[:2] = [1, 1024]
     init = 0.5 * rng.uniform(-1, 1, (B, d))
-    _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-5, path="blocked", far_prec="fp32")
+    errs = []
+    _compare(F, orc, sysname, th, al, hs, Ns, init, tol=1e-5, path="blocked", far_prec="fp32",
+             errs=errs)
+    from tests import reduced_bounds as RB
+    RB.check(f"orders_fp32_{sysname}", max(errs), 1e-5)
     name = "linear" if sysname.startswith("linear") else sysname
     y32, _, _ = F.solve_batch(name, th, al, hs, Ns, init, path="blocked", far_prec="fp32")
     y64, _, _ = F.solve_batch(name, th, al, hs, Ns, init, path="blocked")

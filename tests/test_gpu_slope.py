@@ -11,6 +11,8 @@ that much larger relative to the solution."""
 import numpy as np
 import pytest
 
+from tests import reduced_bounds as RB
+
 from tests.conftest import gpu_available
 from tests.test_gpu_direct import _batch_parity, _to_np, relerr
 
@@ -94,7 +96,10 @@ def test_batch_mixed_orders(F, orc, path, sid, d):
     rng = np.random.default_rng(40 + sid)
     w = _mixed_batch(rng, 12, sid, d)
     w["N"][:3] = [1, 256, 511]  # one row, a full block, block + 255 rows
-    _batch_parity(F, orc, w, tol=FP32_BOUND if path.endswith("fp32") else 1e-11, path=path)
+    worst = _batch_parity(F, orc, w, tol=FP32_BOUND if path.endswith("fp32") else 1e-11,
+                          path=path)
+    if path.endswith("fp32"):
+        RB.check(f"slope_mixed_fp32_sys{sid}_d{d}", worst, FP32_BOUND)
 
 
 def test_batch_alpha_le_one_ignores_slope_row(F):
@@ -143,6 +148,7 @@ def test_shared_grid_above_one(F, orc, far_prec, tol):
     assert err <= tol
     if far_prec != "fp64":
         assert err > 1e-12
+        RB.check(f"slope_shared_grid_{far_prec}", err, FP32_BOUND)
 
 
 def test_captured_solve_above_one(F, orc):

@@ -2,7 +2,8 @@
 path on the caller's inputs and keeps the fastest. Checked: the report
 (knob, candidates, positive times, a valid choice), that the tuned plan's
 results are right (single trajectory: the far workgroup count does not change
-any sum's order, so bitwise equal to the untuned solve; shared grid: the split
+any sum's order, so bitwise equal to the untuned solve; batches: the group
+of source blocks per far launch does not either; shared grid: the split
 changes the summation order only, so within the FP64 bound of the oracle),
 determinism of the tuned plan, and paths with nothing to choose."""
 import numpy as np
@@ -65,11 +66,45 @@ def test_tune_shared_grid(F, orc):
     assert relerr(_to_np(y1), ref) <= 1e-11
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tune_batched_blocked_source_group(F, orc, prec):
+    """The ragged batched BLOCKED path (Rossler, per-instance alpha, lengths
+    around the block edges up to 40 blocks): the tuner times groups of 1, 2
+    and 4 source blocks per far launch. Every group size adds the same windows
+    to every target in the same order, so the rows left by the last candidate
+    (4) and the rows of the tuned plan are bitwise those of an untuned plan
+    (2), which match the oracle."""
+    from paper_1611_08678_amd import workloads as W
+    w = W.rossler_batch(batch=48, n_lo=1, n_hi=10000, seed=19)
+    w["N"][:6] = [1, 255, 256, 511, 767, 1024]
+    Ns, B = w["N"], 48
+    plan = F.fabm_plan("rossler", 3, "blocked", prec, B, int(Ns.max()), int(Ns.sum()))
+    ws, ro, y0d, thd, y, st = _buffers(F, plan, Ns, w["y0"], w["theta"])
+    rep = F.fabm_tune(plan, ws, w["alpha"], w["h"], Ns, y0d, thd, ro, y, st)
+    assert rep["knob"] == "source_group" and rep["candidates"] == [1, 2, 4]
+    assert all(t > 0 for t in rep["seconds"]) and 0 <= rep["chosen"] < 3
+    y4 = _to_np(y).copy()
+    y1, _, s1 = F.solve_batch("rossler", w["theta"], w["alpha"], w["h"], Ns, w["y0"], plan=plan)
+    y2, _, s2 = F.solve_batch("rossler", w["theta"], w["alpha"], w["h"], Ns, w["y0"],
+                              path="blocked", far_prec=prec)
+    a, b = _to_np(y1), _to_np(y2)
+    assert np.array_equal(_to_np(s1), _to_np(s2))
+    same = lambda u, v: np.array_equal(np.isnan(u), np.isnan(v)) and np.array_equal(
+        u[~np.isnan(u)], v[~np.isnan(v)])
+    assert same(a, b) and same(y4, b)
+    ref, roff, rst = orc.solve_batch(2, w["theta"], w["alpha"], w["h"], Ns, w["y0"])
+    ok = rst == 0
+    assert np.all(_to_np(s2)[ok] == 0)
+    for i in np.nonzero(ok)[0][:12]:
+        sl = slice(roff[i], roff[i] + Ns[i] + 1)
+        assert relerr(b[sl], ref[sl]) <= (1e-5 if prec == "fp32" else 1e-11), i
+
+
 def test_tune_nothing_to_choose(F):
     rng = np.random.default_rng(2)
     B = 3
     th, y0 = rng.uniform(0.5, 2, (B, 1)), rng.uniform(-2, 2, (B, 2))
-    plan = F.fabm_plan("vdp", 2, "blocked", "fp64", B, 700, 3 * 700)
+    plan = F.fabm_plan("vdp", 2, "direct", "fp64", B, 700, 3 * 700)
     ws, ro, y0d, thd, y, st = _buffers(F, plan, [700, 300, 500], y0, th)
     rep = F.fabm_tune(plan, ws, np.full(B, 0.9), np.full(B, 0.01), [700, 300, 500], y0d, thd,
                       ro, y, st)
