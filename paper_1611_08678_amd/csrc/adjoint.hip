@@ -271,20 +271,22 @@ __device__ __forceinline__ void window_adj(dbl4 (&acc)[D], const double *__restr
     const int r16 = lane & 15, kq = lane >> 4;
     const int c = r16 - u + coff;
     const bool ok = c < kSrcCols;
-    const int sbase = (ok ? c : 0) * kColPitch + kq;
-    const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
+    // K slot kq of slice j is source row 4 kq + j: a lane's operands of the
+    // four slices are four consecutive weights and staged values
+    const int sbase = (ok ? c : 0) * kColPitch + 4 * kq;
+    const int64_t wi = kBlk * m + kTile * u + r16 - 4 * kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         double aa[K], ab[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            aa[k] = wa[k * cw + wi - 4 * j];
-            ab[k] = wb[k * cw + wi - 4 * j];
+            aa[k] = wa[k * cw + wi - j];
+            ab[k] = wb[k * cw + wi - j];
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double vu = sB[i * kSrcCols * kColPitch + sbase + 4 * j];
-            const double vv = sB[(D + i) * kSrcCols * kColPitch + sbase + 4 * j];
+            const double vu = sB[i * kSrcCols * kColPitch + sbase + j];
+            const double vv = sB[(D + i) * kSrcCols * kColPitch + sbase + j];
             acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[PC ? i : 0], ok ? vu : 0.0, acc[i],
                                                           0, 0, 0);
             acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ab[PC ? i : 0], ok ? vv : 0.0, acc[i],

@@ -507,20 +507,23 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
     const int r16 = lane & 15, kq = lane >> 4;  // A row sigma / B column rho; K slot
     const int c = r16 - u + coff;
     const bool ok = c < NC;
-    const int sbase = (ok ? c : 0) * kColPitch + kq;
-    const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
+    // K slot kq of slice j is source row tau = 4 kq + j of the column, so a
+    // lane's operands of the four slices are four consecutive weights and
+    // four consecutive staged values (wide loads)
+    const int sbase = (ok ? c : 0) * kColPitch + 4 * kq;
+    const int64_t wi = kBlk * m + kTile * u + r16 - 4 * kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         double ab[K], aa[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            ab[k] = wb[k * cw + wi - 4 * j];
-            aa[k] = wa[k * cw + wi - 4 * j];
+            ab[k] = wb[k * cw + wi - j];
+            aa[k] = wa[k * cw + wi - j];
         }
         double bf[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double v = sB[i * NC * kColPitch + sbase + 4 * j];
+            const double v = sB[i * NC * kColPitch + sbase + j];
             bf[i] = ok ? v : 0.0;
         }
 #pragma unroll
@@ -544,19 +547,20 @@ __device__ __forceinline__ void window_lag_f32(flt4 (&acc)[2][D], const float *_
     constexpr int K = PC ? D : 1;  // one A operand per component with per-component orders
     const int lane = threadIdx.x & (kWave - 1);
     const int r16 = lane & 15, kq = lane >> 4;
-    const int sbase = (r16 - u + coff) * kColPitch + kq;
-    const int64_t wi = kBlk * m + kTile * u + r16 - kq - 1;
+    // K slot kq of slice j is source row 4 kq + j (see window_lag)
+    const int sbase = (r16 - u + coff) * kColPitch + 4 * kq;
+    const int64_t wi = kBlk * m + kTile * u + r16 - 4 * kq - 1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         float ab[K], aa[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            ab[k] = wb[k * cw + wi - 4 * j];
-            aa[k] = wa[k * cw + wi - 4 * j];
+            ab[k] = wb[k * cw + wi - j];
+            aa[k] = wa[k * cw + wi - j];
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const float bf = sB[i * NC * kColPitch + sbase + 4 * j];
+            const float bf = sB[i * NC * kColPitch + sbase + j];
             acc[0][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[PC ? i : 0], bf, acc[0][i], 0, 0, 0);
             acc[1][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[PC ? i : 0], bf, acc[1][i], 0, 0, 0);
         }

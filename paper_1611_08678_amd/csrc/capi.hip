@@ -358,10 +358,10 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         off = align_up(off + sizeof(double) * 3 * (size_t)sumN * (pc ? d : 1));
         L.f = off;
         off = align_up(off + sizeof(double) * (size_t)d * (size_t)sumRows);
-        L.part = off;  // grid-kernel partials [G][2d]
-        off = align_up(off + sizeof(double) * 2 * (size_t)d * kGridMax);
-        L.sync = off;
-        L.n_sync_words = 64;
+        L.part = off;  // grid-kernel partials [2][G][2d] (by step parity)
+        off = align_up(off + sizeof(double) * 4 * (size_t)d * kGridMax);
+        L.sync = off;  // grid-kernel counters and flags, one 256-byte line each
+        L.n_sync_words = 64 * 18;
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
     }
     if (has_slope(pl)) {

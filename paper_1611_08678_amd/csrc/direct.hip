@@ -11,10 +11,11 @@
 //  * k_direct_grid: one long trajectory over the whole GPU (one persistent
 //    workgroup per compute unit, cooperative launch so all are resident).
 //    Each step every workgroup reduces a contiguous slice of [0, t), writes
-//    its partial and signals an arrival counter; workgroup 0 waits for all
-//    arrivals, adds the partials in a fixed order (deterministic), forms row t
-//    and publishes it. Step time is bound by HBM streaming of the history and
-//    weight rows at large t and by the two inter-workgroup hand-offs at small t.
+//    its partial and signals an arrival counter; every workgroup then waits
+//    for all arrivals, adds the partials in a fixed order (deterministic) and
+//    forms row t itself: one inter-workgroup hand-off per step. Step time is
+//    bound by HBM streaming of the history and weight rows at large t and by
+//    that hand-off at small t.
 #include "fabm_device.h"
 #include "fabm_launch.h"
 
@@ -223,10 +224,73 @@ __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict
             for (int i = 0; i < D; ++i) Yh[r * D + i] = __builtin_nan("");
 }
 
-// sync[0]: arrival counter (monotone, G per step); sync[1]: number of final
-// rows published (rows 0..sync[1]-1 of F and Y are complete); sync[2]: step at
-// which the trajectory stopped being finite (0 while finite); sync[3]: abort
-// (a bounded wait timed out). All four are flags in the sense of flag_read.
+// Partial sums of partial_sums, with the newest row k = t - 1 taken from
+// `fl` (formed by this workgroup itself) instead of from memory.
+template <int D>
+__device__ __forceinline__ void partial_sums_last(const double *__restrict__ Fh,
+                                                  const double *__restrict__ wb,
+                                                  const double *__restrict__ wa,
+                                                  const double *__restrict__ wc, int64_t t,
+                                                  int64_t lo, int64_t hi, int tid,
+                                                  const double (&fl)[D], double (&sp)[D],
+                                                  double (&sc)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) sp[i] = sc[i] = 0.0;
+    for (int64_t k = lo + tid; k < hi; k += kBlock) {
+        const double bw = wb[t - 1 - k];
+        const double aw = (k == 0) ? wc[t - 1] : wa[t - 1 - k];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double fk = k == t - 1 ? fl[i] : Fh[k * D + i];
+            sp[i] = fma(bw, fk, sp[i]);
+            sc[i] = fma(aw, fk, sc[i]);
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void partial_sums_orders_last(const double *__restrict__ Fh,
+                                                         const CompOrders<D> &O, int64_t t,
+                                                         int64_t lo, int64_t hi, int tid,
+                                                         const double (&fl)[D], double (&sp)[D],
+                                                         double (&sc)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) sp[i] = sc[i] = 0.0;
+    for (int64_t k = lo + tid; k < hi; k += kBlock) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double bw = O.wb[i][t - 1 - k];
+            const double aw = (k == 0) ? O.wc[i][t - 1] : O.wa[i][t - 1 - k];
+            const double fk = k == t - 1 ? fl[i] : Fh[k * D + i];
+            sp[i] = fma(bw, fk, sp[i]);
+            sc[i] = fma(aw, fk, sc[i]);
+        }
+    }
+}
+
+// One hand-off per step. At step t every workgroup g reduces its slice
+// [t g / G, t (g + 1) / G) of the history (rows up to t - 2 from memory, the
+// newest row t - 1 from its own registers), stores its partial in the
+// buffer of the step's parity and arrives; it then waits until all G
+// partials of step t have arrived, adds them in workgroup order and forms
+// row t itself: every workgroup forms every row, bitwise the same, so no row
+// has to be published before the next step. Workgroup 0 writes the rows to F
+// and Y; a row is read from F two steps later at the earliest, after
+// workgroup 0's release of the step in between.
+// Arrival is two-level so that no counter or flag is shared by more than
+// kGroupSpan workgroups (one atomic line serialises its users): workgroup g
+// adds to the counter of its group g mod 8 (under round-robin dispatch, one
+// XCD); the group's last arrival of the step adds to the top counter, whose
+// last arrival of the step raises the step flag of every group; each
+// workgroup waits on its group's flag. Counters and flags are monotone
+// (compared modulo 2^32), in separate 256-byte lines of `sync`:
+// word 64 x: group counter, 64 (8 + x): group flag, 64 * 16: top counter,
+// 64 * 17: abort (a bounded wait timed out). part: [2][G][2D].
+constexpr int kGroups = 8;     // arrival groups (one per XCD under round-robin dispatch)
+constexpr int kSyncLine = 64;  // words between counters: one 256-byte line each
+
 template <int SYS, int D, bool PC>
 __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restrict__ meta,
                                                         const InstMeta *__restrict__ cmeta,
@@ -244,6 +308,10 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
     __shared__ double red[kWaves][2 * D];
     __shared__ int s_stop;
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    // arrival groups: g mod ngroups, of gsize workgroups each
+    const int ngroups = G < kGroups ? G : kGroups;
+    const int gx = g % ngroups;
+    const uint32_t gsize = (uint32_t)((G - 1 - gx) / ngroups + 1);
     const InstMeta m = meta[0];
     const int64_t N = m.N;
     const double *wb = W + m.w_off, *wa = wb + m.wlen, *wc = wa + m.wlen;
@@ -259,77 +327,96 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
         load_slope<D>(m, y1g, y1);
     }
 
+    double fl[D];  // the newest row's f, formed by this workgroup
+    rhs<SYS, D>(0.0, y0, fl, p);
     if (g == 0 && tid == 0) {
-        double f0[D];
-        rhs<SYS, D>(0.0, y0, f0, p);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            F[i] = f0[i];
+            F[i] = fl[i];
             Y[i] = y0[i];
         }
-        flag_publish(&sync[1], 1u);
     }
-
-    for (int64_t t = 1; t <= N; ++t) {
-        if (tid == 0) {
-            const bool ok = wait_geq(&sync[1], (uint32_t)t, &sync[3], timeout_ticks);
-            s_stop = !ok || flag_read(&sync[2]) != 0u;
-        }
-        __syncthreads();
-        if (s_stop) break;
-        fence_acquire();
+    int64_t dead = 0;      // first non-finite row (all workgroups find the same)
+    bool aborted = false;  // a wait gave up
+    int64_t t = 1;
+    for (; t <= N; ++t) {
         const int64_t lo = (t * g) / G, hi = (t * (g + 1)) / G;
         double sp[D], sc[D];
-        if constexpr (PC) partial_sums_orders<D>(F, O, t, lo, hi, tid, sp, sc);
-        else partial_sums<D>(F, wb, wa, wc, t, lo, hi, tid, sp, sc);
+        if constexpr (PC) partial_sums_orders_last<D>(F, O, t, lo, hi, tid, fl, sp, sc);
+        else partial_sums_last<D>(F, wb, wa, wc, t, lo, hi, tid, fl, sp, sc);
         block_sum2<D>(sp, sc, red, tid);
+        double *pb = part + (int64_t)(t & 1) * G * 2 * D;
         if (tid == 0) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                part[(int64_t)g * 2 * D + i] = sp[i];
-                part[(int64_t)g * 2 * D + D + i] = sc[i];
+                pb[(int64_t)g * 2 * D + i] = sp[i];
+                pb[(int64_t)g * 2 * D + D + i] = sc[i];
             }
+            // release: this partial, and workgroup 0's rows up to t - 1. The
+            // counters are relaxed read-modify-writes; only the last arrival
+            // of a group (and of the top counter) acquires what the others
+            // released before passing it on, so each workgroup pays one
+            // release and one acquire (in wait_geq) per step.
             fence_release();
-            __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ut = (uint32_t)t;
+            const uint32_t got = __hip_atomic_fetch_add(&sync[kSyncLine * gx], 1u,
+                                                        __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (got == gsize * ut) {  // the group's last arrival of step t
+                fence_acquire();
+                fence_release();
+                const uint32_t top = __hip_atomic_fetch_add(&sync[kSyncLine * 16], 1u,
+                                                            __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
+                if (top == (uint32_t)ngroups * ut) {  // the last group: step t complete
+                    fence_acquire();
+                    fence_release();
+                    for (int x = 0; x < ngroups; ++x)
+                        __hip_atomic_store(&sync[kSyncLine * (8 + x)], ut, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            // wait_geq acquires for the whole workgroup (the barrier below
+            // orders the other wavefronts after it)
+            s_stop = !wait_geq(&sync[kSyncLine * (8 + gx)], ut, &sync[kSyncLine * 17],
+                               timeout_ticks);
         }
-        if (g == 0) {
-            if (tid == 0) s_stop = !wait_geq(&sync[0], (uint32_t)(G * t), &sync[3], timeout_ticks);
-            __syncthreads();
-            if (s_stop) break;
-            fence_acquire();
-            double qp[D], qc[D];
+        __syncthreads();
+        if (s_stop) {
+            aborted = true;
+            break;
+        }
+        double qp[D], qc[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            qp[i] = tid < G ? pb[(int64_t)tid * 2 * D + i] : 0.0;
+            qc[i] = tid < G ? pb[(int64_t)tid * 2 * D + D + i] : 0.0;
+        }
+        block_sum2<D>(qp, qc, red, tid);
+        double y[D], f[D], base[D];
+        const double tt = (double)t * m.h;
+        taylor_base<D>(tt, y0, y1, base);
+        if constexpr (PC) pece_update_orders<SYS, D>(O, tt, base, qp, qc, p, y, f);
+        else pece_update<SYS, D>(m, tt, base, qp, qc, p, y, f);
+        if (!finite_all(y) || !finite_all(f)) {
+            dead = t;
+            break;
+        }
+        if (g == 0 && tid == 0) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                qp[i] = tid < G ? part[(int64_t)tid * 2 * D + i] : 0.0;
-                qc[i] = tid < G ? part[(int64_t)tid * 2 * D + D + i] : 0.0;
-            }
-            __syncthreads();  // red[] is reused by the combine below
-            block_sum2<D>(qp, qc, red, tid);
-            if (tid == 0) {
-                double y[D], f[D], base[D];
-                const double tt = (double)t * m.h;
-                taylor_base<D>(tt, y0, y1, base);
-                if constexpr (PC) pece_update_orders<SYS, D>(O, tt, base, qp, qc, p, y, f);
-                else pece_update<SYS, D>(m, tt, base, qp, qc, p, y, f);
-                if (!finite_all(y) || !finite_all(f)) {
-                    flag_max(&sync[2], (uint32_t)t);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        F[t * D + i] = f[i];
-                        Y[t * D + i] = y[i];
-                    }
-                }
-                flag_publish(&sync[1], (uint32_t)(t + 1));
+                F[t * D + i] = f[i];
+                Y[t * D + i] = y[i];
             }
         }
-        __syncthreads();  // red[] reuse in the next step
+#pragma unroll
+        for (int i = 0; i < D; ++i) fl[i] = f[i];
+        __syncthreads();  // red[] is reused by the next step's partial sums
     }
     if (g == 0) {
-        const bool aborted = flag_read(&sync[3]) != 0u;
-        const int64_t dead = flag_read(&sync[2]);
-        // first row not known to be final
-        const int64_t bad = aborted ? (int64_t)flag_read(&sync[1]) : dead;
+        // rows from `bad` on are not final: the first non-finite step, or the
+        // step whose wait gave up
+        const int64_t bad = aborted ? t : dead;
         if (tid == 0) status[0] = aborted ? -1 : dead;
         if (bad)
             for (int64_t r = bad + tid; r <= N; r += kBlock)

@@ -57,7 +57,8 @@ hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, const InstMeta
                             int64_t *status, hipStream_t s);
 
 // DIRECT path, one trajectory spread over the whole GPU (persistent,
-// cooperative launch); `part` holds [G][2d] doubles, `sync` 4 zeroed words.
+// cooperative launch); `part` holds [2][G][2d] doubles, `sync` 18 x 64 zeroed
+// words (counters and flags in lines of their own).
 // Every inter-workgroup wait gives up after `timeout_ticks` of the device's
 // constant-rate wall clock (status -1).
 hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const InstMeta *cmeta,

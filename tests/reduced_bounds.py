@@ -28,17 +28,17 @@ MODEL_FP16X2 = (2 + 1 + 64) * U32
 
 # normwise error vs the FP64 oracle measured for each case on MI355X
 MEASURED = {
-    "blocked_fp32_batch": 1.370e-06,
-    "blocked_fp32_single": 5.449e-06,
-    "fft_far_fp32_windows": 4.302e-06,
-    "orders_fp32_hindmarsh_rose": 1.202e-06,
-    "orders_fp32_linear3": 4.300e-07,
-    "orders_fp32_vdp": 1.659e-06,
-    "rossler_full_fp32_prefix": 1.103e-06,
-    "rossler_full_fp32_reformed": 6.408e-08,   # relative to the history magnitude
-    "slope_mixed_fp32_sys0_d3": 7.229e-06,
-    "slope_mixed_fp32_sys3_d2": 5.679e-06,
-    "slope_mixed_fp32_sys4_d3": 4.506e-05,
+    "blocked_fp32_batch": 1.345e-06,
+    "blocked_fp32_single": 5.573e-06,
+    "fft_far_fp32_windows": 3.343e-06,
+    "orders_fp32_hindmarsh_rose": 1.564e-06,
+    "orders_fp32_linear3": 4.875e-07,
+    "orders_fp32_vdp": 1.488e-06,
+    "rossler_full_fp32_prefix": 1.236e-06,
+    "rossler_full_fp32_reformed": 3.962e-08,   # relative to the history magnitude
+    "slope_mixed_fp32_sys0_d3": 7.335e-06,
+    "slope_mixed_fp32_sys3_d2": 6.692e-06,
+    "slope_mixed_fp32_sys4_d3": 3.883e-05,
     "slope_shared_grid_fp16x2": 1.137e-06,
     "slope_shared_grid_fp32": 1.335e-06,
     "wide_alpha0.05_fp16x2": 2.677e-08,
