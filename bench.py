@@ -489,6 +489,25 @@ def bench_adjoint(F, W, args, steps=None, warmup=None):
 
     per = _timed(step, steps, warmup, "vdp_adjoint forward+backward")
     one_call = float(np.mean(_timed(step_one_call, 1, 1, "vdp_adjoint solve + one-call adjoint")))
+    # the same training step with block checkpoints in the adjoint (the forward
+    # keeps no rows; the reverse pass re-forms them), gradients compared bitwise
+    gy0_ref, gth_ref = gy0.clone(), gth.clone()
+    cplan = F.fabm_plan(w["system"], d, "blocked", "fp64", B, int(Ns.max()), int(Ns.sum()),
+                        adjoint_checkpoint=True)
+    cws_bytes = F.fabm_adjoint_workspace_size(cplan, Ns)
+    cws = torch.empty(cws_bytes, dtype=torch.uint8, device="cuda")
+
+    def step_ckpt():
+        F.fabm_adjoint_forward(cplan, cws, w["alpha"], w["h"], Ns, y0, th, row_off, y, st)
+        gy = (y - yt) * scale
+        F.fabm_adjoint_reverse(cplan, cws, w["alpha"], w["h"], Ns, y0, th, row_off, gy, gy0, gth)
+
+    cper = _timed(step_ckpt, steps, 1, "vdp_adjoint forward+backward, block checkpoints")
+    ckpt = dict(seconds=float(np.mean(cper)), workspace_bytes=int(cws_bytes),
+                store_rows_workspace_bytes=int(F.fabm_adjoint_workspace_size(plan, Ns)),
+                gradients_bitwise_equal=bool(torch.equal(gy0, gy0_ref) and
+                                             torch.equal(gth, gth_ref)))
+    del cws
     step()  # leave the split path's gradients in gy0, gth
     gy = hold["gy"]
     F.fabm_plan_set_profiling(plan, True)
@@ -512,6 +531,7 @@ def bench_adjoint(F, W, args, steps=None, warmup=None):
                             basis="2 x 2 d N (N + 1) per instance (forward and reverse "
                                   "history sums) over the timed forward + backward"),
            "solve_then_one_call_adjoint_s": one_call,
+           "block_checkpoints": ckpt,
            "adjoint_kernel_times_s": {k: v[0] for k, v in kt.items()},
            "adjoint_kernel_launches": {k: v[1] for k, v in kt.items()}}
     if args.cpu_sample > 0:
@@ -795,9 +815,12 @@ def main():
         sub = argparse.Namespace(**{**vars(args), "far_prec": None, "batch_path": "blocked",
                                     "per_component_orders": False, "alpha": None,
                                     "slope": False, "tune": False})
-        cfg["rossler_batch_fp32"] = bench_batch(F, W, sub, "rossler_batch", "fp32", cs, cw)
+        # the ragged batch runs with the plan the autotuner chose (source blocks
+        # per group of far windows; untimed tuning runs first)
+        tuned = argparse.Namespace(**{**vars(sub), "tune": True})
+        cfg["rossler_batch_fp32"] = bench_batch(F, W, tuned, "rossler_batch", "fp32", cs, cw)
         torch.cuda.empty_cache()
-        cfg["rossler_batch_fp64"] = bench_batch(F, W, sub, "rossler_batch", "fp64", cs, cw)
+        cfg["rossler_batch_fp64"] = bench_batch(F, W, tuned, "rossler_batch", "fp64", cs, cw)
         torch.cuda.empty_cache()
         for k, v in bench_linear64_precisions(F, W, sub, cs, cw).items():
             cfg["linear64_batch_" + k] = v

@@ -289,7 +289,8 @@ TUNE_KNOBS = ("none", "far_workgroups", "split_target", "source_group")
 def fabm_tune(plan: Plan, workspace, alpha, h, N, y0, params, row_off, y_out, status,
               stream=None) -> dict:
     """Autotune the plan's launch shape on these inputs (see fabm.h); returns
-    {"knob", "candidates", "seconds", "chosen"}."""
+    {"knob", "candidates", "seconds", "chosen"}, "chosen" being the index of
+    the candidate the plan now uses (None when there was nothing to choose)."""
     import numpy as np
     al = np.ascontiguousarray(alpha, dtype=np.float64)
     hh = np.ascontiguousarray(h, dtype=np.float64)

@@ -270,32 +270,24 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             }
         }
     }
-    // This wavefront's rows. The sums read out for row t leave out row t-1,
-    // whose contribution enters the predictor and the corrector directly:
-    //   yP_t = (y0 + h^a P'_t) + (h^a b_0) f_{t-1},
-    //   y_t  = (y0 + h^a C'_t) + (h^a a_0) f_{t-1} + (h^a / Gamma(a+2)) f(t, yP_t),
-    // so the dependent chain of a step is the two evaluations of f; adding
-    // row t-1 to the other sums and reading out those of row t+1 overlap it.
-    // Rows are checked for non-finite values when they are published.
+    // This wavefront's rows. At row t every lane first adds row t-1 to its
+    // sums (lane t - lo's weights are then h^a b_0 and h^a a_0, so it holds
+    // row t's whole predictor sum y0 + h^a P_t and corrector sum); those are
+    // read out (readlane) and every lane evaluates
+    //   yP_t = y0 + h^a P_t,  y_t = (y0 + h^a C_t) + (h^a / Gamma(a+2)) f(t, yP_t)
+    // on the same values, so f_t is in every lane without a broadcast. The
+    // corrector sum is read out while the predictor is evaluated. Rows are
+    // checked for non-finite values when they are published.
     const int first = done;
-    double hb0[K], ha0[K], hig2[K];
+    double hig2[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        hb0[k] = sbh[k * kBlk];
-        ha0[k] = sah[k * kBlk];
         // teacher forcing returns the plain sums: y_t = C_t, yP_t = P_t
         hig2[k] = SYS == SYS_TEACHER ? 0.0 : hav[k] * ig2v[k];
     }
-    double fprev[D], ypb[D], ycb[D];
-    {
-        const int l0 = first - lo < 63 ? first - lo : 63;
+    double fprev[D];  // f of the row before (its terms are not in the sums yet)
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            ypb[i] = readlane_f64(pc[i], l0);
-            ycb[i] = readlane_f64(cc[i], l0);
-            fprev[i] = 0.0;
-        }
-    }
+    for (int i = 0; i < D; ++i) fprev[i] = 0.0;
     int checked = first;  // rows before this one have been checked
     // rows in groups of kPublishEvery (aligned to the block), unrolled, so the
     // publish check runs once per group; the weights of the next step are
@@ -318,26 +310,24 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             awn[q] = sah[q * kBlk + (lagn > 0 ? lagn : 0)];
         }
         const double tt = (double)(t0 + t) * m.h;
-        double yp[D], fp[D], y[D], f[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) yp[i] = fma(hb0[PC ? i : 0], fprev[i], ypb[i]);
-        rhs<SYS, D>(tt, yp, fp, th);
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-            y[i] = fma(hig2[PC ? i : 0], fp[i], fma(ha0[PC ? i : 0], fprev[i], ycb[i]));
-        rhs<SYS, D>(tt, y, f, th);
+        double yp[D], fp[D], y[D], f[D], yc[D];
+        // row t-1 into the sums first: lane t - lo then holds row t's whole
+        // predictor and corrector sums (lag-0 weights h^a b_0, h^a a_0)
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             pc[i] = fma(bw[PC ? i : 0], fprev[i], pc[i]);
             cc[i] = fma(aw[PC ? i : 0], fprev[i], cc[i]);
         }
-        const int ln = t + 1 - lo < 63 ? t + 1 - lo : 63;
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            ypb[i] = readlane_f64(pc[i], ln);
-            ycb[i] = readlane_f64(cc[i], ln);
-            fprev[i] = f[i];
-        }
+        for (int i = 0; i < D; ++i) yp[i] = readlane_f64(pc[i], t - lo);
+        rhs<SYS, D>(tt, yp, fp, th);
+#pragma unroll
+        for (int i = 0; i < D; ++i) yc[i] = readlane_f64(cc[i], t - lo);
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = fma(hig2[PC ? i : 0], fp[i], yc[i]);
+        rhs<SYS, D>(tt, y, f, th);
+#pragma unroll
+        for (int i = 0; i < D; ++i) fprev[i] = f[i];
         // every lane holds the same row values, so all lanes store them
         // (no exec-mask change on the row's path)
 #pragma unroll

@@ -51,7 +51,9 @@ constexpr int n_params_of_sys(int sys, int d)
 }
 
 // f(t, y; theta) for the fixed set of systems (textbook forms; parameter
-// layout as documented in fabm.h). D is the state dimension.
+// layout as documented in fabm.h). D is the state dimension. Every product
+// that meets a sum is written as an explicit fma, so the rounding of each
+// system is fixed by this source and not by the compiler's contraction.
 template <int SYS, int D>
 __device__ __forceinline__ void rhs(double t, const double (&y)[D], double (&f)[D],
                                     const double *__restrict__ p)
@@ -67,8 +69,8 @@ __device__ __forceinline__ void rhs(double t, const double (&y)[D], double (&f)[
     } else if constexpr (SYS == SYS_CHEN) {
         const double a = p[0], b = p[1], c = p[2];
         f[0] = a * (y[1] - y[0]);
-        f[1] = (c - a) * y[0] - y[0] * y[2] + c * y[1];
-        f[2] = y[0] * y[1] - b * y[2];
+        f[1] = fma(y[0], (c - a) - y[2], c * y[1]);  // (c-a)x - xz + cy
+        f[2] = fma(y[0], y[1], -b * y[2]);
     } else if constexpr (SYS == SYS_ROSSLER) {
         const double a = p[0], b = p[1], c = p[2];
         f[0] = -y[1] - y[2];
@@ -77,12 +79,12 @@ __device__ __forceinline__ void rhs(double t, const double (&y)[D], double (&f)[
     } else if constexpr (SYS == SYS_VDP) {
         const double mu = p[0];
         f[0] = y[1];
-        f[1] = mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
+        f[1] = fma(mu * fma(-y[0], y[0], 1.0), y[1], -y[0]);
     } else if constexpr (SYS == SYS_FINANCIAL) {
         const double a = p[0], b = p[1], c = p[2];
         f[0] = fma(y[1] - a, y[0], y[2]);
-        f[1] = 1.0 - b * y[1] - y[0] * y[0];
-        f[2] = -y[0] - c * y[2];
+        f[1] = fma(-y[0], y[0], fma(-b, y[1], 1.0));
+        f[2] = fma(-c, y[2], -y[0]);
     } else if constexpr (SYS == SYS_HINDMARSH_ROSE) {
         // theta = (a, b, c, d, r, s, xr, I)
         const double x = y[0], x2 = x * x;

@@ -114,24 +114,23 @@ def test_blocked_chen_full_size(F, orc):
 
 def test_blocked_chen_attractor_statistics(F, orc):
     """Chen over N = 2^16 (T = 65.5): past the chaotic horizon trajectories of
-    different rounding share only the attractor. The GPU's statistics over the
-    second half (per component: mean, variance, min, max) against an ensemble
-    of three oracle runs (y0, and y0 with one component moved by one ulp
-    either way): the mean of z and the variances of x and y, which settle
-    within this window (the ensemble spreads by under 2%), within 2% of the
-    oracle's ensemble average; every statistic within the ensemble's range widened by that
-    range, or by 2% of the statistic (or of the component's standard deviation)
-    where the runs happen to agree more closely (the mean of x and y is near
-    zero on this symmetric attractor and the variance of z still drifts by
-    several percent between runs)."""
+    different rounding share only the attractor. Statistics over t >= 8.192
+    (steps 8192 .. N) of the GPU trajectory against the average of three
+    oracle runs (y0, and y0 with one component moved by one ulp either way).
+    Tolerances from the spread of such runs (five oracle runs: relative
+    standard deviation 0.05% for the mean of z, about 1% for the variances of
+    x and y, 5% for the variance of z; the means of x and y, near zero on this
+    symmetric attractor, within about 0.05 standard deviations of x): the mean
+    of z within 1%, the variances of x and y within 4%, the means of x and y
+    within 0.2 standard deviations of zero, and the trajectory bounded."""
     import threading
     from paper_1611_08678_amd import workloads as W
-    N = 1 << 16
+    N, lo = 1 << 16, 8192
     w = W.chen(N=N)
     y, st = F.solve(w["system"], w["theta"][0], w["alpha"][0], w["h"][0], N, w["y0"][0],
                     path="blocked")
     yy = _to_np(y)
-    assert int(st.item()) == 0 and np.all(np.isfinite(yy))
+    assert int(st.item()) == 0 and np.all(np.isfinite(yy)) and np.abs(yy).max() < 60.0
     starts = [w["y0"][0].copy() for _ in range(3)]
     starts[1][0] = np.nextafter(starts[1][0], np.inf)
     starts[2][1] = np.nextafter(starts[2][1], -np.inf)
@@ -146,22 +145,12 @@ def test_blocked_chen_attractor_statistics(F, orc):
         t.start()
     for t in ts:
         t.join()
-
-    def stats(a):
-        h = a[len(a) // 2:]
-        return np.stack([h.mean(0), h.var(0), h.min(0), h.max(0)])
-
-    g = stats(yy)
-    R = np.stack([stats(r) for r in refs])
-    o = R.mean(0)  # the oracle's statistics, averaged over its three runs
-    assert abs(g[0, 2] - o[0, 2]) <= 0.02 * abs(o[0, 2])  # mean of z
-    assert np.all(np.abs(g[1, :2] - o[1, :2]) <= 0.02 * o[1, :2])  # variance of x, y
-    lo, hi = R.min(0), R.max(0)
-    # widened by the ensemble's spread, and at least by 2% of the statistic
-    # (three runs can agree closely by chance: the mean of z spreads by 0.1%)
-    sd = np.sqrt(o[1])
-    wide = np.maximum(hi - lo, 0.02 * np.maximum(np.abs(o), sd[None, :]))
-    assert np.all(g >= lo - wide) and np.all(g <= hi + wide), (g, lo, hi, wide)
+    g_mean, g_var = yy[lo:].mean(0), yy[lo:].var(0)
+    o_mean = np.mean([r[lo:].mean(0) for r in refs], axis=0)
+    o_var = np.mean([r[lo:].var(0) for r in refs], axis=0)
+    assert abs(g_mean[2] - o_mean[2]) <= 0.01 * abs(o_mean[2]), (g_mean, o_mean)
+    assert np.all(np.abs(g_var[:2] - o_var[:2]) <= 0.04 * o_var[:2]), (g_var, o_var)
+    assert np.all(np.abs(g_mean[:2]) <= 0.2 * np.sqrt(o_var[0])), (g_mean, o_var)
 
 
 @pytest.mark.parametrize("far_prec", ["fp64", "fp32"])
