@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
 # reference copy kernel (profiles/k_step_chen_N2p20_pmc.md), valid only for
 # the kernel source it was measured on (sha256 prefix of blocked.hip).
-MEASURED_TRAFFIC = {"k_step": (59.12e6, "66c96f50e43922b2")}
+MEASURED_TRAFFIC = {"k_step": (59.12e6, "e7b8c42bcb1699d9")}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense binary16 matrix rate
@@ -159,14 +159,21 @@ def cpu_baseline(w, n_sample: int, N: int):
 def measured_traffic(kernel: str):
     """Counter-measured HBM bytes per launch, or None if the kernel source has
     changed since the counters were taken."""
-    import hashlib
     val, sha = MEASURED_TRAFFIC.get(kernel, (None, None))
     if val is None:
         return None
-    src = os.path.join(ROOT, "paper_1611_08678_amd", "csrc", "blocked.hip")
-    with open(src, "rb") as f:
-        cur = hashlib.sha256(f.read()).hexdigest()[:16]
-    return val if cur == sha else None
+    return val if kernel_source_hash() == sha else None
+
+
+def kernel_source_hash() -> str:
+    """sha256 prefix of the sources k_step is built from (kernel file and the
+    device headers it includes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("blocked.hip", "fabm_blocked.h", "fabm_device.h"):
+        with open(os.path.join(ROOT, "paper_1611_08678_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def roofline(kt: dict, N: int, d: int, fft_level: int = 0, solve_s: float = None):
