@@ -62,6 +62,7 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 constexpr int kBandWaves = 4;
 constexpr int kPublishEvery = 8;           // rows between counter updates
+constexpr int kBandRows = kBlk + kWave;    // row arrays of the walk: a spare row per lane
 constexpr uint32_t kSpinLimit = 1u << 26;  // polls of the row counter before giving up
 
 __device__ __forceinline__ double readlane_f64(double x, int l)
@@ -103,10 +104,11 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     double *sa = sb + K * 2 * kBlk;   // [K] a lags 0..511
     double *sbh = sa + K * 2 * kBlk;  // [K] h^a b lags 0..255 (this block's sums)
     double *sah = sbh + K * kBlk;     // [K] h^a a lags 0..255
-    double *sF = sah + K * kBlk;      // [256][D] f of this block's rows
-    double *sY = sF + kBlk * D;    // [256][D] y of this block's rows
-    double *sYP = sY + kBlk * D;   // [256][D] predictor values (YPOUT)
-    double *sTh = sYP + (YPOUT ? kBlk * D : 0);  // theta, for systems with many parameters
+    // row arrays: 256 rows of this block and a spare row per lane
+    double *sF = sah + K * kBlk;        // [320][D] f of this block's rows
+    double *sY = sF + kBandRows * D;    // [320][D] y of this block's rows
+    double *sYP = sY + kBandRows * D;   // [320][D] predictor values (YPOUT)
+    double *sTh = sYP + (YPOUT ? kBandRows * D : 0);  // theta, for systems with many parameters
     int *s_cnt = (int *)(sTh + NP);  // rows of this block published so far (> 256: stop)
     int *s_dead = s_cnt + 1;         // first non-finite row (block-relative), -1, or -2
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -270,14 +272,14 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             }
         }
     }
-    // This wavefront's rows. At row t every lane first adds row t-1 to its
-    // sums (lane t - lo's weights are then h^a b_0 and h^a a_0, so it holds
-    // row t's whole predictor sum y0 + h^a P_t and corrector sum); those are
-    // read out (readlane) and every lane evaluates
+    // This wavefront's rows. At row t every lane adds f_{t-1} (held in
+    // scalar registers) to its own sums; lane t - lo's weights are then
+    // h^a b_0 and h^a a_0, so it holds row t's whole predictor sum
+    // y0 + h^a P_t and corrector sum. Every lane evaluates
     //   yP_t = y0 + h^a P_t,  y_t = (y0 + h^a C_t) + (h^a / Gamma(a+2)) f(t, yP_t)
-    // on the same values, so f_t is in every lane without a broadcast. The
-    // corrector sum is read out while the predictor is evaluated. Rows are
-    // checked for non-finite values when they are published.
+    // on its own sums (only lane t - lo's are row t's), and f_t is read out of
+    // lane t - lo (readlane) for the next row: one broadcast of d values per
+    // row. Rows are checked for non-finite values when they are published.
     const int first = done;
     double hig2[K];
 #pragma unroll
@@ -288,72 +290,67 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     double fprev[D];  // f of the row before (its terms are not in the sums yet)
 #pragma unroll
     for (int i = 0; i < D; ++i) fprev[i] = 0.0;
+    // lanes whose row is already formed store their (meaningless) values to
+    // a spare row of their own, lanes of later rows to their row, which the
+    // walk overwrites when it gets there
+    const int row_off = row * D, spare_off = (kBlk + lane) * D;
     int checked = first;  // rows before this one have been checked
     // rows in groups of kPublishEvery (aligned to the block), unrolled, so the
-    // publish check runs once per group; the weights of the next step are
-    // loaded one step ahead
-    int lc0 = row - first;
-    double bw[K], aw[K];
+    // publish check runs once per group; the weights of a group's rows (lag
+    // row - t for the term f_{t-1}) are loaded before the group, so no LDS
+    // load is waited for inside it
+    double bwg[kPublishEvery][K], awg[kPublishEvery][K];
+    auto load_group = [&](const int g) __attribute__((always_inline)) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        bw[k] = sbh[k * kBlk + (lc0 > 0 ? lc0 : 0)];
-        aw[k] = sah[k * kBlk + (lc0 > 0 ? lc0 : 0)];
-    }
-    // one row of the walk; full groups of kPublishEvery rows run without the
-    // per-row range check
-    auto step_row = [&](const int t) __attribute__((always_inline)) {
-        const int lagn = row - t - 1;
-        double bwn[K], awn[K];
+        for (int k = 0; k < kPublishEvery; ++k) {
+            const int lag = row - g - k > 0 ? row - g - k : 0;
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            bwn[q] = sbh[q * kBlk + (lagn > 0 ? lagn : 0)];
-            awn[q] = sah[q * kBlk + (lagn > 0 ? lagn : 0)];
+            for (int q = 0; q < K; ++q) {
+                bwg[k][q] = sbh[q * kBlk + lag];
+                awg[k][q] = sah[q * kBlk + lag];
+            }
         }
+    };
+    // one row of the walk (k: its place in the group); full groups of
+    // kPublishEvery rows run without the per-row range check
+    auto step_row = [&](const int t, const int k) __attribute__((always_inline)) {
         const double tt = (double)(t0 + t) * m.h;
-        double yp[D], fp[D], y[D], f[D], yc[D];
-        // row t-1 into the sums first: lane t - lo then holds row t's whole
+        double fp[D], y[D], f[D];
+        // f_{t-1} into the sums: lane t - lo then holds row t's whole
         // predictor and corrector sums (lag-0 weights h^a b_0, h^a a_0)
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = fma(bw[PC ? i : 0], fprev[i], pc[i]);
-            cc[i] = fma(aw[PC ? i : 0], fprev[i], cc[i]);
+            pc[i] = fma(bwg[k][PC ? i : 0], fprev[i], pc[i]);
+            cc[i] = fma(awg[k][PC ? i : 0], fprev[i], cc[i]);
         }
+        rhs<SYS, D>(tt, pc, fp, th);
 #pragma unroll
-        for (int i = 0; i < D; ++i) yp[i] = readlane_f64(pc[i], t - lo);
-        rhs<SYS, D>(tt, yp, fp, th);
-#pragma unroll
-        for (int i = 0; i < D; ++i) yc[i] = readlane_f64(cc[i], t - lo);
-#pragma unroll
-        for (int i = 0; i < D; ++i) y[i] = fma(hig2[PC ? i : 0], fp[i], yc[i]);
+        for (int i = 0; i < D; ++i) y[i] = fma(hig2[PC ? i : 0], fp[i], cc[i]);
         rhs<SYS, D>(tt, y, f, th);
 #pragma unroll
-        for (int i = 0; i < D; ++i) fprev[i] = f[i];
-        // every lane holds the same row values, so all lanes store them
-        // (no exec-mask change on the row's path)
+        for (int i = 0; i < D; ++i) fprev[i] = readlane_f64(f[i], t - lo);
+        const int o = row >= t ? row_off : spare_off;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            sF[t * D + i] = f[i];
-            sY[t * D + i] = y[i];
-            if constexpr (YPOUT) sYP[t * D + i] = yp[i];
+            sF[o + i] = f[i];
+            sY[o + i] = y[i];
+            if constexpr (YPOUT) sYP[o + i] = pc[i];
         }
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            bw[q] = bwn[q];
-            aw[q] = awn[q];
-        }
-            };
+    };
+    load_group(first & ~(kPublishEvery - 1));
     for (int g0 = first & ~(kPublishEvery - 1); go && g0 < hi; g0 += kPublishEvery) {
         if (g0 >= first && g0 + kPublishEvery <= hi) {
 #pragma unroll
-            for (int k = 0; k < kPublishEvery; ++k) step_row(g0 + k);
+            for (int k = 0; k < kPublishEvery; ++k) step_row(g0 + k, k);
         } else {
 #pragma unroll
             for (int k = 0; k < kPublishEvery; ++k) {
                 const int t = g0 + k;
-                if (t >= first && t < hi) step_row(t);
+                if (t >= first && t < hi) step_row(t, k);
             }
         }
         const int tl = g0 + kPublishEvery < hi ? g0 + kPublishEvery : hi;  // rows formed: < tl
+        load_group(g0 + kPublishEvery);
         {
             __builtin_amdgcn_wave_barrier();
             const int nv = (tl - checked) * 2 * D;
@@ -967,8 +964,8 @@ __global__ void k_step_status(StepArgs A)
 // orders), f / y / predictor rows, theta, two counters.
 static size_t band_smem_bytes(int d, bool pc)
 {
-    return sizeof(double) * (6 * kBlk * (size_t)(pc ? d : 1) + 3 * kBlk * (size_t)d + d * d +
-                             2 * d) +
+    return sizeof(double) * (6 * kBlk * (size_t)(pc ? d : 1) + 3 * kBandRows * (size_t)d +
+                             d * d + 2 * d) +
            16;
 }
 
