@@ -27,6 +27,7 @@
 //    one target per wavefront, accumulated in place in `acc`.
 // Every sum is accumulated in a fixed order, so results are bit-reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "fabm_blocked.h"
 #include "fabm_device.h"
@@ -108,7 +109,9 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     double *sF = sah + K * kBlk;        // [320][D] f of this block's rows
     double *sY = sF + kBandRows * D;    // [320][D] y of this block's rows
     double *sYP = sY + kBandRows * D;   // [320][D] predictor values (YPOUT)
-    double *sTh = sYP + (YPOUT ? kBandRows * D : 0);  // theta, for systems with many parameters
+    // the last wavefront's next-block sums, handed to wavefront 0 ([2][D][64])
+    double *sH = sYP + (YPOUT ? kBandRows * D : 0);
+    double *sTh = sH + 2 * D * kWave;  // theta, for systems with many parameters
     int *s_cnt = (int *)(sTh + NP);  // rows of this block published so far (> 256: stop)
     int *s_dead = s_cnt + 1;         // first non-finite row (block-relative), -1, or -2
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -130,14 +133,9 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
 
     // rows go to Y and YP at row t - yrow0 (0 except in a recompute ring)
     const int64_t ro = (t0 - A.yrow0) * D;
-    // a non-finite state in an earlier block ends the trajectory
-    if (*A.dead != 0u) {
-        for (int e = tid; e < nrows * D; e += nthr) {
-            if (A.Y) A.Y[ro + e] = __builtin_nan("");
-            if constexpr (YPOUT) A.YP[ro + e] = __builtin_nan("");
-        }
-        return;
-    }
+    // a non-finite state in an earlier block ends the trajectory (tested
+    // after the loads below are issued, which read only valid memory)
+    const uint32_t dead_in = __builtin_amdgcn_readfirstlane(*A.dead);
     // theta in registers when short; a linear system's matrix is read from LDS
     constexpr bool kThLds = NP > 12;
     double thr[kThLds || NP == 0 ? 1 : NP], y0[D];
@@ -241,6 +239,13 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             cc[i] = fma(hav[PC ? i : 0], Cs[i], base[i]);
         }
     }
+    if (dead_in != 0u) {
+        for (int e = tid; e < nrows * D; e += nthr) {
+            if (A.Y) A.Y[ro + e] = __builtin_nan("");
+            if constexpr (YPOUT) A.YP[ro + e] = __builtin_nan("");
+        }
+        return;
+    }
     __syncthreads();
 
     // rows this wavefront forms: [lo, hi)
@@ -248,6 +253,65 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     const int hi = 64 * wave + 64 < nrows ? 64 * wave + 64 : nrows;
     int done = J == 0 ? 1 : 0;  // rows already in this wavefront's sums
     bool go = true;
+    // Published rows [r, r + R) into this lane's sums, in row order; the
+    // weights and f values of the R rows are loaded before the first FMA.
+    // Mode Both: this block's and the next block's sums (rows before the
+    // lane's own); Next: the next block's only; NextH: the next block's and
+    // the sums handed over by the last wavefront (target row 192 + lane).
+    constexpr int kLast = kBandWaves - 1;
+    double pnh[D], cnh[D];
+    auto add_rows = [&](const int r, auto nrow, auto mode) __attribute__((always_inline)) {
+        constexpr int R = decltype(nrow)::value;
+        constexpr int M = decltype(mode)::value;
+        double wbn[R][K], wan[R][K], wbh[R][K], wah[R][K], fr[R][D];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int lag = row - r - q - 1;  // >= 0 for rows before the lane's own
+            const int lagh = kWave * kLast + lane - r - q - 1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                wbn[q][k] = sb[k * 2 * kBlk + kBlk + lag];
+                wan[q][k] = sa[k * 2 * kBlk + kBlk + lag];
+                if constexpr (M == 0) {
+                    wbh[q][k] = sbh[k * kBlk + lag];
+                    wah[q][k] = sah[k * kBlk + lag];
+                } else if constexpr (M == 2) {
+                    wbh[q][k] = sb[k * 2 * kBlk + kBlk + lagh];
+                    wah[q][k] = sa[k * 2 * kBlk + kBlk + lagh];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) fr[q][i] = sF[(r + q) * D + i];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int k = PC ? i : 0;
+                if constexpr (M == 0) {
+                    pc[i] = fma(wbh[q][k], fr[q][i], pc[i]);
+                    cc[i] = fma(wah[q][k], fr[q][i], cc[i]);
+                } else if constexpr (M == 2) {
+                    pnh[i] = fma(wbh[q][k], fr[q][i], pnh[i]);
+                    cnh[i] = fma(wah[q][k], fr[q][i], cnh[i]);
+                }
+                pn[i] = fma(wbn[q][k], fr[q][i], pn[i]);
+                cn[i] = fma(wan[q][k], fr[q][i], cn[i]);
+            }
+        }
+    };
+    // rows per batch: four with one table set and d <= 3, else fewer (registers)
+    constexpr int kCatch = K > 1 ? 1 : (D <= 3 ? 4 : 2);
+    using One = std::integral_constant<int, 1>;
+    using Many = std::integral_constant<int, kCatch>;
+    using Both = std::integral_constant<int, 0>;
+    using Next = std::integral_constant<int, 1>;
+    using NextH = std::integral_constant<int, 2>;
+    // In a full block the last wavefront's next-block sums (over the rows
+    // before its own) go to wavefront 0 when its walk starts; wavefront 0 adds
+    // the last wavefront's rows to them as they are published, in row order,
+    // and stores them, so the last wavefront ends with its walk.
+    const bool handoff = nrows == kBlk;
     // rows formed by earlier wavefronts: both blocks' sums
     while (go && done < lo) {
         const int c = __builtin_amdgcn_readfirstlane(band_wait_rows(s_cnt, s_dead, done + 1));
@@ -256,20 +320,14 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             break;
         }
         const int upto = c < lo ? c : lo;
-        for (; done < upto; ++done) {
+        for (; done + kCatch <= upto; done += kCatch) add_rows(done, Many{}, Both{});
+        for (; done < upto; ++done) add_rows(done, One{}, Both{});
+    }
+    if (handoff && go && wave == kLast) {
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const int k = PC ? i : 0;
-                const double bw = sbh[k * kBlk + row - done - 1];
-                const double aw = sah[k * kBlk + row - done - 1];
-                const double bn = sb[k * 2 * kBlk + kBlk + row - done - 1];
-                const double an = sa[k * 2 * kBlk + kBlk + row - done - 1];
-                const double f = sF[done * D + i];
-                pc[i] = fma(bw, f, pc[i]);
-                cc[i] = fma(aw, f, cc[i]);
-                pn[i] = fma(bn, f, pn[i]);
-                cn[i] = fma(an, f, cn[i]);
-            }
+        for (int i = 0; i < D; ++i) {
+            sH[i * kWave + lane] = pn[i];
+            sH[(D + i) * kWave + lane] = cn[i];
         }
     }
     // This wavefront's rows. At row t every lane adds f_{t-1} (held in
@@ -294,21 +352,56 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     // a spare row of their own, lanes of later rows to their row, which the
     // walk overwrites when it gets there
     const int row_off = row * D, spare_off = (kBlk + lane) * D;
-    int checked = first;  // rows before this one have been checked
-    // rows in groups of kPublishEvery (aligned to the block), unrolled, so the
-    // publish check runs once per group; the weights of a group's rows (lag
-    // row - t for the term f_{t-1}) are loaded before the group, so no LDS
-    // load is waited for inside it
-    double bwg[kPublishEvery][K], awg[kPublishEvery][K];
-    auto load_group = [&](const int g) __attribute__((always_inline)) {
-#pragma unroll
-        for (int k = 0; k < kPublishEvery; ++k) {
-            const int lag = row - g - k > 0 ? row - g - k : 0;
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                bwg[k][q] = sbh[q * kBlk + lag];
-                awg[k][q] = sah[q * kBlk + lag];
+    int checked = first;  // check values of rows before this one are loaded
+    // Rows are published in groups, each one group late: the f and y values
+    // of a group are loaded from LDS after it is formed and tested after the
+    // next group, so the walk never waits for them; a non-finite value stops
+    // the walk there (the rows formed after it are never published).
+    int pend_lo = first, pend_hi = first;  // rows of the loaded check values
+    double chk = 0.0;
+    auto settle = [&]() __attribute__((always_inline)) -> bool {
+        if (pend_hi <= pend_lo) return true;
+        const uint64_t mask = __ballot(!isfinite(chk));
+        if (mask) {
+            if (lane == 0) {
+                *s_dead = pend_lo + __builtin_ctzll(mask) / (2 * D);
+                __hip_atomic_store(s_cnt, kBlk + 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
             }
+            return false;
+        }
+        // The rows' LDS stores were issued before this one and a wavefront's
+        // LDS operations are performed in issue order, so a plain store of
+        // the counter (kept after them by a compiler barrier) publishes them
+        // without waiting for the LDS queue to drain.
+        __asm__ __volatile__("" ::: "memory");
+        if (lane == 0)
+            __hip_atomic_store(s_cnt, pend_hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        pend_lo = pend_hi;
+        return true;
+    };
+    // rows in groups of kPublishEvery (aligned to the block), unrolled, so the
+    // publish check runs once per group. The weights of row t (lag row - t
+    // for the term f_{t-1}) come from LDS: with one table set, slot k of a
+    // ring of kPublishEvery holds rows t = k mod kPublishEvery and is reloaded
+    // for row t + kPublishEvery right after row t uses it, so the walk never
+    // waits for them; with one set per component (more registers) each row's
+    // are loaded during the row before (also for systems whose parameters
+    // are read from LDS, which hold more registers).
+    constexpr int kRing = K == 1 && !kThLds ? kPublishEvery : 1;
+    double bwg[kRing][K], awg[kRing][K];
+    auto load_row = [&](const int t, const int sl) __attribute__((always_inline)) {
+        const int lag = row - t > 0 ? row - t : 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            bwg[sl][q] = sbh[q * kBlk + lag];
+            awg[sl][q] = sah[q * kBlk + lag];
+        }
+    };
+    auto load_group = [&](const int g) __attribute__((always_inline)) {
+        if constexpr (kRing > 1) {
+#pragma unroll
+            for (int k = 0; k < kRing; ++k) load_row(g + k, k);
         }
     };
     // one row of the walk (k: its place in the group); full groups of
@@ -316,13 +409,17 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     auto step_row = [&](const int t, const int k) __attribute__((always_inline)) {
         const double tt = (double)(t0 + t) * m.h;
         double fp[D], y[D], f[D];
+        const int sl = kRing > 1 ? k : 0;
         // f_{t-1} into the sums: lane t - lo then holds row t's whole
         // predictor and corrector sums (lag-0 weights h^a b_0, h^a a_0)
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            pc[i] = fma(bwg[k][PC ? i : 0], fprev[i], pc[i]);
-            cc[i] = fma(awg[k][PC ? i : 0], fprev[i], cc[i]);
+            pc[i] = fma(bwg[sl][PC ? i : 0], fprev[i], pc[i]);
+            cc[i] = fma(awg[sl][PC ? i : 0], fprev[i], cc[i]);
         }
+        // the slot's weights for the row a group later (one table set), or
+        // for the next row
+        load_row(kRing > 1 ? t + kPublishEvery : t + 1, sl);
         rhs<SYS, D>(tt, pc, fp, th);
 #pragma unroll
         for (int i = 0; i < D; ++i) y[i] = fma(hig2[PC ? i : 0], fp[i], cc[i]);
@@ -337,72 +434,80 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
             if constexpr (YPOUT) sYP[o + i] = pc[i];
         }
     };
-    load_group(first & ~(kPublishEvery - 1));
-    for (int g0 = first & ~(kPublishEvery - 1); go && g0 < hi; g0 += kPublishEvery) {
-        if (g0 >= first && g0 + kPublishEvery <= hi) {
-#pragma unroll
-            for (int k = 0; k < kPublishEvery; ++k) step_row(g0 + k, k);
-        } else {
-#pragma unroll
-            for (int k = 0; k < kPublishEvery; ++k) {
-                const int t = g0 + k;
-                if (t >= first && t < hi) step_row(t, k);
-            }
-        }
-        const int tl = g0 + kPublishEvery < hi ? g0 + kPublishEvery : hi;  // rows formed: < tl
-        load_group(g0 + kPublishEvery);
-        {
-            __builtin_amdgcn_wave_barrier();
-            const int nv = (tl - checked) * 2 * D;
-            bool bad = false;
-            if (lane < nv) {
-                const int r = checked + lane / (2 * D), kk = lane % (2 * D);
-                bad = !isfinite(kk < D ? sF[r * D + kk] : sY[r * D + kk - D]);
-            }
-            const uint64_t mask = __ballot(bad);
-            if (mask) {
-                if (lane == 0) {
-                    *s_dead = checked + __builtin_ctzll(mask) / (2 * D);
-                    __hip_atomic_store(s_cnt, kBlk + 1, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-                go = false;
-                break;
-            }
-            checked = tl;
-            if (lane == 0)
-                __hip_atomic_store(s_cnt, tl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        done = tl;
-    }
-    if (go) {
-        // own rows into block J+1 (f_t was written to LDS by lane 0 of this
-        // wavefront), then rows formed by later wavefronts
+    if constexpr (kRing > 1)
+        load_group(first & ~(kPublishEvery - 1));
+    else
+        load_row(first, 0);
+    // end of a group of rows [., tl): the group before is checked (its
+    // values were loaded a group ago) and published, and this group's f and
+    // y values (one per lane) are loaded for the check after the next group
+    auto end_group = [&](const int tl) __attribute__((always_inline)) -> bool {
+        if (!settle()) return false;
         __builtin_amdgcn_wave_barrier();
-        for (int t = first; t < hi; ++t) {
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const int k = PC ? i : 0;
-                const double bn = sb[k * 2 * kBlk + kBlk + row - t - 1];
-                const double an = sa[k * 2 * kBlk + kBlk + row - t - 1];
-                const double f = sF[t * D + i];
-                pn[i] = fma(bn, f, pn[i]);
-                cn[i] = fma(an, f, cn[i]);
-            }
+        const int nv = (tl - checked) * 2 * D;
+        chk = 0.0;
+        if (lane < nv) {
+            const int r = checked + lane / (2 * D), kk = lane % (2 * D);
+            chk = kk < D ? sF[r * D + kk] : sY[r * D + kk - D];
         }
+        pend_lo = checked;
+        pend_hi = tl;
+        checked = tl;
+        done = tl;
+        return true;
+    };
+    // a group with rows outside [first, hi) (block 0's first row, a ragged
+    // last block): each row's range checked
+    auto partial_group = [&](const int g0) __attribute__((always_inline)) -> bool {
+#pragma unroll
+        for (int k = 0; k < kPublishEvery; ++k) {
+            const int t = g0 + k;
+            if (t >= first && t < hi)
+                step_row(t, k);
+            else if constexpr (kRing > 1)
+                load_row(t + kPublishEvery, k);  // keep the slot a group ahead
+        }
+        return end_group(g0 + kPublishEvery < hi ? g0 + kPublishEvery : hi);
+    };
+    int g0 = first & ~(kPublishEvery - 1);
+    if (go && g0 < hi && (g0 < first || g0 + kPublishEvery > hi)) {
+        go = partial_group(g0);
+        g0 += kPublishEvery;
+    }
+    for (; go && g0 + kPublishEvery <= hi; g0 += kPublishEvery) {
+#pragma unroll
+        for (int k = 0; k < kPublishEvery; ++k) step_row(g0 + k, k);
+        go = end_group(g0 + kPublishEvery);
+    }
+    if (go && g0 < hi) go = partial_group(g0);
+    if (go && !settle()) go = false;
+    if (go && !(handoff && wave == kLast)) {
+        // own rows into block J+1, then rows formed by later wavefronts
+        // (the next block's weights are at lag 256 + row - t - 1 >= 0)
+        __builtin_amdgcn_wave_barrier();
+        int t = first;
+        for (; t + kCatch <= hi; t += kCatch) add_rows(t, Many{}, Next{});
+        for (; t < hi; ++t) add_rows(t, One{}, Next{});
+        const bool take = handoff && wave == 0;  // uniform
+        bool have = false;
         while (done < nrows) {
             const int c = __builtin_amdgcn_readfirstlane(band_wait_rows(s_cnt, s_dead, done + 1));
             if (c < 0) break;
-            for (; done < c; ++done) {
+            const int cut = take && c > kWave * kLast ? kWave * kLast : c;
+            for (; done + kCatch <= cut; done += kCatch) add_rows(done, Many{}, Next{});
+            for (; done < cut; ++done) add_rows(done, One{}, Next{});
+            if (done < c) {  // the last wavefront's rows (wavefront 0 of a full block)
+                if (!have) {
+                    // written before the last wavefront published any row
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    const int k = PC ? i : 0;
-                    const double bn = sb[k * 2 * kBlk + kBlk + row - done - 1];
-                    const double an = sa[k * 2 * kBlk + kBlk + row - done - 1];
-                    const double f = sF[done * D + i];
-                    pn[i] = fma(bn, f, pn[i]);
-                    cn[i] = fma(an, f, cn[i]);
+                    for (int i = 0; i < D; ++i) {
+                        pnh[i] = sH[i * kWave + lane];
+                        cnh[i] = sH[(D + i) * kWave + lane];
+                    }
+                    have = true;
                 }
+                for (; done + kCatch <= c; done += kCatch) add_rows(done, Many{}, NextH{});
+                for (; done < c; ++done) add_rows(done, One{}, NextH{});
             }
         }
     }
@@ -427,10 +532,19 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     }
     if (dead == -1) {
         double *cout = A.carry + (int64_t)((J + 1) & 1) * 2 * D * kBlk;
+        if (!(handoff && wave == kLast)) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            cout[i * kBlk + row] = pn[i];
-            cout[(D + i) * kBlk + row] = cn[i];
+            for (int i = 0; i < D; ++i) {
+                cout[i * kBlk + row] = pn[i];
+                cout[(D + i) * kBlk + row] = cn[i];
+            }
+        }
+        if (handoff && wave == 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                cout[i * kBlk + kWave * kLast + lane] = pnh[i];
+                cout[(D + i) * kBlk + kWave * kLast + lane] = cnh[i];
+            }
         }
     } else if (tid == 0) {
         *A.dead = dead == -2 ? kDeadWatchdog : (uint32_t)(t0 + dead);
@@ -965,7 +1079,7 @@ __global__ void k_step_status(StepArgs A)
 static size_t band_smem_bytes(int d, bool pc)
 {
     return sizeof(double) * (6 * kBlk * (size_t)(pc ? d : 1) + 3 * kBandRows * (size_t)d +
-                             d * d + 2 * d) +
+                             2 * kWave * (size_t)d + d * d + 2 * d) +
            16;
 }
 
