@@ -12,6 +12,7 @@
 // workgroup).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "fabm_device.h"
 #include "fabm_launch.h"
@@ -206,6 +207,13 @@ __global__ __launch_bounds__(256) void k_wide_far_f32(WideArgs A, int s, int spl
 // ---------------------------------------------------------------------------
 constexpr int kT16Row = 2 * LW;                    // halves per shifted copy
 constexpr int kT16Q = 2 * 2 * 8 * kT16Row;         // halves per lag block q
+// In LDS each copy is padded by one 16-byte entry: the eight lanes that read
+// together (sigma = 0..7 or 8..15 of one 16-lane group) take the same entry of
+// eight different copies, which 256-byte copies would put in one bank.
+constexpr int kT16Ent = kT16Row / 8;               // 16-byte entries per copy
+constexpr int kT16Pitch = kT16Ent + 1;             // entries per copy in LDS
+constexpr int kT16Copies = 2 * 2 * 8;              // (table, part, shift) copies
+static_assert(kT16Q / 8 == kT16Copies * kT16Ent, "operand table layout");
 
 __global__ __launch_bounds__(256) void k_wide_t16(WideArgs A, _Float16 *T16, int32_t *T16exp)
 {
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(256) void k_wide_t16(WideArgs A, _Float16 *T16, int
 // the current block is multiplied.
 __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int splits)
 {
-    __shared__ half8 sT[2][kT16Q / 8];  // [buffer][table, part, copy, entry / 8]
+    __shared__ half8 sT[2][kT16Copies * kT16Pitch];  // [buffer][table, part, copy][entry]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, sig = lane & 15;
     int I0, I1;
@@ -263,26 +271,54 @@ __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int spl
 
     const half8 *T16 = (const half8 *)A.T16;
     const half8 *Fh = (const half8 *)A.Fhi, *Fl = (const half8 *)A.Flo;
-    // history operands of one block: rows 32 ks + 8 (l/16) .. +7 of this column
-    half8 bh[2], bl[2], nh[2], nl[2];
-    int ef = 0, nef = 0;
-    auto load_b = [&](int I, half8 (&h)[2], half8 (&l)[2], int &e) {
+    // History operands of a block (rows 32 ks + 8 (l/16) .. +7 of this
+    // column) in a ring of three: block I's are loaded while block I - 2 is
+    // multiplied, two blocks of HBM latency ahead.
+    half8 bh[3][2], bl[3][2];
+    int ef[3] = {0, 0, 0};
+    auto load_b = [&](const int I, auto SLOT) __attribute__((always_inline)) {
+        constexpr int R = decltype(SLOT)::value;
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             const int64_t o = ((int64_t)I * (LW / 8) + 4 * ks + g) * cp + col;
-            h[ks] = Fh[o];
-            l[ks] = Fl[o];
+            bh[R][ks] = Fh[o];
+            bl[R][ks] = Fl[o];
         }
-        e = A.Fexp[(int64_t)I * cp + col];
+        ef[R] = A.Fexp[(int64_t)I * cp + col];
     };
+    // LDS slot of table entry e (= copy * 16 + entry) of a lag block
+    const int st0 = (tid / kT16Ent) * kT16Pitch + tid % kT16Ent;
+    const int st1 = ((tid + 256) / kT16Ent) * kT16Pitch + (tid + 256) % kT16Ent;
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
+    using C2 = std::integral_constant<int, 2>;
     if (I0 < I1) {
         const half8 *src = T16 + (int64_t)(s - I0) * (kT16Q / 8);
-        sT[0][tid] = src[tid];
-        sT[0][tid + 256] = src[tid + 256];
-        load_b(I0, bh, bl, ef);
+        sT[0][st0] = src[tid];
+        sT[0][st1] = src[tid + 256];
+        load_b(I0, C0{});
+        if (I0 + 1 < I1) load_b(I0 + 1, C1{});
     }
     __syncthreads();
-    for (int I = I0; I < I1; ++I) {
+    // Block I's products go to one of two sets of binary32 sums while the
+    // other set (block I - 1's) is scaled and added into binary64, so the
+    // matrix cores are not drained before every conversion.
+    flt4 c32[2][2][4];  // [set][table][rt]
+    double psc[2] = {0.0, 0.0};  // scales of the block in the other set
+    auto convert = [&](auto SET) __attribute__((always_inline)) {
+        constexpr int S = decltype(SET)::value;
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[tb][rt][v] = fma((double)c32[S][tb][rt][v], psc[tb], acc[tb][rt][v]);
+    };
+    // block I: sum set S = (I - I0) mod 2, history slot R = (I - I0) mod 3
+    auto block = [&](const int I, auto SET, auto SLOT) __attribute__((always_inline)) {
+        constexpr int S = decltype(SET)::value;
+        constexpr int R = decltype(SLOT)::value;
         const int buf = (I - I0) & 1;
         const bool more = I + 1 < I1;
         const int q = s - I;
@@ -291,14 +327,13 @@ __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int spl
             const half8 *src = T16 + (int64_t)(q - 1) * (kT16Q / 8);
             tnext[0] = src[tid];
             tnext[1] = src[tid + 256];
-            load_b(I + 1, nh, nl, nef);
         }
+        if (I + 2 < I1) load_b(I + 2, std::integral_constant<int, (R + 2) % 3>{});
         const int ew0 = A.T16exp[q * 2 + 0], ew1 = A.T16exp[q * 2 + 1];
-        flt4 c32[2][4];
 #pragma unroll
         for (int tb = 0; tb < 2; ++tb)
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) c32[tb][rt] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int rt = 0; rt < 4; ++rt) c32[S][tb][rt] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
         const half8 *tw = sT[buf];
 #pragma unroll
         for (int j = -2; j <= 3; ++j) {  // j = rt - 2 ks
@@ -307,8 +342,8 @@ __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int spl
             half8 ah[2], al[2];
 #pragma unroll
             for (int tb = 0; tb < 2; ++tb) {
-                ah[tb] = tw[((tb * 2 + 0) * 8 + shift) * (kT16Row / 8) + m8];
-                al[tb] = tw[((tb * 2 + 1) * 8 + shift) * (kT16Row / 8) + m8];
+                ah[tb] = tw[((tb * 2 + 0) * 8 + shift) * kT16Pitch + m8];
+                al[tb] = tw[((tb * 2 + 1) * 8 + shift) * kT16Pitch + m8];
             }
 #pragma unroll
             for (int prod = 0; prod < 3; ++prod)
@@ -319,31 +354,43 @@ __global__ __launch_bounds__(256) void k_wide_far_f16(WideArgs A, int s, int spl
 #pragma unroll
                     for (int tb = 0; tb < 2; ++tb) {
                         const half8 a = prod == 2 ? al[tb] : ah[tb];
-                        const half8 b = prod == 1 ? bl[ks] : bh[ks];
-                        c32[tb][rt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c32[tb][rt], 0, 0, 0);
+                        const half8 b = prod == 1 ? bl[R][ks] : bh[R][ks];
+                        c32[S][tb][rt] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c32[S][tb][rt], 0, 0, 0);
                     }
                 }
         }
-#pragma unroll
-        for (int tb = 0; tb < 2; ++tb) {
-            const double sc = ldexp(1.0, (tb ? ew1 : ew0) + ef);
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[tb][rt][v] = fma((double)c32[tb][rt][v], sc, acc[tb][rt][v]);
-        }
+        // the block before (other set), while these products run
+        if (I > I0) convert(std::integral_constant<int, 1 - S>{});
+        psc[0] = ldexp(1.0, ew0 + ef[R]);
+        psc[1] = ldexp(1.0, ew1 + ef[R]);
         if (more) {
-            sT[buf ^ 1][tid] = tnext[0];
-            sT[buf ^ 1][tid + 256] = tnext[1];
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bh[ks] = nh[ks];
-                bl[ks] = nl[ks];
-            }
-            ef = nef;
+            sT[buf ^ 1][st0] = tnext[0];
+            sT[buf ^ 1][st1] = tnext[1];
         }
         __syncthreads();
+    };
+    // six blocks per trip (both set and slot patterns repeat), then the rest
+    int I = I0;
+    for (; I + 6 <= I1; I += 6) {
+        block(I, C0{}, C0{});
+        block(I + 1, C1{}, C1{});
+        block(I + 2, C0{}, C2{});
+        block(I + 3, C1{}, C0{});
+        block(I + 4, C0{}, C1{});
+        block(I + 5, C1{}, C2{});
+    }
+    if (I < I1) block(I, C0{}, C0{});
+    if (I + 1 < I1) block(I + 1, C1{}, C1{});
+    if (I + 2 < I1) block(I + 2, C0{}, C2{});
+    if (I + 3 < I1) block(I + 3, C1{}, C0{});
+    if (I + 4 < I1) block(I + 4, C0{}, C1{});
+    // the last block's sums: set (I1 - 1 - I0) mod 2
+    if (I1 > I0) {
+        if (((I1 - 1 - I0) & 1) == 0)
+            convert(C0{});
+        else
+            convert(C1{});
     }
     store_tiles<true>(A, blockIdx.y, col, acc);
 }
