@@ -358,10 +358,10 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         off = align_up(off + sizeof(double) * 3 * (size_t)sumN * (pc ? d : 1));
         L.f = off;
         off = align_up(off + sizeof(double) * (size_t)d * (size_t)sumRows);
-        L.part = off;  // grid-kernel partials [2][G][2d] (by step parity)
-        off = align_up(off + sizeof(double) * 4 * (size_t)d * kGridMax);
-        L.sync = off;  // grid-kernel counters and flags, one 256-byte line each
-        L.n_sync_words = 64 * 18;
+        L.part = off;  // grid-kernel partial slots, by workgroup and step parity
+        off = align_up(off + sizeof(double) * fabm::direct_grid_part_doubles(kGridMax));
+        L.sync = off;  // grid-kernel abort word and step tags, one line each
+        L.n_sync_words = fabm::direct_grid_sync_words(kGridMax);
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
     }
     if (has_slope(pl)) {

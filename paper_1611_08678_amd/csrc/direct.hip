@@ -224,25 +224,47 @@ __global__ __launch_bounds__(kBlock) void k_direct_wg(const InstMeta *__restrict
             for (int i = 0; i < D; ++i) Yh[r * D + i] = __builtin_nan("");
 }
 
-// Partial sums of partial_sums, with the newest row k = t - 1 taken from
-// `fl` (formed by this workgroup itself) instead of from memory.
+// Values shared between workgroups on different XCDs (each XCD has its own
+// L2): written with agent-scope atomic stores (through to the device's
+// coherence point) and read with agent-scope atomic loads (from it), so no
+// L2 write-back or invalidation is needed for them.
+__device__ __forceinline__ void coh_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double coh_load(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this thread's earlier stores have been acknowledged (vmcnt(0));
+// the compiler moves no memory operation across it.
+__device__ __forceinline__ void stores_done()
+{
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
+    __asm__ __volatile__("" ::: "memory");
+}
+
+// Partial sums for target T over k in [lo, hi) (strided by the block), every
+// history row read at the coherence point except row kreg, taken from `fl`
+// (formed by this workgroup itself).
 template <int D>
-__device__ __forceinline__ void partial_sums_last(const double *__restrict__ Fh,
-                                                  const double *__restrict__ wb,
-                                                  const double *__restrict__ wa,
-                                                  const double *__restrict__ wc, int64_t t,
-                                                  int64_t lo, int64_t hi, int tid,
-                                                  const double (&fl)[D], double (&sp)[D],
-                                                  double (&sc)[D])
+__device__ __forceinline__ void partial_sums_coh(const double *__restrict__ Fh,
+                                                 const double *__restrict__ wb,
+                                                 const double *__restrict__ wa,
+                                                 const double *__restrict__ wc, int64_t T,
+                                                 int64_t lo, int64_t hi, int tid, int64_t kreg,
+                                                 const double (&fl)[D], double (&sp)[D],
+                                                 double (&sc)[D])
 {
 #pragma unroll
     for (int i = 0; i < D; ++i) sp[i] = sc[i] = 0.0;
     for (int64_t k = lo + tid; k < hi; k += kBlock) {
-        const double bw = wb[t - 1 - k];
-        const double aw = (k == 0) ? wc[t - 1] : wa[t - 1 - k];
+        const double bw = wb[T - 1 - k];
+        const double aw = (k == 0) ? wc[T - 1] : wa[T - 1 - k];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double fk = k == t - 1 ? fl[i] : Fh[k * D + i];
+            const double fk = k == kreg ? fl[i] : coh_load(&Fh[k * D + i]);
             sp[i] = fma(bw, fk, sp[i]);
             sc[i] = fma(aw, fk, sc[i]);
         }
@@ -250,46 +272,65 @@ __device__ __forceinline__ void partial_sums_last(const double *__restrict__ Fh,
 }
 
 template <int D>
-__device__ __forceinline__ void partial_sums_orders_last(const double *__restrict__ Fh,
-                                                         const CompOrders<D> &O, int64_t t,
-                                                         int64_t lo, int64_t hi, int tid,
-                                                         const double (&fl)[D], double (&sp)[D],
-                                                         double (&sc)[D])
+__device__ __forceinline__ void partial_sums_orders_coh(const double *__restrict__ Fh,
+                                                        const CompOrders<D> &O, int64_t T,
+                                                        int64_t lo, int64_t hi, int tid,
+                                                        int64_t kreg, const double (&fl)[D],
+                                                        double (&sp)[D], double (&sc)[D])
 {
 #pragma unroll
     for (int i = 0; i < D; ++i) sp[i] = sc[i] = 0.0;
     for (int64_t k = lo + tid; k < hi; k += kBlock) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double bw = O.wb[i][t - 1 - k];
-            const double aw = (k == 0) ? O.wc[i][t - 1] : O.wa[i][t - 1 - k];
-            const double fk = k == t - 1 ? fl[i] : Fh[k * D + i];
+            const double bw = O.wb[i][T - 1 - k];
+            const double aw = (k == 0) ? O.wc[i][T - 1] : O.wa[i][T - 1 - k];
+            const double fk = k == kreg ? fl[i] : coh_load(&Fh[k * D + i]);
             sp[i] = fma(bw, fk, sp[i]);
             sc[i] = fma(aw, fk, sc[i]);
         }
+    }
+}
+
+// Spin until the step tag *p has reached v (modulo 2^32), or *abort is
+// raised, or the wall clock passes `deadline` (then *abort is raised). Every
+// wait is bounded, so a mistake ends the launch with an error status instead
+// of a hung GPU.
+__device__ __forceinline__ bool wait_tag(uint32_t *p, uint32_t v, uint32_t *abort,
+                                         uint64_t deadline)
+{
+    for (;;) {
+        if ((int32_t)(flag_read(p) - v) >= 0) return true;
+        if (flag_read(abort) != 0u) return false;
+        if (wall_clock64() > deadline) {
+            flag_max(abort, 1u);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
     }
 }
 
 // One hand-off per step. At step t every workgroup g reduces its slice
 // [t g / G, t (g + 1) / G) of the history (rows up to t - 2 from memory, the
-// newest row t - 1 from its own registers), stores its partial in the
-// buffer of the step's parity and arrives; it then waits until all G
-// partials of step t have arrived, adds them in workgroup order and forms
-// row t itself: every workgroup forms every row, bitwise the same, so no row
-// has to be published before the next step. Workgroup 0 writes the rows to F
-// and Y; a row is read from F two steps later at the earliest, after
-// workgroup 0's release of the step in between.
-// Arrival is two-level so that no counter or flag is shared by more than
-// kGroupSpan workgroups (one atomic line serialises its users): workgroup g
-// adds to the counter of its group g mod 8 (under round-robin dispatch, one
-// XCD); the group's last arrival of the step adds to the top counter, whose
-// last arrival of the step raises the step flag of every group; each
-// workgroup waits on its group's flag. Counters and flags are monotone
-// (compared modulo 2^32), in separate 256-byte lines of `sync`:
-// word 64 x: group counter, 64 (8 + x): group flag, 64 * 16: top counter,
-// 64 * 17: abort (a bounded wait timed out). part: [2][G][2D].
-constexpr int kGroups = 8;     // arrival groups (one per XCD under round-robin dispatch)
-constexpr int kSyncLine = 64;  // words between counters: one 256-byte line each
+// newest row t - 1 from its own registers), stores its partial in its slot of
+// the step's parity and then the step number in its tag; thread j of every
+// workgroup waits for workgroup j's tag, reads its partial, and the partials
+// are added in workgroup order, so every workgroup forms row t itself,
+// bitwise the same, and no row has to be published before the next step.
+// Workgroup 0 writes the rows to F (through to the coherence point) and Y.
+// Ordering without cache maintenance: partials, tags and history rows are
+// stored and loaded at the coherence point; a workgroup's tag is stored only
+// after its earlier stores are acknowledged (workgroup 0's row t - 1 among
+// them), and a row is read two steps after it was formed, after the tag of
+// the step in between. A slot of parity t & 1 is rewritten at step t + 2 only
+// after its writer has read every partial of step t + 1, i.e. after every
+// workgroup has finished reading step t's. Tags start at zero (the sync words
+// are cleared before the launch); kTagPitch words apart (one 128-byte line
+// each); abort word at kSyncLine * 17.
+constexpr int kSyncLine = 64;   // words per line of the sync area
+constexpr int kTagBase = kSyncLine * 18;
+constexpr int kTagPitch = 32;   // words between step tags
+constexpr int kSlot = 16;       // doubles per partial slot (2d <= 8 used)
 
 template <int SYS, int D, bool PC>
 __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restrict__ meta,
@@ -305,17 +346,15 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
                                                         uint32_t *__restrict__ sync,
                                                         uint64_t timeout_ticks)
 {
-    __shared__ double red[kWaves][2 * D];
+    __shared__ double red[kWaves][2 * D], red2[kWaves][2 * D];
     __shared__ int s_stop;
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
-    // arrival groups: g mod ngroups, of gsize workgroups each
-    const int ngroups = G < kGroups ? G : kGroups;
-    const int gx = g % ngroups;
-    const uint32_t gsize = (uint32_t)((G - 1 - gx) / ngroups + 1);
     const InstMeta m = meta[0];
     const int64_t N = m.N;
     const double *wb = W + m.w_off, *wa = wb + m.wlen, *wc = wa + m.wlen;
     const double *p = params;
+    uint32_t *tags = sync + kTagBase;
+    uint32_t *abort = sync + kSyncLine * 17;
     double y0[D], y1[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = y0g[i];
@@ -332,67 +371,84 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
     if (g == 0 && tid == 0) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            F[i] = fl[i];
+            coh_store(&F[i], fl[i]);
             Y[i] = y0[i];
         }
     }
     int64_t dead = 0;      // first non-finite row (all workgroups find the same)
     bool aborted = false;  // a wait gave up
+    const uint64_t deadline_step = timeout_ticks;
+    // this thread's sums for the current target over its slice without the
+    // newest row, formed during the step before (none for t = 1)
+    double pp[D], pq[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) pp[i] = pq[i] = 0.0;
     int64_t t = 1;
     for (; t <= N; ++t) {
+        if (tid == 0) s_stop = 0;
         const int64_t lo = (t * g) / G, hi = (t * (g + 1)) / G;
+        // the newest row t - 1 completes the sums (it is the last k of the
+        // thread that holds it, as in a plain pass over the slice)
         double sp[D], sc[D];
-        if constexpr (PC) partial_sums_orders_last<D>(F, O, t, lo, hi, tid, fl, sp, sc);
-        else partial_sums_last<D>(F, wb, wa, wc, t, lo, hi, tid, fl, sp, sc);
-        block_sum2<D>(sp, sc, red, tid);
-        double *pb = part + (int64_t)(t & 1) * G * 2 * D;
-        if (tid == 0) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            sp[i] = pp[i];
+            sc[i] = pq[i];
+        }
+        if (t - 1 >= lo && t - 1 < hi && (int)((t - 1 - lo) % kBlock) == tid) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                pb[(int64_t)g * 2 * D + i] = sp[i];
-                pb[(int64_t)g * 2 * D + D + i] = sc[i];
+                const double bw = PC ? O.wb[i][0] : wb[0];
+                const double aw = t == 1 ? (PC ? O.wc[i][0] : wc[0]) : (PC ? O.wa[i][0] : wa[0]);
+                sp[i] = fma(bw, fl[i], sp[i]);
+                sc[i] = fma(aw, fl[i], sc[i]);
             }
-            // release: this partial, and workgroup 0's rows up to t - 1. The
-            // counters are relaxed read-modify-writes; only the last arrival
-            // of a group (and of the top counter) acquires what the others
-            // released before passing it on, so each workgroup pays one
-            // release and one acquire (in wait_geq) per step.
-            fence_release();
-            const uint32_t ut = (uint32_t)t;
-            const uint32_t got = __hip_atomic_fetch_add(&sync[kSyncLine * gx], 1u,
-                                                        __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (got == gsize * ut) {  // the group's last arrival of step t
-                fence_acquire();
-                fence_release();
-                const uint32_t top = __hip_atomic_fetch_add(&sync[kSyncLine * 16], 1u,
-                                                            __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT) + 1u;
-                if (top == (uint32_t)ngroups * ut) {  // the last group: step t complete
-                    fence_acquire();
-                    fence_release();
-                    for (int x = 0; x < ngroups; ++x)
-                        __hip_atomic_store(&sync[kSyncLine * (8 + x)], ut, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            // wait_geq acquires for the whole workgroup (the barrier below
-            // orders the other wavefronts after it)
-            s_stop = !wait_geq(&sync[kSyncLine * (8 + gx)], ut, &sync[kSyncLine * 17],
-                               timeout_ticks);
         }
-        __syncthreads();
+        block_sum2<D>(sp, sc, red, tid);
+        const int par = (int)(t & 1);
+        if (tid == 0) {
+            double *slot = part + ((int64_t)par * G + g) * kSlot;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                coh_store(&slot[i], sp[i]);
+                coh_store(&slot[D + i], sc[i]);
+            }
+            stores_done();
+            __hip_atomic_store(&tags[(par * G + g) * kTagPitch], (uint32_t)t, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // While the other partials of step t arrive: the sums for target t + 1
+        // over its slice up to row t - 1 (row t - 1 from registers, earlier
+        // rows from memory: row t - 2 was stored before workgroup 0's tag of
+        // step t - 1)
+        if (t < N) {
+            const int64_t lo1 = ((t + 1) * g) / G, hi1 = ((t + 1) * (g + 1)) / G;
+            const int64_t hm = hi1 < t ? hi1 : t;
+            if constexpr (PC) partial_sums_orders_coh<D>(F, O, t + 1, lo1, hm, tid, t - 1, fl, pp, pq);
+            else partial_sums_coh<D>(F, wb, wa, wc, t + 1, lo1, hm, tid, t - 1, fl, pp, pq);
+        }
+        double qp[D], qc[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) qp[i] = qc[i] = 0.0;
+        if (tid < G) {
+            const bool ok = wait_tag(&tags[(par * G + tid) * kTagPitch], (uint32_t)t, abort,
+                                     wall_clock64() + deadline_step);
+            if (ok) {
+                const double *q = part + ((int64_t)par * G + tid) * kSlot;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    qp[i] = coh_load(&q[i]);
+                    qc[i] = coh_load(&q[D + i]);
+                }
+            } else {
+                s_stop = 1;
+            }
+        }
+        block_sum2<D>(qp, qc, red2, tid);
         if (s_stop) {
             aborted = true;
             break;
         }
-        double qp[D], qc[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            qp[i] = tid < G ? pb[(int64_t)tid * 2 * D + i] : 0.0;
-            qc[i] = tid < G ? pb[(int64_t)tid * 2 * D + D + i] : 0.0;
-        }
-        block_sum2<D>(qp, qc, red, tid);
         double y[D], f[D], base[D];
         const double tt = (double)t * m.h;
         taylor_base<D>(tt, y0, y1, base);
@@ -405,13 +461,13 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
         if (g == 0 && tid == 0) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                F[t * D + i] = f[i];
+                coh_store(&F[t * D + i], f[i]);
                 Y[t * D + i] = y[i];
             }
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) fl[i] = f[i];
-        __syncthreads();  // red[] is reused by the next step's partial sums
+        __syncthreads();  // red and red2 are reused by the next step
     }
     if (g == 0) {
         // rows from `bad` on are not final: the first non-finite step, or the
@@ -584,6 +640,9 @@ hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, const InstMeta
 #undef FABM_WG_CASE
     return hipErrorInvalidValue;
 }
+
+size_t direct_grid_part_doubles(int G) { return (size_t)2 * kSlot * (size_t)G; }
+size_t direct_grid_sync_words(int G) { return (size_t)kTagBase + (size_t)2 * kTagPitch * (size_t)G; }
 
 hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const InstMeta *cmeta,
                               const double *params, const double *y0, const double *y1,
