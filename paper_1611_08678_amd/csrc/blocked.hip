@@ -97,7 +97,8 @@ __device__ __forceinline__ int band_wait_rows(int *s_cnt, int *s_dead, int need)
 // per component (component k's tables at k * 3 wlen from the instance's,
 // its scalars in A.cmeta[k]).
 template <int SYS, int D, bool YPOUT, bool PC = false>
-__device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
+__device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv, int J,
+                                           char *smem)
 {
     constexpr int NP = n_params_of_sys(SYS, D);
     constexpr int K = PC ? D : 1;     // weight tables held
@@ -105,10 +106,10 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     double *sa = sb + K * 2 * kBlk;   // [K] a lags 0..511
     double *sbh = sa + K * 2 * kBlk;  // [K] h^a b lags 0..255 (this block's sums)
     double *sah = sbh + K * kBlk;     // [K] h^a a lags 0..255
-    // row arrays: 256 rows of this block and a spare row per lane
-    double *sF = sah + K * kBlk;        // [320][D] f of this block's rows
-    double *sY = sF + kBandRows * D;    // [320][D] y of this block's rows
-    double *sYP = sY + kBandRows * D;   // [320][D] predictor values (YPOUT)
+    // row arrays: 256 rows of this block and a spare row per lane; a row of
+    // sFY is f then y (one contiguous store of 2D values per formed row)
+    double *sFY = sah + K * kBlk;           // [320][2D] f and y of this block's rows
+    double *sYP = sFY + kBandRows * 2 * D;  // [320][D] predictor values (YPOUT)
     // the last wavefront's next-block sums, handed to wavefront 0 ([2][D][64])
     double *sH = sYP + (YPOUT ? kBandRows * D : 0);
     double *sTh = sH + 2 * D * kWave;  // theta, for systems with many parameters
@@ -116,7 +117,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     int *s_dead = s_cnt + 1;         // first non-finite row (block-relative), -1, or -2
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const InstMeta m = A.meta[0];
+    const InstMeta m = mv;  // the instance's entry (a kernel argument on the single path)
     const int64_t N = m.N;
     const int64_t pitch = (int64_t)A.NB * kBlk;
     const double *wb = A.W, *wa = wb + m.wlen, *wc = wa + m.wlen;
@@ -174,8 +175,8 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         if (J == 0) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                sF[i] = f0[i];
-                sY[i] = y0[i];
+                sFY[i] = f0[i];
+                sFY[D + i] = y0[i];
                 if constexpr (YPOUT) sYP[i] = y0[i];
             }
         }
@@ -281,7 +282,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
                 }
             }
 #pragma unroll
-            for (int i = 0; i < D; ++i) fr[q][i] = sF[(r + q) * D + i];
+            for (int i = 0; i < D; ++i) fr[q][i] = sFY[(r + q) * 2 * D + i];
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -429,8 +430,8 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         const int o = row >= t ? row_off : spare_off;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            sF[o + i] = f[i];
-            sY[o + i] = y[i];
+            sFY[2 * o + i] = f[i];
+            sFY[2 * o + D + i] = y[i];
             if constexpr (YPOUT) sYP[o + i] = pc[i];
         }
     };
@@ -448,7 +449,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
         chk = 0.0;
         if (lane < nv) {
             const int r = checked + lane / (2 * D), kk = lane % (2 * D);
-            chk = kk < D ? sF[r * D + kk] : sY[r * D + kk - D];
+            chk = sFY[r * 2 * D + kk];
         }
         pend_lo = checked;
         pend_hi = tl;
@@ -517,7 +518,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     const int valid = dead == -1 ? nrows : (dead < 0 ? 0 : dead);
     if (A.Y) {
         for (int e = tid; e < nrows * D; e += nthr)
-            A.Y[ro + e] = e / D < valid ? sY[e] : __builtin_nan("");
+            A.Y[ro + e] = e / D < valid ? sFY[(e / D) * 2 * D + D + e % D] : __builtin_nan("");
     }
     if constexpr (YPOUT) {
         for (int e = tid; e < nrows * D; e += nthr)
@@ -528,7 +529,7 @@ __device__ __forceinline__ void band_block(const InstView &A, int J, char *smem)
     if (A.recompute) return;
     for (int e = tid; e < valid; e += nthr) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) A.Fc[i * pitch + t0 + e] = sF[e * D + i];
+        for (int i = 0; i < D; ++i) A.Fc[i * pitch + t0 + e] = sFY[e * 2 * D + i];
     }
     if (dead == -1) {
         double *cout = A.carry + (int64_t)((J + 1) & 1) * 2 * D * kBlk;
@@ -847,7 +848,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
     const InstView V = single_view(A);
     if (b == 0) {
         // teacher forcing writes the predictor sums as well
-        if (wave < kBandWaves) band_block<SYS, D, SYS == SYS_TEACHER, PC>(V, s + 1, smem);
+        if (wave < kBandWaves)
+            band_block<SYS, D, SYS == SYS_TEACHER, PC>(V, A.m0, s + 1, smem);
         return;
     }
     if (*A.dead != 0u) return;  // the trajectory has ended; later rows are NaN
@@ -909,7 +911,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_step_batch(BatchArgs A, int s
     int q = blockIdx.x;
     if (q < nband) {
         const InstView V = batch_view<D>(A, A.order[q]);
-        band_block<SYS, D, YPOUT, PC>(V, s + 1, smem);
+        band_block<SYS, D, YPOUT, PC>(V, V.meta[0], s + 1, smem);
         return;
     }
     q -= nband;
@@ -1048,7 +1050,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_recompute_batch(BatchArgs A, 
     V.yrow0 = K * kBlk;
     V.carry = cb;
     V.recompute = 1;
-    band_block<SYS, D, true, PC>(V, (int)K, smem);
+    band_block<SYS, D, true, PC>(V, V.meta[0], (int)K, smem);
 }
 
 __global__ void k_batch_status(BatchArgs A)

@@ -665,6 +665,7 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     if (L.path == Path::Blocked) {
         fabm::StepArgs A{};
         A.meta = dmeta;
+        A.m0 = hm[0];
         A.cmeta = dcmeta;
         A.params = params;
         A.y0 = y0;
@@ -1469,6 +1470,7 @@ fabm_status fabm_history_sums(double alpha, int64_t N, int32_t dim, const double
         return st;
     fabm::StepArgs A{};
     A.meta = dmeta;
+    A.m0 = m;
     A.params = ftf;
     A.y0 = y0;
     A.Y = yc;

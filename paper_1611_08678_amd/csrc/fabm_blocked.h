@@ -57,6 +57,7 @@ struct InstView {
 
 struct StepArgs {
     const InstMeta *meta;
+    InstMeta m0;        // meta[0] by value (the band reads it without a memory round trip)
     const InstMeta *cmeta;  // non-commensurate orders: [D] per-component entries, or null
     const double *params;
     const double *y0;
