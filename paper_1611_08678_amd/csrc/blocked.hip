@@ -313,6 +313,35 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
     // the last wavefront's rows to them as they are published, in row order,
     // and stores them, so the last wavefront ends with its walk.
     const bool handoff = nrows == kBlk;
+    // rows in groups of kPublishEvery (aligned to the block), unrolled, so the
+    // publish check runs once per group. The weights of row t (lag row - t
+    // for the term f_{t-1}) come from LDS: with one table set, slot k of a
+    // ring of kPublishEvery holds rows t = k mod kPublishEvery and is reloaded
+    // for row t + kPublishEvery right after row t uses it, so the walk never
+    // waits for them; with one set per component (more registers) each row's
+    // are loaded during the row before (also for systems whose parameters
+    // are read from LDS, which hold more registers).
+    constexpr int kRing = K == 1 && !kThLds ? kPublishEvery : 1;
+    double bwg[kRing][K], awg[kRing][K];
+    auto load_row = [&](const int t, const int sl) __attribute__((always_inline)) {
+        const int lag = row - t > 0 ? row - t : 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            bwg[sl][q] = sbh[q * kBlk + lag];
+            awg[sl][q] = sah[q * kBlk + lag];
+        }
+    };
+    auto load_group = [&](const int g) __attribute__((always_inline)) {
+        if constexpr (kRing > 1) {
+#pragma unroll
+            for (int k = 0; k < kRing; ++k) load_row(g + k, k);
+        }
+    };
+    // the first group's weights load while the rows before it are added
+    // (the walk starts at row lo, or at row 1 in block 0, both in group lo);
+    // systems with many parameters in registers load them after (registers)
+    constexpr bool kHoist = kRing > 1 && NP <= 4;
+    if constexpr (kHoist) load_group(lo);
     // rows formed by earlier wavefronts: both blocks' sums
     while (go && done < lo) {
         const int c = __builtin_amdgcn_readfirstlane(band_wait_rows(s_cnt, s_dead, done + 1));
@@ -381,30 +410,6 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
         pend_lo = pend_hi;
         return true;
     };
-    // rows in groups of kPublishEvery (aligned to the block), unrolled, so the
-    // publish check runs once per group. The weights of row t (lag row - t
-    // for the term f_{t-1}) come from LDS: with one table set, slot k of a
-    // ring of kPublishEvery holds rows t = k mod kPublishEvery and is reloaded
-    // for row t + kPublishEvery right after row t uses it, so the walk never
-    // waits for them; with one set per component (more registers) each row's
-    // are loaded during the row before (also for systems whose parameters
-    // are read from LDS, which hold more registers).
-    constexpr int kRing = K == 1 && !kThLds ? kPublishEvery : 1;
-    double bwg[kRing][K], awg[kRing][K];
-    auto load_row = [&](const int t, const int sl) __attribute__((always_inline)) {
-        const int lag = row - t > 0 ? row - t : 0;
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            bwg[sl][q] = sbh[q * kBlk + lag];
-            awg[sl][q] = sah[q * kBlk + lag];
-        }
-    };
-    auto load_group = [&](const int g) __attribute__((always_inline)) {
-        if constexpr (kRing > 1) {
-#pragma unroll
-            for (int k = 0; k < kRing; ++k) load_row(g + k, k);
-        }
-    };
     // one row of the walk (k: its place in the group); full groups of
     // kPublishEvery rows run without the per-row range check
     auto step_row = [&](const int t, const int k) __attribute__((always_inline)) {
@@ -435,10 +440,10 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
             if constexpr (YPOUT) sYP[o + i] = pc[i];
         }
     };
-    if constexpr (kRing > 1)
-        load_group(first & ~(kPublishEvery - 1));
-    else
+    if constexpr (kRing == 1)
         load_row(first, 0);
+    else if constexpr (!kHoist)
+        load_group(lo);
     // end of a group of rows [., tl): the group before is checked (its
     // values were loaded a group ago) and published, and this group's f and
     // y values (one per lane) are loaded for the check after the next group
