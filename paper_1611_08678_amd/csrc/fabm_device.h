@@ -223,53 +223,18 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-
 // Flags shared between workgroups on different XCDs (each XCD has its own
-// L2). Flag writes are read-modify-write atomics, performed at the device's
-// coherence point. A flag read is an agent-scope atomic load
-// (__hip_atomic_load, agent scope; emitted for gfx950 as global_load_dword
-// with the sc1 bit, which reads past the XCD's own L2); data published under
-// a flag is made visible by the
-// release fence before the flag write and the acquire fence after the flag
-// read.
+// L2): read with an agent-scope atomic load (emitted for gfx950 as
+// global_load_dword with the sc1 bit, which reads at the device's coherence
+// point, past the XCD's own L2) and raised with an agent-scope atomic
+// read-modify-write (performed at that point).
 __device__ __forceinline__ uint32_t flag_read(uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void flag_publish(uint32_t *p, uint32_t v)
-{
-    fence_release();
-    __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void flag_max(uint32_t *p, uint32_t v)
 {
     __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Spin until *p >= v modulo 2^32 (then acquire), or until *abort becomes nonzero or
-// `timeout_ticks` of the constant-rate wall clock have passed (then *abort is
-// raised and false is returned). Every wait of a persistent kernel is bounded
-// this way, so a scheduling mistake ends the launch with an error instead of a
-// hung GPU.
-__device__ __forceinline__ bool wait_geq(uint32_t *p, uint32_t v, uint32_t *abort,
-                                         uint64_t timeout_ticks)
-{
-    const uint64_t deadline = wall_clock64() + timeout_ticks;
-    for (;;) {
-        // wrap-safe: the counters are monotone and never more than 2^31 apart
-        if ((int32_t)(flag_read(p) - v) >= 0) {
-            fence_acquire();
-            return true;
-        }
-        if (flag_read(abort) != 0u) return false;
-        if (wall_clock64() > deadline) {
-            flag_max(abort, 1u);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
 }
 
 }  // namespace fabm
