@@ -51,15 +51,17 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 // Band: block J walked row by row by wavefronts 0..3 of workgroup 0.
 //
 // Wavefront w holds, one per lane, the sums of rows 64 w + l of block J and
-// of block J+1, and forms rows 64 w .. 64 w + 63 itself. At row t its sums in
-// lane t - 64 w are read out (readlane) and every lane evaluates the predictor
-// and corrector with those same values, so f_t is present in all lanes without
-// a broadcast; each lane then adds w[T-1-t] f_t to its own target T of block
-// J. Nothing else is on that chain: rows are published in LDS (f_t, y_t, and a
-// row counter every 8 rows), the other wavefronts add them to their sums as
-// they appear, and the contributions of the wavefront's own rows to block J+1
-// are added after its turn. Every target's sums are still accumulated in row
-// order. The sums of block J+1 go to the next launch through `carry`.
+// of block J+1, and forms rows 64 w .. 64 w + 63 itself. At row t every lane
+// adds f_{t-1} to its own sums, so lane t - 64 w holds row t's whole
+// predictor and corrector sums; every lane evaluates the predictor and
+// corrector on its own sums and f_t is read out of lane t - 64 w (readlane)
+// for the next row. Nothing else is on that chain: rows are published in LDS
+// (f_t, y_t, and a row counter every 8 rows, each group checked for
+// non-finite values one group late), the other wavefronts add them to their
+// sums as they appear, the contributions of a wavefront's own rows to block
+// J+1 are added after its turn, and the last wavefront's next-block sums are
+// finished by wavefront 0. Every target's sums are accumulated in row order.
+// The sums of block J+1 go to the next launch through `carry`.
 // ---------------------------------------------------------------------------
 constexpr int kBandWaves = 4;
 constexpr int kPublishEvery = 8;           // rows between counter updates
