@@ -268,6 +268,35 @@ def test_blocked_batch_blowup_and_determinism(F, orc):
     assert np.array_equal(_to_np(runs[0][0]), _to_np(runs[1][0]), equal_nan=True)
 
 
+def test_blocked_blowup_rows_at_every_group_position(F, orc):
+    """The band checks rows for non-finite values in groups of 8, one group
+    late, and hands rows between wavefronts every 64 and between launches
+    every 256: blow-ups placed at every position of a group, across a
+    wavefront boundary (row 640) and a block boundary (row 768) are flagged
+    at the oracle's step, with NaN rows after it and the rows before it at
+    1e-11. y' = 20 y grows until binary64 overflows; y0 = 10^-k moves the
+    first non-finite step by about two rows per k (steps 603..798)."""
+    ks = list(range(0, 24)) + list(range(70, 100))
+    B = len(ks)
+    w = dict(system=0, d=1, theta=np.tile([20.0, 0.0, 0.0], (B, 1)), alpha=np.full(B, 0.9),
+             h=np.full(B, 0.05), N=np.full(B, 1500),
+             y0=np.array([[10.0 ** (-k)] for k in ks]))
+    _batch_parity(F, orc, w, path="blocked")
+    # the single-trajectory pipeline around the wavefront and block boundaries
+    for k in (18, 19, 20, 83, 84, 85):
+        th = np.array([20.0, 0.0, 0.0])
+        y, st = F.solve("linear", th, 0.9, 0.05, 1500, [10.0 ** (-k)], path="blocked")
+        ref, _, _, rst = orc.solve(0, th, 0.9, 0.05, 1500, [10.0 ** (-k)])
+        g = int(st.item())
+        assert g > 0 and abs(g - rst) <= 1, (k, g, rst)
+        if g != rst:  # both sides at the top of the binary64 range (see _batch_parity)
+            assert np.abs(ref[min(g, rst) - 1]).max() > np.finfo(np.float64).max / 1e3
+        yy = _to_np(y)
+        assert np.all(np.isnan(yy[g:])) and np.all(np.isfinite(yy[:g]))
+        kk = min(g, rst)
+        assert relerr(yy[:kk], ref[:kk]) <= 1e-11
+
+
 # FP32 far windows: weights and history rounded to binary32 and 64 products
 # per window summed in binary32, added to binary64 sums. A priori the far sum
 # carries about (2 + 64) u32 sum|w||f| (u32 = 2^-24) and y a small multiple of
