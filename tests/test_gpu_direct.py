@@ -192,6 +192,24 @@ def test_chen_grid_direct_prefix_and_teacher_forced(F, orc):
     assert np.all(np.abs(_to_np(Cs) - rC) <= 1e-13 * aC + 1e-300)
 
 
+def test_grid_direct_blowup(F, orc):
+    """The whole-GPU kernel (N >= 8192 single trajectory): y' = 2 y overflows
+    binary64 at the oracle's step; every workgroup forms that row, finds it
+    non-finite and stops at the same step; rows after it are NaN."""
+    th = np.array([2.0, 0.0, 0.0])
+    N = 9000
+    y, st = F.solve("linear", th, 0.9, 0.05, N, [1.0], path="direct")
+    ref, _, _, rst = orc.solve(0, th, 0.9, 0.05, N, [1.0])
+    g = int(st.item())
+    assert rst > 0 and abs(g - rst) <= 1, (g, rst)
+    if g != rst:  # both sides at the top of the binary64 range (see _batch_parity)
+        assert np.abs(ref[min(g, rst) - 1]).max() > np.finfo(np.float64).max / 1e3
+    yy = _to_np(y)
+    assert np.all(np.isnan(yy[g:])) and np.all(np.isfinite(yy[:g]))
+    k = min(g, rst)
+    assert relerr(yy[:k], ref[:k]) <= 1e-11
+
+
 def test_grid_direct_deterministic(F):
     from paper_1611_08678_amd import workloads as W
     w = W.chen(N=9000)
