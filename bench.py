@@ -738,6 +738,14 @@ def bench_chen(F, W, args):
         results[path] = r
         print(f"# {path}: solve times {['%.4f' % s for s in r['solve_s']]} s", file=sys.stderr,
               flush=True)
+    if "blocked" in results and not args.no_configs and args.fft_level == 0 and N >= 1 << 18:
+        # beside the headline: the same solve with the far history of block
+        # squares of level 9 and above by FFT convolution (sub-quadratic variant)
+        rf = time_path(F, w, "blocked", max(3, min(args.steps, 5)), 1, kernel_times=False,
+                       fft_level=9)
+        results["blocked_fft_level9"] = rf
+        print(f"# blocked, FFT squares of level 9: solve times "
+              f"{['%.4f' % s for s in rf['solve_s']]} s", file=sys.stderr, flush=True)
     head = "blocked" if "blocked" in results else "direct"
     r = results[head]
     t = float(np.mean(r["solve_s"]))
