@@ -358,9 +358,9 @@ Layout layout_for(const fabm_plan_s *pl, int64_t batch, const int64_t *N, bool a
         off = align_up(off + sizeof(double) * 3 * (size_t)sumN * (pc ? d : 1));
         L.f = off;
         off = align_up(off + sizeof(double) * (size_t)d * (size_t)sumRows);
-        L.part = off;  // grid-kernel partial slots, by workgroup and step parity
+        L.part = off;  // grid-kernel partial slots, by workgroup in three step buffers
         off = align_up(off + sizeof(double) * fabm::direct_grid_part_doubles(kGridMax));
-        L.sync = off;  // grid-kernel abort word and step tags, one line each
+        L.sync = off;  // grid-kernel abort word
         L.n_sync_words = fabm::direct_grid_sync_words(kGridMax);
         off = align_up(off + sizeof(uint32_t) * L.n_sync_words);
     }
@@ -693,6 +693,11 @@ fabm_status run_solve(fabm_plan_s *pl, void *ws, int64_t batch, const double *al
     double *F = (double *)(base + L.f);
     if (batch == 1 && N[0] >= kGridDirectMinSteps) {
         double *part = (double *)(base + L.part);
+        // every partial slot starts marked empty
+        if ((st = ok_or_device(fabm::launch_fill_u32(
+                 (uint32_t *)part, (int64_t)(2 * fabm::direct_grid_part_doubles(kGridMax)),
+                 fabm::direct_grid_empty_word(), s))) != FABM_OK)
+            return st;
         if (T) HIP_TRY(T->begin(fabm::KC_DIRECT_GRID, s));
         st = ok_or_device(fabm::launch_direct_grid(pl->desc.system, d, pl->grid_G, dmeta, dcmeta,
                                                    params, y0, y1, F, W, Yi, status, part, sync,

@@ -292,15 +292,54 @@ __device__ __forceinline__ void partial_sums_orders_coh(const double *__restrict
     }
 }
 
-// Spin until the step tag *p has reached v (modulo 2^32), or *abort is
-// raised, or the wall clock passes `deadline` (then *abort is raised). Every
-// wait is bounded, so a mistake ends the launch with an error status instead
-// of a hung GPU.
-__device__ __forceinline__ bool wait_tag(uint32_t *p, uint32_t v, uint32_t *abort,
-                                         uint64_t deadline)
+// One hand-off per step. At step t every workgroup g reduces its slice
+// [t g / G, t (g + 1) / G) of the history (rows up to t - 2 from memory, the
+// newest row t - 1 from its own registers) and stores its partial in its slot
+// of buffer t mod 3; thread j of every workgroup waits until workgroup j's
+// slot holds values (the slot's previous contents were replaced by a marker
+// value no arithmetic produces), reads them, and the partials are added in
+// workgroup order, so every workgroup forms row t itself, bitwise the same,
+// and no row has to be published before the next step. Workgroup 0 writes
+// the rows to F (through to the coherence point) and Y.
+// Ordering without cache maintenance: partials, markers and history rows are
+// stored and loaded at the coherence point. At the start of step t a
+// workgroup marks its slot of step t + 1 (buffer (t + 1) mod 3, last read at
+// step t - 2, and every workgroup has finished reading step t - 2 before it
+// stored its step t - 1 partial, all of which this workgroup has read); its
+// step t partial is stored only after its earlier stores are acknowledged
+// (the marking, and workgroup 0's row t - 1), so a reader that sees a
+// workgroup's step t values finds its step t + 1 slot marked, and a history
+// row, read two steps after it was formed, is in place. Every slot starts
+// marked (filled before the launch); abort word at kSyncLine * 17.
+constexpr int kSyncLine = 64;   // words per line of the sync area
+constexpr int kSlot = 16;       // doubles per partial slot (2d <= 8 used; 128 bytes)
+constexpr int kSlotBuffers = 3;
+// the marker of an empty slot: a signalling NaN (arithmetic yields quiet NaNs)
+constexpr uint32_t kEmptyWord = 0xFFF4A5A5u;
+constexpr uint64_t kEmptyBits = ((uint64_t)kEmptyWord << 32) | kEmptyWord;
+
+__device__ __forceinline__ bool slot_empty(double v)
+{
+    return __builtin_bit_cast(uint64_t, v) == kEmptyBits;
+}
+
+// Spin until every value of slot q is present (then they are in qp, qc), or
+// *abort is raised, or the wall clock passes `deadline` (then *abort is
+// raised). Every wait is bounded, so a mistake ends the launch with an error
+// status instead of a hung GPU.
+template <int D>
+__device__ __forceinline__ bool wait_slot(const double *q, double (&qp)[D], double (&qc)[D],
+                                          uint32_t *abort, uint64_t deadline)
 {
     for (;;) {
-        if ((int32_t)(flag_read(p) - v) >= 0) return true;
+        bool full = true;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            qp[i] = coh_load(&q[i]);
+            qc[i] = coh_load(&q[D + i]);
+            full = full && !slot_empty(qp[i]) && !slot_empty(qc[i]);
+        }
+        if (full) return true;
         if (flag_read(abort) != 0u) return false;
         if (wall_clock64() > deadline) {
             flag_max(abort, 1u);
@@ -309,28 +348,6 @@ __device__ __forceinline__ bool wait_tag(uint32_t *p, uint32_t v, uint32_t *abor
         __builtin_amdgcn_s_sleep(1);
     }
 }
-
-// One hand-off per step. At step t every workgroup g reduces its slice
-// [t g / G, t (g + 1) / G) of the history (rows up to t - 2 from memory, the
-// newest row t - 1 from its own registers), stores its partial in its slot of
-// the step's parity and then the step number in its tag; thread j of every
-// workgroup waits for workgroup j's tag, reads its partial, and the partials
-// are added in workgroup order, so every workgroup forms row t itself,
-// bitwise the same, and no row has to be published before the next step.
-// Workgroup 0 writes the rows to F (through to the coherence point) and Y.
-// Ordering without cache maintenance: partials, tags and history rows are
-// stored and loaded at the coherence point; a workgroup's tag is stored only
-// after its earlier stores are acknowledged (workgroup 0's row t - 1 among
-// them), and a row is read two steps after it was formed, after the tag of
-// the step in between. A slot of parity t & 1 is rewritten at step t + 2 only
-// after its writer has read every partial of step t + 1, i.e. after every
-// workgroup has finished reading step t's. Tags start at zero (the sync words
-// are cleared before the launch); kTagPitch words apart (one 128-byte line
-// each); abort word at kSyncLine * 17.
-constexpr int kSyncLine = 64;   // words per line of the sync area
-constexpr int kTagBase = kSyncLine * 18;
-constexpr int kTagPitch = 32;   // words between step tags
-constexpr int kSlot = 16;       // doubles per partial slot (2d <= 8 used)
 
 template <int SYS, int D, bool PC>
 __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restrict__ meta,
@@ -353,7 +370,6 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
     const int64_t N = m.N;
     const double *wb = W + m.w_off, *wa = wb + m.wlen, *wc = wa + m.wlen;
     const double *p = params;
-    uint32_t *tags = sync + kTagBase;
     uint32_t *abort = sync + kSyncLine * 17;
     double y0[D], y1[D];
 #pragma unroll
@@ -385,7 +401,14 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
     for (int i = 0; i < D; ++i) pp[i] = pq[i] = 0.0;
     int64_t t = 1;
     for (; t <= N; ++t) {
-        if (tid == 0) s_stop = 0;
+        if (tid == 0) {
+            s_stop = 0;
+            // mark this workgroup's slot of step t + 1
+            double *nx = part + ((int64_t)((t + 1) % kSlotBuffers) * G + g) * kSlot;
+            const double empty = __builtin_bit_cast(double, kEmptyBits);
+#pragma unroll
+            for (int i = 0; i < 2 * D; ++i) coh_store(&nx[i], empty);
+        }
         const int64_t lo = (t * g) / G, hi = (t * (g + 1)) / G;
         // the newest row t - 1 completes the sums (it is the last k of the
         // thread that holds it, as in a plain pass over the slice)
@@ -405,22 +428,21 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
             }
         }
         block_sum2<D>(sp, sc, red, tid);
-        const int par = (int)(t & 1);
+        const int buf = (int)(t % kSlotBuffers);
         if (tid == 0) {
-            double *slot = part + ((int64_t)par * G + g) * kSlot;
+            // the marking above and workgroup 0's row t - 1 first
+            stores_done();
+            double *slot = part + ((int64_t)buf * G + g) * kSlot;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 coh_store(&slot[i], sp[i]);
                 coh_store(&slot[D + i], sc[i]);
             }
-            stores_done();
-            __hip_atomic_store(&tags[(par * G + g) * kTagPitch], (uint32_t)t, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
         }
         // While the other partials of step t arrive: the sums for target t + 1
         // over its slice up to row t - 1 (row t - 1 from registers, earlier
-        // rows from memory: row t - 2 was stored before workgroup 0's tag of
-        // step t - 1)
+        // rows from memory: row t - 2 was stored before workgroup 0's partial
+        // of step t - 1)
         if (t < N) {
             const int64_t lo1 = ((t + 1) * g) / G, hi1 = ((t + 1) * (g + 1)) / G;
             const int64_t hm = hi1 < t ? hi1 : t;
@@ -431,16 +453,10 @@ __global__ __launch_bounds__(kBlock) void k_direct_grid(const InstMeta *__restri
 #pragma unroll
         for (int i = 0; i < D; ++i) qp[i] = qc[i] = 0.0;
         if (tid < G) {
-            const bool ok = wait_tag(&tags[(par * G + tid) * kTagPitch], (uint32_t)t, abort,
-                                     wall_clock64() + deadline_step);
-            if (ok) {
-                const double *q = part + ((int64_t)par * G + tid) * kSlot;
+            const double *q = part + ((int64_t)buf * G + tid) * kSlot;
+            if (!wait_slot<D>(q, qp, qc, abort, wall_clock64() + deadline_step)) {
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    qp[i] = coh_load(&q[i]);
-                    qc[i] = coh_load(&q[D + i]);
-                }
-            } else {
+                for (int i = 0; i < D; ++i) qp[i] = qc[i] = 0.0;
                 s_stop = 1;
             }
         }
@@ -641,8 +657,9 @@ hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, const InstMeta
     return hipErrorInvalidValue;
 }
 
-size_t direct_grid_part_doubles(int G) { return (size_t)2 * kSlot * (size_t)G; }
-size_t direct_grid_sync_words(int G) { return (size_t)kTagBase + (size_t)2 * kTagPitch * (size_t)G; }
+size_t direct_grid_part_doubles(int G) { return (size_t)kSlotBuffers * kSlot * (size_t)G; }
+size_t direct_grid_sync_words(int) { return (size_t)kSyncLine * 18; }
+uint32_t direct_grid_empty_word() { return kEmptyWord; }
 
 hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const InstMeta *cmeta,
                               const double *params, const double *y0, const double *y1,

@@ -57,13 +57,15 @@ hipError_t launch_direct_wg(int sys, int d, const InstMeta *meta, const InstMeta
                             int64_t *status, hipStream_t s);
 
 // DIRECT path, one trajectory spread over the whole GPU (persistent,
-// cooperative launch); `part` holds direct_grid_part_doubles(G) doubles (one
-// partial slot per workgroup and step parity), `sync` direct_grid_sync_words(G)
-// zeroed words (abort word and one step tag per workgroup and parity, in lines
-// of their own). Every inter-workgroup wait gives up after `timeout_ticks` of
-// the device's constant-rate wall clock (status -1).
+// cooperative launch); `part` holds direct_grid_part_doubles(G) doubles (a
+// partial slot per workgroup in each of three step buffers), every 32-bit
+// word set to direct_grid_empty_word() before the launch; `sync`
+// direct_grid_sync_words(G) zeroed words (the abort word). Every
+// inter-workgroup wait gives up after `timeout_ticks` of the device's
+// constant-rate wall clock (status -1).
 size_t direct_grid_part_doubles(int G);
 size_t direct_grid_sync_words(int G);
+uint32_t direct_grid_empty_word();
 hipError_t launch_direct_grid(int sys, int d, int G, const InstMeta *meta, const InstMeta *cmeta,
                               const double *params, const double *y0, const double *y1,
                               double *F, const double *W, double *Y, int64_t *status,
