@@ -600,6 +600,15 @@ __device__ __forceinline__ void stage_sources(const InstView &A, int s, T *sB, i
     }
 }
 
+// Far and near sums are stored through to memory (agent-scope stores): no
+// workgroup of the same launch reads them again, and the launch that does
+// may run on another XCD, so lines left dirty in this XCD's L2 would only be
+// written back when the launch ends, lengthening it.
+__device__ __forceinline__ void store_through(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One column lag q = 16 m + u of a target block, for both weight tables and
 // all components, added into `acc` (one wavefront). The history column of
 // lane rho is staged column rho - u + coff; columns past the staged range
@@ -732,7 +741,7 @@ __device__ __forceinline__ void far_target_f32(const InstView &A, int s, int J, 
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) aj[(t * D + i) * kBlk + e[v]] = x[t][i][v];
+            for (int v = 0; v < 4; ++v) store_through(&aj[(t * D + i) * kBlk + e[v]], x[t][i][v]);
 }
 
 // Far windows of target block J from the NP source blocks s - NP + 1 .. s
@@ -769,7 +778,7 @@ __device__ __forceinline__ void far_target(const InstView &A, int s, int J, cons
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) aj[((t * D + i) * 4 + v) * kWave] = acc[t][i][v];
+            for (int v = 0; v < 4; ++v) store_through(&aj[((t * D + i) * 4 + v) * kWave], acc[t][i][v]);
 }
 
 // Near part of target block J = s + 2: column lags 17..47, i.e. window m = 2
@@ -814,7 +823,7 @@ __device__ __forceinline__ void near_part(const InstView &A, int s, const double
             double v = s == 0 ? 0.0 : aj[e];
 #pragma unroll
             for (int k = 0; k < NW; ++k) v += red[k * 2 * D * kBlk + e];
-            aj[e] = v;
+            store_through(&aj[e], v);
         }
     } else {
         for (int k = 0; k < NW; ++k) {
@@ -832,7 +841,7 @@ __device__ __forceinline__ void near_part(const InstView &A, int s, const double
             __syncthreads();
         }
         for (int e = tid; e < 2 * D * kBlk; e += NW * kWave)
-            aj[e] = (s == 0 ? 0.0 : aj[e]) + red[e];
+            store_through(&aj[e], (s == 0 ? 0.0 : aj[e]) + red[e]);
     }
 }
 
