@@ -30,6 +30,14 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
+// Far sums are stored through to memory (agent-scope stores): the kernels
+// that read them run later, on any XCD, so lines left dirty in the storing
+// XCD's L2 would only be written back at the end of the launch.
+__device__ __forceinline__ void store_through(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Source blocks [I0, I1) of split p out of `splits` for target block s.
 __device__ __forceinline__ void split_range(int s, int p, int splits, int &I0, int &I1)
 {
@@ -53,7 +61,7 @@ __device__ __forceinline__ void store_tiles(const WideArgs &A, int p, int64_t co
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * rt + (F32ROWS ? 4 * g + v : 4 * v + g);
-                out[((int64_t)tb * LW + row) * A.cp + col] = acc[tb][rt][v];
+                store_through(&out[((int64_t)tb * LW + row) * A.cp + col], acc[tb][rt][v]);
             }
 }
 
@@ -402,7 +410,7 @@ __global__ __launch_bounds__(256) void k_wide_reduce(double *part, int64_t n, in
          e += (int64_t)gridDim.x * 256) {
         double v = part[e];
         for (int p = 1; p < splits; ++p) v += part[(int64_t)p * n + e];
-        part[e] = v;
+        store_through(&part[e], v);
     }
 }
 
