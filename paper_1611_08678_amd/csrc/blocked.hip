@@ -654,6 +654,57 @@ __device__ __forceinline__ void window_lag(dbl4 (&acc)[2][D], const double *__re
     }
 }
 
+// window_lag for one weight table `w` (b or a): the same products, in the
+// same order, into that table's accumulators only.
+template <int D, bool PC = false>
+__device__ __forceinline__ void window_lag_table(dbl4 (&acc)[D], const double *__restrict__ w,
+                                                 const double *sB, int64_t m, int u,
+                                                 int64_t cw = 0)
+{
+    constexpr int K = PC ? D : 1;
+    constexpr int NC = kSrcCols;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int sbase = (r16 - u + kTile - 1) * kColPitch + 4 * kq;
+    const int64_t wi = kBlk * m + kTile * u + r16 - 4 * kq - 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double a[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) a[k] = w[k * cw + wi - j];
+        double bf[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) bf[i] = sB[i * NC * kColPitch + sbase + j];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[PC ? i : 0], bf[i], acc[i], 0, 0, 0);
+    }
+}
+
+template <int D, bool PC = false>
+__device__ __forceinline__ void window_lag_table_f32(flt4 (&acc)[D], const float *__restrict__ w,
+                                                     const float *sB, int64_t m, int u,
+                                                     int64_t cw = 0)
+{
+    constexpr int K = PC ? D : 1;
+    constexpr int NC = kSrcCols;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int sbase = (r16 - u + kTile - 1) * kColPitch + 4 * kq;
+    const int64_t wi = kBlk * m + kTile * u + r16 - 4 * kq - 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float a[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) a[k] = w[k * cw + wi - j];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const float bf = sB[i * NC * kColPitch + sbase + j];
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[PC ? i : 0], bf, acc[i], 0, 0, 0);
+        }
+    }
+}
+
 // The same column lag on the binary32 matrix cores (v_mfma_f32_16x16x4f32):
 // weights and history rounded to binary32, products summed in binary32.
 template <int D, int NC = kSrcCols, bool PC = false>
@@ -781,6 +832,66 @@ __device__ __forceinline__ void far_target(const InstView &A, int s, int J, cons
             for (int v = 0; v < 4; ++v) store_through(&aj[((t * D + i) * 4 + v) * kWave], acc[t][i][v]);
 }
 
+// Far window of target block J from source block s for one weight table
+// (tb 0: b, the predictor sums; 1: a, the corrector sums): a work unit of
+// half a target, so the far work of a launch splits over the wavefronts in
+// finer pieces. Each table's sums take the same products in the same order
+// as in far_target.
+template <int D, bool PC = false>
+__device__ __forceinline__ void far_target_table(const InstView &A, int s, int J, int tb,
+                                                 const double *sB, bool first)
+{
+    const InstMeta m = A.meta[0];
+    const double *w = A.W + (tb ? m.wlen : 0);
+    const int64_t cw = 3 * m.wlen;
+    const int lane = threadIdx.x & (kWave - 1);
+    double *aj = A.acc + (int64_t)J * 2 * D * kBlk + (int64_t)tb * D * kBlk + lane;
+    dbl4 acc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][v] = first ? 0.0 : aj[(i * 4 + v) * kWave];
+    const int64_t mm = J - s;
+#pragma unroll 2
+    for (int u = 0; u < kTile; ++u) window_lag_table<D, PC>(acc, w, sB, mm, u, cw);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) store_through(&aj[(i * 4 + v) * kWave], acc[i][v]);
+}
+
+template <int D, bool PC = false>
+__device__ __forceinline__ void far_target_table_f32(const InstView &A, int s, int J, int tb,
+                                                     const float *sB, bool first)
+{
+    const InstMeta m = A.meta[0];
+    const float *w = A.W32 + (tb ? m.wlen : 0);
+    const int64_t cw = 2 * m.wlen;
+    const int lane = threadIdx.x & (kWave - 1);
+    double *aj = A.acc + (int64_t)J * 2 * D * kBlk + (int64_t)tb * D * kBlk;
+    int e[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int sig = f32_result_row(lane, v), rho = lane & 15;
+        e[v] = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
+    }
+    double x[D][4];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[i][v] = first ? 0.0 : aj[i * kBlk + e[v]];
+    flt4 acc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[i] = (flt4){0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t mm = J - s;
+#pragma unroll 2
+    for (int u = 0; u < kTile; ++u) window_lag_table_f32<D, PC>(acc, w, sB, mm, u, cw);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) store_through(&aj[i * kBlk + e[v]], x[i][v] + (double)acc[i][v]);
+}
+
 // Near part of target block J = s + 2: column lags 17..47, i.e. window m = 2
 // (all u, staged columns rho - u + 15) and window m = 1 for u = 1..15
 // (staged columns rho - u + 31, masked past column 30), split over the first
@@ -852,12 +963,14 @@ __device__ __forceinline__ InstView single_view(const StepArgs &A)
 }
 
 // Launch s of the single-trajectory pipeline; `wpw` wavefronts of each far
-// workgroup take part (wavefront g of G handles targets s + 3 + g + k G). With
+// workgroup take part (wavefront g of G handles work units g + k G: target
+// s + 3 + u, or with `halves` weight table u % 2 of target s + 3 + u / 2,
+// when there are more targets than far wavefronts). With
 // the far history of larger distances in FFT squares, far targets end at block
 // `jend` and the far windows take no source rows below `flo` (0 otherwise).
 template <int SYS, int D, bool F32, bool PC = false>
 __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wpw, int jend,
-                                                       int64_t flo)
+                                                       int64_t flo, int halves)
 {
     extern __shared__ __align__(16) char smem[];
     const int b = blockIdx.x, wave = threadIdx.x >> 6;
@@ -881,16 +994,28 @@ __global__ __launch_bounds__(kStepThreads) void k_step(StepArgs A, int s, int wp
         }
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
-        for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
-            far_target<D, 1, PC>(V, s, J, sB, s == 0);
+        if (halves) {
+            const int nu = 2 * (jend - (s + 3));
+            for (int k = (b - 2) * wpw + wave; k < nu; k += G)
+                far_target_table<D, PC>(V, s, s + 3 + (k >> 1), k & 1, sB, s == 0);
+        } else {
+            for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
+                far_target<D, 1, PC>(V, s, J, sB, s == 0);
+        }
     } else {
         float *sB = (float *)smem;
         stage_sources<D, float>(V, s, sB, flo);
         __syncthreads();
         if (wave >= wpw) return;
         const int G = ((int)gridDim.x - 2) * wpw;
-        for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
-            far_target_f32<D, 1, PC>(V, s, J, sB, s == 0);
+        if (halves) {
+            const int nu = 2 * (jend - (s + 3));
+            for (int k = (b - 2) * wpw + wave; k < nu; k += G)
+                far_target_table_f32<D, PC>(V, s, s + 3 + (k >> 1), k & 1, sB, s == 0);
+        } else {
+            for (int J = s + 3 + (b - 2) * wpw + wave; J < jend; J += G)
+                far_target_f32<D, 1, PC>(V, s, J, sB, s == 0);
+        }
     }
 }
 
@@ -1110,20 +1235,28 @@ size_t step_smem_bytes(int d, bool pc)
     return std::max(band, std::max(near, exclusive));
 }
 
-// Grid of launch s: band, near and far workgroups, and the number of active
-// wavefronts per far workgroup (one target each, four per round of SIMDs).
+// Grid of launch s: band, near and far workgroups, the number of active
+// wavefronts per far workgroup (one work unit each, four per round of
+// SIMDs), and the work unit: a whole target, or (`halves`, when the targets
+// outnumber the far wavefronts, so some wavefronts take several) a target's
+// window for one weight table, which splits the far work more evenly.
 // Launch shape of step s: band and near workgroups plus up to far_cap far
 // workgroups of wpw wavefronts (the far loop strides over the targets, so any
 // cap covers all of them).
-void step_grid(int NB, int jend, int s, int *grid, int *wpw, int far_cap)
+void step_grid(int NB, int jend, int s, int *grid, int *wpw, int far_cap, int *halves)
 {
     *grid = 1;
     *wpw = 0;
+    *halves = 0;
     if (s < 0 || s + 2 > NB - 1) return;
     *grid = 2;
-    const int nt = std::min(jend, NB) - (s + 3);  // far targets
+    int nt = std::min(jend, NB) - (s + 3);  // far targets
     if (nt <= 0) return;
     const int cap = std::max(1, std::min(far_cap > 0 ? far_cap : kMaxFarWg, kMaxFarWg));
+    if (nt > cap * (kStepThreads / kWave)) {
+        *halves = 1;
+        nt *= 2;  // work units
+    }
     const int per_round = 4 * cap;
     const int rounds = std::min((nt + per_round - 1) / per_round, kStepThreads / kWave / 4);
     *wpw = 4 * rounds;
@@ -1157,10 +1290,11 @@ static hipError_t enqueue_steps_t(const StepArgs &A, hipStream_t st, KernelTimer
         int grid, wpw;
         const int jend = fft ? fft_far_target_end(A.NB, A.fft_level, s) : A.NB;
         const int64_t flo = fft && fft_far_mask_prev(A.fft_level, s) ? (int64_t)kBlk * s : 0;
-        step_grid(A.NB, jend, s, &grid, &wpw, A.far_cap);
+        int halves;
+        step_grid(A.NB, jend, s, &grid, &wpw, A.far_cap, &halves);
         if (T) FABM_STEP_TRY("timer begin", T->begin(KC_BLOCKED_STEP, st));
         hipLaunchKernelGGL((k_step<SYS, D, F32, PC>), dim3(grid), dim3(kStepThreads), smem, st, A,
-                           s, wpw, jend, flo);
+                           s, wpw, jend, flo, halves);
         FABM_STEP_TRY("launch k_step", hipGetLastError());
         if (T) FABM_STEP_TRY("timer end", T->end(st));
         if (fft && fft_far_square_at(A.NB, A.fft_level, s) >= 0) {

@@ -80,7 +80,7 @@ hipError_t enqueue_steps(int sys, int d, bool f32, const StepArgs &A, hipStream_
                          KernelTimer *T, const char **where);
 int step_block_len();
 size_t step_smem_bytes(int d, bool pc = false);
-void step_grid(int NB, int jend, int s, int *grid, int *wpw, int far_cap);
+void step_grid(int NB, int jend, int s, int *grid, int *wpw, int far_cap, int *halves);
 
 // Sub-quadratic far history of the step pipeline (fft_far.hip). Level l of
 // the dyadic squares covers 2^l source blocks; the host enqueues at most one
