@@ -326,7 +326,10 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
     constexpr int kRing = K == 1 && !kThLds ? kPublishEvery : 1;
     double bwg[kRing][K], awg[kRing][K];
     auto load_row = [&](const int t, const int sl) __attribute__((always_inline)) {
-        const int lag = row - t > 0 ? row - t : 0;
+        // lanes whose row is formed (row < t) read below the table, inside
+        // the tables staged before it (lag >= -(kBlk + kPublishEvery)); their
+        // sums are not used again
+        const int lag = row - t;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             bwg[sl][q] = sbh[q * kBlk + lag];
@@ -384,6 +387,7 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
     // a spare row of their own, lanes of later rows to their row, which the
     // walk overwrites when it gets there
     const int row_off = row * D, spare_off = (kBlk + lane) * D;
+    double *const fy_row = sFY + 2 * row_off, *const fy_spare = sFY + 2 * spare_off;
     int checked = first;  // check values of rows before this one are loaded
     // Rows are published in groups, each one group late: the f and y values
     // of a group are loaded from LDS after it is formed and tested after the
@@ -434,12 +438,13 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
         rhs<SYS, D>(tt, y, f, th);
 #pragma unroll
         for (int i = 0; i < D; ++i) fprev[i] = readlane_f64(f[i], t - lo);
-        const int o = row >= t ? row_off : spare_off;
+        const bool own = row >= t;
+        double *const fy = own ? fy_row : fy_spare;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            sFY[2 * o + i] = f[i];
-            sFY[2 * o + D + i] = y[i];
-            if constexpr (YPOUT) sYP[o + i] = pc[i];
+            fy[i] = f[i];
+            fy[D + i] = y[i];
+            if constexpr (YPOUT) sYP[(own ? row_off : spare_off) + i] = pc[i];
         }
     };
     if constexpr (kRing == 1)
