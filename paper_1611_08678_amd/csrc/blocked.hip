@@ -138,7 +138,7 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
     const int64_t ro = (t0 - A.yrow0) * D;
     // a non-finite state in an earlier block ends the trajectory (tested
     // after the loads below are issued, which read only valid memory)
-    const uint32_t dead_in = __builtin_amdgcn_readfirstlane(*A.dead);
+    const uint32_t dead_ld = *A.dead;
     // theta in registers when short; a linear system's matrix is read from LDS
     constexpr bool kThLds = NP > 12;
     double thr[kThLds || NP == 0 ? 1 : NP], y0[D];
@@ -152,15 +152,41 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
     const double *th = SYS == SYS_TEACHER ? A.params : kThLds ? sTh : thr;
 #pragma unroll
     for (int i = 0; i < D; ++i) y0[i] = A.y0[i];
+    // the weight tables' entries of this thread (lags tid and tid + kBlk),
+    // loaded with the rest of the prologue's reads and stored to LDS after
+    // them, so the prologue waits for memory once
+    static_assert(nthr == kBlk, "one thread per lag of the staged tables");
+    double wst[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        for (int j = tid; j < 2 * kBlk; j += nthr) {
-            sb[k * 2 * kBlk + j] = wb[k * cw + j];
-            sa[k * 2 * kBlk + j] = wa[k * cw + j];
-        }
-        for (int j = tid; j < kBlk; j += nthr) {
-            sbh[k * kBlk + j] = hav[k] * wb[k * cw + j];
-            sah[k * kBlk + j] = hav[k] * wa[k * cw + j];
+        wst[k][0] = wb[k * cw + tid];
+        wst[k][1] = wb[k * cw + tid + kBlk];
+        wst[k][2] = wa[k * cw + tid];
+        wst[k][3] = wa[k * cw + tid + kBlk];
+    }
+    // The reads of a later block's sums, issued here for every block (each
+    // address lies inside its array for any J; block 0 does not use them):
+    // f_0, the carried sums, the near and far sums and the c - a weights.
+    const int row = 64 * wave + lane;
+    const int64_t T = t0 + row;
+    double f0ld[D], cinP[D], cinC[D], accP[D], accC[D], wcT[D], waT[D];
+    {
+        const double *cin = A.carry + (int64_t)(J & 1) * 2 * D * kBlk;
+        // near + far sums, stored in MFMA result order: row 16 rho + sigma
+        // is element sigma/4 of lane 16 (sigma % 4) + rho
+        const int rho = row >> 4, sig = row & 15;
+        const int e = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
+        const double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int64_t o = PC ? i * cw : 0;
+            f0ld[i] = A.Fc[i * pitch];
+            cinP[i] = cin[i * kBlk + row];
+            cinC[i] = cin[(D + i) * kBlk + row];
+            accP[i] = aj[i * kBlk + e];
+            accC[i] = aj[(D + i) * kBlk + e];
+            wcT[i] = wc[o + T - 1];
+            waT[i] = wa[o + T - 1];
         }
     }
     // f_0 (block 0 forms row 0 here; later blocks need it for the c - a fix)
@@ -169,7 +195,7 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
         rhs<SYS, D>(0.0, y0, f0, A.params);
     } else {
 #pragma unroll
-        for (int i = 0; i < D; ++i) f0[i] = A.Fc[i * pitch];
+        for (int i = 0; i < D; ++i) f0[i] = f0ld[i];
     }
     if (tid == 0) {
         *s_cnt = J == 0 ? 1 : 0;
@@ -187,8 +213,6 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
     // y0 + h^a C (what the predictor and corrector add the newest term to;
     // for orders above one y0 + t_T y'(0) in place of y0), of the next block
     // as plain P and C (handed over through `carry`).
-    const int row = 64 * wave + lane;
-    const int64_t T = t0 + row;
     double base[D];
     {
         double y1[D];
@@ -213,27 +237,20 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
             cn[i] = wc[o + kBlk + row - 1] * f0[i];
         }
     } else {
-        const double *cin = A.carry + (int64_t)(J & 1) * 2 * D * kBlk;
         double P[D], Cs[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            P[i] = cin[i * kBlk + row];
-            Cs[i] = cin[(D + i) * kBlk + row];
+            P[i] = cinP[i];
+            Cs[i] = cinC[i];
             pn[i] = cn[i] = 0.0;
         }
         if (J >= 2) {
-            // near + far sums, stored in MFMA result order: row 16 rho + sigma
-            // is element sigma/4 of lane 16 (sigma % 4) + rho
-            const int rho = row >> 4, sig = row & 15;
-            const int e = (sig >> 2) * kWave + 16 * (sig & 3) + rho;
-            const double *aj = A.acc + (int64_t)J * 2 * D * kBlk;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const int64_t o = PC ? i * cw : 0;
-                const double dca = wc[o + T - 1] - wa[o + T - 1];
-                P[i] += aj[i * kBlk + e];
+                const double dca = wcT[i] - waT[i];
+                P[i] += accP[i];
                 // source row 0 takes c_{T-1} where the tiles used a_{T-1}
-                Cs[i] = fma(dca, f0[i], Cs[i] + aj[(D + i) * kBlk + e]);
+                Cs[i] = fma(dca, f0[i], Cs[i] + accC[i]);
             }
         }
 #pragma unroll
@@ -242,12 +259,22 @@ __device__ __forceinline__ void band_block(const InstView &A, const InstMeta &mv
             cc[i] = fma(hav[PC ? i : 0], Cs[i], base[i]);
         }
     }
+    const uint32_t dead_in = __builtin_amdgcn_readfirstlane(dead_ld);
     if (dead_in != 0u) {
         for (int e = tid; e < nrows * D; e += nthr) {
             if (A.Y) A.Y[ro + e] = __builtin_nan("");
             if constexpr (YPOUT) A.YP[ro + e] = __builtin_nan("");
         }
         return;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        sb[k * 2 * kBlk + tid] = wst[k][0];
+        sb[k * 2 * kBlk + tid + kBlk] = wst[k][1];
+        sa[k * 2 * kBlk + tid] = wst[k][2];
+        sa[k * 2 * kBlk + tid + kBlk] = wst[k][3];
+        sbh[k * kBlk + tid] = hav[k] * wst[k][0];
+        sah[k * kBlk + tid] = hav[k] * wst[k][2];
     }
     __syncthreads();
 
