@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
 # reference copy kernel (profiles/k_step_chen_N2p20_pmc.md), valid only for
 # the kernel source it was measured on (sha256 prefix of blocked.hip).
-MEASURED_TRAFFIC = {"k_step": (59.02e6, "8cc1ad5d284d3765")}
+MEASURED_TRAFFIC = {"k_step": (59.04e6, "59d76e7be25d90c6")}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense binary16 matrix rate
