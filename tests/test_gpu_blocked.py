@@ -204,6 +204,34 @@ def test_blocked_hindmarsh_rose_longest_table_size(F, orc):
         assert np.all(np.abs(yy[t] - yt) <= tol), (t, yy[t], yt, mag)
 
 
+def test_blocked_hindmarsh_rose_longest_table_size_fp32(F, orc):
+    """N = 3e6 with binary32 far windows: while a launch's far targets
+    outnumber the far wavefronts (the first ~7650 launches) each target's
+    window is split into one work unit per weight table, here in the binary32
+    form. Status 0, finite and inside the attractor's box, and sampled rows,
+    among them rows formed while those launches ran, re-formed by the oracle
+    from the GPU's own history within 2^-17 of the history magnitude (the
+    binary32 far sums round each term at 2^-24; the bound used for the
+    Rossler batch at full size)."""
+    from paper_1611_08678_amd import workloads as W
+    N = W.TABLE2_N[-1]
+    w = W.hindmarsh_rose(N=N)
+    th, a, h, y0 = w["theta"][0], w["alpha"][0], w["h"][0], w["y0"][0]
+    y, st = F.solve("hindmarsh_rose", th, a, h, N, y0, path="blocked", far_prec="fp32")
+    yy = _to_np(y)
+    assert int(st.item()) == 0
+    assert np.all(np.isfinite(yy))
+    assert np.all(np.abs(yy[:, 0]) < 3) and np.all(np.abs(yy[:, 1]) < 20)
+    assert np.all(np.abs(yy[:, 2]) < 6)
+    u = np.finfo(np.float64).eps / 2
+    wts = orc.weights(a, N)
+    f = orc.rhs_rows(w["system"], th, h, yy)
+    for t in (4097, 100_000, 1_000_000, 1_900_003, 2_500_000, N):
+        yt, mag = orc.step_from_history(w["system"], th, a, h, t, y0, f, wts)
+        tol = 2.0 ** -17 * mag + 4 * u * np.abs(yt)
+        assert np.all(np.abs(yy[t] - yt) <= tol), (t, yy[t], yt, mag)
+
+
 def test_blocked_kernel_times(F):
     """The profiling interface reports one step launch per 256-row block."""
     import torch
